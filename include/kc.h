@@ -1,0 +1,130 @@
+/* kc.h -- C ABI of libkc.so, a sorting-based canonical k-mer counter for AMD MI355X
+ * (gfx950).
+ *
+ * What is computed (the method of "High-Performance Sorting-Based k-mer Counting in
+ * Distributed Memory with Flexible Hybrid Parallelism", Li & Guidi, ICPP 2024):
+ *   every window of k consecutive bases inside a read is a k-mer (Section 2.1); its
+ *   canonical value is the smaller of its 2-bit value (A0 C1 G2 T3, first base most
+ *   significant) and that of its reverse complement; all canonical k-mers are sorted so
+ *   that equal values are adjacent and each value is counted as one run (Section 3.1);
+ *   the result is the frequency histogram and the (k-mer, count) pairs whose count lies
+ *   in [min_freq, max_freq] (Section 3.1; the bounds 2 and 50 of Section 4).  Counts are
+ *   exact (Section 3.3).  Internally the k-mers travel as supermers grouped by
+ *   minimizer (Section 3.2) into HBM buckets that stand in for the paper's tasks
+ *   (Section 3.4); `m` only steers that grouping and never changes the result.
+ *
+ * Input layout: read r is reads[offsets[r] .. offsets[r+1]); offsets has n_reads + 1
+ * non-decreasing entries.  Bytes A C G T (either case) are bases; any other byte
+ * invalidates every window that covers it.
+ *
+ * Output layout: pairs in ascending canonical value; a k-mer takes key_words 64-bit
+ * words (1 for k <= 31; 2 for 32 <= k <= 63, stored {low, high}).  hist has hist_len
+ * bins: bin 0 is 0, bin c (1 <= c <= hist_len-2) counts distinct k-mers seen exactly c
+ * times and bin hist_len-1 those seen hist_len-1 times or more; the histogram covers
+ * every distinct k-mer, before the frequency filter.
+ *
+ * Errors: every call returns KC_OK (0) or a negative code; kc_last_error() gives a
+ * message for the calling thread.  On error, outputs are zeroed and nothing leaks.
+ */
+#ifndef KC_H
+#define KC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KC_OK 0
+#define KC_EINVAL (-1)     /* bad argument: k, m, frequency bounds, hist_len, NULL, offsets, size */
+#define KC_ENOMEM (-2)     /* device workspace larger than the budget or than free HBM */
+#define KC_EDEVICE (-3)    /* HIP runtime error */
+#define KC_ETRUNC (-4)     /* a caller-provided device output buffer is too small */
+#define KC_EAGAIN (-5)     /* not complete yet (server poll) */
+#define KC_ECANCELED (-6)  /* job was cancelled */
+
+/* Tuning knobs.  A zero field means "choose automatically". */
+typedef struct kc_config {
+  uint32_t log2_buckets;   /* buckets B = 2^log2_buckets (1..20); 0 = from the input size */
+  uint32_t force_hbm;      /* 1 = send every bucket through the HBM sort path (testing) */
+  uint32_t small_variant;  /* on-chip sort block shape: 0 auto, 1 = 256x16, 2 = 512x16 */
+  uint32_t reserved;
+  uint64_t hbm_budget;     /* max workspace bytes; 0 = no limit other than free HBM */
+} kc_config;
+
+/* Totals of one count, as also written to device memory by kc_count_device. */
+typedef struct kc_totals {
+  uint64_t n_pairs;        /* k-mers with min_freq <= count <= max_freq */
+  uint64_t n_windows;      /* valid k-mer windows (= sum of all counts) */
+  uint64_t n_distinct;     /* distinct canonical k-mers (= sum of hist) */
+  uint64_t overflow_sum;   /* sum of the counts of k-mers in the last histogram bin */
+  uint64_t max_count;
+  uint64_t n_records;      /* supermer records the partition wrote */
+  uint64_t flags;          /* internal status; 0 on success */
+  uint64_t large_keys;     /* k-mers sorted through the HBM path (large buckets) */
+} kc_totals;
+
+typedef struct kc_result {
+  uint64_t n_pairs;
+  uint32_t key_words;
+  uint64_t *kmers;         /* n_pairs * key_words words, ascending */
+  uint32_t *counts;        /* n_pairs */
+  uint64_t *hist;          /* hist_len bins */
+  uint64_t hist_len;
+  kc_totals totals;
+} kc_result;
+
+/* Version string of the library. */
+const char *kc_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *kc_last_error(void);
+
+/* Host API.  Count the canonical k-mers of a read set held in host memory.
+ *   reads, offsets: host pointers (borrowed, not modified); total bases = offsets[n_reads].
+ *   k in [1, 63]; m in [1, min(k-1, 32)]; 1 <= min_freq <= max_freq; hist_len >= 2.
+ *   cfg may be NULL.  On KC_OK, *out owns host arrays that kc_result_free releases.
+ *   Errors: KC_EINVAL (arguments, non-monotone offsets, more than 2^32-1 windows),
+ *   KC_ENOMEM, KC_EDEVICE. */
+int kc_count(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k, int m,
+             uint32_t min_freq, uint32_t max_freq, uint64_t hist_len, const kc_config *cfg,
+             kc_result *out);
+
+/* Release the arrays of a kc_result filled by kc_count (safe on a zeroed result). */
+void kc_result_free(kc_result *res);
+
+/* Bytes of device workspace kc_count_device needs for a read buffer of total_bases
+ * bytes split into n_reads reads, at this k (0 on bad arguments). */
+size_t kc_workspace_size(uint64_t total_bases, uint64_t n_reads, int k, const kc_config *cfg);
+
+/* Device API.  Same count with every buffer in device memory owned by the caller.
+ *   d_reads: total_bases bytes; d_offsets: n_reads + 1 entries (values <= total_bases).
+ *   d_workspace: at least kc_workspace_size(total_bases, n_reads, k, cfg) bytes, 256-byte
+ *   aligned.  Outputs: d_kmers (pair_capacity * key_words words), d_counts
+ *   (pair_capacity), d_hist (hist_len u64), d_totals (one kc_totals).
+ *   stream: a hipStream_t (NULL = the default stream); all work is queued on it.
+ *   The call waits for the stream, copies the totals to *totals_out (may be NULL) and
+ *   returns KC_ETRUNC when n_pairs > pair_capacity (the first pair_capacity pairs are
+ *   written, totals give the size needed); KC_EINVAL if the offsets are not monotone
+ *   or exceed total_bases.  Calls on one workspace must not overlap. */
+int kc_count_device(const uint8_t *d_reads, uint64_t total_bases, const uint64_t *d_offsets,
+                    uint64_t n_reads, int k, int m, uint32_t min_freq, uint32_t max_freq,
+                    uint64_t hist_len, const kc_config *cfg, void *d_workspace, size_t workspace_bytes,
+                    uint64_t *d_kmers, uint32_t *d_counts, uint64_t pair_capacity, uint64_t *d_hist,
+                    kc_totals *d_totals, void *stream, kc_totals *totals_out);
+
+/* As kc_count_device but returns right after queueing the work (no wait, no KC_ETRUNC
+ * or offset check at return): read *d_totals after synchronizing the stream;
+ * totals.flags != 0 marks a failed count and n_pairs > pair_capacity a truncation. */
+int kc_count_device_async(const uint8_t *d_reads, uint64_t total_bases, const uint64_t *d_offsets,
+                          uint64_t n_reads, int k, int m, uint32_t min_freq, uint32_t max_freq,
+                          uint64_t hist_len, const kc_config *cfg, void *d_workspace,
+                          size_t workspace_bytes, uint64_t *d_kmers, uint32_t *d_counts,
+                          uint64_t pair_capacity, uint64_t *d_hist, kc_totals *d_totals, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KC_H */

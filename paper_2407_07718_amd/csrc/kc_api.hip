@@ -1,0 +1,509 @@
+// libkc.so: host runtime and C ABI of the k-mer counter (see include/kc.h).
+//
+// One count is a fixed sequence of kernels on one stream.  Every data-dependent size
+// (records, bucket lists, large k-mers, runs, survivors) stays in device memory and is
+// read by the kernels themselves, so the sequence needs no host round trip until the
+// final totals -- which is also what lets a batch of counts be captured as one graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/kc.h"
+#include "kc_common.hpp"
+#include "kc_count.hpp"
+#include "kc_partition.hpp"
+#include "kc_sort.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(KC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int RADIX_T = 256;
+constexpr int RADIX_ITEMS_64 = 16;
+constexpr int RADIX_ITEMS_128 = 8;
+
+inline u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
+inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
+
+// Sizes and byte offsets of every workspace region for one (input size, k, config).
+struct Plan {
+  int k = 0, m = 0, key_words = 0, rec_words = 0, gmax = 0, log_b = 0;
+  u32 B = 0, cap = 0, variant = 1;
+  u64 R = 0, n_reads = 0, n_max = 0;   // bases, reads, bound on windows
+  u64 rec_cap = 0, surv_cap = 0;
+  u32 nb_large = 1, nb_surv = 1;        // radix blocks
+  // offsets into the workspace
+  u64 o_packed, o_nmask, o_starts, o_recA, o_recB, o_bid, o_bcnt, o_recoff, o_cursor, o_small, o_large,
+      o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_bc, o_hp, o_surv0k, o_surv0c, o_surv1k, o_surv1c;
+  u64 n_packed, n_mask, bytes = 0;
+};
+
+// Control words (all zeroed at the start of a count).
+enum Ctrl : int {
+  C_COUNTERS = 0,   // [0] records, [1] windows
+  C_META = 2,       // [0] n_small, [1] n_large, [2] large k-mers, [3] records
+  C_FLAGS = 6,
+  C_QUEUE = 7,
+  C_SURV_N = 8,
+  C_NRUNS = 9,
+  C_SURV_NC = 10,   // survivors, clamped to capacity
+  C_WORDS = 16
+};
+
+u32 default_variant(int key_words) { return key_words == 1 ? 1u : 1u; }
+u32 small_cap(int key_words, u32 variant) {
+  if (key_words == 1) return variant == 2 ? 512u * 16u : 256u * 16u;
+  return variant == 2 ? 512u * 8u : 256u * 8u;
+}
+
+bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, const kc_config* cfg,
+               Plan* p) {
+  p->k = k;
+  p->m = m;
+  p->R = R;
+  p->n_reads = n_reads;
+  p->n_max = n_max;
+  p->key_words = k <= 31 ? 1 : 2;
+  p->rec_words = k <= 31 ? 4 : 8;
+  const int cap_bases = k <= 31 ? 61 : 125;
+  p->gmax = std::min(64, cap_bases - k + 1);
+  p->variant = (cfg && cfg->small_variant) ? cfg->small_variant : default_variant(p->key_words);
+  if (p->variant > 2) return false;
+  p->cap = small_cap(p->key_words, p->variant);
+  if (cfg && cfg->force_hbm) p->cap = 0;
+  if (cfg && cfg->log2_buckets) {
+    if (cfg->log2_buckets > 20) return false;
+    p->log_b = (int)cfg->log2_buckets;
+  } else {
+    // mean bucket about a third of the on-chip capacity
+    const u64 target = std::max<u64>(1, small_cap(p->key_words, p->variant) / 3);
+    int lb = 1;
+    while (lb < 20 && (n_max >> lb) > target) ++lb;
+    p->log_b = lb;
+  }
+  p->B = 1u << p->log_b;
+  p->rec_cap = std::max<u64>(1, n_max);
+  p->surv_cap = std::max<u64>(1, n_max / std::max<u32>(1, min_freq));
+  const u64 w = 8ull * p->key_words;
+  const u64 tile = (u64)RADIX_T * (p->key_words == 1 ? RADIX_ITEMS_64 : RADIX_ITEMS_128);
+  p->nb_large = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(n_max, tile * 2)));
+  p->nb_surv = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(p->surv_cap, tile * 2)));
+  p->n_packed = R / 16 + 16;
+  p->n_mask = R / 32 + 16;
+  u64 o = 0;
+  auto take = [&](u64 bytes) {
+    u64 r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  const u64 rb = 4ull * p->rec_words;
+  p->o_packed = take(4 * p->n_packed);
+  p->o_nmask = take(4 * p->n_mask);
+  p->o_starts = take(4 * p->n_mask);
+  // unsorted records; after the scatter the same bytes hold the two large-key arrays
+  p->o_recA = take(std::max(rb * p->rec_cap, 2 * w * p->rec_cap));
+  p->o_recB = take(rb * p->rec_cap);
+  p->o_bid = take(4 * p->rec_cap);
+  p->o_bcnt = take(8ull * p->B);
+  p->o_recoff = take(4ull * (p->B + 1));
+  p->o_cursor = take(4ull * p->B);
+  p->o_small = take(4ull * p->B);
+  p->o_large = take(4ull * p->B);
+  p->o_lkoff = take(8ull * p->B);
+  p->o_ctrl = take(8ull * C_WORDS);
+  p->o_cnt_large = take(4ull * 256 * p->nb_large);
+  p->o_cnt_surv = take(4ull * 256 * p->nb_surv);
+  p->o_bc = take(4ull * 1024);
+  p->o_hp = take(4 * p->rec_cap);
+  p->o_surv0k = take(w * p->surv_cap);
+  p->o_surv0c = take(4 * p->surv_cap);
+  p->o_surv1k = take(w * p->surv_cap);
+  p->o_surv1c = take(4 * p->surv_cap);
+  p->bytes = o;
+  return true;
+}
+
+int check_args(int k, int m, uint32_t lo, uint32_t hi, uint64_t hist_len) {
+  if (k < 1 || k > 63) return fail(KC_EINVAL, "k=%d outside [1, 63]", k);
+  if (m < 1 || m > std::min(k - 1, 32)) return fail(KC_EINVAL, "m=%d outside [1, min(k-1, 32)] for k=%d", m, k);
+  if (lo < 1 || lo > hi) return fail(KC_EINVAL, "frequency bounds [%u, %u] invalid", lo, hi);
+  if (hist_len < 2) return fail(KC_EINVAL, "hist_len=%llu < 2", (unsigned long long)hist_len);
+  return KC_OK;
+}
+
+int device_info(int* n_cu) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  return KC_OK;
+}
+
+template <typename K>
+K* at(void* ws, u64 off) {
+  return reinterpret_cast<K*>(reinterpret_cast<char*>(ws) + off);
+}
+
+template <typename K, bool HASV>
+int radix_sort(K* k0, K* k1, u32* v0, u32* v1, const u64* n_ptr, u32* counts, u32 nb, int nbits,
+               hipStream_t st, bool* in_second) {
+  constexpr int ITEMS = sizeof(K) == 8 ? RADIX_ITEMS_64 : RADIX_ITEMS_128;
+  K* src = k0;
+  K* dst = k1;
+  u32* vs = v0;
+  u32* vd = v1;
+  int passes = 0;
+  for (int sh = 0; sh < nbits; sh += 8) {
+    hipLaunchKernelGGL((k_radix_upsweep<K>), dim3(nb), dim3(256), 0, st, src, n_ptr, counts, sh);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, counts, (u64)256 * nb, (u64*)nullptr);
+    hipLaunchKernelGGL((k_radix_downsweep<K, HASV, RADIX_T, ITEMS>), dim3(nb), dim3(RADIX_T), 0, st, src, dst, vs,
+                       vd, n_ptr, counts, sh);
+    std::swap(src, dst);
+    std::swap(vs, vd);
+    ++passes;
+  }
+  *in_second = (passes & 1) != 0;
+  HIP_TRY(hipGetLastError());
+  return KC_OK;
+}
+
+__global__ void k_clamp(const u64* src, u64 cap, u64* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = min(*src, cap);
+}
+
+__global__ void k_totals_meta(DevTotals* tot, const u64* meta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) tot->large_keys = meta[2];
+}
+
+inline dim3 grid_for(u64 n, u32 block, u32 max_blocks = 1u << 20) {
+  return dim3((u32)std::max<u64>(1, std::min<u64>(max_blocks, ceil_div(n, block))));
+}
+
+// Queue one full count on `st`.
+template <typename K>
+int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_offsets, uint32_t lo, uint32_t hi,
+            uint64_t hist_len, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap, uint64_t* d_hist,
+            DevTotals* d_tot, hipStream_t st) {
+  int n_cu = 0;
+  int rc = device_info(&n_cu);
+  if (rc) return rc;
+  u32* packed = at<u32>(ws, P.o_packed);
+  u32* nmask = at<u32>(ws, P.o_nmask);
+  u32* starts = at<u32>(ws, P.o_starts);
+  u32* recA = at<u32>(ws, P.o_recA);
+  u32* recB = at<u32>(ws, P.o_recB);
+  u32* bid = at<u32>(ws, P.o_bid);
+  u64* bcnt = at<u64>(ws, P.o_bcnt);
+  u32* recoff = at<u32>(ws, P.o_recoff);
+  u32* cursor = at<u32>(ws, P.o_cursor);
+  u32* small = at<u32>(ws, P.o_small);
+  u32* large = at<u32>(ws, P.o_large);
+  u64* lkoff = at<u64>(ws, P.o_lkoff);
+  u64* ctrl = at<u64>(ws, P.o_ctrl);
+  u32* cnt_large = at<u32>(ws, P.o_cnt_large);
+  u32* cnt_surv = at<u32>(ws, P.o_cnt_surv);
+  u32* bc = at<u32>(ws, P.o_bc);
+  u32* hp = at<u32>(ws, P.o_hp);
+  K* s0k = at<K>(ws, P.o_surv0k);
+  u32* s0c = at<u32>(ws, P.o_surv0c);
+  K* s1k = at<K>(ws, P.o_surv1k);
+  u32* s1c = at<u32>(ws, P.o_surv1c);
+  u64* counters = ctrl + C_COUNTERS;
+  u64* meta = ctrl + C_META;
+  u32* flags = reinterpret_cast<u32*>(ctrl + C_FLAGS);
+  u32* queue = reinterpret_cast<u32*>(ctrl + C_QUEUE);
+  u64* surv_n = ctrl + C_SURV_N;
+  u64* nruns = ctrl + C_NRUNS;
+  u64* surv_nc = ctrl + C_SURV_NC;
+
+  // zero everything that accumulates
+  auto fill = [&](void* p, u64 n_words) {
+    if (n_words)
+      hipLaunchKernelGGL(k_fill_u32, grid_for(n_words, 256, 4096), dim3(256), 0, st, (u32*)p, n_words, 0u);
+  };
+  fill(ctrl, 2ull * C_WORDS);
+  fill(bcnt, 2ull * P.B);
+  fill(d_hist, 2ull * hist_len);
+  fill(d_tot, sizeof(DevTotals) / 4);
+  fill(starts, P.n_mask);
+  const u64 n32 = ceil_div(P.R, 32);
+  fill(packed + 2 * n32, P.n_packed - 2 * n32);
+  fill(nmask + n32, P.n_mask - n32);
+
+  // ---- stage 1: encode, read starts, minimizers and supermers, bucket partition
+  if (P.R) hipLaunchKernelGGL(k_pack, grid_for(n32, 256), dim3(256), 0, st, d_reads, P.R, packed, nmask);
+  if (P.n_reads)
+    hipLaunchKernelGGL(k_read_starts, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, starts,
+                       flags);
+  ExtractArgs ea;
+  ea.packed = packed;
+  ea.nmask = nmask;
+  ea.starts = starts;
+  ea.offsets = d_offsets;
+  ea.n_reads = P.n_reads;
+  ea.R = P.R;
+  ea.k = P.k;
+  ea.m = P.m;
+  ea.log_b = P.log_b;
+  ea.gmax = P.gmax;
+  ea.rec_words = P.rec_words;
+  const u32 adv = (u32)(64 - (P.k - P.m + 1) + 1);
+  ea.span = adv * 16u;
+  ea.rec = recA;
+  ea.bid = bid;
+  ea.bcnt = bcnt;
+  ea.counters = counters;
+  ea.rec_cap = P.rec_cap;
+  const u64 n_spans = ceil_div(std::max<u64>(1, P.R), ea.span);
+  hipLaunchKernelGGL(k_extract, grid_for(n_spans, 4, 8192), dim3(256), 0, st, ea);
+  hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(1024), 0, st, bcnt, P.B, P.cap, recoff, cursor, small, large, lkoff,
+                     meta);
+  hipLaunchKernelGGL(k_scatter_records, grid_for(P.rec_cap, 256, 8192), dim3(256), 0, st, recA, bid, counters,
+                     P.rec_cap, cursor, recB, P.rec_words);
+
+  // ---- stage 3: per bucket sort + count
+  CountArgs ca;
+  ca.rec = recB;
+  ca.rec_off = recoff;
+  ca.bcnt = bcnt;
+  ca.small_list = small;
+  ca.large_list = large;
+  ca.large_koff = lkoff;
+  ca.meta = meta;
+  ca.queue = queue;
+  ca.k = P.k;
+  ca.rec_words = P.rec_words;
+  ca.min_freq = lo;
+  ca.max_freq = hi;
+  ca.hist_len = hist_len;
+  ca.hist = d_hist;
+  ca.tot = d_tot;
+  ca.surv_k = s0k;
+  ca.surv_c = s0c;
+  ca.surv_n = surv_n;
+  ca.surv_cap = P.surv_cap;
+  constexpr bool WIDE = sizeof(K) == 16;
+  if (P.cap > 0) {
+    if (P.variant == 2) {
+      constexpr int T = 512, IT = WIDE ? 8 : 16;
+      int per_cu = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
+      hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+    } else {
+      constexpr int T = 256, IT = WIDE ? 8 : 16;
+      int per_cu = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
+      hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+    }
+  }
+  // large buckets: expand into HBM, radix sort, count runs
+  K* lk0 = reinterpret_cast<K*>(recA);
+  K* lk1 = lk0 + P.rec_cap;
+  hipLaunchKernelGGL((k_expand_large<K, 256>), dim3(1024), dim3(256), 0, st, ca, lk0);
+  bool second = false;
+  rc = radix_sort<K, false>(lk0, lk1, nullptr, nullptr, meta + 2, cnt_large, P.nb_large, 2 * P.k, st, &second);
+  if (rc) return rc;
+  K* lks = second ? lk1 : lk0;
+  hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, meta + 2, bc);
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, bc, (u64)P.nb_large, nruns);
+  hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, meta + 2, bc, hp);
+  hipLaunchKernelGGL((k_rle_runs<K>), dim3(std::max(1, n_cu) * 4), dim3(256), 0, st, ca, lks, meta + 2, hp, nruns);
+
+  // ---- output: survivors in ascending key order
+  hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, surv_n, P.surv_cap, surv_nc);
+  rc = radix_sort<K, true>(s0k, s1k, s0c, s1c, surv_nc, cnt_surv, P.nb_surv, 2 * P.k, st, &second);
+  if (rc) return rc;
+  K* ok = second ? s1k : s0k;
+  u32* oc = second ? s1c : s0c;
+  hipLaunchKernelGGL((k_copy_pairs<K>), grid_for(P.surv_cap, 256, 4096), dim3(256), 0, st, ok, oc, surv_nc, pair_cap,
+                     reinterpret_cast<K*>(d_kmers), d_counts);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags);
+  hipLaunchKernelGGL(k_totals_meta, dim3(1), dim3(64), 0, st, d_tot, meta);
+  HIP_TRY(hipGetLastError());
+  return KC_OK;
+}
+
+int enqueue_any(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_offsets, uint32_t lo, uint32_t hi,
+                uint64_t hist_len, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap, uint64_t* d_hist,
+                DevTotals* d_tot, hipStream_t st) {
+  if (P.key_words == 1)
+    return enqueue<u64>(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_hist, d_tot, st);
+  return enqueue<k128>(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_hist, d_tot, st);
+}
+
+int device_common(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* d_offsets, uint64_t n_reads, int k,
+                  int m, uint32_t lo, uint32_t hi, uint64_t hist_len, const kc_config* cfg, void* ws, size_t ws_bytes,
+                  uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap, uint64_t* d_hist, kc_totals* d_tot,
+                  void* stream) {
+  int rc = check_args(k, m, lo, hi, hist_len);
+  if (rc) return rc;
+  if ((total_bases && !d_reads) || !d_offsets || !ws || !d_hist || !d_tot || (pair_cap && (!d_kmers || !d_counts)))
+    return fail(KC_EINVAL, "NULL device pointer");
+  if (total_bases >= (1ull << 32)) return fail(KC_EINVAL, "total_bases=%llu >= 2^32", (unsigned long long)total_bases);
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(KC_EINVAL, "workspace not 256-byte aligned");
+  Plan P;
+  if (!make_plan(total_bases, n_reads, total_bases, k, m, 1, cfg, &P))
+    return fail(KC_EINVAL, "bad kc_config");
+  if (ws_bytes < P.bytes)
+    return fail(KC_EINVAL, "workspace of %zu bytes < %llu needed", ws_bytes, (unsigned long long)P.bytes);
+  if (cfg && cfg->hbm_budget && P.bytes > cfg->hbm_budget)
+    return fail(KC_ENOMEM, "workspace %llu bytes > budget %llu", (unsigned long long)P.bytes,
+                (unsigned long long)cfg->hbm_budget);
+  return enqueue_any(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_hist,
+                     reinterpret_cast<DevTotals*>(d_tot), reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // namespace
+
+static_assert(sizeof(DevTotals) == sizeof(kc_totals), "device and ABI totals differ");
+
+extern "C" {
+
+const char* kc_version(void) { return "kc 0.1 (gfx950)"; }
+
+const char* kc_last_error(void) { return g_err.c_str(); }
+
+size_t kc_workspace_size(uint64_t total_bases, uint64_t n_reads, int k, const kc_config* cfg) {
+  if (k < 1 || k > 63) return 0;
+  Plan P;
+  if (!make_plan(total_bases, n_reads, total_bases, k, 1, 1, cfg, &P)) return 0;
+  return (size_t)P.bytes;
+}
+
+int kc_count_device_async(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* d_offsets, uint64_t n_reads,
+                          int k, int m, uint32_t min_freq, uint32_t max_freq, uint64_t hist_len, const kc_config* cfg,
+                          void* d_workspace, size_t workspace_bytes, uint64_t* d_kmers, uint32_t* d_counts,
+                          uint64_t pair_capacity, uint64_t* d_hist, kc_totals* d_totals, void* stream) {
+  g_err.clear();
+  return device_common(d_reads, total_bases, d_offsets, n_reads, k, m, min_freq, max_freq, hist_len, cfg, d_workspace,
+                       workspace_bytes, d_kmers, d_counts, pair_capacity, d_hist, d_totals, stream);
+}
+
+int kc_count_device(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* d_offsets, uint64_t n_reads, int k,
+                    int m, uint32_t min_freq, uint32_t max_freq, uint64_t hist_len, const kc_config* cfg,
+                    void* d_workspace, size_t workspace_bytes, uint64_t* d_kmers, uint32_t* d_counts,
+                    uint64_t pair_capacity, uint64_t* d_hist, kc_totals* d_totals, void* stream,
+                    kc_totals* totals_out) {
+  g_err.clear();
+  int rc = device_common(d_reads, total_bases, d_offsets, n_reads, k, m, min_freq, max_freq, hist_len, cfg,
+                         d_workspace, workspace_bytes, d_kmers, d_counts, pair_capacity, d_hist, d_totals, stream);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  kc_totals t;
+  HIP_TRY(hipMemcpyAsync(&t, d_totals, sizeof(t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (totals_out) *totals_out = t;
+  if (t.flags & 1) return fail(KC_EINVAL, "offsets are not non-decreasing or exceed total_bases");
+  if (t.flags) return fail(KC_EDEVICE, "internal capacity exceeded (flags=%llu)", (unsigned long long)t.flags);
+  if (t.n_pairs > pair_capacity)
+    return fail(KC_ETRUNC, "%llu pairs > capacity %llu", (unsigned long long)t.n_pairs,
+                (unsigned long long)pair_capacity);
+  return KC_OK;
+}
+
+void kc_result_free(kc_result* r) {
+  if (!r) return;
+  free(r->kmers);
+  free(r->counts);
+  free(r->hist);
+  memset(r, 0, sizeof(*r));
+}
+
+int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int m, uint32_t min_freq,
+             uint32_t max_freq, uint64_t hist_len, const kc_config* cfg, kc_result* out) {
+  g_err.clear();
+  if (!out) return fail(KC_EINVAL, "out is NULL");
+  memset(out, 0, sizeof(*out));
+  int rc = check_args(k, m, min_freq, max_freq, hist_len);
+  if (rc) return rc;
+  if (!offsets || (n_reads && !reads)) return fail(KC_EINVAL, "NULL host pointer");
+  // offsets must be non-decreasing; windows bound from the read lengths
+  u64 n_max = 0;
+  for (u64 r = 0; r < n_reads; ++r) {
+    if (offsets[r + 1] < offsets[r]) return fail(KC_EINVAL, "offsets decrease at read %llu", (unsigned long long)r);
+    const u64 L = offsets[r + 1] - offsets[r];
+    if (L >= (u64)k) n_max += L - (u64)k + 1;
+  }
+  const u64 R = n_reads ? offsets[n_reads] : 0;
+  if (n_max >= (1ull << 32) || R >= (1ull << 32))
+    return fail(KC_EINVAL, "%llu windows / %llu bases exceed 2^32 - 1", (unsigned long long)n_max,
+                (unsigned long long)R);
+  Plan P;
+  if (!make_plan(R, n_reads, n_max, k, m, min_freq, cfg, &P)) return fail(KC_EINVAL, "bad kc_config");
+  if (cfg && cfg->hbm_budget && P.bytes > cfg->hbm_budget)
+    return fail(KC_ENOMEM, "workspace %llu bytes > budget %llu", (unsigned long long)P.bytes,
+                (unsigned long long)cfg->hbm_budget);
+  const u64 w = 8ull * P.key_words;
+  const u64 in_bytes = align_up(R + 16, 256) + align_up(8 * (n_reads + 1), 256);
+  const u64 out_bytes = align_up(w * P.surv_cap, 256) + align_up(4 * P.surv_cap, 256) + align_up(sizeof(kc_totals), 256) +
+                        align_up(8 * hist_len, 256);
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  if (P.bytes + in_bytes + out_bytes > free_b)
+    return fail(KC_ENOMEM, "needs %llu bytes of HBM, %zu free", (unsigned long long)(P.bytes + in_bytes + out_bytes),
+                free_b);
+  char* dmem = nullptr;
+  HIP_TRY(hipMalloc(&dmem, P.bytes + in_bytes + out_bytes));
+  void* ws = dmem;
+  uint8_t* d_reads = reinterpret_cast<uint8_t*>(dmem + P.bytes);
+  uint64_t* d_offsets = reinterpret_cast<uint64_t*>(dmem + P.bytes + align_up(R + 16, 256));
+  char* ob = dmem + P.bytes + in_bytes;
+  uint64_t* d_kmers = reinterpret_cast<uint64_t*>(ob);
+  uint32_t* d_counts = reinterpret_cast<uint32_t*>(ob + align_up(w * P.surv_cap, 256));
+  kc_totals* d_tot = reinterpret_cast<kc_totals*>(ob + align_up(w * P.surv_cap, 256) + align_up(4 * P.surv_cap, 256));
+  uint64_t* d_hist = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(d_tot) + align_up(sizeof(kc_totals), 256));
+  hipStream_t st = nullptr;
+  auto cleanup = [&](int code) {
+    (void)hipFree(dmem);
+    if (code) kc_result_free(out);
+    return code;
+  };
+  if (R && hipMemcpyAsync(d_reads, reads, R, hipMemcpyHostToDevice, st) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "H2D reads failed"));
+  if (hipMemcpyAsync(d_offsets, offsets, 8 * (n_reads + 1), hipMemcpyHostToDevice, st) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "H2D offsets failed"));
+  rc = enqueue_any(P, ws, d_reads, d_offsets, min_freq, max_freq, hist_len, d_kmers, d_counts, P.surv_cap, d_hist,
+                   reinterpret_cast<DevTotals*>(d_tot), st);
+  if (rc) return cleanup(rc);
+  kc_totals t;
+  if (hipMemcpyAsync(&t, d_tot, sizeof(t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "count failed: %s", hipGetErrorString(hipGetLastError())));
+  if (t.flags) return cleanup(fail(KC_EDEVICE, "internal capacity exceeded (flags=%llu)", (unsigned long long)t.flags));
+  out->n_pairs = t.n_pairs;
+  out->key_words = (uint32_t)P.key_words;
+  out->hist_len = hist_len;
+  out->totals = t;
+  out->kmers = (uint64_t*)malloc(std::max<u64>(1, t.n_pairs * P.key_words) * 8);
+  out->counts = (uint32_t*)malloc(std::max<u64>(1, t.n_pairs) * 4);
+  out->hist = (uint64_t*)malloc(hist_len * 8);
+  if (!out->kmers || !out->counts || !out->hist) return cleanup(fail(KC_ENOMEM, "host allocation failed"));
+  if ((t.n_pairs && (hipMemcpy(out->kmers, d_kmers, t.n_pairs * w, hipMemcpyDeviceToHost) != hipSuccess ||
+                     hipMemcpy(out->counts, d_counts, t.n_pairs * 4, hipMemcpyDeviceToHost) != hipSuccess)) ||
+      hipMemcpy(out->hist, d_hist, hist_len * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "D2H failed"));
+  return cleanup(KC_OK);
+}
+
+}  // extern "C"

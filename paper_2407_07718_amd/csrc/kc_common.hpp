@@ -1,0 +1,110 @@
+// Shared device helpers for the k-mer counting kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef uint16_t u16;
+typedef uint8_t u8;
+
+// 128-bit key for 32 <= k <= 63: the canonical value as {low word, high word}.
+struct k128 {
+  u64 lo, hi;
+};
+
+__device__ __forceinline__ bool key_eq(u64 a, u64 b) { return a == b; }
+__device__ __forceinline__ bool key_eq(k128 a, k128 b) { return a.lo == b.lo && a.hi == b.hi; }
+__device__ __forceinline__ bool key_lt(u64 a, u64 b) { return a < b; }
+__device__ __forceinline__ bool key_lt(k128 a, k128 b) {
+  return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+// 8-bit radix digit starting at bit `sh` (a multiple of 8, so it never straddles words).
+__device__ __forceinline__ u32 key_digit(u64 k, int sh) { return (u32)(k >> sh) & 0xFFu; }
+__device__ __forceinline__ u32 key_digit(k128 k, int sh) {
+  return sh >= 64 ? (u32)(k.hi >> (sh - 64)) & 0xFFu : (u32)(k.lo >> sh) & 0xFFu;
+}
+template <typename K> __device__ __forceinline__ K key_zero();
+template <> __device__ __forceinline__ u64 key_zero<u64>() { return 0; }
+template <> __device__ __forceinline__ k128 key_zero<k128>() { return k128{0, 0}; }
+
+// Reverse the order of the 32 two-bit groups of x (base j <-> base 31-j).
+__device__ __forceinline__ u64 rev2_64(u64 x) {
+  x = __builtin_bitreverse64(x);
+  return ((x >> 1) & 0x5555555555555555ull) | ((x & 0x5555555555555555ull) << 1);
+}
+
+// Score of a canonical m-mer: the upper half of MurmurHash3's 64-bit finalizer
+// (the paper scores m-mers with MurmurHash3; any fixed mixer keeps the method exact).
+__device__ __forceinline__ u32 mmer_score(u64 x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return (u32)(x >> 32);
+}
+
+// 32 bases (64 bits) of the 2-bit stream starting at base q; base q in bits 0-1.
+// The array must hold three readable words past word q/16.
+__device__ __forceinline__ u64 bases64(const u32* __restrict__ p, u64 q) {
+  u64 w = q >> 4;
+  u32 sh = (u32)(q & 15) * 2;
+  u64 a = (u64)p[w] | ((u64)p[w + 1] << 32);
+  u64 b = p[w + 2];
+  return sh ? (a >> sh) | (b << (64 - sh)) : a;
+}
+// 64 bits of a one-bit-per-base mask starting at base q.
+__device__ __forceinline__ u64 bits64(const u32* __restrict__ p, u64 q) {
+  u64 w = q >> 5;
+  u32 sh = (u32)(q & 31);
+  u64 a = (u64)p[w] | ((u64)p[w + 1] << 32);
+  u64 b = p[w + 2];
+  return sh ? (a >> sh) | (b << (64 - sh)) : a;
+}
+
+__device__ __forceinline__ u32 lane_id() { return threadIdx.x & 63u; }
+// number of set bits of m in lanes below this lane
+__device__ __forceinline__ u32 mbcnt64(u64 m) {
+  return __builtin_amdgcn_mbcnt_hi((u32)(m >> 32), __builtin_amdgcn_mbcnt_lo((u32)m, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const u32 lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T o = __shfl_up(v, d, 64);
+    if (lane >= (u32)d) v += o;
+  }
+  return v;
+}
+
+// Exclusive prefix sum over a whole block (blockDim.x a multiple of 64, <= 1024).
+// `scratch` holds at least 17 values of T.  Returns the exclusive prefix; *total is
+// the block sum.  Contains barriers: every thread of the block must call it.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* scratch, T* total) {
+  const u32 lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  T inc = wave_inclusive_scan<T>(v);
+  if (lane == 63) scratch[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    T x = threadIdx.x < nw ? scratch[threadIdx.x] : (T)0;
+    T xi = wave_inclusive_scan<T>(x);
+    if (threadIdx.x < nw) scratch[threadIdx.x] = xi - x;
+    if (threadIdx.x == nw - 1) scratch[16] = xi;
+  }
+  __syncthreads();
+  T r = scratch[wave] + inc - v;
+  *total = scratch[16];
+  __syncthreads();
+  return r;
+}
+
+// Bounded-size fill (used instead of hipMemsetAsync so that a captured graph holds
+// only kernel nodes).
+__global__ void k_fill_u32(u32* __restrict__ p, u64 n, u32 v) {
+  for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
+}

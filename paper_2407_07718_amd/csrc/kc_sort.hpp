@@ -1,0 +1,218 @@
+// LSD radix sort of canonical k-mer keys (u64 for k <= 31, k128 for k <= 63), 8-bit
+// digits over the low 2k bits.
+//
+// Paper mapping: the k-mers are sorted so that equal values become adjacent (Section
+// 3.1); the paper uses the CPU radix sorts RADULS (out of place) and PARADIS (in place)
+// with O(n*d) work (Section 2.3, Section 3.1).  Here the sort is a stable LSD radix
+// sort written for wave64: each pass ranks a tile of keys by digit with
+//  * a per-wave table of lane masks in LDS: every lane ORs its lane bit into the entry
+//    of its digit, then reads the entry back, so each lane learns which lanes of its
+//    wave share its digit (an order-free way to get the wave's match masks);
+//  * mbcnt over that mask for the lane's rank among equal digits (stable by lane);
+//  * per-wave running digit counts in LDS across the wave's batches, and one block
+//    scan over (digit, wave) for the tile offsets.
+// Buckets that fit on chip are sorted entirely in LDS (lds_sort); larger key arrays go
+// through HBM passes: per-block digit counts (upsweep), one scan, then a downsweep that
+// ranks each tile, stages it in LDS in digit order and writes runs per digit.
+#pragma once
+#include "kc_common.hpp"
+
+template <int W>
+struct RankSmem {
+  u64 tbl[W][256];   // lane masks per digit; all zero between uses
+  u32 cnt[W][256];   // per-wave digit counts, then the items' base offsets
+  u32 dstart[257];   // per-digit exclusive start within the tile; [256] = tile size
+  u64 scr[17];       // block-scan scratch
+};
+
+// Rank the active items of a tile by digit.  Item j of lane l of wave v is tile element
+// (v*per + j)*64 + l; it is active iff that index is < n.  On return rk[j] holds the
+// item's stable position in digit order and S.dstart the per-digit starts.
+// Every thread of the block must call this (it contains barriers).
+template <int T, int ITEMS>
+__device__ __forceinline__ void rank_by_digit(const u32 (&dg)[ITEMS], u32 (&rk)[ITEMS], int per, u32 n,
+                                              RankSmem<T / 64>& S) {
+  constexpr int W = T / 64;
+  const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  u32* cntf = &S.cnt[0][0];
+  for (u32 i = tid; i < W * 256; i += T) cntf[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (j < per) {
+      const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+      const bool act = idx < n;
+      const u32 d = dg[j];
+      u64 mask = 0;
+      if (act) {
+        atomicOr((unsigned long long*)&S.tbl[wave][d], (unsigned long long)(1ull << lane));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (act) mask = S.tbl[wave][d];
+      const u32 lr = mbcnt64(mask);
+      const u32 base = act ? S.cnt[wave][d] : 0u;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (act && lr == 0) {
+        S.cnt[wave][d] = base + (u32)__popcll(mask);
+        S.tbl[wave][d] = 0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      rk[j] = base + lr;
+    }
+  }
+  __syncthreads();
+  u32 tot = 0;
+  if (tid < 256) {
+#pragma unroll
+    for (int v = 0; v < W; ++v) {
+      u32 c = S.cnt[v][tid];
+      S.cnt[v][tid] = tot;
+      tot += c;
+    }
+  }
+  u64 all;
+  const u64 start = block_exclusive_scan<u64>((u64)tot, S.scr, &all);
+  if (tid < 256) {
+    S.dstart[tid] = (u32)start;
+#pragma unroll
+    for (int v = 0; v < W; ++v) S.cnt[v][tid] += (u32)start;
+  }
+  if (tid == 0) S.dstart[256] = (u32)all;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (j < per) rk[j] += S.cnt[wave][dg[j]];
+  }
+}
+
+// Sort keys[0, n) in LDS by bits [0, nbits), n <= T * ITEMS.
+template <typename K, int T, int ITEMS>
+__device__ void lds_sort(K* keys, u32 n, int nbits, RankSmem<T / 64>& S) {
+  constexpr int W = T / 64;
+  const u32 lane = lane_id(), wave = threadIdx.x >> 6;
+  const int per = (int)((n + 64u * W - 1) / (64u * W));
+  for (int sh = 0; sh < nbits; sh += 8) {
+    K kr[ITEMS];
+    u32 dg[ITEMS], rk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+        kr[j] = idx < n ? keys[idx] : key_zero<K>();
+        dg[j] = key_digit(kr[j], sh);
+      }
+    }
+    rank_by_digit<T, ITEMS>(dg, rk, per, n, S);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+        if (idx < n) keys[rk[j]] = kr[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------- HBM passes
+// Block b of nb owns elements [b*per, min(n, (b+1)*per)), per = ceil(n / nb).
+__device__ __forceinline__ void block_range(u64 n, u32 nb, u64* s, u64* e) {
+  const u64 per = (n + nb - 1) / nb;
+  *s = min(n, (u64)blockIdx.x * per);
+  *e = min(n, *s + per);
+}
+
+// counts[d * nb + b] = number of keys of block b with digit d.
+template <typename K>
+__global__ __launch_bounds__(256) void k_radix_upsweep(const K* __restrict__ keys, const u64* __restrict__ n_ptr,
+                                                       u32* __restrict__ counts, int sh) {
+  __shared__ u32 h[4][256];
+  const u32 nb = gridDim.x, tid = threadIdx.x, wave = tid >> 6;
+  for (u32 i = tid; i < 4 * 256; i += 256) (&h[0][0])[i] = 0;
+  __syncthreads();
+  u64 s, e;
+  block_range(*n_ptr, nb, &s, &e);
+  for (u64 i = s + tid; i < e; i += 256) atomicAdd(&h[wave][key_digit(keys[i], sh)], 1u);
+  __syncthreads();
+  counts[(u64)tid * nb + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+}
+
+// In-place exclusive scan of data[0, n) by one block; *total = sum (if non-null).
+__global__ __launch_bounds__(1024) void k_scan_u32(u32* __restrict__ data, u64 n, u64* __restrict__ total) {
+  __shared__ u64 scr[17];
+  const u32 T = blockDim.x, t = threadIdx.x;
+  const u64 per = (n + T - 1) / T;
+  const u64 s = min(n, (u64)t * per), e = min(n, s + per);
+  u64 sum = 0;
+  for (u64 i = s; i < e; ++i) sum += data[i];
+  u64 all;
+  u64 run = block_exclusive_scan<u64>(sum, scr, &all);
+  for (u64 i = s; i < e; ++i) {
+    u32 v = data[i];
+    data[i] = (u32)run;
+    run += v;
+  }
+  if (t == 0 && total) *total = all;
+}
+
+// Stable scatter of one pass.  Each tile of T*ITEMS keys is ranked by digit, staged in
+// LDS in digit order and written out as one run per digit.
+template <typename K, bool HASV, int T, int ITEMS>
+__global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin, K* __restrict__ kout,
+                                                       const u32* __restrict__ vin, u32* __restrict__ vout,
+                                                       const u64* __restrict__ n_ptr, const u32* __restrict__ counts,
+                                                       int sh) {
+  constexpr int W = T / 64, TILE = T * ITEMS;
+  __shared__ RankSmem<W> S;
+  __shared__ K stage_k[TILE];
+  __shared__ u32 stage_v[HASV ? TILE : 1];
+  __shared__ u32 run_base[256];
+  const u32 nb = gridDim.x, tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  for (u32 i = tid; i < W * 256; i += T) (&S.tbl[0][0])[i] = 0;
+  if (tid < 256) run_base[tid] = counts[(u64)tid * nb + blockIdx.x];
+  __syncthreads();
+  u64 s, e;
+  block_range(*n_ptr, nb, &s, &e);
+  for (u64 t0 = s; t0 < e; t0 += TILE) {
+    const u32 nt = (u32)min((u64)TILE, e - t0);
+    const int per = (int)((nt + 64u * W - 1) / (64u * W));
+    K kr[ITEMS];
+    u32 vr[ITEMS], dg[ITEMS], rk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+        if (idx < nt) {
+          kr[j] = kin[t0 + idx];
+          if (HASV) vr[j] = vin[t0 + idx];
+        } else {
+          kr[j] = key_zero<K>();
+          vr[j] = 0;
+        }
+        dg[j] = key_digit(kr[j], sh);
+      }
+    }
+    rank_by_digit<T, ITEMS>(dg, rk, per, nt, S);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+        if (idx < nt) {
+          stage_k[rk[j]] = kr[j];
+          if (HASV) stage_v[rk[j]] = vr[j];
+        }
+      }
+    }
+    __syncthreads();
+    for (u32 i = tid; i < nt; i += T) {
+      const K key = stage_k[i];
+      const u32 d = key_digit(key, sh);
+      const u64 dst = (u64)run_base[d] + (i - S.dstart[d]);
+      kout[dst] = key;
+      if (HASV) vout[dst] = stage_v[i];
+    }
+    __syncthreads();
+    if (tid < 256) run_base[tid] += S.dstart[tid + 1] - S.dstart[tid];
+    __syncthreads();
+  }
+}

@@ -1,0 +1,151 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: bit-exact pairs,
+histogram and totals on seeded inputs, at small sizes spanning many tiles, spans and
+buckets with ragged tails, at the short-read configuration's full size, and on the
+method's edge cases."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_07718_amd import synth
+from tests.gpu_util import assert_same, check, device_count
+
+pytestmark = pytest.mark.gpu
+
+
+def _kc():
+    from paper_2407_07718_amd import kc
+    return kc
+
+
+def _genome_reads(seed, n_reads, lo_len, hi_len, genome=4000, p_sub=0.01, p_n=0.002, p_indel=0.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = synth.uniform_genome(rng, genome)
+    lens = rng.integers(lo_len, hi_len + 1, n_reads)
+    return synth.sample_reads(rng, g, lens, p_sub=p_sub, p_n=p_n, p_indel=p_indel)
+
+
+def test_tiny_config():
+    rs = synth.tiny_config()
+    check(rs.reads, rs.offsets, rs.k, rs.m, rs.min_freq, rs.max_freq, 65536, label="tiny")
+
+
+@pytest.mark.parametrize("k", [2, 3, 5, 8, 11, 15, 16, 17, 21, 27, 30, 31])
+def test_random_u64_keys(k):
+    rng = np.random.Generator(np.random.PCG64(500 + k))
+    reads, offsets = _genome_reads(k, 400, 0, 400)
+    m = int(rng.integers(1, min(k - 1, 32) + 1)) if k > 2 else 1
+    lo = int(rng.integers(1, 4))
+    check(reads, offsets, k, m, lo, lo + int(rng.integers(0, 40)), int(rng.integers(2, 300)), label=f"u64 k{k}")
+
+
+@pytest.mark.parametrize("k", [32, 33, 40, 47, 51, 55, 63])
+def test_random_u128_keys(k):
+    rng = np.random.Generator(np.random.PCG64(600 + k))
+    reads, offsets = _genome_reads(k, 300, 0, 600)
+    m = int(rng.integers(1, 33))
+    check(reads, offsets, k, m, 1, 1000, 257, label=f"u128 k{k}")
+
+
+@pytest.mark.parametrize("m", [1, 7, 15, 21, 30])
+def test_m_does_not_change_result(m):
+    reads, offsets = _genome_reads(77, 300, 100, 300)
+    ref = oracle.count(reads, offsets, 31, 2, 50, 1000)
+    got = device_count(reads, offsets, 31, m, 2, 50, 1000)
+    assert_same(got, ref, f"m={m}")
+
+
+@pytest.mark.parametrize("cfg", [dict(force_hbm=True), dict(log2_buckets=1), dict(log2_buckets=20),
+                                 dict(small_variant=2), dict(log2_buckets=4, small_variant=2)])
+@pytest.mark.parametrize("k", [31, 51])
+def test_paths_and_bucket_counts(cfg, k):
+    kc = _kc()
+    reads, offsets = _genome_reads(900 + k, 600, 50, 500, genome=20000)
+    check(reads, offsets, k, 17, 2, 100, 1024, cfg=kc.make_config(**cfg), label=f"{cfg}")
+
+
+def test_long_reads_cross_spans():
+    reads, offsets = _genome_reads(3, 12, 20000, 60000, genome=100000, p_sub=0.001, p_n=0.0, p_indel=0.0005)
+    check(reads, offsets, 31, 21, 2, 200, 4096, label="long reads")
+    check(reads, offsets, 51, 21, 2, 200, 4096, label="long reads k51")
+
+
+def test_heavy_hitters_and_homopolymers():
+    # one k-mer with a huge count (a single oversized bucket) next to ordinary reads
+    reads, offsets = _genome_reads(11, 200, 100, 200)
+    seqs = [bytes(reads[int(offsets[i]):int(offsets[i + 1])]).decode() for i in range(len(offsets) - 1)]
+    seqs += ["A" * 5000, "T" * 3000, "AC" * 4000, "ACGT" * 2000]
+    r, o = synth.from_strings(seqs)
+    check(r, o, 31, 15, 1, 100000, 65536, label="homopolymer")
+    check(r, o, 21, 11, 2, 50, 100, label="homopolymer k21")
+    check(r, o, 63, 32, 1, 100000, 65536, label="homopolymer k63")
+
+
+def test_edge_cases():
+    cases = [
+        ([], 31, 15),
+        (["ACGT", "", "AC"], 31, 15),
+        (["N" * 100, "n" * 64], 21, 11),
+        (["ACGTNACGTN" * 30], 5, 2),
+        (["A" * 31], 31, 15),
+        (["ACGT" * 8], 32, 16),
+        (["GATTACA"], 3, 2),
+    ]
+    for seqs, k, m in cases:
+        r, o = synth.from_strings(seqs)
+        check(r, o, k, m, 1, 10, 16, label=f"edge {seqs[:1]} k{k}")
+        check(r, o, k, m, 1, 1, 2, label=f"edge H2 {seqs[:1]} k{k}")
+
+
+def test_lowercase_and_other_bytes():
+    rng = np.random.Generator(np.random.PCG64(4))
+    reads, offsets = synth.random_small(rng, 500, 120, p_bad=0.05)
+    check(reads, offsets, 9, 4, 1, 5, 8, label="random bytes k9")
+    check(reads, offsets, 33, 10, 1, 5, 8, label="random bytes k33")
+
+
+def test_truncation_and_bad_offsets():
+    import torch
+    kc = _kc()
+    rs = synth.tiny_config()
+    dev = torch.device("cuda:0")
+    d_reads = torch.from_numpy(np.ascontiguousarray(rs.reads)).to(dev)
+    d_offsets = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
+    ref = oracle.count(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, 65536)
+    ctr = kc.DeviceCounter(rs.n_bases, rs.n_reads, rs.k, rs.m, rs.min_freq, rs.max_freq, 65536, pair_capacity=10)
+    with pytest.raises(kc.KCError) as e:
+        ctr.count(d_reads, d_offsets)
+    assert e.value.code == kc.KC_ETRUNC
+    assert int(ctr.totals[0].item()) == ref.n_pairs
+    got = ctr.kmers.cpu().numpy().view(np.uint64)
+    assert np.array_equal(got[:10], ref.kmers[:10])
+    bad = rs.offsets.copy()
+    bad[5], bad[6] = bad[6], bad[5]
+    ctr2 = kc.DeviceCounter(rs.n_bases, rs.n_reads, rs.k, rs.m, rs.min_freq, rs.max_freq, 65536)
+    with pytest.raises(kc.KCError) as e:
+        ctr2.count(d_reads, torch.from_numpy(bad.view(np.int64)).to(dev))
+    assert e.value.code == kc.KC_EINVAL
+
+
+def test_host_api_matches_oracle():
+    kc = _kc()
+    reads, offsets = _genome_reads(21, 300, 0, 300)
+    for k, m in [(31, 15), (45, 20)]:
+        got = kc.kc_count(reads, offsets, k, m, 2, 30, 500)
+        ref = oracle.count(reads, offsets, k, 2, 30, 500)
+        assert_same(got, ref, f"host api k{k}")
+
+
+def test_deterministic():
+    rs = synth.tiny_config()
+    a = device_count(rs.reads, rs.offsets, rs.k, rs.m, 1, 1000, 300)
+    b = device_count(rs.reads, rs.offsets, rs.k, rs.m, 1, 1000, 300)
+    assert np.array_equal(a.kmers, b.kmers) and np.array_equal(a.counts, b.counts)
+    assert np.array_equal(a.hist, b.hist)
+
+
+def test_short_read_config_full_size():
+    rs = synth.config(2)
+    print(f"case short-read full size: bases={rs.n_bases} reads={rs.n_reads}", flush=True)
+    got = device_count(rs.reads, rs.offsets, rs.k, rs.m, rs.min_freq, rs.max_freq, 65536)
+    ref = oracle.count(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, 65536)
+    assert_same(got, ref, "short-read full size")
