@@ -123,6 +123,25 @@ int kc_count_device_async(const uint8_t *d_reads, uint64_t total_bases, const ui
                           size_t workspace_bytes, uint64_t *d_kmers, uint32_t *d_counts,
                           uint64_t pair_capacity, uint64_t *d_hist, kc_totals *d_totals, void *stream);
 
+/* Stage timing.  While enabled (kc_profile(1)), each count queued by this thread records
+ * HIP events on its own stream at the boundaries of its stages:
+ *   0 encode      (zero fills, 2-bit pack, read-start marks)
+ *   1 extract     (minimizers, supermers, per-bucket counts)       -- one kernel
+ *   2 partition   (bucket plan + record scatter)
+ *   3 small_sort  (on-chip sort and run count of small buckets)     -- one kernel
+ *   4 large_path  (expand, HBM radix sort and run count of large buckets)
+ *   5 output      (survivor sort by key, copy, totals)
+ * kc_profile_read waits for those events and returns, per stage, the summed
+ * milliseconds over all counts recorded since the last read (then resets). */
+#define KC_N_STAGES 6
+typedef struct kc_stage_times {
+  double ms[KC_N_STAGES];
+  uint64_t n_counts;
+} kc_stage_times;
+
+int kc_profile(int enable);
+int kc_profile_read(kc_stage_times *out);
+
 #ifdef __cplusplus
 }
 #endif

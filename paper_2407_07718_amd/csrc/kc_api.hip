@@ -24,6 +24,19 @@ namespace {
 
 thread_local std::string g_err;
 
+// Stage events of profiled counts (see kc_profile in kc.h).
+struct StageEvents {
+  hipEvent_t ev[KC_N_STAGES + 1];
+};
+thread_local bool g_profile = false;
+thread_local std::vector<StageEvents> g_ev_pool;
+thread_local size_t g_ev_used = 0;
+thread_local StageEvents* g_ev_cur = nullptr;
+
+void stage_mark(int i, hipStream_t st) {
+  if (g_ev_cur) (void)hipEventRecord(g_ev_cur->ev[i], st);
+}
+
 int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -50,27 +63,34 @@ inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 // Sizes and byte offsets of every workspace region for one (input size, k, config).
 struct Plan {
   int k = 0, m = 0, key_words = 0, rec_words = 0, gmax = 0, log_b = 0;
-  u32 B = 0, cap = 0, variant = 1;
+  u32 B = 0, cap = 0, cap_chunk = 0, variant = 1;
+  u64 chunk_cap = 0, kl_cap = 0;
   u64 R = 0, n_reads = 0, n_max = 0;   // bases, reads, bound on windows
   u64 rec_cap = 0, surv_cap = 0;
+  u64 slots = 0, n_span_cap = 0, n_span_alloc = 0;  // sparse record slots of the extract stage
+  u32 span = 0;
   u32 nb_large = 1, nb_surv = 1;        // radix blocks
   // offsets into the workspace
   u64 o_packed, o_nmask, o_starts, o_recA, o_recB, o_bid, o_bcnt, o_recoff, o_cursor, o_small, o_large,
-      o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_bc, o_hp, o_surv0k, o_surv0c, o_surv1k, o_surv1c;
+      o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_tot_large, o_tot_surv, o_bc, o_hp, o_surv0k, o_surv0c, o_surv1k,
+      o_surv1c, o_spancnt, o_chstart, o_chlen, o_kl0k, o_kl0c, o_kl1k, o_kl1c;
   u64 n_packed, n_mask, bytes = 0;
 };
 
 // Control words (all zeroed at the start of a count).
 enum Ctrl : int {
   C_COUNTERS = 0,   // [0] records, [1] windows
-  C_META = 2,       // [0] n_small, [1] n_large, [2] large k-mers, [3] records
-  C_FLAGS = 6,
-  C_QUEUE = 7,
-  C_SURV_N = 8,
-  C_NRUNS = 9,
-  C_SURV_NC = 10,   // survivors, clamped to capacity
+  C_META = 2,       // 5 words: n_small, n_large, large k-mers, records, n_chunks
+  C_FLAGS = 8,
+  C_QUEUE = 9,
+  C_SURV_N = 10,
+  C_NRUNS = 11,
+  C_SURV_NC = 12,   // survivors, clamped to capacity
+  C_KL_N = 13,      // (k-mer, count) list entries
+  C_KL_NC = 14,     // ... clamped to capacity
   C_WORDS = 16
 };
+static_assert(C_META + 5 <= C_FLAGS, "meta overlaps the flags");
 
 u32 default_variant(int key_words) { return key_words == 1 ? 1u : 1u; }
 u32 small_cap(int key_words, u32 variant) {
@@ -91,8 +111,8 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->gmax = std::min(64, cap_bases - k + 1);
   p->variant = (cfg && cfg->small_variant) ? cfg->small_variant : default_variant(p->key_words);
   if (p->variant > 2) return false;
-  p->cap = small_cap(p->key_words, p->variant);
-  if (cfg && cfg->force_hbm) p->cap = 0;
+  p->cap_chunk = small_cap(p->key_words, p->variant);
+  p->cap = (cfg && cfg->force_hbm) ? 0u : p->cap_chunk;
   if (cfg && cfg->log2_buckets) {
     if (cfg->log2_buckets > 20) return false;
     p->log_b = (int)cfg->log2_buckets;
@@ -105,6 +125,12 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   }
   p->B = 1u << p->log_b;
   p->rec_cap = std::max<u64>(1, n_max);
+  // each wave span of the extract stage owns `span` record slots; the slot region is
+  // sized for any m (span <= 16 * 63)
+  p->span = 16u * (u32)(64 - k + m);
+  p->slots = R + 16 * 64;
+  p->n_span_cap = (std::max<u64>(R, 1) + p->span - 1) / p->span;
+  p->n_span_alloc = R / 32 + 2;
   p->surv_cap = std::max<u64>(1, n_max / std::max<u32>(1, min_freq));
   const u64 w = 8ull * p->key_words;
   const u64 tile = (u64)RADIX_T * (p->key_words == 1 ? RADIX_ITEMS_64 : RADIX_ITEMS_128);
@@ -123,9 +149,10 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_nmask = take(4 * p->n_mask);
   p->o_starts = take(4 * p->n_mask);
   // unsorted records; after the scatter the same bytes hold the two large-key arrays
-  p->o_recA = take(std::max(rb * p->rec_cap, 2 * w * p->rec_cap));
+  p->o_recA = take(std::max(rb * p->slots, 2 * w * p->rec_cap));
   p->o_recB = take(rb * p->rec_cap);
-  p->o_bid = take(4 * p->rec_cap);
+  p->o_bid = take(4 * p->slots);
+  p->o_spancnt = take(4 * p->n_span_alloc);
   p->o_bcnt = take(8ull * p->B);
   p->o_recoff = take(4ull * (p->B + 1));
   p->o_cursor = take(4ull * p->B);
@@ -135,12 +162,23 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_ctrl = take(8ull * C_WORDS);
   p->o_cnt_large = take(4ull * 256 * p->nb_large);
   p->o_cnt_surv = take(4ull * 256 * p->nb_surv);
+  p->o_tot_large = take(4ull * 256);
+  p->o_tot_surv = take(4ull * 256);
   p->o_bc = take(4ull * 1024);
   p->o_hp = take(4 * p->rec_cap);
   p->o_surv0k = take(w * p->surv_cap);
   p->o_surv0c = take(4 * p->surv_cap);
   p->o_surv1k = take(w * p->surv_cap);
   p->o_surv1c = take(4 * p->surv_cap);
+  // chunks of large buckets and their (k-mer, count) lists
+  p->chunk_cap = p->rec_cap / p->cap_chunk + p->B + 1;
+  p->kl_cap = p->rec_cap;
+  p->o_chstart = take(8 * p->chunk_cap);
+  p->o_chlen = take(4 * p->chunk_cap);
+  p->o_kl0k = take(w * p->kl_cap);
+  p->o_kl0c = take(4 * p->kl_cap);
+  p->o_kl1k = take(w * p->kl_cap);
+  p->o_kl1c = take(4 * p->kl_cap);
   p->bytes = o;
   return true;
 }
@@ -166,7 +204,7 @@ K* at(void* ws, u64 off) {
 }
 
 template <typename K, bool HASV>
-int radix_sort(K* k0, K* k1, u32* v0, u32* v1, const u64* n_ptr, u32* counts, u32 nb, int nbits,
+int radix_sort(K* k0, K* k1, u32* v0, u32* v1, const u64* n_ptr, u32* counts, u32* totals, u32 nb, int nbits,
                hipStream_t st, bool* in_second) {
   constexpr int ITEMS = sizeof(K) == 8 ? RADIX_ITEMS_64 : RADIX_ITEMS_128;
   K* src = k0;
@@ -176,9 +214,9 @@ int radix_sort(K* k0, K* k1, u32* v0, u32* v1, const u64* n_ptr, u32* counts, u3
   int passes = 0;
   for (int sh = 0; sh < nbits; sh += 8) {
     hipLaunchKernelGGL((k_radix_upsweep<K>), dim3(nb), dim3(256), 0, st, src, n_ptr, counts, sh);
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, counts, (u64)256 * nb, (u64*)nullptr);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, st, counts, nb, totals);
     hipLaunchKernelGGL((k_radix_downsweep<K, HASV, RADIX_T, ITEMS>), dim3(nb), dim3(RADIX_T), 0, st, src, dst, vs,
-                       vd, n_ptr, counts, sh);
+                       vd, n_ptr, counts, totals, sh);
     std::swap(src, dst);
     std::swap(vs, vd);
     ++passes;
@@ -223,6 +261,15 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u64* ctrl = at<u64>(ws, P.o_ctrl);
   u32* cnt_large = at<u32>(ws, P.o_cnt_large);
   u32* cnt_surv = at<u32>(ws, P.o_cnt_surv);
+  u32* tot_large = at<u32>(ws, P.o_tot_large);
+  u32* tot_surv = at<u32>(ws, P.o_tot_surv);
+  u32* spancnt = at<u32>(ws, P.o_spancnt);
+  u64* chstart = at<u64>(ws, P.o_chstart);
+  u32* chlen = at<u32>(ws, P.o_chlen);
+  K* kl0k = at<K>(ws, P.o_kl0k);
+  u32* kl0c = at<u32>(ws, P.o_kl0c);
+  K* kl1k = at<K>(ws, P.o_kl1k);
+  u32* kl1c = at<u32>(ws, P.o_kl1c);
   u32* bc = at<u32>(ws, P.o_bc);
   u32* hp = at<u32>(ws, P.o_hp);
   K* s0k = at<K>(ws, P.o_surv0k);
@@ -236,17 +283,21 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u64* surv_n = ctrl + C_SURV_N;
   u64* nruns = ctrl + C_NRUNS;
   u64* surv_nc = ctrl + C_SURV_NC;
+  u64* kl_n = ctrl + C_KL_N;
+  u64* kl_nc = ctrl + C_KL_NC;
 
   // zero everything that accumulates
   auto fill = [&](void* p, u64 n_words) {
     if (n_words)
       hipLaunchKernelGGL(k_fill_u32, grid_for(n_words, 256, 4096), dim3(256), 0, st, (u32*)p, n_words, 0u);
   };
+  stage_mark(0, st);
   fill(ctrl, 2ull * C_WORDS);
   fill(bcnt, 2ull * P.B);
   fill(d_hist, 2ull * hist_len);
   fill(d_tot, sizeof(DevTotals) / 4);
   fill(starts, P.n_mask);
+  fill(spancnt, P.n_span_cap);
   const u64 n32 = ceil_div(P.R, 32);
   fill(packed + 2 * n32, P.n_packed - 2 * n32);
   fill(nmask + n32, P.n_mask - n32);
@@ -268,20 +319,23 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ea.log_b = P.log_b;
   ea.gmax = P.gmax;
   ea.rec_words = P.rec_words;
-  const u32 adv = (u32)(64 - (P.k - P.m + 1) + 1);
-  ea.span = adv * 16u;
+  ea.span = P.span;
   ea.rec = recA;
   ea.bid = bid;
+  ea.span_cnt = spancnt;
   ea.bcnt = bcnt;
   ea.counters = counters;
-  ea.rec_cap = P.rec_cap;
-  const u64 n_spans = ceil_div(std::max<u64>(1, P.R), ea.span);
+  ea.n_span_cap = P.n_span_cap;
+  const u64 n_spans = P.n_span_cap;
+  stage_mark(1, st);
   hipLaunchKernelGGL(k_extract, grid_for(n_spans, 4, 8192), dim3(256), 0, st, ea);
-  hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(1024), 0, st, bcnt, P.B, P.cap, recoff, cursor, small, large, lkoff,
-                     meta);
-  hipLaunchKernelGGL(k_scatter_records, grid_for(P.rec_cap, 256, 8192), dim3(256), 0, st, recA, bid, counters,
-                     P.rec_cap, cursor, recB, P.rec_words);
+  stage_mark(2, st);
+  hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(1024), 0, st, bcnt, P.B, P.cap, P.cap_chunk, recoff, cursor, small,
+                     large, lkoff, chstart, chlen, P.chunk_cap, meta);
+  hipLaunchKernelGGL(k_scatter_records, grid_for(P.n_span_cap, 4, 16384), dim3(256), 0, st, recA, bid, spancnt,
+                     P.n_span_cap, P.span, cursor, P.rec_cap, recB, P.rec_words);
 
+  stage_mark(3, st);
   // ---- stage 3: per bucket sort + count
   CountArgs ca;
   ca.rec = recB;
@@ -290,6 +344,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ca.small_list = small;
   ca.large_list = large;
   ca.large_koff = lkoff;
+  ca.chunk_start = chstart;
+  ca.chunk_len = chlen;
   ca.meta = meta;
   ca.queue = queue;
   ca.k = P.k;
@@ -303,36 +359,43 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ca.surv_c = s0c;
   ca.surv_n = surv_n;
   ca.surv_cap = P.surv_cap;
-  constexpr bool WIDE = sizeof(K) == 16;
-  if (P.cap > 0) {
-    if (P.variant == 2) {
-      constexpr int T = 512, IT = WIDE ? 8 : 16;
-      int per_cu = 0;
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
-      hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
-    } else {
-      constexpr int T = 256, IT = WIDE ? 8 : 16;
-      int per_cu = 0;
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
-      hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
-    }
-  }
-  // large buckets: expand into HBM, radix sort, count runs
-  K* lk0 = reinterpret_cast<K*>(recA);
-  K* lk1 = lk0 + P.rec_cap;
+  K* lk0 = reinterpret_cast<K*>(recA);   // unsorted records are dead after the scatter
+  ca.lkeys = lk0;
+  ca.kl_k = kl0k;
+  ca.kl_c = kl0c;
+  ca.kl_n = kl_n;
+  ca.kl_cap = P.kl_cap;
+  // large buckets: expand their k-mers into HBM, cut later into chunks
   hipLaunchKernelGGL((k_expand_large<K, 256>), dim3(1024), dim3(256), 0, st, ca, lk0);
+  constexpr bool WIDE = sizeof(K) == 16;
+  if (P.variant == 2) {
+    constexpr int T = 512, IT = WIDE ? 8 : 16;
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
+    hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+  } else {
+    constexpr int T = 256, IT = WIDE ? 8 : 16;
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
+    hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+  }
+  stage_mark(4, st);
+  // merge the chunks' (k-mer, count) lists: sort by k-mer, sum the counts of each run
+  hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, kl_n, P.kl_cap, kl_nc);
   bool second = false;
-  rc = radix_sort<K, false>(lk0, lk1, nullptr, nullptr, meta + 2, cnt_large, P.nb_large, 2 * P.k, st, &second);
+  rc = radix_sort<K, true>(kl0k, kl1k, kl0c, kl1c, kl_nc, cnt_large, tot_large, P.nb_large, 2 * P.k, st, &second);
   if (rc) return rc;
-  K* lks = second ? lk1 : lk0;
-  hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, meta + 2, bc);
+  K* lks = second ? kl1k : kl0k;
+  u32* lvs = second ? kl1c : kl0c;
+  hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc);
   hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, bc, (u64)P.nb_large, nruns);
-  hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, meta + 2, bc, hp);
-  hipLaunchKernelGGL((k_rle_runs<K>), dim3(std::max(1, n_cu) * 4), dim3(256), 0, st, ca, lks, meta + 2, hp, nruns);
+  hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc, hp);
+  hipLaunchKernelGGL((k_rle_runs<K>), dim3(std::max(1, n_cu) * 4), dim3(256), 0, st, ca, lks, lvs, kl_nc, hp, nruns);
 
+  stage_mark(5, st);
   // ---- output: survivors in ascending key order
   hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, surv_n, P.surv_cap, surv_nc);
-  rc = radix_sort<K, true>(s0k, s1k, s0c, s1c, surv_nc, cnt_surv, P.nb_surv, 2 * P.k, st, &second);
+  rc = radix_sort<K, true>(s0k, s1k, s0c, s1c, surv_nc, cnt_surv, tot_surv, P.nb_surv, 2 * P.k, st, &second);
   if (rc) return rc;
   K* ok = second ? s1k : s0k;
   u32* oc = second ? s1c : s0c;
@@ -340,6 +403,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
                      reinterpret_cast<K*>(d_kmers), d_counts);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags);
   hipLaunchKernelGGL(k_totals_meta, dim3(1), dim3(64), 0, st, d_tot, meta);
+  stage_mark(6, st);
   HIP_TRY(hipGetLastError());
   return KC_OK;
 }
@@ -347,6 +411,15 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
 int enqueue_any(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_offsets, uint32_t lo, uint32_t hi,
                 uint64_t hist_len, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap, uint64_t* d_hist,
                 DevTotals* d_tot, hipStream_t st) {
+  g_ev_cur = nullptr;
+  if (g_profile) {
+    if (g_ev_used == g_ev_pool.size()) {
+      StageEvents e;
+      for (int i = 0; i <= KC_N_STAGES; ++i) HIP_TRY(hipEventCreate(&e.ev[i]));
+      g_ev_pool.push_back(e);
+    }
+    g_ev_cur = &g_ev_pool[g_ev_used++];
+  }
   if (P.key_words == 1)
     return enqueue<u64>(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_hist, d_tot, st);
   return enqueue<k128>(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_hist, d_tot, st);
@@ -419,6 +492,29 @@ int kc_count_device(const uint8_t* d_reads, uint64_t total_bases, const uint64_t
   if (t.n_pairs > pair_capacity)
     return fail(KC_ETRUNC, "%llu pairs > capacity %llu", (unsigned long long)t.n_pairs,
                 (unsigned long long)pair_capacity);
+  return KC_OK;
+}
+
+int kc_profile(int enable) {
+  g_profile = enable != 0;
+  return KC_OK;
+}
+
+int kc_profile_read(kc_stage_times* out) {
+  g_err.clear();
+  if (!out) return fail(KC_EINVAL, "out is NULL");
+  memset(out, 0, sizeof(*out));
+  for (size_t c = 0; c < g_ev_used; ++c) {
+    StageEvents& e = g_ev_pool[c];
+    HIP_TRY(hipEventSynchronize(e.ev[KC_N_STAGES]));
+    for (int i = 0; i < KC_N_STAGES; ++i) {
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, e.ev[i], e.ev[i + 1]));
+      out->ms[i] += ms;
+    }
+  }
+  out->n_counts = g_ev_used;
+  g_ev_used = 0;
   return KC_OK;
 }
 

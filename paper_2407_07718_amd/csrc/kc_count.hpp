@@ -29,8 +29,10 @@ struct CountArgs {
   const u32* small_list;
   const u32* large_list;
   const u64* large_koff;
-  const u64* meta;         // n_small, n_large, large k-mers, records
-  u32* queue;              // work-queue cursor for small buckets
+  const u64* chunk_start;  // chunks of large buckets: first key in lkeys ...
+  const u32* chunk_len;    // ... and length (<= cap)
+  const u64* meta;         // n_small, n_large, large k-mers, records, n_chunks
+  u32* queue;              // work-queue cursor: chunks first, then small buckets
   int k;
   int rec_words;
   u32 min_freq, max_freq;
@@ -41,6 +43,11 @@ struct CountArgs {
   u32* surv_c;             // ... and counts
   u64* surv_n;             // survivor cursor
   u64 surv_cap;
+  const void* lkeys;       // expanded keys of the large buckets
+  void* kl_k;              // (k-mer, count) lists of the chunks: keys ...
+  u32* kl_c;               // ... and counts
+  u64* kl_n;               // list cursor
+  u64 kl_cap;
 };
 
 // ---------------------------------------------------------------------------- expand
@@ -134,92 +141,248 @@ __device__ __forceinline__ void flush_stats(const RunSink& S, u64 ndist) {
   }
 }
 
-// ---------------------------------------------------------------------------- small buckets
-// Persistent blocks drain the list of small buckets.  For each: expand its records into
-// LDS, LSD-sort in LDS, find run heads, then count, histogram and filter the runs.
+// ---------------------------------------------------------------------------- on-chip sort
+// Shared memory of one block of the bucket kernel.
 template <typename K, int T, int ITEMS>
-__global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
-  constexpr int W = T / 64, CAP = T * ITEMS;
-  static_assert(ITEMS <= 16, "run heads reuse the rank table as u16[CAP]");
-  __shared__ K keys[CAP];
-  __shared__ RankSmem<W> S;
-  __shared__ u32 hist_s[256];
-  __shared__ u32 sh_item, lmax;
-  __shared__ u64 scr[17];
-  const u32 tid = threadIdx.x;
-  u64* tblf = &S.tbl[0][0];
-  for (u32 i = tid; i < W * 256; i += T) tblf[i] = 0;
-  for (u32 i = tid; i < 256; i += T) hist_s[i] = 0;
-  if (tid == 0) lmax = 0;
-  RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax};
-  const u64 n_small = A.meta[0];
-  const int nbits = 2 * A.k;
-  u64 ndist = 0;
-  K* skeys = reinterpret_cast<K*>(A.surv_k);
-  for (;;) {
-    __syncthreads();
-    if (tid == 0) sh_item = atomicAdd(A.queue, 1u);
-    __syncthreads();
-    const u32 item = sh_item;
-    if (item >= n_small) break;
-    const u32 b = A.small_list[item];
-    const u32 r0 = A.rec_off[b], nr = A.rec_off[b + 1] - r0;
-    const u32 nk = (u32)A.bcnt[b];
-    // expand: thread t takes a contiguous range of records
-    const u32 pr = (nr + T - 1) / T;
-    const u32 ra = min(nr, tid * pr), rb = min(nr, ra + pr);
-    u64 gsum = 0;
-    for (u32 r = ra; r < rb; ++r) gsum += record_g(A.rec, (u64)r0 + r, A.rec_words);
-    u64 gall;
-    u64 off = block_exclusive_scan<u64>(gsum, scr, &gall);
-    for (u32 r = ra; r < rb; ++r) {
-      const u32 g = record_g(A.rec, (u64)r0 + r, A.rec_words);
-      if (off + g <= (u64)CAP) expand_record(A.rec, (u64)r0 + r, A.k, keys + off, g);
-      off += g;
+struct BucketSmem {
+  static constexpr int W = T / 64, CAP = T * ITEMS;
+  K keys[CAP];
+  union {
+    struct {
+      u64 tbl[W][256];              // lane masks per digit; all zero between uses
+      u32 cnt[2][W][256];           // per-wave digit counts -> per-wave digit offsets
+    } r;
+    u16 hp[CAP];                    // run heads after the sort
+  } u;
+  u32 gtot[4];                      // digit-group totals of the current pass
+  u32 hist_s[256];
+  u32 wtot[W];
+  u32 item, lmax;
+  u64 scr[17];
+};
+
+// Lanes of one wave that share digit d with this lane, as a lane mask.  Every active lane
+// ORs its bit into the wave's table entry of its digit and reads the entry back; when
+// neighbouring lanes hold equal digits (frequent once equal keys cluster) only the
+// first lane of each such run ORs the bits of the whole run, so that the LDS atomics
+// of a wave do not pile up on one address.
+__device__ __forceinline__ u64 digit_peers(u64* tbl, u32 d, bool act) {
+  const u32 lane = lane_id();
+  const u32 dp = (u32)__shfl_up((int)d, 1, 64);
+  const bool ap = __shfl_up((int)act, 1, 64) != 0;
+  const bool same = act && lane > 0 && ap && dp == d;
+  const u64 S = __ballot(same);
+  if (S == 0) {
+    if (act) atomicOr((unsigned long long*)&tbl[d], (unsigned long long)(1ull << lane));
+  } else {
+    // run starts: active lanes not continuing the previous lane's digit
+    const u64 L = __ballot(act && !same);
+    const u64 actm = __ballot(act);   // (ballots stay outside divergent branches)
+    if (act && !same) {
+      const u64 above = L & ~((lane == 63) ? ~0ull : ((2ull << lane) - 1));   // starts after this lane
+      const u32 nl = above ? (u32)__builtin_ctzll(above) : 64u;
+      const u64 upto = (nl == 64) ? ~0ull : ((1ull << nl) - 1);
+      const u64 run = upto & ~((1ull << lane) - 1) & actm;
+      atomicOr((unsigned long long*)&tbl[d], (unsigned long long)run);
     }
-    __syncthreads();
-    const u32 n = min(nk, (u32)CAP);
-    lds_sort<K, T, ITEMS>(keys, n, nbits, S);
-    // run heads in order -> hp (u16 positions in the now all-zero rank table)
-    u16* hp = reinterpret_cast<u16*>(tblf);
-    u32 nruns = 0;
-    for (u32 c0 = 0; c0 < n; c0 += T) {
-      const u32 i = c0 + tid;
-      const bool head = i < n && (i == 0 || !key_eq(keys[i], keys[i - 1]));
-      u64 tot;
-      const u64 ex = block_exclusive_scan<u64>(head ? 1ull : 0ull, scr, &tot);
-      if (head) hp[nruns + (u32)ex] = (u16)i;
-      nruns += (u32)tot;
-    }
-    __syncthreads();
-    // runs: statistics, then survivors
-    u32 nsurv = 0;
-    for (u32 r = tid; r < nruns; r += T) {
-      const u32 s = hp[r], e = (r + 1 < nruns) ? hp[r + 1] : n;
-      const u32 c = e - s;
-      run_stats(sink, c);
-      nsurv += (c >= A.min_freq && c <= A.max_freq) ? 1u : 0u;
-    }
-    u64 sall;
-    u64 sp = block_exclusive_scan<u64>((u64)nsurv, scr, &sall);
-    __shared__ u64 sbase;
-    if (tid == 0) sbase = sall ? atomicAdd((unsigned long long*)A.surv_n, (unsigned long long)sall) : 0ull;
-    __syncthreads();
-    u64 dst = sbase + sp;
-    for (u32 r = tid; r < nruns; r += T) {
-      const u32 s = hp[r], e = (r + 1 < nruns) ? hp[r + 1] : n;
-      const u32 c = e - s;
-      if (c >= A.min_freq && c <= A.max_freq) {
-        if (dst < A.surv_cap) {
-          skeys[dst] = keys[s];
-          A.surv_c[dst] = c;
+  }
+  return act ? tbl[d] : 0ull;
+}
+
+// LSD radix sort of keys[0, n) over bits [0, 8*np) in LDS.  Per pass: each item is
+// ranked among the equal digits of its wave (digit_peers + mbcnt; the lowest lane adds
+// the group size to the wave's running count); then threads 0..255 turn the counts into
+// per-wave offsets -- prefix over waves within a digit, wave scan over 64 digits, and
+// a 4-entry prefix over digit groups applied at the scatter.
+template <typename K, int T, int ITEMS>
+__device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n, int np) {
+  constexpr int W = T / 64;
+  const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  for (u32 i = tid; i < W * 256; i += T) {
+    (&S.u.r.tbl[0][0])[i] = 0;
+    (&S.u.r.cnt[0][0][0])[i] = 0;
+    (&S.u.r.cnt[1][0][0])[i] = 0;
+  }
+  __syncthreads();
+  const int per = (int)((n + 64u * W - 1) / (64u * W));
+  for (int p = 0; p < np; ++p) {
+    u32(*C)[256] = S.u.r.cnt[p & 1];
+    K kr[ITEMS];
+    u32 rk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+        const bool act = idx < n;
+        kr[j] = act ? S.keys[idx] : key_zero<K>();
+        const u32 d = key_digit(kr[j], 8 * p);
+        const u64 mask = digit_peers(S.u.r.tbl[wave], d, act);
+        const u32 base = act ? C[wave][d] : 0u;
+        const u32 lr = mbcnt64(mask);
+        if (act && lr == 0) {
+          C[wave][d] = base + (u32)__popcll(mask);
+          S.u.r.tbl[wave][d] = 0;
         }
-        ++dst;
+        rk[j] = base + lr;
       }
     }
-    ndist += nruns;
     __syncthreads();
-    for (u32 i = tid; i < W * 256; i += T) tblf[i] = 0;
+    if (tid < 256) {
+      // prefix over waves within digit tid, then over the 64 digits of this wave
+      u32 col = 0;
+#pragma unroll
+      for (int v = 0; v < W; ++v) {
+        const u32 x = C[v][tid];
+        C[v][tid] = col;
+        col += x;
+      }
+      const u32 inc = wave_inclusive_scan<u32>(col);
+      const u32 ex = inc - col;
+#pragma unroll
+      for (int v = 0; v < W; ++v) C[v][tid] += ex;
+      if (lane == 63) S.gtot[wave] = inc;
+    }
+    __syncthreads();
+    const u32 g1 = S.gtot[0], g2 = g1 + S.gtot[1], g3 = g2 + S.gtot[2];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+        if (idx < n) {
+          const u32 d = key_digit(kr[j], 8 * p);
+          const u32 gb = d < 128 ? (d < 64 ? 0u : g1) : (d < 192 ? g2 : g3);
+          S.keys[C[wave][d] + gb + rk[j]] = kr[j];
+        }
+      }
+    }
+    // the other count table is free again: clear it for the next pass
+    u32* nxt = &S.u.r.cnt[(p + 1) & 1][0][0];
+    for (u32 i = tid; i < W * 256; i += T) nxt[i] = 0;
+    __syncthreads();
+  }
+}
+
+// Run heads of the sorted keys[0, n) -> S.u.hp[0, nruns) in order.  Returns nruns.
+template <typename K, int T, int ITEMS>
+__device__ __forceinline__ u32 run_heads(BucketSmem<K, T, ITEMS>& S, u32 n) {
+  constexpr int W = T / 64;
+  const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int per = (int)((n + 64u * W - 1) / (64u * W));
+  u32 run = 0;
+  for (int j = 0; j < per; ++j) {
+    const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+    const bool head = idx < n && (idx == 0 || !key_eq(S.keys[idx], S.keys[idx - 1]));
+    run += (u32)__popcll(__ballot(head));
+  }
+  if (lane == 0) S.wtot[wave] = run;
+  __syncthreads();
+  u32 base = 0, all = 0;
+  for (u32 v = 0; v < (u32)W; ++v) {
+    const u32 t = S.wtot[v];
+    base += v < wave ? t : 0u;
+    all += t;
+  }
+  for (int j = 0; j < per; ++j) {
+    const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+    const bool head = idx < n && (idx == 0 || !key_eq(S.keys[idx], S.keys[idx - 1]));
+    const u64 m = __ballot(head);
+    if (head) S.u.hp[base + mbcnt64(m)] = (u16)idx;
+    base += (u32)__popcll(m);
+  }
+  __syncthreads();
+  return all;
+}
+
+// ---------------------------------------------------------------------------- bucket kernel
+// Persistent blocks drain one queue of work items.  Items [0, n_chunks) are chunks of
+// large buckets: their keys (already expanded in HBM) are sorted and run-counted on
+// chip into (k-mer, count) lists -- the paper's kmerlist form of a heavy-hitter task
+// (Section 3.4) -- merged later through HBM.  Items after that are small buckets:
+// their supermers are expanded into LDS, sorted, and their runs are final counts.
+template <typename K, int T, int ITEMS>
+__global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
+  using SM = BucketSmem<K, T, ITEMS>;
+  constexpr int CAP = SM::CAP;
+  __shared__ SM S;
+  const u32 tid = threadIdx.x;
+  for (u32 i = tid; i < 256; i += T) S.hist_s[i] = 0;
+  if (tid == 0) S.lmax = 0;
+  RunSink sink{S.hist_s, A.hist_len, A.hist, A.tot, &S.lmax};
+  const u64 n_small = A.meta[0], n_chunks = A.meta[4];
+  const int np = (2 * A.k + 7) / 8;
+  u64 ndist = 0;
+  K* skeys = reinterpret_cast<K*>(A.surv_k);
+  K* lkeys = reinterpret_cast<K*>(const_cast<void*>(A.lkeys));
+  K* klk = reinterpret_cast<K*>(A.kl_k);
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) S.item = atomicAdd(A.queue, 1u);
+    __syncthreads();
+    const u32 item = S.item;
+    if (item >= n_chunks + n_small) break;
+    const bool chunk = item < n_chunks;
+    u32 n;
+    if (chunk) {
+      const u64 ks = A.chunk_start[item];
+      n = min(A.chunk_len[item], (u32)CAP);
+      for (u32 i = tid; i < n; i += T) S.keys[i] = lkeys[ks + i];
+    } else {
+      const u32 b = A.small_list[item - n_chunks];
+      const u32 r0 = A.rec_off[b], nr = A.rec_off[b + 1] - r0;
+      n = min((u32)A.bcnt[b], (u32)CAP);
+      // expand: thread t takes a contiguous range of records
+      const u32 pr = (nr + T - 1) / T;
+      const u32 ra = min(nr, tid * pr), rb = min(nr, ra + pr);
+      u64 gsum = 0;
+      for (u32 r = ra; r < rb; ++r) gsum += record_g(A.rec, (u64)r0 + r, A.rec_words);
+      u64 gall;
+      u64 off = block_exclusive_scan<u64>(gsum, S.scr, &gall);
+      for (u32 r = ra; r < rb; ++r) {
+        const u32 g = record_g(A.rec, (u64)r0 + r, A.rec_words);
+        if (off + g <= (u64)CAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + off, g);
+        off += g;
+      }
+    }
+    __syncthreads();
+    bucket_sort<K, T, ITEMS>(S, n, np);
+    const u32 nruns = run_heads<K, T, ITEMS>(S, n);
+    // runs: uniform rounds so every lane of a wave takes part in the ballots
+    const u32 rounds = (nruns + T - 1) / T;
+    for (u32 rd = 0; rd < rounds; ++rd) {
+      const u32 r = rd * T + tid;
+      bool emit = false;
+      u32 s = 0, c = 0;
+      if (r < nruns) {
+        s = S.u.hp[r];
+        c = ((r + 1 < nruns) ? (u32)S.u.hp[r + 1] : n) - s;
+        if (chunk) {
+          emit = true;
+        } else {
+          run_stats(sink, c);
+          emit = c >= A.min_freq && c <= A.max_freq;
+        }
+      }
+      const u64 m = __ballot(emit);
+      if (m) {
+        u64 base = 0;
+        if (lane_id() == 0)
+          base = atomicAdd((unsigned long long*)(chunk ? A.kl_n : A.surv_n), (unsigned long long)__popcll(m));
+        base = __shfl(base, 0, 64);
+        if (emit) {
+          const u64 dst = base + mbcnt64(m);
+          if (chunk) {
+            if (dst < A.kl_cap) {
+              klk[dst] = S.keys[s];
+              A.kl_c[dst] = c;
+            }
+          } else if (dst < A.surv_cap) {
+            skeys[dst] = S.keys[s];
+            A.surv_c[dst] = c;
+          }
+        }
+      }
+    }
+    if (!chunk) ndist += nruns;
   }
   __syncthreads();
   flush_stats(sink, tid == 0 ? ndist : 0);
@@ -280,22 +443,23 @@ __global__ __launch_bounds__(256) void k_rle_heads(const K* __restrict__ keys, c
   }
 }
 
-// One thread per run of the large-key array.
+// One thread per run of the sorted (k-mer, count) list: the run's count is the sum of
+// its entries' counts (the merge of the chunks' lists).
 template <typename K>
-__global__ __launch_bounds__(256) void k_rle_runs(CountArgs A, const K* __restrict__ keys,
+__global__ __launch_bounds__(256) void k_rle_runs(CountArgs A, const K* __restrict__ keys, const u32* __restrict__ vals,
                                                   const u64* __restrict__ n_ptr, const u32* __restrict__ hp,
                                                   const u64* __restrict__ nruns_ptr) {
   __shared__ u32 hist_s[256];
   __shared__ u32 lmax;
+  __shared__ u64 ndb;
   for (u32 i = threadIdx.x; i < 256; i += blockDim.x) hist_s[i] = 0;
-  if (threadIdx.x == 0) lmax = 0;
+  if (threadIdx.x == 0) { lmax = 0; ndb = 0; }
   __syncthreads();
   RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax};
   const u64 n = *n_ptr, nruns = *nruns_ptr;
   K* skeys = reinterpret_cast<K*>(A.surv_k);
   u64 nd = 0;
   const u64 stride = (u64)gridDim.x * blockDim.x;
-  // iterate so that every lane of a wave runs the same number of rounds
   const u64 rounds = (nruns + stride - 1) / stride;
   for (u64 rd = 0; rd < rounds; ++rd) {
     const u64 r = rd * stride + blockIdx.x * (u64)blockDim.x + threadIdx.x;
@@ -304,7 +468,7 @@ __global__ __launch_bounds__(256) void k_rle_runs(CountArgs A, const K* __restri
     if (r < nruns) {
       s = hp[r];
       const u64 e = (r + 1 < nruns) ? hp[r + 1] : n;
-      c = e - s;
+      for (u64 i = s; i < e; ++i) c += vals[i];
       run_stats(sink, c);
       surv = c >= A.min_freq && c <= A.max_freq;
       ++nd;
@@ -323,10 +487,6 @@ __global__ __launch_bounds__(256) void k_rle_runs(CountArgs A, const K* __restri
       }
     }
   }
-  // per-block distinct count
-  __shared__ u64 ndb;
-  if (threadIdx.x == 0) ndb = 0;
-  __syncthreads();
   if (nd) atomicAdd((unsigned long long*)&ndb, (unsigned long long)nd);
   __syncthreads();
   flush_stats(sink, threadIdx.x == 0 ? ndb : 0);

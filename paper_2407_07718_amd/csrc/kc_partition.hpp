@@ -73,11 +73,12 @@ struct ExtractArgs {
   u64 n_reads, R;
   int k, m, log_b, gmax, rec_words;
   u32 span;            // k-mer windows per wave span (a multiple of the tile advance)
-  u32* rec;            // unsorted supermer records, rec_words u32 each
-  u32* bid;            // bucket of each record
+  u32* rec;            // records of span s at slots [s*span, s*span + span_cnt[s])
+  u32* bid;            // bucket of each record slot
+  u32* span_cnt;       // records written per span
   u64* bcnt;           // per bucket: (records << 32) | k-mers
   u64* counters;       // [0] records written, [1] valid windows
-  u64 rec_cap;
+  u64 n_span_cap;      // spans the record region holds
 };
 
 // Sliding minimum over `w` consecutive lanes: lane l gets min(v[l..l+w-1]).
@@ -96,7 +97,7 @@ __device__ __forceinline__ u32 window_min(u32 v, int w) {
 // A supermer record holds its bases, two bits each from bit 0, and (g - 1) in the top
 // six bits, g being the number of k-mers it carries.
 __device__ __forceinline__ void write_record(const ExtractArgs& A, u64 slot, u64 start, u32 g, u32 bucket) {
-  if (slot < A.rec_cap) {
+  {
     const u32 nb2 = 2u * (g + (u32)A.k - 1u);       // bits of bases
     if (A.rec_words == 4) {
       u64 w0 = bases64(A.packed, start), w1 = bases64(A.packed, start + 32);
@@ -146,12 +147,16 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
   const u64 mmask = (m >= 32) ? ~0ull : ((1ull << (2 * m)) - 1);
   const u64 kmask1 = (1ull << k) - 1;
   const u64 kmask2 = (1ull << (k - 1)) - 1;
-  const int shift_b = 32 - A.log_b;
+  const u32 bmask = (1u << A.log_b) - 1u;
   u64 my_windows = 0;
 
-  for (u64 s = wave; s < n_spans; s += n_waves) {
+  const u64 n_sp = min(n_spans, A.n_span_cap);
+  u64 my_records = 0;
+  for (u64 s = wave; s < n_sp; s += n_waves) {
     const u64 S0 = lo + s * A.span;
     const u64 S1 = min(S0 + A.span, lo + n_pos);
+    const u64 slot0 = s * (u64)A.span;   // records of this span: slot0 + [0, written)
+    u32 written = 0;
     bool c_open = false;
     u32 c_b = 0, c_pos = 0;
     u64 c_p = 0;
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
         u64 sb = bits64(A.starts, q + 1) & kmask2;
         valid = (nb == 0) && (sb == 0);
       }
-      const u32 b = A.log_b ? (mn >> shift_b) : 0u;
+      const u32 b = mn & bmask;   // destination = score mod B (B a power of two)
       // runs of valid windows with one bucket
       const u32 b_prev = (u32)__shfl_up((int)b, 1, 64);
       const int v_prev = __shfl_up((int)valid, 1, 64);
@@ -192,11 +197,10 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
       const u64 CL = __ballot(close);
       const u32 n_close = (u32)__popcll(CL) + (carry_close ? 1u : 0u);
       if (n_close) {
-        u64 base = 0;
-        if (lane == 0) base = atomicAdd((unsigned long long*)&A.counters[0], (unsigned long long)n_close);
-        base = __shfl(base, 0, 64);
+        const u64 base = slot0 + written;
         if (carry_close && lane == 0) write_record(A, base, c_p - (c_pos % gmax), c_pos % gmax + 1, c_b);
         if (close) write_record(A, base + (carry_close ? 1 : 0) + mbcnt64(CL), q - (pos % gmax), pos % gmax + 1, b);
+        written += n_close;
       }
       my_windows += (u64)__popcll(__ballot(valid));
       // carry the window in the last tile lane
@@ -209,50 +213,67 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
       }
     }
     if (c_open) {
-      if (lane == 0) {
-        u64 slot = atomicAdd((unsigned long long*)&A.counters[0], 1ull);
-        write_record(A, slot, c_p - (c_pos % gmax), c_pos % gmax + 1, c_b);
-      }
+      if (lane == 0) write_record(A, slot0 + written, c_p - (c_pos % gmax), c_pos % gmax + 1, c_b);
+      ++written;
     }
+    if (lane == 0) A.span_cnt[s] = written;
+    my_records += written;
   }
   if (lane == 0 && my_windows) atomicAdd((unsigned long long*)&A.counters[1], (unsigned long long)my_windows);
+  if (lane == 0 && my_records) atomicAdd((unsigned long long*)&A.counters[0], (unsigned long long)my_records);
 }
 
 // ---------------------------------------------------------------------------- bucket plan
 // One block: exclusive scans over the B buckets giving record offsets, scatter cursors,
-// the list of small buckets (sorted on chip) and of large ones (k-mers > cap, sorted
-// through HBM) with their k-mer offsets in the large-key array.
-// meta: [0] n_small, [1] n_large, [2] large k-mers, [3] total records.
-__global__ __launch_bounds__(1024) void k_bucket_plan(const u64* __restrict__ bcnt, u32 B, u32 cap,
-                                                      u32* __restrict__ rec_off, u32* __restrict__ cursor,
-                                                      u32* __restrict__ small_list, u32* __restrict__ large_list,
-                                                      u64* __restrict__ large_koff, u64* __restrict__ meta) {
+// the list of small buckets (k-mers <= cap_small: sorted on chip from their records) and
+// of large ones, with their k-mer offsets in the large-key array and their cut into
+// chunks of at most cap_chunk k-mers.
+// meta: [0] n_small, [1] n_large, [2] large k-mers, [3] total records, [4] n_chunks.
+__global__ __launch_bounds__(1024) void k_bucket_plan(const u64* __restrict__ bcnt, u32 B, u32 cap_small,
+                                                      u32 cap_chunk, u32* __restrict__ rec_off,
+                                                      u32* __restrict__ cursor, u32* __restrict__ small_list,
+                                                      u32* __restrict__ large_list, u64* __restrict__ large_koff,
+                                                      u64* __restrict__ chunk_start, u32* __restrict__ chunk_len,
+                                                      u64 chunk_cap, u64* __restrict__ meta) {
   __shared__ u64 scratch[17];
   const u32 T = blockDim.x, t = threadIdx.x;
   const u32 per = (B + T - 1) / T;
   const u32 b0 = min(B, t * per), b1 = min(B, b0 + per);
-  u64 srec = 0, ssmall = 0, slarge = 0, slk = 0;
+  u64 srec = 0, ssmall = 0, slarge = 0, slk = 0, sch = 0;
   for (u32 b = b0; b < b1; ++b) {
     u64 c = bcnt[b];
     u32 nk = (u32)c, nr = (u32)(c >> 32);
     srec += nr;
-    if (nk > cap) { slarge += 1; slk += nk; }
-    else if (nk > 0) ssmall += 1;
+    if (nk > cap_small) {
+      slarge += 1;
+      slk += nk;
+      sch += (nk + cap_chunk - 1) / cap_chunk;
+    } else if (nk > 0) {
+      ssmall += 1;
+    }
   }
-  u64 tot_rec, tot_small, tot_large, tot_lk;
+  u64 tot_rec, tot_small, tot_large, tot_lk, tot_ch;
   u64 prec = block_exclusive_scan<u64>(srec, scratch, &tot_rec);
   u64 psmall = block_exclusive_scan<u64>(ssmall, scratch, &tot_small);
   u64 plarge = block_exclusive_scan<u64>(slarge, scratch, &tot_large);
   u64 plk = block_exclusive_scan<u64>(slk, scratch, &tot_lk);
+  u64 pch = block_exclusive_scan<u64>(sch, scratch, &tot_ch);
   for (u32 b = b0; b < b1; ++b) {
     u64 c = bcnt[b];
     u32 nk = (u32)c, nr = (u32)(c >> 32);
     rec_off[b] = (u32)prec;
     cursor[b] = (u32)prec;
     prec += nr;
-    if (nk > cap) {
+    if (nk > cap_small) {
       large_list[plarge] = b;
       large_koff[b] = plk;
+      for (u32 o = 0; o < nk; o += cap_chunk) {
+        if (pch < chunk_cap) {
+          chunk_start[pch] = plk + o;
+          chunk_len[pch] = min(cap_chunk, nk - o);
+        }
+        ++pch;
+      }
       plarge += 1;
       plk += nk;
     } else if (nk > 0) {
@@ -265,19 +286,25 @@ __global__ __launch_bounds__(1024) void k_bucket_plan(const u64* __restrict__ bc
     meta[1] = tot_large;
     meta[2] = tot_lk;
     meta[3] = tot_rec;
+    meta[4] = min(tot_ch, chunk_cap);
   }
 }
 
 // Move every record to its bucket's range (order inside a bucket does not matter: the
-// bucket is sorted next).
+// bucket is sorted next).  One wave per span of the extract stage.
 __global__ __launch_bounds__(256) void k_scatter_records(const u32* __restrict__ rec, const u32* __restrict__ bid,
-                                                         const u64* __restrict__ counters, u64 rec_cap,
-                                                         u32* __restrict__ cursor, u32* __restrict__ rec_out,
-                                                         int rec_words) {
-  const u64 n = min(counters[0], rec_cap);
-  for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+                                                         const u32* __restrict__ span_cnt, u64 n_span_cap, u32 span,
+                                                         u32* __restrict__ cursor, u64 rec_out_cap,
+                                                         u32* __restrict__ rec_out, int rec_words) {
+  const u64 wave = (blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6;
+  const u64 n_waves = ((u64)gridDim.x * blockDim.x) >> 6;
+  for (u64 sp = wave; sp < n_span_cap; sp += n_waves) {
+   const u32 cnt = span_cnt[sp];
+   for (u32 j = lane_id(); j < cnt; j += 64) {
+    const u64 i = sp * (u64)span + j;
     const u32 b = bid[i];
     const u32 slot = atomicAdd(&cursor[b], 1u);
+    if (slot >= rec_out_cap) continue;
     if (rec_words == 4) {
       reinterpret_cast<uint4*>(rec_out)[slot] = reinterpret_cast<const uint4*>(rec)[i];
     } else {
@@ -286,5 +313,6 @@ __global__ __launch_bounds__(256) void k_scatter_records(const u32* __restrict__
       d[0] = s[0];
       d[1] = s[1];
     }
+   }
   }
 }

@@ -155,13 +155,32 @@ __global__ __launch_bounds__(1024) void k_scan_u32(u32* __restrict__ data, u64 n
   if (t == 0 && total) *total = all;
 }
 
+// Row d of counts (one digit over all nb blocks) -> exclusive prefix over blocks, and
+// totals[d] = the row sum.  One block per digit.
+__global__ __launch_bounds__(256) void k_radix_rowscan(u32* __restrict__ counts, u32 nb, u32* __restrict__ totals) {
+  __shared__ u64 scr[17];
+  u32* row = counts + (u64)blockIdx.x * nb;
+  const u32 per = (nb + 255) / 256;
+  const u32 s = min(nb, threadIdx.x * per), e = min(nb, s + per);
+  u64 sum = 0;
+  for (u32 i = s; i < e; ++i) sum += row[i];
+  u64 all;
+  u64 run = block_exclusive_scan<u64>(sum, scr, &all);
+  for (u32 i = s; i < e; ++i) {
+    const u32 v = row[i];
+    row[i] = (u32)run;
+    run += v;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = (u32)all;
+}
+
 // Stable scatter of one pass.  Each tile of T*ITEMS keys is ranked by digit, staged in
 // LDS in digit order and written out as one run per digit.
 template <typename K, bool HASV, int T, int ITEMS>
 __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin, K* __restrict__ kout,
                                                        const u32* __restrict__ vin, u32* __restrict__ vout,
                                                        const u64* __restrict__ n_ptr, const u32* __restrict__ counts,
-                                                       int sh) {
+                                                       const u32* __restrict__ totals, int sh) {
   constexpr int W = T / 64, TILE = T * ITEMS;
   __shared__ RankSmem<W> S;
   __shared__ K stage_k[TILE];
@@ -169,7 +188,13 @@ __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin
   __shared__ u32 run_base[256];
   const u32 nb = gridDim.x, tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   for (u32 i = tid; i < W * 256; i += T) (&S.tbl[0][0])[i] = 0;
-  if (tid < 256) run_base[tid] = counts[(u64)tid * nb + blockIdx.x];
+  {
+    // digit d of this block starts at (sum of all smaller digits) + (digit d in earlier blocks)
+    const u64 t = tid < 256 ? totals[tid] : 0u;
+    u64 all;
+    const u64 dbase = block_exclusive_scan<u64>(t, S.scr, &all);
+    if (tid < 256) run_base[tid] = (u32)dbase + counts[(u64)tid * nb + blockIdx.x];
+  }
   __syncthreads();
   u64 s, e;
   block_range(*n_ptr, nb, &s, &e);

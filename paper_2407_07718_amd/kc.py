@@ -48,6 +48,14 @@ class kc_result(ctypes.Structure):
                 ("hist", ctypes.POINTER(ctypes.c_uint64)), ("hist_len", ctypes.c_uint64), ("totals", kc_totals)]
 
 
+KC_N_STAGES = 6
+STAGES = ["encode", "extract", "partition", "small_sort", "large_path", "output"]
+
+
+class kc_stage_times(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * KC_N_STAGES), ("n_counts", ctypes.c_uint64)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
@@ -66,6 +74,10 @@ def _load() -> ctypes.CDLL:
     lib.kc_count_device.restype = i32
     lib.kc_count_device_async.argtypes = dev_args
     lib.kc_count_device_async.restype = i32
+    lib.kc_profile.argtypes = [i32]
+    lib.kc_profile.restype = i32
+    lib.kc_profile_read.argtypes = [ctypes.POINTER(kc_stage_times)]
+    lib.kc_profile_read.restype = i32
     return lib
 
 
@@ -83,6 +95,19 @@ def kc_last_error() -> str:
 def _check(rc: int) -> None:
     if rc != KC_OK:
         raise KCError(rc, kc_last_error())
+
+
+def kc_profile(enable: bool) -> None:
+    _check(_lib.kc_profile(int(enable)))
+
+
+def kc_profile_read() -> dict:
+    """Summed per-stage milliseconds of the counts profiled since the last read."""
+    t = kc_stage_times()
+    _check(_lib.kc_profile_read(ctypes.byref(t)))
+    out = {name: float(t.ms[i]) for i, name in enumerate(STAGES)}
+    out["n_counts"] = int(t.n_counts)
+    return out
 
 
 def make_config(log2_buckets: int = 0, force_hbm: bool = False, small_variant: int = 0,
