@@ -54,6 +54,9 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int RADIX_T = 256;
+constexpr u32 WAVE_CAP_64 = 1024, WAVE_CAP_128 = 512;   // k-mers of a bucket sorted by one wave
+constexpr int WAVES_PER_BLOCK = 4;
+constexpr u32 RUN_BLOCKS = 1024;   // blocks of the merged-run kernel
 constexpr int RADIX_ITEMS_64 = 16;
 constexpr int RADIX_ITEMS_128 = 8;
 
@@ -63,7 +66,7 @@ inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 // Sizes and byte offsets of every workspace region for one (input size, k, config).
 struct Plan {
   int k = 0, m = 0, key_words = 0, rec_words = 0, gmax = 0, log_b = 0;
-  u32 B = 0, cap = 0, cap_chunk = 0, variant = 1;
+  u32 B = 0, cap = 0, cap_chunk = 0, cap_tiny = 0, variant = 1;
   u64 chunk_cap = 0, kl_cap = 0;
   u64 R = 0, n_reads = 0, n_max = 0;   // bases, reads, bound on windows
   u64 rec_cap = 0, surv_cap = 0;
@@ -73,14 +76,15 @@ struct Plan {
   // offsets into the workspace
   u64 o_packed, o_nmask, o_starts, o_recA, o_recB, o_bid, o_bcnt, o_recoff, o_cursor, o_small, o_large,
       o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_tot_large, o_tot_surv, o_bc, o_hp, o_surv0k, o_surv0c, o_surv1k,
-      o_surv1c, o_spancnt, o_chstart, o_chlen, o_kl0k, o_kl0c, o_kl1k, o_kl1c;
+      o_surv1c, o_spancnt, o_chstart, o_chlen, o_kl0k, o_kl0c, o_kl1k, o_kl1c, o_tiny, o_kall, o_klsc, o_klcnt,
+      o_kloff, o_scnt, o_soff;
   u64 n_packed, n_mask, bytes = 0;
 };
 
 // Control words (all zeroed at the start of a count).
 enum Ctrl : int {
   C_COUNTERS = 0,   // [0] records, [1] windows
-  C_META = 2,       // 5 words: n_small, n_large, large k-mers, records, n_chunks
+  C_META = 2,       // 6 words: n_small, n_large, large k-mers, records, n_chunks, n_tiny
   C_FLAGS = 8,
   C_QUEUE = 9,
   C_SURV_N = 10,
@@ -88,9 +92,10 @@ enum Ctrl : int {
   C_SURV_NC = 12,   // survivors, clamped to capacity
   C_KL_N = 13,      // (k-mer, count) list entries
   C_KL_NC = 14,     // ... clamped to capacity
+  C_WQUEUE = 15,    // work-queue cursor of the wave kernel
   C_WORDS = 16
 };
-static_assert(C_META + 5 <= C_FLAGS, "meta overlaps the flags");
+static_assert(C_META + 6 <= C_FLAGS, "meta overlaps the flags");
 
 u32 default_variant(int key_words) { return key_words == 1 ? 1u : 1u; }
 u32 small_cap(int key_words, u32 variant) {
@@ -113,6 +118,7 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   if (p->variant > 2) return false;
   p->cap_chunk = small_cap(p->key_words, p->variant);
   p->cap = (cfg && cfg->force_hbm) ? 0u : p->cap_chunk;
+  p->cap_tiny = (cfg && cfg->force_hbm) ? 0u : (p->key_words == 1 ? WAVE_CAP_64 : WAVE_CAP_128);
   if (cfg && cfg->log2_buckets) {
     if (cfg->log2_buckets > 20) return false;
     p->log_b = (int)cfg->log2_buckets;
@@ -131,7 +137,8 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->slots = R + 16 * 64;
   p->n_span_cap = (std::max<u64>(R, 1) + p->span - 1) / p->span;
   p->n_span_alloc = R / 32 + 2;
-  p->surv_cap = std::max<u64>(1, n_max / std::max<u32>(1, min_freq));
+  (void)min_freq;
+  p->surv_cap = std::max<u64>(1, n_max);   // survivors sit at their bucket's k-mer slots first
   const u64 w = 8ull * p->key_words;
   const u64 tile = (u64)RADIX_T * (p->key_words == 1 ? RADIX_ITEMS_64 : RADIX_ITEMS_128);
   p->nb_large = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(n_max, tile * 2)));
@@ -157,6 +164,7 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_recoff = take(4ull * (p->B + 1));
   p->o_cursor = take(4ull * p->B);
   p->o_small = take(4ull * p->B);
+  p->o_tiny = take(4ull * p->B);
   p->o_large = take(4ull * p->B);
   p->o_lkoff = take(8ull * p->B);
   p->o_ctrl = take(8ull * C_WORDS);
@@ -179,6 +187,12 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_kl0c = take(4 * p->kl_cap);
   p->o_kl1k = take(w * p->kl_cap);
   p->o_kl1c = take(4 * p->kl_cap);
+  p->o_kall = take(8ull * p->B);
+  p->o_klsc = take(4 * p->kl_cap);
+  p->o_klcnt = take(4 * p->chunk_cap);
+  p->o_kloff = take(4 * p->chunk_cap);
+  p->o_scnt = take(4ull * (p->B + RUN_BLOCKS));
+  p->o_soff = take(4ull * (p->B + RUN_BLOCKS));
   p->bytes = o;
   return true;
 }
@@ -256,6 +270,13 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u32* recoff = at<u32>(ws, P.o_recoff);
   u32* cursor = at<u32>(ws, P.o_cursor);
   u32* small = at<u32>(ws, P.o_small);
+  u32* tiny = at<u32>(ws, P.o_tiny);
+  u64* kall = at<u64>(ws, P.o_kall);
+  u32* klsc = at<u32>(ws, P.o_klsc);
+  u32* klcnt = at<u32>(ws, P.o_klcnt);
+  u32* kloff = at<u32>(ws, P.o_kloff);
+  u32* scnt = at<u32>(ws, P.o_scnt);
+  u32* soff = at<u32>(ws, P.o_soff);
   u32* large = at<u32>(ws, P.o_large);
   u64* lkoff = at<u64>(ws, P.o_lkoff);
   u64* ctrl = at<u64>(ws, P.o_ctrl);
@@ -298,6 +319,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   fill(d_tot, sizeof(DevTotals) / 4);
   fill(starts, P.n_mask);
   fill(spancnt, P.n_span_cap);
+  fill(scnt, P.B);
   const u64 n32 = ceil_div(P.R, 32);
   fill(packed + 2 * n32, P.n_packed - 2 * n32);
   fill(nmask + n32, P.n_mask - n32);
@@ -330,8 +352,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   stage_mark(1, st);
   hipLaunchKernelGGL(k_extract, grid_for(n_spans, 4, 8192), dim3(256), 0, st, ea);
   stage_mark(2, st);
-  hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(1024), 0, st, bcnt, P.B, P.cap, P.cap_chunk, recoff, cursor, small,
-                     large, lkoff, chstart, chlen, P.chunk_cap, meta);
+  hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(1024), 0, st, bcnt, P.B, P.cap_tiny, P.cap, P.cap_chunk, tiny, recoff,
+                     cursor, small, large, lkoff, chstart, chlen, P.chunk_cap, kall, meta);
   hipLaunchKernelGGL(k_scatter_records, grid_for(P.n_span_cap, 4, 16384), dim3(256), 0, st, recA, bid, spancnt,
                      P.n_span_cap, P.span, cursor, P.rec_cap, recB, P.rec_words);
 
@@ -347,7 +369,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ca.chunk_start = chstart;
   ca.chunk_len = chlen;
   ca.meta = meta;
-  ca.queue = queue;
+  ca.kall_off = kall;
   ca.k = P.k;
   ca.rec_words = P.rec_words;
   ca.min_freq = lo;
@@ -355,16 +377,14 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ca.hist_len = hist_len;
   ca.hist = d_hist;
   ca.tot = d_tot;
-  ca.surv_k = s0k;
+  ca.surv_k = s0k;           // sparse: bucket b's survivors at kall[b] + i
   ca.surv_c = s0c;
-  ca.surv_n = surv_n;
-  ca.surv_cap = P.surv_cap;
+  ca.surv_cnt = scnt;
   K* lk0 = reinterpret_cast<K*>(recA);   // unsorted records are dead after the scatter
   ca.lkeys = lk0;
-  ca.kl_k = kl0k;
-  ca.kl_c = kl0c;
-  ca.kl_n = kl_n;
-  ca.kl_cap = P.kl_cap;
+  ca.kl_k = lk0;             // a chunk's list overwrites its own keys (read into LDS first)
+  ca.kl_c = klsc;
+  ca.kl_cnt = klcnt;
   // large buckets: expand their k-mers into HBM, cut later into chunks
   hipLaunchKernelGGL((k_expand_large<K, 256>), dim3(1024), dim3(256), 0, st, ca, lk0);
   constexpr bool WIDE = sizeof(K) == 16;
@@ -379,26 +399,46 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
     hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
   }
+  {
+    constexpr u32 WC = WIDE ? WAVE_CAP_128 : WAVE_CAP_64;
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_sort_count<K, WC, WAVES_PER_BLOCK>,
+                                                         WAVES_PER_BLOCK * 64, 0));
+    hipLaunchKernelGGL((k_wave_sort_count<K, WC, WAVES_PER_BLOCK>), dim3(std::max(1, per_cu) * n_cu),
+                       dim3(WAVES_PER_BLOCK * 64), 0, st, ca, tiny, meta + 5);
+  }
   stage_mark(4, st);
-  // merge the chunks' (k-mer, count) lists: sort by k-mer, sum the counts of each run
+  // merge the chunks' (k-mer, count) lists: compact, sort by k-mer, sum each run's counts
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, klcnt, kloff, meta + 4, P.chunk_cap, kl_n);
+  hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.chunk_cap, 4, 4096), dim3(256), 0, st, lk0, klsc, chstart,
+                     (const u64*)nullptr, 0u, klcnt, kloff, meta + 4, P.chunk_cap, kl0k, kl0c);
   hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, kl_n, P.kl_cap, kl_nc);
   bool second = false;
   rc = radix_sort<K, true>(kl0k, kl1k, kl0c, kl1c, kl_nc, cnt_large, tot_large, P.nb_large, 2 * P.k, st, &second);
   if (rc) return rc;
   K* lks = second ? kl1k : kl0k;
   u32* lvs = second ? kl1c : kl0c;
+  K* fk = second ? kl0k : kl1k;     // the free buffer holds the merged runs' survivors
+  u32* fc = second ? kl0c : kl1c;
   hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc);
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, bc, (u64)P.nb_large, nruns);
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, bc, bc, (const u64*)nullptr, (u64)P.nb_large, nruns);
   hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc, hp);
-  hipLaunchKernelGGL((k_rle_runs<K>), dim3(std::max(1, n_cu) * 4), dim3(256), 0, st, ca, lks, lvs, kl_nc, hp, nruns);
+  hipLaunchKernelGGL((k_rle_runs<K>), dim3(RUN_BLOCKS), dim3(256), 0, st, ca, lks, lvs, kl_nc, hp, nruns, fk, fc,
+                     scnt + P.B);
 
   stage_mark(5, st);
-  // ---- output: survivors in ascending key order
+  // ---- output: compact the survivors (buckets, then merged runs), sort them by key
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, scnt, soff, (const u64*)nullptr, (u64)P.B + RUN_BLOCKS,
+                     surv_n);
+  hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.B, 4, 4096), dim3(256), 0, st, s0k, s0c, kall, (const u64*)nullptr,
+                     0u, scnt, soff, (const u64*)nullptr, (u64)P.B, s1k, s1c);
+  hipLaunchKernelGGL((k_gather_segments<K>), grid_for(RUN_BLOCKS, 4, 4096), dim3(256), 0, st, fk, fc, (const u64*)nullptr,
+                     nruns, RUN_BLOCKS, scnt + P.B, soff + P.B, (const u64*)nullptr, (u64)RUN_BLOCKS, s1k, s1c);
   hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, surv_n, P.surv_cap, surv_nc);
-  rc = radix_sort<K, true>(s0k, s1k, s0c, s1c, surv_nc, cnt_surv, tot_surv, P.nb_surv, 2 * P.k, st, &second);
+  rc = radix_sort<K, true>(s1k, s0k, s1c, s0c, surv_nc, cnt_surv, tot_surv, P.nb_surv, 2 * P.k, st, &second);
   if (rc) return rc;
-  K* ok = second ? s1k : s0k;
-  u32* oc = second ? s1c : s0c;
+  K* ok = second ? s0k : s1k;
+  u32* oc = second ? s0c : s1c;
   hipLaunchKernelGGL((k_copy_pairs<K>), grid_for(P.surv_cap, 256, 4096), dim3(256), 0, st, ok, oc, surv_nc, pair_cap,
                      reinterpret_cast<K*>(d_kmers), d_counts);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags);

@@ -31,23 +31,21 @@ struct CountArgs {
   const u64* large_koff;
   const u64* chunk_start;  // chunks of large buckets: first key in lkeys ...
   const u32* chunk_len;    // ... and length (<= cap)
-  const u64* meta;         // n_small, n_large, large k-mers, records, n_chunks
-  u32* queue;              // work-queue cursor: chunks first, then small buckets
+  const u64* meta;         // n_small, n_large, large k-mers, records, n_chunks, n_tiny
+  const u64* kall_off;     // per bucket: first k-mer slot (prefix of k-mers over all buckets)
   int k;
   int rec_words;
   u32 min_freq, max_freq;
   u64 hist_len;
   u64* hist;               // [hist_len]
   DevTotals* tot;
-  void* surv_k;            // survivors: keys ...
+  void* surv_k;            // survivors of bucket b at slots kall_off[b] + i: keys ...
   u32* surv_c;             // ... and counts
-  u64* surv_n;             // survivor cursor
-  u64 surv_cap;
+  u32* surv_cnt;           // survivors per bucket
   const void* lkeys;       // expanded keys of the large buckets
-  void* kl_k;              // (k-mer, count) lists of the chunks: keys ...
-  u32* kl_c;               // ... and counts
-  u64* kl_n;               // list cursor
-  u64 kl_cap;
+  void* kl_k;              // (k-mer, count) list of chunk c at slots chunk_start[c] + i
+  u32* kl_c;
+  u32* kl_cnt;             // list length per chunk
 };
 
 // ---------------------------------------------------------------------------- expand
@@ -97,7 +95,8 @@ __device__ __forceinline__ void expand_record(const u32* __restrict__ rec, u64 r
   dst[0] = key_lt(F, RC) ? F : RC;
   for (u32 j = 1; j < g; ++j) {
     const u32 p = j + (u32)k - 1;
-    const u64 c = (w[p >> 5] >> (2 * (p & 31))) & 3ull;
+    const u64 wsel = p < 64 ? (p < 32 ? w[0] : w[1]) : (p < 96 ? w[2] : w[3]);   // no dynamic register index
+    const u64 c = (wsel >> (2 * (p & 31))) & 3ull;
     // F = ((F << 2) | c) masked to 2k bits
     F.hi = ((F.hi << 2) | (F.lo >> 62)) & mhi;
     F.lo = (F.lo << 2) | c;
@@ -119,13 +118,14 @@ struct RunSink {
   u64* hist;
   DevTotals* tot;
   u32* lmax;               // LDS running max
+  unsigned long long* lover;   // LDS sum of counts in the last bin
 };
 
 __device__ __forceinline__ void run_stats(const RunSink& S, u64 c) {
   const u64 bin = c < S.hist_len - 1 ? c : S.hist_len - 1;
   if (bin < 256) atomicAdd(&S.hist_s[bin], 1u);
   else atomicAdd((unsigned long long*)&S.hist[bin], 1ull);
-  if (c >= S.hist_len - 1) atomicAdd((unsigned long long*)&S.tot->overflow_sum, (unsigned long long)c);
+  if (c >= S.hist_len - 1) atomicAdd(S.lover, (unsigned long long)c);
   atomicMax(S.lmax, (u32)min(c, (u64)0xFFFFFFFFu));
 }
 
@@ -137,6 +137,7 @@ __device__ __forceinline__ void flush_stats(const RunSink& S, u64 ndist) {
   }
   if (threadIdx.x == 0) {
     atomicMax((unsigned long long*)&S.tot->max_count, (unsigned long long)*S.lmax);
+    if (*S.lover) atomicAdd((unsigned long long*)&S.tot->overflow_sum, *S.lover);
     if (ndist) atomicAdd((unsigned long long*)&S.tot->n_distinct, (unsigned long long)ndist);
   }
 }
@@ -160,6 +161,37 @@ struct BucketSmem {
   u32 item, lmax;
   u64 scr[17];
 };
+
+// Key above every canonical k-mer (which uses only the low 2k bits): pads a bucket to
+// whole waves.  Its digit is 0xFF in every pass, so a stable sort keeps the padding
+// after all real keys and the padded lanes need no masking.
+template <typename K> __device__ __forceinline__ K key_pad();
+template <> __device__ __forceinline__ u64 key_pad<u64>() { return ~0ull; }
+template <> __device__ __forceinline__ k128 key_pad<k128>() { return k128{~0ull, ~0ull}; }
+
+// v of the previous lane (lane 0 gets `fill`): one DPP wave_shr:1 move.
+__device__ __forceinline__ u32 prev_lane(u32 v, u32 fill) {
+  return (u32)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xF, 0xF, false);
+}
+
+// Lanes of a fully active wave that share digit d with this lane, as a lane mask.  Every
+// lane ORs its bit into the wave's table entry of its digit and reads the entry back;
+// when neighbouring lanes hold equal digits (frequent once equal keys cluster) only the
+// first lane of each such run ORs the bits of the whole run, so that the LDS atomics of
+// a wave do not pile up on one address.
+__device__ __forceinline__ u64 digit_peers_full(u64* tbl, u32 d, u64 ge_mask) {
+  const u32 lane = lane_id();
+  const bool same = prev_lane(d, d ^ 1u) == d;   // lane 0 never matches
+  const u64 S = __ballot(same);
+  u64 bits = 1ull << lane;
+  if (S != 0) {
+    // run of this lane: up to (not including) the next lane that starts a run
+    const u64 starts_after = ~S & (ge_mask << 1);
+    bits = ((starts_after & (0ull - starts_after)) - 1ull) & ge_mask;
+  }
+  if (!same) atomicOr((unsigned long long*)&tbl[d], (unsigned long long)bits);
+  return tbl[d];
+}
 
 // Lanes of one wave that share digit d with this lane, as a lane mask.  Every active lane
 // ORs its bit into the wave's table entry of its digit and reads the entry back; when
@@ -195,16 +227,17 @@ __device__ __forceinline__ u64 digit_peers(u64* tbl, u32 d, bool act) {
 // per-wave offsets -- prefix over waves within a digit, wave scan over 64 digits, and
 // a 4-entry prefix over digit groups applied at the scatter.
 template <typename K, int T, int ITEMS>
-__device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n, int np) {
+__device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pad, int np) {
   constexpr int W = T / 64;
   const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const u64 ge = ~((1ull << lane) - 1ull);
   for (u32 i = tid; i < W * 256; i += T) {
     (&S.u.r.tbl[0][0])[i] = 0;
     (&S.u.r.cnt[0][0][0])[i] = 0;
     (&S.u.r.cnt[1][0][0])[i] = 0;
   }
   __syncthreads();
-  const int per = (int)((n + 64u * W - 1) / (64u * W));
+  const int per = (int)(n_pad / (64u * W));
   for (int p = 0; p < np; ++p) {
     u32(*C)[256] = S.u.r.cnt[p & 1];
     K kr[ITEMS];
@@ -212,14 +245,12 @@ __device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n, i
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       if (j < per) {
-        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
-        const bool act = idx < n;
-        kr[j] = act ? S.keys[idx] : key_zero<K>();
+        kr[j] = S.keys[(wave * (u32)per + (u32)j) * 64u + lane];
         const u32 d = key_digit(kr[j], 8 * p);
-        const u64 mask = digit_peers(S.u.r.tbl[wave], d, act);
-        const u32 base = act ? C[wave][d] : 0u;
+        const u64 mask = digit_peers_full(S.u.r.tbl[wave], d, ge);
+        const u32 base = C[wave][d];
         const u32 lr = mbcnt64(mask);
-        if (act && lr == 0) {
+        if (lr == 0) {
           C[wave][d] = base + (u32)__popcll(mask);
           S.u.r.tbl[wave][d] = 0;
         }
@@ -247,12 +278,9 @@ __device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n, i
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       if (j < per) {
-        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
-        if (idx < n) {
-          const u32 d = key_digit(kr[j], 8 * p);
-          const u32 gb = d < 128 ? (d < 64 ? 0u : g1) : (d < 192 ? g2 : g3);
-          S.keys[C[wave][d] + gb + rk[j]] = kr[j];
-        }
+        const u32 d = key_digit(kr[j], 8 * p);
+        const u32 gb = d < 128 ? (d < 64 ? 0u : g1) : (d < 192 ? g2 : g3);
+        S.keys[C[wave][d] + gb + rk[j]] = kr[j];
       }
     }
     // the other count table is free again: clear it for the next pass
@@ -294,40 +322,75 @@ __device__ __forceinline__ u32 run_heads(BucketSmem<K, T, ITEMS>& S, u32 n) {
 }
 
 // ---------------------------------------------------------------------------- bucket kernel
-// Persistent blocks drain one queue of work items.  Items [0, n_chunks) are chunks of
-// large buckets: their keys (already expanded in HBM) are sorted and run-counted on
-// chip into (k-mer, count) lists -- the paper's kmerlist form of a heavy-hitter task
-// (Section 3.4) -- merged later through HBM.  Items after that are small buckets:
-// their supermers are expanded into LDS, sorted, and their runs are final counts.
+// Emit the runs of a sorted block of keys.  Runs [0, nruns) with heads hp; a run is kept
+// when `final` and its count is in range (and feeds the statistics), or always for a
+// chunk list.  Kept runs go to dst_k/dst_c[0, kept) in run order; returns kept.
+// Block-wide (barriers inside).
+template <typename K>
+__device__ __forceinline__ u32 emit_runs_block(const K* keys, const u16* hp, u32 nruns, u32 n, bool final, u32 lo,
+                                               u32 hi, const RunSink& sink, K* dst_k, u32* dst_c, u64* scr) {
+  u32 kept = 0;
+  for (u32 c0 = 0; c0 < nruns; c0 += blockDim.x) {
+    const u32 r = c0 + threadIdx.x;
+    bool emit = false;
+    u32 s = 0, c = 0;
+    if (r < nruns) {
+      s = hp[r];
+      c = ((r + 1 < nruns) ? (u32)hp[r + 1] : n) - s;
+      if (final) {
+        run_stats(sink, c);
+        emit = c >= lo && c <= hi;
+      } else {
+        emit = true;
+      }
+    }
+    u64 tot;
+    const u64 ex = block_exclusive_scan<u64>(emit ? 1ull : 0ull, scr, &tot);
+    if (emit) {
+      dst_k[kept + ex] = keys[s];
+      dst_c[kept + ex] = c;
+    }
+    kept += (u32)tot;
+  }
+  return kept;
+}
+
+// Persistent blocks take work items round-robin (item = block, block + grid, ...).
+// Items [0, n_chunks) are chunks of large buckets: their keys (already expanded in HBM)
+// are sorted and run-counted on chip into (k-mer, count) lists -- the paper's kmerlist
+// form of a heavy-hitter task (Section 3.4) -- merged later through HBM.  Items after
+// that are small buckets: their supermers are expanded into LDS, sorted, and their runs
+// are final counts.  Every item writes its output to its own slot range.
 template <typename K, int T, int ITEMS>
 __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
   using SM = BucketSmem<K, T, ITEMS>;
   constexpr int CAP = SM::CAP;
   __shared__ SM S;
+  __shared__ unsigned long long lover;
   const u32 tid = threadIdx.x;
   for (u32 i = tid; i < 256; i += T) S.hist_s[i] = 0;
-  if (tid == 0) S.lmax = 0;
-  RunSink sink{S.hist_s, A.hist_len, A.hist, A.tot, &S.lmax};
+  if (tid == 0) {
+    S.lmax = 0;
+    lover = 0;
+  }
+  RunSink sink{S.hist_s, A.hist_len, A.hist, A.tot, &S.lmax, &lover};
   const u64 n_small = A.meta[0], n_chunks = A.meta[4];
   const int np = (2 * A.k + 7) / 8;
   u64 ndist = 0;
   K* skeys = reinterpret_cast<K*>(A.surv_k);
-  K* lkeys = reinterpret_cast<K*>(const_cast<void*>(A.lkeys));
+  const K* lkeys = reinterpret_cast<const K*>(A.lkeys);
   K* klk = reinterpret_cast<K*>(A.kl_k);
-  for (;;) {
+  for (u64 item = blockIdx.x; item < n_chunks + n_small; item += gridDim.x) {
     __syncthreads();
-    if (tid == 0) S.item = atomicAdd(A.queue, 1u);
-    __syncthreads();
-    const u32 item = S.item;
-    if (item >= n_chunks + n_small) break;
     const bool chunk = item < n_chunks;
-    u32 n;
+    u32 n, b = 0;
+    u64 ks = 0;
     if (chunk) {
-      const u64 ks = A.chunk_start[item];
+      ks = A.chunk_start[item];
       n = min(A.chunk_len[item], (u32)CAP);
       for (u32 i = tid; i < n; i += T) S.keys[i] = lkeys[ks + i];
     } else {
-      const u32 b = A.small_list[item - n_chunks];
+      b = A.small_list[item - n_chunks];
       const u32 r0 = A.rec_off[b], nr = A.rec_off[b + 1] - r0;
       n = min((u32)A.bcnt[b], (u32)CAP);
       // expand: thread t takes a contiguous range of records
@@ -343,49 +406,164 @@ __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
         off += g;
       }
     }
+    // pad to whole waves of every wave of the block
+    constexpr u32 WB = 64u * (T / 64);
+    const u32 n_pad = (n + WB - 1) / WB * WB;
+    for (u32 i = n + tid; i < n_pad; i += T) S.keys[i] = key_pad<K>();
     __syncthreads();
-    bucket_sort<K, T, ITEMS>(S, n, np);
+    bucket_sort<K, T, ITEMS>(S, n_pad, np);
     const u32 nruns = run_heads<K, T, ITEMS>(S, n);
-    // runs: uniform rounds so every lane of a wave takes part in the ballots
-    const u32 rounds = (nruns + T - 1) / T;
-    for (u32 rd = 0; rd < rounds; ++rd) {
-      const u32 r = rd * T + tid;
+    if (chunk) {
+      const u32 kept = emit_runs_block<K>(S.keys, S.u.hp, nruns, n, false, 0, 0, sink, klk + ks, A.kl_c + ks, S.scr);
+      if (tid == 0) A.kl_cnt[item] = kept;
+    } else {
+      const u64 so = A.kall_off[b];
+      const u32 kept = emit_runs_block<K>(S.keys, S.u.hp, nruns, n, true, A.min_freq, A.max_freq, sink, skeys + so,
+                                          A.surv_c + so, S.scr);
+      if (tid == 0) A.surv_cnt[b] = kept;
+      ndist += nruns;
+    }
+  }
+  __syncthreads();
+  flush_stats(sink, tid == 0 ? ndist : 0);
+}
+
+// ---------------------------------------------------------------------------- wave kernel
+// Small buckets (at most WCAP k-mers) are sorted by one wave each, in the wave's own
+// slice of LDS, with no block barriers: the waves of a block are independent and hide
+// each other's LDS latency.
+template <typename K, int WCAP>
+struct WaveSmem {
+  K keys[WCAP];
+  union {
+    struct {
+      u64 tbl[256];                 // lane masks per digit; all zero between uses
+      u32 cnt[256];                 // digit counts -> digit offsets
+    } r;
+    u16 hp[WCAP];                   // run heads after the sort
+  } u;
+};
+
+template <typename K, int WCAP>
+__device__ __forceinline__ void wave_sort(WaveSmem<K, WCAP>& S, u32 n_pad, int np) {
+  constexpr int ITEMS = WCAP / 64;
+  const u32 lane = lane_id();
+  const u64 ge = ~((1ull << lane) - 1ull);
+  const int per = (int)(n_pad / 64);
+  for (int p = 0; p < np; ++p) {
+    K kr[ITEMS];
+    u32 rk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        kr[j] = S.keys[(u32)j * 64u + lane];
+        const u32 d = key_digit(kr[j], 8 * p);
+        const u64 mask = digit_peers_full(S.u.r.tbl, d, ge);
+        const u32 base = S.u.r.cnt[d];
+        const u32 lr = mbcnt64(mask);
+        if (lr == 0) {
+          S.u.r.cnt[d] = base + (u32)__popcll(mask);
+          S.u.r.tbl[d] = 0;
+        }
+        rk[j] = base + lr;
+      }
+    }
+    // counts -> exclusive digit offsets; lane l owns digits 4l..4l+3
+    const u32 c0 = S.u.r.cnt[4 * lane], c1 = S.u.r.cnt[4 * lane + 1], c2 = S.u.r.cnt[4 * lane + 2],
+              c3 = S.u.r.cnt[4 * lane + 3];
+    const u32 s4 = c0 + c1 + c2 + c3;
+    const u32 ex = wave_inclusive_scan<u32>(s4) - s4;
+    S.u.r.cnt[4 * lane] = ex;
+    S.u.r.cnt[4 * lane + 1] = ex + c0;
+    S.u.r.cnt[4 * lane + 2] = ex + c0 + c1;
+    S.u.r.cnt[4 * lane + 3] = ex + c0 + c1 + c2;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) S.keys[S.u.r.cnt[key_digit(kr[j], 8 * p)] + rk[j]] = kr[j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S.u.r.cnt[4 * lane + i] = 0;
+  }
+}
+
+template <typename K, int WCAP, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const u32* __restrict__ tiny_list,
+                                                               const u64* __restrict__ n_tiny_ptr) {
+  static_assert(WCAP * 2 <= 256 * 12, "run heads reuse the rank tables");
+  __shared__ WaveSmem<K, WCAP> WS[WPB];
+  __shared__ u32 hist_s[256];
+  __shared__ u32 lmax;
+  __shared__ unsigned long long lover;
+  __shared__ u64 ndb;
+  const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  for (u32 i = tid; i < 256; i += blockDim.x) hist_s[i] = 0;
+  if (tid == 0) { lmax = 0; ndb = 0; lover = 0; }
+  __syncthreads();
+  RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax, &lover};
+  WaveSmem<K, WCAP>& S = WS[wave];
+  const u64 n_tiny = *n_tiny_ptr;
+  const int np = (2 * A.k + 7) / 8;
+  K* skeys = reinterpret_cast<K*>(A.surv_k);
+  u64 ndist = 0;
+  const u64 gw = (u64)blockIdx.x * WPB + wave, nw = (u64)gridDim.x * WPB;
+  for (u64 item = gw; item < n_tiny; item += nw) {
+    for (u32 i = lane; i < 256; i += 64) {
+      S.u.r.tbl[i] = 0;
+      S.u.r.cnt[i] = 0;
+    }
+    const u32 b = tiny_list[item];
+    const u32 r0 = A.rec_off[b], nr = A.rec_off[b + 1] - r0;
+    const u32 n = min((u32)A.bcnt[b], (u32)WCAP);
+    // expand 64 records at a time; each lane writes its record's k-mers
+    u32 off = 0;
+    for (u32 c0 = 0; c0 < nr; c0 += 64) {
+      const u32 r = c0 + lane;
+      const u32 g = r < nr ? record_g(A.rec, (u64)r0 + r, A.rec_words) : 0u;
+      const u32 inc = wave_inclusive_scan<u32>(g);
+      const u32 o = off + inc - g;
+      if (g && o + g <= (u32)WCAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + o, g);
+      off += (u32)__shfl((int)inc, 63, 64);
+    }
+    const u32 n_pad = (n + 63u) & ~63u;
+    for (u32 i = n + lane; i < n_pad; i += 64) S.keys[i] = key_pad<K>();
+    wave_sort<K, WCAP>(S, n_pad, np);
+    // run heads
+    const int per = (int)((n + 63) / 64);
+    u32 nruns = 0;
+    for (int j = 0; j < per; ++j) {
+      const u32 idx = (u32)j * 64u + lane;
+      const bool head = idx < n && (idx == 0 || !key_eq(S.keys[idx], S.keys[idx - 1]));
+      const u64 m = __ballot(head);
+      if (head) S.u.hp[nruns + mbcnt64(m)] = (u16)idx;
+      nruns += (u32)__popcll(m);
+    }
+    // runs: statistics, survivors to this bucket's slots
+    const u64 so = A.kall_off[b];
+    u32 kept = 0;
+    for (u32 c0 = 0; c0 < nruns; c0 += 64) {
+      const u32 r = c0 + lane;
       bool emit = false;
       u32 s = 0, c = 0;
       if (r < nruns) {
         s = S.u.hp[r];
         c = ((r + 1 < nruns) ? (u32)S.u.hp[r + 1] : n) - s;
-        if (chunk) {
-          emit = true;
-        } else {
-          run_stats(sink, c);
-          emit = c >= A.min_freq && c <= A.max_freq;
-        }
+        run_stats(sink, c);
+        emit = c >= A.min_freq && c <= A.max_freq;
       }
       const u64 m = __ballot(emit);
-      if (m) {
-        u64 base = 0;
-        if (lane_id() == 0)
-          base = atomicAdd((unsigned long long*)(chunk ? A.kl_n : A.surv_n), (unsigned long long)__popcll(m));
-        base = __shfl(base, 0, 64);
-        if (emit) {
-          const u64 dst = base + mbcnt64(m);
-          if (chunk) {
-            if (dst < A.kl_cap) {
-              klk[dst] = S.keys[s];
-              A.kl_c[dst] = c;
-            }
-          } else if (dst < A.surv_cap) {
-            skeys[dst] = S.keys[s];
-            A.surv_c[dst] = c;
-          }
-        }
+      if (emit) {
+        const u64 dst = so + kept + mbcnt64(m);
+        skeys[dst] = S.keys[s];
+        A.surv_c[dst] = c;
       }
+      kept += (u32)__popcll(m);
     }
-    if (!chunk) ndist += nruns;
+    if (lane == 0) A.surv_cnt[b] = kept;
+    ndist += nruns;
   }
+  if (lane == 0 && ndist) atomicAdd((unsigned long long*)&ndb, (unsigned long long)ndist);
   __syncthreads();
-  flush_stats(sink, tid == 0 ? ndist : 0);
+  flush_stats(sink, tid == 0 ? ndb : 0);
 }
 
 // ---------------------------------------------------------------------------- large buckets
@@ -443,53 +621,82 @@ __global__ __launch_bounds__(256) void k_rle_heads(const K* __restrict__ keys, c
   }
 }
 
-// One thread per run of the sorted (k-mer, count) list: the run's count is the sum of
-// its entries' counts (the merge of the chunks' lists).
+// Runs of the sorted (k-mer, count) list: a run's count is the sum of its entries'
+// counts (the merge of the chunks' lists).  Block b takes a contiguous range of runs
+// [rs, re); its survivors go to slots rs + i and their number to blk_cnt[b].
 template <typename K>
 __global__ __launch_bounds__(256) void k_rle_runs(CountArgs A, const K* __restrict__ keys, const u32* __restrict__ vals,
                                                   const u64* __restrict__ n_ptr, const u32* __restrict__ hp,
-                                                  const u64* __restrict__ nruns_ptr) {
+                                                  const u64* __restrict__ nruns_ptr, K* __restrict__ out_k,
+                                                  u32* __restrict__ out_c, u32* __restrict__ blk_cnt) {
   __shared__ u32 hist_s[256];
   __shared__ u32 lmax;
-  __shared__ u64 ndb;
+  __shared__ unsigned long long lover;
+  __shared__ u64 scr[17];
   for (u32 i = threadIdx.x; i < 256; i += blockDim.x) hist_s[i] = 0;
-  if (threadIdx.x == 0) { lmax = 0; ndb = 0; }
+  if (threadIdx.x == 0) { lmax = 0; lover = 0; }
   __syncthreads();
-  RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax};
+  RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax, &lover};
   const u64 n = *n_ptr, nruns = *nruns_ptr;
-  K* skeys = reinterpret_cast<K*>(A.surv_k);
-  u64 nd = 0;
-  const u64 stride = (u64)gridDim.x * blockDim.x;
-  const u64 rounds = (nruns + stride - 1) / stride;
-  for (u64 rd = 0; rd < rounds; ++rd) {
-    const u64 r = rd * stride + blockIdx.x * (u64)blockDim.x + threadIdx.x;
+  u64 rs, re;
+  block_range(nruns, gridDim.x, &rs, &re);
+  u64 kept = 0;
+  for (u64 c0 = rs; c0 < re; c0 += blockDim.x) {
+    const u64 r = c0 + threadIdx.x;
     bool surv = false;
     u64 c = 0, s = 0;
-    if (r < nruns) {
+    if (r < re) {
       s = hp[r];
       const u64 e = (r + 1 < nruns) ? hp[r + 1] : n;
       for (u64 i = s; i < e; ++i) c += vals[i];
       run_stats(sink, c);
       surv = c >= A.min_freq && c <= A.max_freq;
-      ++nd;
     }
-    const u64 m = __ballot(surv);
-    u64 base = 0;
-    if (m) {
-      if (lane_id() == 0) base = atomicAdd((unsigned long long*)A.surv_n, (unsigned long long)__popcll(m));
-      base = __shfl(base, 0, 64);
-    }
+    u64 tot;
+    const u64 ex = block_exclusive_scan<u64>(surv ? 1ull : 0ull, scr, &tot);
     if (surv) {
-      const u64 dst = base + mbcnt64(m);
-      if (dst < A.surv_cap) {
-        skeys[dst] = keys[s];
-        A.surv_c[dst] = (u32)c;
-      }
+      out_k[rs + kept + ex] = keys[s];
+      out_c[rs + kept + ex] = (u32)c;
+    }
+    kept += tot;
+  }
+  if (threadIdx.x == 0) blk_cnt[blockIdx.x] = (u32)kept;
+  flush_stats(sink, threadIdx.x == 0 ? (re - rs) : 0);
+}
+
+// Gather of sparse segments into one dense array: segment i holds cnt[i] entries at
+// src + base, base = base_arr[i] -- or, when base_arr is null, the first run of block i
+// of k_rle_runs over *base_range_n runs -- and lands at dst + off[i], off being the
+// exclusive scan of cnt.  One wave per segment.
+template <typename K>
+__global__ __launch_bounds__(256) void k_gather_segments(const K* __restrict__ src_k, const u32* __restrict__ src_c,
+                                                         const u64* __restrict__ base_arr,
+                                                         const u64* __restrict__ base_range_n, u32 base_range_nb,
+                                                         const u32* __restrict__ cnt, const u32* __restrict__ off,
+                                                         const u64* __restrict__ n_seg_ptr, u64 n_seg_max,
+                                                         K* __restrict__ dst_k, u32* __restrict__ dst_c) {
+  const u64 n_seg = n_seg_ptr ? min(*n_seg_ptr, n_seg_max) : n_seg_max;
+  const u64 wave = (blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6;
+  const u64 n_waves = ((u64)gridDim.x * blockDim.x) >> 6;
+  const u32 lane = lane_id();
+  for (u64 i = wave; i < n_seg; i += n_waves) {
+    const u32 c = cnt[i];
+    if (!c) continue;
+    u64 base;
+    if (base_arr) {
+      base = base_arr[i];
+    } else {
+      // block ranges of k_rle_runs over base_range_n runs
+      const u64 nr = *base_range_n;
+      const u64 per = (nr + base_range_nb - 1) / base_range_nb;
+      base = min(nr, i * per);
+    }
+    const u64 o = off[i];
+    for (u32 j = lane; j < c; j += 64) {
+      dst_k[o + j] = src_k[base + j];
+      dst_c[o + j] = src_c[base + j];
     }
   }
-  if (nd) atomicAdd((unsigned long long*)&ndb, (unsigned long long)nd);
-  __syncthreads();
-  flush_stats(sink, threadIdx.x == 0 ? ndb : 0);
 }
 
 // ---------------------------------------------------------------------------- output

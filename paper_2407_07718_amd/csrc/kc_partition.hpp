@@ -225,45 +225,56 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
 
 // ---------------------------------------------------------------------------- bucket plan
 // One block: exclusive scans over the B buckets giving record offsets, scatter cursors,
-// the list of small buckets (k-mers <= cap_small: sorted on chip from their records) and
-// of large ones, with their k-mer offsets in the large-key array and their cut into
-// chunks of at most cap_chunk k-mers.
-// meta: [0] n_small, [1] n_large, [2] large k-mers, [3] total records, [4] n_chunks.
-__global__ __launch_bounds__(1024) void k_bucket_plan(const u64* __restrict__ bcnt, u32 B, u32 cap_small,
-                                                      u32 cap_chunk, u32* __restrict__ rec_off,
+// the lists of tiny buckets (k-mers <= cap_tiny: one wave each) and small ones
+// (<= cap_small: one block each), both sorted on chip from their records, and the large
+// ones, with their k-mer offsets in the large-key array and their cut into chunks of at
+// most cap_chunk k-mers.
+// meta: [0] n_small, [1] n_large, [2] large k-mers, [3] total records, [4] n_chunks,
+//       [5] n_tiny.
+__global__ __launch_bounds__(1024) void k_bucket_plan(const u64* __restrict__ bcnt, u32 B, u32 cap_tiny,
+                                                      u32 cap_small, u32 cap_chunk, u32* __restrict__ tiny_list,
+                                                      u32* __restrict__ rec_off,
                                                       u32* __restrict__ cursor, u32* __restrict__ small_list,
                                                       u32* __restrict__ large_list, u64* __restrict__ large_koff,
                                                       u64* __restrict__ chunk_start, u32* __restrict__ chunk_len,
-                                                      u64 chunk_cap, u64* __restrict__ meta) {
+                                                      u64 chunk_cap, u64* __restrict__ kall_off,
+                                                      u64* __restrict__ meta) {
   __shared__ u64 scratch[17];
   const u32 T = blockDim.x, t = threadIdx.x;
   const u32 per = (B + T - 1) / T;
   const u32 b0 = min(B, t * per), b1 = min(B, b0 + per);
-  u64 srec = 0, ssmall = 0, slarge = 0, slk = 0, sch = 0;
+  u64 srec = 0, ssmall = 0, slarge = 0, slk = 0, sch = 0, stiny = 0, sk = 0;
   for (u32 b = b0; b < b1; ++b) {
     u64 c = bcnt[b];
     u32 nk = (u32)c, nr = (u32)(c >> 32);
     srec += nr;
+    sk += nk;
     if (nk > cap_small) {
       slarge += 1;
       slk += nk;
       sch += (nk + cap_chunk - 1) / cap_chunk;
-    } else if (nk > 0) {
+    } else if (nk > cap_tiny) {
       ssmall += 1;
+    } else if (nk > 0) {
+      stiny += 1;
     }
   }
-  u64 tot_rec, tot_small, tot_large, tot_lk, tot_ch;
+  u64 tot_rec, tot_small, tot_large, tot_lk, tot_ch, tot_tiny, tot_k;
   u64 prec = block_exclusive_scan<u64>(srec, scratch, &tot_rec);
   u64 psmall = block_exclusive_scan<u64>(ssmall, scratch, &tot_small);
   u64 plarge = block_exclusive_scan<u64>(slarge, scratch, &tot_large);
   u64 plk = block_exclusive_scan<u64>(slk, scratch, &tot_lk);
   u64 pch = block_exclusive_scan<u64>(sch, scratch, &tot_ch);
+  u64 ptiny = block_exclusive_scan<u64>(stiny, scratch, &tot_tiny);
+  u64 pk = block_exclusive_scan<u64>(sk, scratch, &tot_k);
   for (u32 b = b0; b < b1; ++b) {
     u64 c = bcnt[b];
     u32 nk = (u32)c, nr = (u32)(c >> 32);
     rec_off[b] = (u32)prec;
     cursor[b] = (u32)prec;
     prec += nr;
+    kall_off[b] = pk;
+    pk += nk;
     if (nk > cap_small) {
       large_list[plarge] = b;
       large_koff[b] = plk;
@@ -276,8 +287,10 @@ __global__ __launch_bounds__(1024) void k_bucket_plan(const u64* __restrict__ bc
       }
       plarge += 1;
       plk += nk;
-    } else if (nk > 0) {
+    } else if (nk > cap_tiny) {
       small_list[psmall++] = b;
+    } else if (nk > 0) {
+      tiny_list[ptiny++] = b;
     }
   }
   if (t == 0) {
@@ -287,6 +300,7 @@ __global__ __launch_bounds__(1024) void k_bucket_plan(const u64* __restrict__ bc
     meta[2] = tot_lk;
     meta[3] = tot_rec;
     meta[4] = min(tot_ch, chunk_cap);
+    meta[5] = tot_tiny;
   }
 }
 

@@ -137,19 +137,22 @@ __global__ __launch_bounds__(256) void k_radix_upsweep(const K* __restrict__ key
   counts[(u64)tid * nb + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
 }
 
-// In-place exclusive scan of data[0, n) by one block; *total = sum (if non-null).
-__global__ __launch_bounds__(1024) void k_scan_u32(u32* __restrict__ data, u64 n, u64* __restrict__ total) {
+// Exclusive scan out[i] = sum of in[0, i) for i < n by one block; n = min(*n_ptr, n_max)
+// when n_ptr is given, else n_max; *total = sum (if non-null).  in and out may alias.
+__global__ __launch_bounds__(1024) void k_scan_u32(const u32* __restrict__ in, u32* __restrict__ out,
+                                                   const u64* __restrict__ n_ptr, u64 n_max, u64* __restrict__ total) {
   __shared__ u64 scr[17];
+  const u64 n = n_ptr ? min(*n_ptr, n_max) : n_max;
   const u32 T = blockDim.x, t = threadIdx.x;
   const u64 per = (n + T - 1) / T;
   const u64 s = min(n, (u64)t * per), e = min(n, s + per);
   u64 sum = 0;
-  for (u64 i = s; i < e; ++i) sum += data[i];
+  for (u64 i = s; i < e; ++i) sum += in[i];
   u64 all;
   u64 run = block_exclusive_scan<u64>(sum, scr, &all);
   for (u64 i = s; i < e; ++i) {
-    u32 v = data[i];
-    data[i] = (u32)run;
+    const u32 v = in[i];
+    out[i] = (u32)run;
     run += v;
   }
   if (t == 0 && total) *total = all;
