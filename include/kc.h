@@ -62,7 +62,15 @@ typedef struct kc_totals {
   uint64_t max_count;
   uint64_t n_records;      /* supermer records the partition wrote */
   uint64_t flags;          /* internal status; 0 on success */
-  uint64_t large_keys;     /* k-mers sorted through the HBM path (large buckets) */
+  uint64_t large_keys;     /* k-mers of large buckets (cut into chunks, merged through HBM) */
+  uint64_t tiny_buckets;   /* buckets sorted by one wave each */
+  uint64_t tiny_kmers;
+  uint64_t small_buckets;  /* buckets sorted by one block each */
+  uint64_t small_kmers;
+  uint64_t large_buckets;
+  uint64_t chunks;         /* on-chip chunks of the large buckets */
+  uint64_t list_entries;   /* (k-mer, count) entries the chunks produced */
+  uint64_t buckets;        /* B */
 } kc_totals;
 
 typedef struct kc_result {
@@ -126,14 +134,16 @@ int kc_count_device_async(const uint8_t *d_reads, uint64_t total_bases, const ui
 /* Stage timing.  While enabled (kc_profile(1)), each count queued by this thread records
  * HIP events on its own stream at the boundaries of its stages:
  *   0 encode      (zero fills, 2-bit pack, read-start marks)
- *   1 extract     (minimizers, supermers, per-bucket counts)       -- one kernel
- *   2 partition   (bucket plan + record scatter)
- *   3 small_sort  (on-chip sort and run count of small buckets)     -- one kernel
- *   4 large_path  (expand, HBM radix sort and run count of large buckets)
- *   5 output      (survivor sort by key, copy, totals)
+ *   1 extract     (minimizers, supermers into span slots)           -- one kernel
+ *   2 partition   (two-pass record partition into buckets, bucket plan)
+ *   3 expand      (k-mers of large buckets into HBM)                -- one kernel
+ *   4 block_sort  (small buckets and chunks: one block each)       -- one kernel
+ *   5 wave_sort   (tiny buckets: one wave each)                     -- one kernel
+ *   6 merge       (chunk lists: compact, HBM radix sort, summed runs)
+ *   7 output      (survivor compaction, sort by key, copy, totals)
  * kc_profile_read waits for those events and returns, per stage, the summed
  * milliseconds over all counts recorded since the last read (then resets). */
-#define KC_N_STAGES 6
+#define KC_N_STAGES 8
 typedef struct kc_stage_times {
   double ms[KC_N_STAGES];
   uint64_t n_counts;

@@ -77,25 +77,25 @@ struct Plan {
   u64 o_packed, o_nmask, o_starts, o_recA, o_recB, o_bid, o_bcnt, o_recoff, o_cursor, o_small, o_large,
       o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_tot_large, o_tot_surv, o_bc, o_hp, o_surv0k, o_surv0c, o_surv1k,
       o_surv1c, o_spancnt, o_chstart, o_chlen, o_kl0k, o_kl0c, o_kl1k, o_kl1c, o_tiny, o_kall, o_klsc, o_klcnt,
-      o_kloff, o_scnt, o_soff;
+      o_kloff, o_scnt, o_soff, o_bsum, o_scanbuf, o_ptmp_rec, o_ptmp_bid, o_phist;
+  int log_c = 0, log_f = 0;
+  u32 part_nblk = 1, part_spb = 1;
   u64 n_packed, n_mask, bytes = 0;
 };
 
 // Control words (all zeroed at the start of a count).
 enum Ctrl : int {
   C_COUNTERS = 0,   // [0] records, [1] windows
-  C_META = 2,       // 6 words: n_small, n_large, large k-mers, records, n_chunks, n_tiny
-  C_FLAGS = 8,
-  C_QUEUE = 9,
-  C_SURV_N = 10,
-  C_NRUNS = 11,
-  C_SURV_NC = 12,   // survivors, clamped to capacity
-  C_KL_N = 13,      // (k-mer, count) list entries
-  C_KL_NC = 14,     // ... clamped to capacity
-  C_WQUEUE = 15,    // work-queue cursor of the wave kernel
+  C_META = 2,       // 8 words, see k_plan_scan
+  C_FLAGS = 10,
+  C_SURV_N = 11,
+  C_NRUNS = 12,
+  C_SURV_NC = 13,   // survivors, clamped to capacity
+  C_KL_N = 14,      // (k-mer, count) list entries
+  C_KL_NC = 15,     // ... clamped to capacity
   C_WORDS = 16
 };
-static_assert(C_META + 6 <= C_FLAGS, "meta overlaps the flags");
+static_assert(C_META + 8 <= C_FLAGS, "meta overlaps the flags");
 
 u32 default_variant(int key_words) { return key_words == 1 ? 1u : 1u; }
 u32 small_cap(int key_words, u32 variant) {
@@ -130,6 +130,8 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
     p->log_b = lb;
   }
   p->B = 1u << p->log_b;
+  p->log_c = std::min(9, p->log_b);
+  p->log_f = p->log_b - p->log_c;
   p->rec_cap = std::max<u64>(1, n_max);
   // each wave span of the extract stage owns `span` record slots; the slot region is
   // sized for any m (span <= 16 * 63)
@@ -137,6 +139,8 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->slots = R + 16 * 64;
   p->n_span_cap = (std::max<u64>(R, 1) + p->span - 1) / p->span;
   p->n_span_alloc = R / 32 + 2;
+  p->part_nblk = (u32)std::min<u64>(8192, std::max<u64>(1, p->n_span_cap));
+  p->part_spb = (u32)((p->n_span_cap + p->part_nblk - 1) / p->part_nblk);
   (void)min_freq;
   p->surv_cap = std::max<u64>(1, n_max);   // survivors sit at their bucket's k-mer slots first
   const u64 w = 8ull * p->key_words;
@@ -193,6 +197,11 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_kloff = take(4 * p->chunk_cap);
   p->o_scnt = take(4ull * (p->B + RUN_BLOCKS));
   p->o_soff = take(4ull * (p->B + RUN_BLOCKS));
+  p->o_bsum = take(8ull * PLAN_Q * (p->B / PLAN_BLOCK + 1));
+  p->o_scanbuf = take(8ull * 1024);
+  p->o_ptmp_rec = take(rb * p->rec_cap);
+  p->o_ptmp_bid = take(4 * p->rec_cap);
+  p->o_phist = take(4ull * ((u64)1 << p->log_c) * p->part_nblk);
   p->bytes = o;
   return true;
 }
@@ -244,8 +253,26 @@ __global__ void k_clamp(const u64* src, u64 cap, u64* dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = min(*src, cap);
 }
 
-__global__ void k_totals_meta(DevTotals* tot, const u64* meta) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) tot->large_keys = meta[2];
+__global__ void k_totals_meta(DevTotals* tot, const u64* meta, const u64* kl_n, u32 B) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    tot->large_keys = meta[2];
+    tot->tiny_buckets = meta[5];
+    tot->tiny_kmers = meta[6];
+    tot->small_buckets = meta[0];
+    tot->small_kmers = meta[7];
+    tot->large_buckets = meta[1];
+    tot->chunks = meta[4];
+    tot->list_entries = *kl_n;
+    tot->buckets = B;
+  }
+}
+
+// Device-wide exclusive scan (see k_scan_reduce); n_max must be <= 1024 * SCAN_BLOCK.
+void scan_u32(const u32* in, u32* out, const u64* n_ptr, u64 n_max, u64* total, u64* bsum, hipStream_t st) {
+  const u32 nb = (u32)std::max<u64>(1, (n_max + SCAN_BLOCK - 1) / SCAN_BLOCK);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_T), 0, st, in, n_ptr, n_max, bsum);
+  hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, bsum, nb, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_T), 0, st, in, out, n_ptr, n_max, bsum);
 }
 
 inline dim3 grid_for(u64 n, u32 block, u32 max_blocks = 1u << 20) {
@@ -277,6 +304,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u32* kloff = at<u32>(ws, P.o_kloff);
   u32* scnt = at<u32>(ws, P.o_scnt);
   u32* soff = at<u32>(ws, P.o_soff);
+  u64* bsum = at<u64>(ws, P.o_bsum);
+  u64* scanbuf = at<u64>(ws, P.o_scanbuf);
   u32* large = at<u32>(ws, P.o_large);
   u64* lkoff = at<u64>(ws, P.o_lkoff);
   u64* ctrl = at<u64>(ws, P.o_ctrl);
@@ -300,7 +329,6 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u64* counters = ctrl + C_COUNTERS;
   u64* meta = ctrl + C_META;
   u32* flags = reinterpret_cast<u32*>(ctrl + C_FLAGS);
-  u32* queue = reinterpret_cast<u32*>(ctrl + C_QUEUE);
   u64* surv_n = ctrl + C_SURV_N;
   u64* nruns = ctrl + C_NRUNS;
   u64* surv_nc = ctrl + C_SURV_NC;
@@ -314,7 +342,6 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   };
   stage_mark(0, st);
   fill(ctrl, 2ull * C_WORDS);
-  fill(bcnt, 2ull * P.B);
   fill(d_hist, 2ull * hist_len);
   fill(d_tot, sizeof(DevTotals) / 4);
   fill(starts, P.n_mask);
@@ -340,25 +367,53 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ea.m = P.m;
   ea.log_b = P.log_b;
   ea.gmax = P.gmax;
+  ea.gmax_magic = (u32)(((1ull << 32) + (u64)P.gmax - 1) / (u64)P.gmax);
   ea.rec_words = P.rec_words;
   ea.span = P.span;
   ea.rec = recA;
   ea.bid = bid;
   ea.span_cnt = spancnt;
-  ea.bcnt = bcnt;
   ea.counters = counters;
   ea.n_span_cap = P.n_span_cap;
   const u64 n_spans = P.n_span_cap;
   stage_mark(1, st);
   hipLaunchKernelGGL(k_extract, grid_for(n_spans, 4, 8192), dim3(256), 0, st, ea);
   stage_mark(2, st);
-  hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(1024), 0, st, bcnt, P.B, P.cap_tiny, P.cap, P.cap_chunk, tiny, recoff,
-                     cursor, small, large, lkoff, chstart, chlen, P.chunk_cap, kall, meta);
-  hipLaunchKernelGGL(k_scatter_records, grid_for(P.n_span_cap, 4, 16384), dim3(256), 0, st, recA, bid, spancnt,
-                     P.n_span_cap, P.span, cursor, P.rec_cap, recB, P.rec_words);
+  {
+    PartArgs pp;
+    pp.rec = recA;
+    pp.bid = bid;
+    pp.span_cnt = spancnt;
+    pp.n_span = P.n_span_cap;
+    pp.span = P.span;
+    pp.spb = P.part_spb;
+    pp.nblk = P.part_nblk;
+    pp.log_c = P.log_c;
+    pp.log_f = P.log_f;
+    pp.rec_words = P.rec_words;
+    pp.hist = at<u32>(ws, P.o_phist);
+    pp.tmp_rec = at<u32>(ws, P.o_ptmp_rec);
+    pp.tmp_bid = at<u32>(ws, P.o_ptmp_bid);
+    pp.rec_out = recB;
+    pp.bcnt = bcnt;
+    pp.n_rec_ptr = counters;
+    const u64 nh = ((u64)1 << P.log_c) * P.part_nblk;
+    hipLaunchKernelGGL(k_part_coarse<false>, dim3(P.part_nblk), dim3(256), 0, st, pp);
+    scan_u32(pp.hist, pp.hist, (const u64*)nullptr, nh, (u64*)nullptr, scanbuf, st);
+    hipLaunchKernelGGL(k_part_coarse<true>, dim3(P.part_nblk), dim3(256), 0, st, pp);
+    hipLaunchKernelGGL(k_part_fine, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
+  }
+  {
+    PlanArgs pa{bcnt, P.B, P.cap_tiny, P.cap, P.cap_chunk, bsum, tiny, recoff, cursor, small, large, lkoff, chstart,
+                chlen, P.chunk_cap, kall, meta};
+    const u32 nbp = (P.B + PLAN_BLOCK - 1) / PLAN_BLOCK;
+    hipLaunchKernelGGL(k_plan_reduce, dim3(nbp), dim3(PLAN_T), 0, st, pa);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, st, pa, nbp);
+    hipLaunchKernelGGL(k_plan_write, dim3(nbp), dim3(PLAN_T), 0, st, pa);
+  }
 
   stage_mark(3, st);
-  // ---- stage 3: per bucket sort + count
+  // ---- per bucket sort + count
   CountArgs ca;
   ca.rec = recB;
   ca.rec_off = recoff;
@@ -387,6 +442,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ca.kl_cnt = klcnt;
   // large buckets: expand their k-mers into HBM, cut later into chunks
   hipLaunchKernelGGL((k_expand_large<K, 256>), dim3(1024), dim3(256), 0, st, ca, lk0);
+  stage_mark(4, st);
   constexpr bool WIDE = sizeof(K) == 16;
   if (P.variant == 2) {
     constexpr int T = 512, IT = WIDE ? 8 : 16;
@@ -399,6 +455,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
     hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
   }
+  stage_mark(5, st);
   {
     constexpr u32 WC = WIDE ? WAVE_CAP_128 : WAVE_CAP_64;
     int per_cu = 0;
@@ -407,9 +464,9 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     hipLaunchKernelGGL((k_wave_sort_count<K, WC, WAVES_PER_BLOCK>), dim3(std::max(1, per_cu) * n_cu),
                        dim3(WAVES_PER_BLOCK * 64), 0, st, ca, tiny, meta + 5);
   }
-  stage_mark(4, st);
+  stage_mark(6, st);
   // merge the chunks' (k-mer, count) lists: compact, sort by k-mer, sum each run's counts
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, klcnt, kloff, meta + 4, P.chunk_cap, kl_n);
+  scan_u32(klcnt, kloff, meta + 4, P.chunk_cap, kl_n, scanbuf, st);
   hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.chunk_cap, 4, 4096), dim3(256), 0, st, lk0, klsc, chstart,
                      (const u64*)nullptr, 0u, klcnt, kloff, meta + 4, P.chunk_cap, kl0k, kl0c);
   hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, kl_n, P.kl_cap, kl_nc);
@@ -426,10 +483,9 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   hipLaunchKernelGGL((k_rle_runs<K>), dim3(RUN_BLOCKS), dim3(256), 0, st, ca, lks, lvs, kl_nc, hp, nruns, fk, fc,
                      scnt + P.B);
 
-  stage_mark(5, st);
+  stage_mark(7, st);
   // ---- output: compact the survivors (buckets, then merged runs), sort them by key
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, scnt, soff, (const u64*)nullptr, (u64)P.B + RUN_BLOCKS,
-                     surv_n);
+  scan_u32(scnt, soff, (const u64*)nullptr, (u64)P.B + RUN_BLOCKS, surv_n, scanbuf, st);
   hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.B, 4, 4096), dim3(256), 0, st, s0k, s0c, kall, (const u64*)nullptr,
                      0u, scnt, soff, (const u64*)nullptr, (u64)P.B, s1k, s1c);
   hipLaunchKernelGGL((k_gather_segments<K>), grid_for(RUN_BLOCKS, 4, 4096), dim3(256), 0, st, fk, fc, (const u64*)nullptr,
@@ -442,8 +498,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   hipLaunchKernelGGL((k_copy_pairs<K>), grid_for(P.surv_cap, 256, 4096), dim3(256), 0, st, ok, oc, surv_nc, pair_cap,
                      reinterpret_cast<K*>(d_kmers), d_counts);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags);
-  hipLaunchKernelGGL(k_totals_meta, dim3(1), dim3(64), 0, st, d_tot, meta);
-  stage_mark(6, st);
+  hipLaunchKernelGGL(k_totals_meta, dim3(1), dim3(64), 0, st, d_tot, meta, kl_n, P.B);
+  stage_mark(8, st);
   HIP_TRY(hipGetLastError());
   return KC_OK;
 }

@@ -81,6 +81,23 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
   return v;
 }
 
+// Inclusive prefix sum of u32 over the 64 lanes of a wave with DPP moves: shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes, then the last lane of row 0 / row 2 is added
+// to rows 1 / 3 (row_bcast:15) and lane 31 to rows 2 and 3 (row_bcast:31).
+__device__ __forceinline__ u32 wave_scan_u32(u32 x) {
+  x += (u32)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);   // row_shr:1
+  x += (u32)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);   // row_shr:2
+  x += (u32)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);   // row_shr:4
+  x += (u32)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);   // row_shr:8
+  x += (u32)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  x += (u32)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return x;
+}
+
+// q / d and q % d for q < 2^26, 1 <= d <= 64, with magic = ceil(2^32 / d): exact because
+// the rounding error of magic stays below 1/d over that range.
+__device__ __forceinline__ u32 div_small(u32 q, u32 magic) { return __umulhi(q, magic); }
+
 // Exclusive prefix sum over a whole block (blockDim.x a multiple of 64, <= 1024).
 // `scratch` holds at least 17 values of T.  Returns the exclusive prefix; *total is
 // the block sum.  Contains barriers: every thread of the block must call it.

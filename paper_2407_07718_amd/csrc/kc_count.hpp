@@ -19,7 +19,8 @@ struct DevTotals {
   u64 max_count;
   u64 n_records;      // supermer records written
   u64 flags;          // bit 0: bad offsets, bit 1: record buffer overflow, bit 2: survivor overflow
-  u64 large_keys;     // k-mers routed through the HBM sort path
+  u64 large_keys;     // k-mers of large buckets
+  u64 tiny_buckets, tiny_kmers, small_buckets, small_kmers, large_buckets, chunks, list_entries, buckets;
 };
 
 struct CountArgs {
@@ -243,9 +244,11 @@ __device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pa
     K kr[ITEMS];
     u32 rk[ITEMS];
 #pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (j < per) kr[j] = S.keys[(wave * (u32)per + (u32)j) * 64u + lane];
+#pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       if (j < per) {
-        kr[j] = S.keys[(wave * (u32)per + (u32)j) * 64u + lane];
         const u32 d = key_digit(kr[j], 8 * p);
         const u64 mask = digit_peers_full(S.u.r.tbl[wave], d, ge);
         const u32 base = C[wave][d];
@@ -267,7 +270,7 @@ __device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pa
         C[v][tid] = col;
         col += x;
       }
-      const u32 inc = wave_inclusive_scan<u32>(col);
+      const u32 inc = wave_scan_u32(col);
       const u32 ex = inc - col;
 #pragma unroll
       for (int v = 0; v < W; ++v) C[v][tid] += ex;
@@ -454,9 +457,11 @@ __device__ __forceinline__ void wave_sort(WaveSmem<K, WCAP>& S, u32 n_pad, int n
     K kr[ITEMS];
     u32 rk[ITEMS];
 #pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (j < per) kr[j] = S.keys[(u32)j * 64u + lane];
+#pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       if (j < per) {
-        kr[j] = S.keys[(u32)j * 64u + lane];
         const u32 d = key_digit(kr[j], 8 * p);
         const u64 mask = digit_peers_full(S.u.r.tbl, d, ge);
         const u32 base = S.u.r.cnt[d];
@@ -472,7 +477,7 @@ __device__ __forceinline__ void wave_sort(WaveSmem<K, WCAP>& S, u32 n_pad, int n
     const u32 c0 = S.u.r.cnt[4 * lane], c1 = S.u.r.cnt[4 * lane + 1], c2 = S.u.r.cnt[4 * lane + 2],
               c3 = S.u.r.cnt[4 * lane + 3];
     const u32 s4 = c0 + c1 + c2 + c3;
-    const u32 ex = wave_inclusive_scan<u32>(s4) - s4;
+    const u32 ex = wave_scan_u32(s4) - s4;
     S.u.r.cnt[4 * lane] = ex;
     S.u.r.cnt[4 * lane + 1] = ex + c0;
     S.u.r.cnt[4 * lane + 2] = ex + c0 + c1;
@@ -519,7 +524,7 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
     for (u32 c0 = 0; c0 < nr; c0 += 64) {
       const u32 r = c0 + lane;
       const u32 g = r < nr ? record_g(A.rec, (u64)r0 + r, A.rec_words) : 0u;
-      const u32 inc = wave_inclusive_scan<u32>(g);
+      const u32 inc = wave_scan_u32(g);
       const u32 o = off + inc - g;
       if (g && o + g <= (u32)WCAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + o, g);
       off += (u32)__shfl((int)inc, 63, 64);

@@ -72,11 +72,11 @@ struct ExtractArgs {
   const u64* offsets;
   u64 n_reads, R;
   int k, m, log_b, gmax, rec_words;
+  u32 gmax_magic;      // ceil(2^32 / gmax)
   u32 span;            // k-mer windows per wave span (a multiple of the tile advance)
   u32* rec;            // records of span s at slots [s*span, s*span + span_cnt[s])
   u32* bid;            // bucket of each record slot
   u32* span_cnt;       // records written per span
-  u64* bcnt;           // per bucket: (records << 32) | k-mers
   u64* counters;       // [0] records written, [1] valid windows
   u64 n_span_cap;      // spans the record region holds
 };
@@ -123,7 +123,6 @@ __device__ __forceinline__ void write_record(const ExtractArgs& A, u64 slot, u64
     }
     A.bid[slot] = bucket;
   }
-  atomicAdd((unsigned long long*)&A.bcnt[bucket], (unsigned long long)((1ull << 32) | g));
 }
 
 // Each wave walks one span of window positions in tiles of 64 lanes.  Lane l of a tile
@@ -187,7 +186,8 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
       u32 pos;
       if (le) pos = lane - (63u - (u32)__clzll(le));
       else pos = c_pos + 1 + lane;
-      const bool head = valid && (pos % gmax == 0);
+      const u32 pm = pos - div_small(pos, A.gmax_magic) * gmax;   // pos % gmax
+      const bool head = valid && (pm == 0);
       const int nv = __shfl_down((int)valid, 1, 64);
       const int nh = __shfl_down((int)head, 1, 64);
       const bool close = valid && (lane < (u32)(adv - 1)) && (!nv || nh);
@@ -198,8 +198,11 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
       const u32 n_close = (u32)__popcll(CL) + (carry_close ? 1u : 0u);
       if (n_close) {
         const u64 base = slot0 + written;
-        if (carry_close && lane == 0) write_record(A, base, c_p - (c_pos % gmax), c_pos % gmax + 1, c_b);
-        if (close) write_record(A, base + (carry_close ? 1 : 0) + mbcnt64(CL), q - (pos % gmax), pos % gmax + 1, b);
+        if (carry_close && lane == 0) {
+          const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
+          write_record(A, base, c_p - cm, cm + 1, c_b);
+        }
+        if (close) write_record(A, base + (carry_close ? 1 : 0) + mbcnt64(CL), q - pm, pm + 1, b);
         written += n_close;
       }
       my_windows += (u64)__popcll(__ballot(valid));
@@ -213,7 +216,10 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
       }
     }
     if (c_open) {
-      if (lane == 0) write_record(A, slot0 + written, c_p - (c_pos % gmax), c_pos % gmax + 1, c_b);
+      if (lane == 0) {
+        const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
+        write_record(A, slot0 + written, c_p - cm, cm + 1, c_b);
+      }
       ++written;
     }
     if (lane == 0) A.span_cnt[s] = written;
@@ -224,109 +230,242 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
 }
 
 // ---------------------------------------------------------------------------- bucket plan
-// One block: exclusive scans over the B buckets giving record offsets, scatter cursors,
-// the lists of tiny buckets (k-mers <= cap_tiny: one wave each) and small ones
-// (<= cap_small: one block each), both sorted on chip from their records, and the large
-// ones, with their k-mer offsets in the large-key array and their cut into chunks of at
-// most cap_chunk k-mers.
-// meta: [0] n_small, [1] n_large, [2] large k-mers, [3] total records, [4] n_chunks,
-//       [5] n_tiny.
-__global__ __launch_bounds__(1024) void k_bucket_plan(const u64* __restrict__ bcnt, u32 B, u32 cap_tiny,
-                                                      u32 cap_small, u32 cap_chunk, u32* __restrict__ tiny_list,
-                                                      u32* __restrict__ rec_off,
-                                                      u32* __restrict__ cursor, u32* __restrict__ small_list,
-                                                      u32* __restrict__ large_list, u64* __restrict__ large_koff,
-                                                      u64* __restrict__ chunk_start, u32* __restrict__ chunk_len,
-                                                      u64 chunk_cap, u64* __restrict__ kall_off,
-                                                      u64* __restrict__ meta) {
-  __shared__ u64 scratch[17];
-  const u32 T = blockDim.x, t = threadIdx.x;
-  const u32 per = (B + T - 1) / T;
-  const u32 b0 = min(B, t * per), b1 = min(B, b0 + per);
-  u64 srec = 0, ssmall = 0, slarge = 0, slk = 0, sch = 0, stiny = 0, sk = 0;
-  for (u32 b = b0; b < b1; ++b) {
-    u64 c = bcnt[b];
-    u32 nk = (u32)c, nr = (u32)(c >> 32);
-    srec += nr;
-    sk += nk;
-    if (nk > cap_small) {
-      slarge += 1;
-      slk += nk;
-      sch += (nk + cap_chunk - 1) / cap_chunk;
-    } else if (nk > cap_tiny) {
-      ssmall += 1;
-    } else if (nk > 0) {
-      stiny += 1;
+// The plan classifies buckets by k-mer count n: tiny (n <= cap_tiny, one wave each),
+// small (n <= cap_small, one block each) -- both sorted on chip from their records --
+// and large (cut into chunks of at most cap_chunk k-mers, see the counting stage).  It
+// is three kernels: per-block sums, one scan of the block sums, then the writes.
+// Quantities per bucket: q0 records, q1 k-mers, q2 classes packed (tiny | small << 21 |
+// large << 42), q3 k-mers of large buckets, q4 chunks, q5 k-mers of tiny buckets, q6
+// k-mers of small buckets.
+// meta: [0] n_small, [1] n_large, [2] large k-mers, [3] records, [4] n_chunks, [5] n_tiny,
+//       [6] tiny k-mers, [7] small k-mers.
+constexpr u32 PLAN_PER_THREAD = 4, PLAN_T = 256, PLAN_BLOCK = PLAN_PER_THREAD * PLAN_T;
+constexpr int PLAN_Q = 7;
+
+struct PlanArgs {
+  const u64* bcnt;
+  u32 B, cap_tiny, cap_small, cap_chunk;
+  u64* bsum;             // [nblocks][PLAN_Q] block sums -> block offsets
+  u32* tiny_list;
+  u32* rec_off;          // [B + 1]
+  u32* cursor;
+  u32* small_list;
+  u32* large_list;
+  u64* large_koff;
+  u64* chunk_start;
+  u32* chunk_len;
+  u64 chunk_cap;
+  u64* kall_off;
+  u64* meta;
+};
+
+__device__ __forceinline__ void plan_quantities(const PlanArgs& P, u64 c, u64 q[PLAN_Q]) {
+  const u32 nk = (u32)c, nr = (u32)(c >> 32);
+  q[0] = nr;
+  q[1] = nk;
+  q[2] = nk > P.cap_small ? (1ull << 42) : nk > P.cap_tiny ? (1ull << 21) : nk > 0 ? 1ull : 0ull;
+  q[3] = nk > P.cap_small ? nk : 0;
+  q[4] = nk > P.cap_small ? (nk + P.cap_chunk - 1) / P.cap_chunk : 0;
+  q[5] = nk <= P.cap_tiny ? nk : 0;
+  q[6] = (nk > P.cap_tiny && nk <= P.cap_small) ? nk : 0;
+}
+
+__global__ __launch_bounds__(PLAN_T) void k_plan_reduce(PlanArgs P) {
+  __shared__ u64 scr[17];
+  const u32 b0 = blockIdx.x * PLAN_BLOCK + threadIdx.x * PLAN_PER_THREAD;
+  u64 sum[PLAN_Q] = {0, 0, 0, 0, 0, 0, 0};
+  for (u32 i = 0; i < PLAN_PER_THREAD; ++i) {
+    if (b0 + i < P.B) {
+      u64 q[PLAN_Q];
+      plan_quantities(P, P.bcnt[b0 + i], q);
+      for (int j = 0; j < PLAN_Q; ++j) sum[j] += q[j];
     }
   }
-  u64 tot_rec, tot_small, tot_large, tot_lk, tot_ch, tot_tiny, tot_k;
-  u64 prec = block_exclusive_scan<u64>(srec, scratch, &tot_rec);
-  u64 psmall = block_exclusive_scan<u64>(ssmall, scratch, &tot_small);
-  u64 plarge = block_exclusive_scan<u64>(slarge, scratch, &tot_large);
-  u64 plk = block_exclusive_scan<u64>(slk, scratch, &tot_lk);
-  u64 pch = block_exclusive_scan<u64>(sch, scratch, &tot_ch);
-  u64 ptiny = block_exclusive_scan<u64>(stiny, scratch, &tot_tiny);
-  u64 pk = block_exclusive_scan<u64>(sk, scratch, &tot_k);
-  for (u32 b = b0; b < b1; ++b) {
-    u64 c = bcnt[b];
-    u32 nk = (u32)c, nr = (u32)(c >> 32);
-    rec_off[b] = (u32)prec;
-    cursor[b] = (u32)prec;
-    prec += nr;
-    kall_off[b] = pk;
-    pk += nk;
-    if (nk > cap_small) {
-      large_list[plarge] = b;
-      large_koff[b] = plk;
-      for (u32 o = 0; o < nk; o += cap_chunk) {
-        if (pch < chunk_cap) {
-          chunk_start[pch] = plk + o;
-          chunk_len[pch] = min(cap_chunk, nk - o);
-        }
-        ++pch;
-      }
-      plarge += 1;
-      plk += nk;
-    } else if (nk > cap_tiny) {
-      small_list[psmall++] = b;
-    } else if (nk > 0) {
-      tiny_list[ptiny++] = b;
-    }
-  }
-  if (t == 0) {
-    rec_off[B] = (u32)tot_rec;
-    meta[0] = tot_small;
-    meta[1] = tot_large;
-    meta[2] = tot_lk;
-    meta[3] = tot_rec;
-    meta[4] = min(tot_ch, chunk_cap);
-    meta[5] = tot_tiny;
+  for (int j = 0; j < PLAN_Q; ++j) {
+    u64 tot;
+    block_exclusive_scan<u64>(sum[j], scr, &tot);
+    if (threadIdx.x == 0) P.bsum[(u64)blockIdx.x * PLAN_Q + j] = tot;
   }
 }
 
-// Move every record to its bucket's range (order inside a bucket does not matter: the
-// bucket is sorted next).  One wave per span of the extract stage.
-__global__ __launch_bounds__(256) void k_scatter_records(const u32* __restrict__ rec, const u32* __restrict__ bid,
-                                                         const u32* __restrict__ span_cnt, u64 n_span_cap, u32 span,
-                                                         u32* __restrict__ cursor, u64 rec_out_cap,
-                                                         u32* __restrict__ rec_out, int rec_words) {
-  const u64 wave = (blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6;
-  const u64 n_waves = ((u64)gridDim.x * blockDim.x) >> 6;
-  for (u64 sp = wave; sp < n_span_cap; sp += n_waves) {
-   const u32 cnt = span_cnt[sp];
-   for (u32 j = lane_id(); j < cnt; j += 64) {
-    const u64 i = sp * (u64)span + j;
-    const u32 b = bid[i];
-    const u32 slot = atomicAdd(&cursor[b], 1u);
-    if (slot >= rec_out_cap) continue;
-    if (rec_words == 4) {
-      reinterpret_cast<uint4*>(rec_out)[slot] = reinterpret_cast<const uint4*>(rec)[i];
-    } else {
-      const uint4* s = reinterpret_cast<const uint4*>(rec) + 2 * i;
-      uint4* d = reinterpret_cast<uint4*>(rec_out) + 2 * (u64)slot;
-      d[0] = s[0];
-      d[1] = s[1];
+// One block: exclusive scan of the block sums (in place) and the totals.
+__global__ __launch_bounds__(1024) void k_plan_scan(PlanArgs P, u32 nblocks) {
+  __shared__ u64 scr[17];
+  const u32 per = (nblocks + blockDim.x - 1) / blockDim.x;
+  const u32 s = min(nblocks, threadIdx.x * per), e = min(nblocks, s + per);
+  u64 tot[PLAN_Q];
+  for (int j = 0; j < PLAN_Q; ++j) {
+    u64 sum = 0;
+    for (u32 i = s; i < e; ++i) sum += P.bsum[(u64)i * PLAN_Q + j];
+    u64 run = block_exclusive_scan<u64>(sum, scr, &tot[j]);
+    for (u32 i = s; i < e; ++i) {
+      const u64 v = P.bsum[(u64)i * PLAN_Q + j];
+      P.bsum[(u64)i * PLAN_Q + j] = run;
+      run += v;
     }
-   }
+  }
+  if (threadIdx.x == 0) {
+    P.rec_off[P.B] = (u32)tot[0];
+    P.meta[0] = (tot[2] >> 21) & ((1ull << 21) - 1);
+    P.meta[1] = tot[2] >> 42;
+    P.meta[2] = tot[3];
+    P.meta[3] = tot[0];
+    P.meta[4] = min(tot[4], P.chunk_cap);
+    P.meta[5] = tot[2] & ((1ull << 21) - 1);
+    P.meta[6] = tot[5];
+    P.meta[7] = tot[6];
+  }
+}
+
+__global__ __launch_bounds__(PLAN_T) void k_plan_write(PlanArgs P) {
+  __shared__ u64 scr[17];
+  const u32 b0 = blockIdx.x * PLAN_BLOCK + threadIdx.x * PLAN_PER_THREAD;
+  u64 c[PLAN_PER_THREAD];
+  u64 sum[PLAN_Q] = {0, 0, 0, 0, 0, 0, 0};
+  for (u32 i = 0; i < PLAN_PER_THREAD; ++i) {
+    c[i] = (b0 + i < P.B) ? P.bcnt[b0 + i] : 0ull;
+    u64 q[PLAN_Q];
+    plan_quantities(P, c[i], q);
+    for (int j = 0; j < PLAN_Q; ++j) sum[j] += q[j];
+  }
+  u64 off[PLAN_Q];
+  for (int j = 0; j < PLAN_Q; ++j) {
+    u64 tot;
+    off[j] = block_exclusive_scan<u64>(sum[j], scr, &tot) + P.bsum[(u64)blockIdx.x * PLAN_Q + j];
+  }
+  u64 prec = off[0], pk = off[1], plk = off[3], pch = off[4];
+  u64 ptiny = off[2] & ((1ull << 21) - 1), psmall = (off[2] >> 21) & ((1ull << 21) - 1), plarge = off[2] >> 42;
+  for (u32 i = 0; i < PLAN_PER_THREAD; ++i) {
+    const u32 b = b0 + i;
+    if (b >= P.B) break;
+    const u32 nk = (u32)c[i], nr = (u32)(c[i] >> 32);
+    P.rec_off[b] = (u32)prec;
+    P.cursor[b] = (u32)prec;
+    prec += nr;
+    P.kall_off[b] = pk;
+    pk += nk;
+    if (nk > P.cap_small) {
+      P.large_list[plarge++] = b;
+      P.large_koff[b] = plk;
+      for (u32 o = 0; o < nk; o += P.cap_chunk) {
+        if (pch < P.chunk_cap) {
+          P.chunk_start[pch] = plk + o;
+          P.chunk_len[pch] = min(P.cap_chunk, nk - o);
+        }
+        ++pch;
+      }
+      plk += nk;
+    } else if (nk > P.cap_tiny) {
+      P.small_list[psmall++] = b;
+    } else if (nk > 0) {
+      P.tiny_list[ptiny++] = b;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- partition
+// Records move from their extract-span slots into bucket order in two passes with no
+// global atomics: a coarse pass on the top log_c bits of the bucket (per-block LDS
+// histograms, one device-wide scan, a scatter with LDS cursors) and a fine pass, one
+// block per coarse group, that counts records and k-mers per bucket in LDS, writes the
+// bucket table and places each record in its bucket.  Order inside a bucket is free:
+// the bucket is sorted afterwards.
+struct PartArgs {
+  const u32* rec;          // span slots
+  const u32* bid;
+  const u32* span_cnt;
+  u64 n_span;              // spans
+  u32 span;                // slots per span
+  u32 spb;                 // spans per coarse-pass block
+  u32 nblk;                // coarse-pass blocks
+  int log_c, log_f;        // bucket = (coarse << log_f) | fine
+  int rec_words;
+  u32* hist;               // [C][nblk] counts -> offsets (digit-major)
+  u32* tmp_rec;            // records grouped by coarse digit
+  u32* tmp_bid;
+  u32* rec_out;            // records in bucket order
+  u64* bcnt;               // per bucket: (records << 32) | k-mers
+  const u64* n_rec_ptr;    // records in total
+};
+
+__device__ __forceinline__ void copy_record(const u32* __restrict__ src, u64 i, u32* __restrict__ dst, u64 j,
+                                            int rec_words) {
+  if (rec_words == 4) {
+    reinterpret_cast<uint4*>(dst)[j] = reinterpret_cast<const uint4*>(src)[i];
+  } else {
+    const uint4* s = reinterpret_cast<const uint4*>(src) + 2 * i;
+    uint4* d = reinterpret_cast<uint4*>(dst) + 2 * j;
+    d[0] = s[0];
+    d[1] = s[1];
+  }
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_part_coarse(PartArgs P) {
+  __shared__ u32 h[512];
+  const u32 C = 1u << P.log_c;
+  const u32 wave = threadIdx.x >> 6, lane = lane_id();
+  for (u32 i = threadIdx.x; i < C; i += 256) h[i] = SCATTER ? P.hist[(u64)i * P.nblk + blockIdx.x] : 0u;
+  __syncthreads();
+  const u64 s0 = (u64)blockIdx.x * P.spb;
+  const u64 s1 = min(P.n_span, s0 + P.spb);
+  for (u64 sp = s0 + wave; sp < s1; sp += 4) {
+    const u32 cnt = P.span_cnt[sp];
+    for (u32 j = lane; j < cnt; j += 64) {
+      const u64 i = sp * (u64)P.span + j;
+      const u32 b = P.bid[i];
+      const u32 c = b >> P.log_f;
+      if (SCATTER) {
+        const u32 pos = atomicAdd(&h[c], 1u);
+        copy_record(P.rec, i, P.tmp_rec, pos, P.rec_words);
+        P.tmp_bid[pos] = b;
+      } else {
+        atomicAdd(&h[c], 1u);
+      }
+    }
+  }
+  if (!SCATTER) {
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < C; i += 256) P.hist[(u64)i * P.nblk + blockIdx.x] = h[i];
+  }
+}
+
+// One block per coarse group c: records [start(c), start(c+1)) of tmp.
+__global__ __launch_bounds__(1024) void k_part_fine(PartArgs P) {
+  __shared__ u32 cr[2048], ck[2048], cur[2048];
+  __shared__ u64 scr[17];
+  const u32 F = 1u << P.log_f, C = 1u << P.log_c, c = blockIdx.x, T = blockDim.x;
+  const u64 n_rec = *P.n_rec_ptr;
+  const u64 g0 = P.hist[(u64)c * P.nblk];
+  const u64 g1 = (c + 1 < C) ? (u64)P.hist[(u64)(c + 1) * P.nblk] : n_rec;
+  for (u32 i = threadIdx.x; i < F; i += T) {
+    cr[i] = 0;
+    ck[i] = 0;
+  }
+  __syncthreads();
+  for (u64 i = g0 + threadIdx.x; i < g1; i += T) {
+    const u32 f = P.tmp_bid[i] & (F - 1);
+    const u32 g = (P.tmp_rec[i * (u64)P.rec_words + P.rec_words - 1] >> 26) + 1u;
+    atomicAdd(&cr[f], 1u);
+    atomicAdd(&ck[f], g);
+  }
+  __syncthreads();
+  // exclusive prefix of the record counts over the F buckets of the group
+  const u32 per = (F + T - 1) / T;
+  const u32 fa = min(F, threadIdx.x * per), fb = min(F, fa + per);
+  u64 sum = 0;
+  for (u32 f = fa; f < fb; ++f) sum += cr[f];
+  u64 tot;
+  u64 run = block_exclusive_scan<u64>(sum, scr, &tot) + g0;
+  for (u32 f = fa; f < fb; ++f) {
+    cur[f] = (u32)run;
+    P.bcnt[((u64)c << P.log_f) + f] = ((u64)cr[f] << 32) | ck[f];
+    run += cr[f];
+  }
+  __syncthreads();
+  for (u64 i = g0 + threadIdx.x; i < g1; i += T) {
+    const u32 f = P.tmp_bid[i] & (F - 1);
+    const u32 pos = atomicAdd(&cur[f], 1u);
+    copy_record(P.tmp_rec, i, P.rec_out, pos, P.rec_words);
   }
 }

@@ -158,6 +158,56 @@ __global__ __launch_bounds__(1024) void k_scan_u32(const u32* __restrict__ in, u
   if (t == 0 && total) *total = all;
 }
 
+// Device-wide exclusive scan of u32 counts in three kernels (block sums, scan of the
+// block sums, apply): n = min(*n_ptr, n_max) (n_max alone if n_ptr is null); blocks of
+// SCAN_T threads take SCAN_BLOCK consecutive elements.  bsum holds ceil(n_max /
+// SCAN_BLOCK) <= 1024 entries.  *total = sum.  in and out may alias.
+constexpr u32 SCAN_T = 256, SCAN_PER = 16, SCAN_BLOCK = SCAN_T * SCAN_PER;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const u32* __restrict__ in, const u64* __restrict__ n_ptr,
+                                                        u64 n_max, u64* __restrict__ bsum) {
+  __shared__ u64 scr[17];
+  const u64 n = n_ptr ? min(*n_ptr, n_max) : n_max;
+  const u64 i0 = (u64)blockIdx.x * SCAN_BLOCK + (u64)threadIdx.x * SCAN_PER;
+  u64 sum = 0;
+  for (u32 i = 0; i < SCAN_PER; ++i)
+    if (i0 + i < n) sum += in[i0 + i];
+  u64 tot;
+  block_exclusive_scan<u64>(sum, scr, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_mid(u64* __restrict__ bsum, u32 nb, u64* __restrict__ total) {
+  __shared__ u64 scr[17];
+  const u64 v = threadIdx.x < nb ? bsum[threadIdx.x] : 0ull;
+  u64 tot;
+  const u64 ex = block_exclusive_scan<u64>(v, scr, &tot);
+  if (threadIdx.x < nb) bsum[threadIdx.x] = ex;
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_apply(const u32* __restrict__ in, u32* __restrict__ out,
+                                                       const u64* __restrict__ n_ptr, u64 n_max,
+                                                       const u64* __restrict__ bsum) {
+  __shared__ u64 scr[17];
+  const u64 n = n_ptr ? min(*n_ptr, n_max) : n_max;
+  const u64 i0 = (u64)blockIdx.x * SCAN_BLOCK + (u64)threadIdx.x * SCAN_PER;
+  u32 v[SCAN_PER];
+  u64 sum = 0;
+#pragma unroll
+  for (u32 i = 0; i < SCAN_PER; ++i) {
+    v[i] = (i0 + i < n) ? in[i0 + i] : 0u;
+    sum += v[i];
+  }
+  u64 tot;
+  u64 run = block_exclusive_scan<u64>(sum, scr, &tot) + bsum[blockIdx.x];
+#pragma unroll
+  for (u32 i = 0; i < SCAN_PER; ++i) {
+    if (i0 + i < n) out[i0 + i] = (u32)run;
+    run += v[i];
+  }
+}
+
 // Row d of counts (one digit over all nb blocks) -> exclusive prefix over blocks, and
 // totals[d] = the row sum.  One block per digit.
 __global__ __launch_bounds__(256) void k_radix_rowscan(u32* __restrict__ counts, u32 nb, u32* __restrict__ totals) {

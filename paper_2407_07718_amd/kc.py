@@ -36,7 +36,10 @@ class kc_config(ctypes.Structure):
 class kc_totals(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_uint64), ("n_windows", ctypes.c_uint64), ("n_distinct", ctypes.c_uint64),
                 ("overflow_sum", ctypes.c_uint64), ("max_count", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
-                ("flags", ctypes.c_uint64), ("large_keys", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint64), ("large_keys", ctypes.c_uint64), ("tiny_buckets", ctypes.c_uint64),
+                ("tiny_kmers", ctypes.c_uint64), ("small_buckets", ctypes.c_uint64), ("small_kmers", ctypes.c_uint64),
+                ("large_buckets", ctypes.c_uint64), ("chunks", ctypes.c_uint64), ("list_entries", ctypes.c_uint64),
+                ("buckets", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -48,8 +51,8 @@ class kc_result(ctypes.Structure):
                 ("hist", ctypes.POINTER(ctypes.c_uint64)), ("hist_len", ctypes.c_uint64), ("totals", kc_totals)]
 
 
-KC_N_STAGES = 6
-STAGES = ["encode", "extract", "partition", "small_sort", "large_path", "output"]
+KC_N_STAGES = 8
+STAGES = ["encode", "extract", "partition", "expand", "block_sort", "wave_sort", "merge", "output"]
 
 
 class kc_stage_times(ctypes.Structure):
@@ -162,7 +165,7 @@ def kc_count_device(d_reads, d_offsets, k: int, m: int, min_freq: int, max_freq:
                     stream=None, sync: bool = True) -> Optional[dict]:
     """Device API on torch tensors: d_reads uint8, d_offsets int64 (n_reads+1),
     d_workspace uint8 of kc_workspace_size bytes, d_kmers int64 [cap, key_words],
-    d_counts int32 [cap], d_hist int64 [hist_len], d_totals int64 [8].  ``stream`` is a
+    d_counts int32 [cap], d_hist int64 [hist_len], d_totals int64 [16] (one kc_totals).  ``stream`` is a
     torch.cuda.Stream (None: torch's current stream).  With ``sync`` the call waits and
     returns the totals; otherwise it only queues the work."""
     import torch
@@ -198,7 +201,7 @@ class DeviceCounter:
         self.kmers = torch.empty((cap, self.key_words), dtype=torch.int64, device=device)
         self.counts = torch.empty(cap, dtype=torch.int32, device=device)
         self.hist = torch.empty(hist_len, dtype=torch.int64, device=device)
-        self.totals = torch.zeros(8, dtype=torch.int64, device=device)
+        self.totals = torch.zeros(ctypes.sizeof(kc_totals) // 8, dtype=torch.int64, device=device)
 
     def count(self, d_reads, d_offsets, stream=None, sync: bool = True):
         return kc_count_device(d_reads, d_offsets, self.k, self.m, self.lo, self.hi, self.H, self.cfg,
