@@ -47,10 +47,12 @@ extern "C" {
 /* Tuning knobs.  A zero field means "choose automatically". */
 typedef struct kc_config {
   uint32_t log2_buckets;   /* buckets B = 2^log2_buckets (1..20); 0 = from the input size */
-  uint32_t force_hbm;      /* 1 = send every bucket through the HBM sort path (testing) */
+  uint32_t force_hbm;      /* 1 = route every bucket through the chunk-list merge (testing) */
   uint32_t small_variant;  /* on-chip sort block shape: 0 auto, 1 = 256x16, 2 = 512x16 */
-  uint32_t reserved;
-  uint64_t hbm_budget;     /* max workspace bytes; 0 = no limit other than free HBM */
+  uint32_t lanes;          /* batch / server: concurrent stream lanes (0 = 8) */
+  uint64_t hbm_budget;     /* max device bytes; 0 = no limit other than free HBM */
+  uint32_t no_graph;       /* batch: 1 = plain stream launches instead of one hipGraph */
+  uint32_t autotune;       /* batch: 1 = tune bucket count and block shape per job class */
 } kc_config;
 
 /* Totals of one count, as also written to device memory by kc_count_device. */
@@ -130,6 +132,83 @@ int kc_count_device_async(const uint8_t *d_reads, uint64_t total_bases, const ui
                           uint64_t hist_len, const kc_config *cfg, void *d_workspace,
                           size_t workspace_bytes, uint64_t *d_kmers, uint32_t *d_counts,
                           uint64_t pair_capacity, uint64_t *d_hist, kc_totals *d_totals, void *stream);
+
+/* ---------------------------------------------------------------- batched counting
+ * One read set of a batch (or a server request).  reads/offsets are host pointers for
+ * kc_count_batch and kc_server_submit (borrowed until the call returns / the job is
+ * admitted), device pointers for kc_count_batch_device. */
+typedef struct kc_job {
+  const uint8_t *reads;
+  const uint64_t *offsets;
+  uint64_t n_reads;
+  int k, m;
+  uint32_t min_freq, max_freq;
+  uint64_t hist_len;
+} kc_job;
+
+/* Count n_jobs independent read sets in one go (host buffers in, host results out).
+ * All inputs are copied to the device once; jobs are assigned to cfg->lanes stream
+ * lanes by the greedy largest-first rule (each lane with its own workspace) and the
+ * whole schedule is captured as one hipGraph and launched once (cfg->no_graph = 1 to
+ * launch on plain streams instead).  Each job's result equals kc_count of that job.
+ * outs[i] is filled for every job on KC_OK (free each with kc_result_free).  Jobs may
+ * mix k; a job with bad arguments fails the whole call with KC_EINVAL before any
+ * device work. */
+int kc_count_batch(uint32_t n_jobs, const kc_job *jobs, const kc_config *cfg, kc_result *outs);
+
+/* A prepared batch over device-resident inputs, for repeated launches (benchmarks,
+ * pipelines): kc_batch_create captures the schedule into a hipGraph over the given
+ * device jobs, kc_batch_run launches it on `stream` (and waits), kc_batch_result
+ * copies one job's outputs to the host, kc_batch_destroy frees everything. */
+typedef struct kc_batch kc_batch;
+int kc_batch_create(uint32_t n_jobs, const kc_job *device_jobs, const kc_config *cfg, kc_batch **out);
+int kc_batch_run(kc_batch *b, void *stream);
+int kc_batch_result(kc_batch *b, uint32_t job, kc_result *out);
+int kc_batch_destroy(kc_batch *b);
+
+/* Autotuner: times the count of one representative job under candidate bucket counts
+ * and block shapes and returns the fastest setting in *out (its other fields copied
+ * from base).  Results are remembered per (key width, k, size class, read-length
+ * class) for the life of the process and reused by kc_count_batch with autotune set. */
+int kc_autotune(const kc_job *device_job, const kc_config *base, kc_config *out, double *best_ms);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop on one GPU.  Requests are admitted in arrival order when their
+ * estimated footprint (read bytes x k, as the deployment sizes it) fits the remaining
+ * HBM budget and a stream slot is free; admitted requests run concurrently on their
+ * own streams and workspaces, so requests that arrive while others are on the GPU
+ * overlap with them.  Results are identical to kc_count of the same job. */
+typedef struct kc_server_cfg {
+  uint64_t hbm_budget;     /* admission budget: sum of estimated footprints in flight */
+  uint32_t slots;          /* requests in flight at most (streams); 0 = 8 */
+  uint32_t reserved;       /* must be 0 */
+  uint64_t arena_bytes;    /* device memory the server allocates once and carves each
+                              request's inputs, workspace and outputs from (first fit);
+                              0 = hbm_budget.  A request whose actual bytes exceed the
+                              whole arena fails with KC_ENOMEM. */
+  kc_config count;         /* tuning of each count (log2_buckets etc.) */
+} kc_server_cfg;
+
+typedef struct kc_timing {
+  double submit_s;         /* seconds on the server clock */
+  double admit_s;
+  double done_s;
+  uint64_t footprint;      /* estimated bytes used for admission */
+} kc_timing;
+
+typedef struct kc_server kc_server;
+int kc_server_create(const kc_server_cfg *cfg, kc_server **out);
+/* Never blocks: copies the job's host inputs and queues it.  *ticket identifies it. */
+int kc_server_submit(kc_server *s, const kc_job *job, uint64_t *ticket);
+/* KC_EAGAIN while the job is queued or running; KC_OK once *out holds its result
+ * (then the ticket is retired); KC_ECANCELED for a cancelled job. */
+int kc_server_poll(kc_server *s, uint64_t ticket, kc_result *out, kc_timing *t);
+/* Cancels a job that is still queued (KC_EINVAL if it was admitted or is unknown). */
+int kc_server_cancel(kc_server *s, uint64_t ticket);
+/* Seconds on the server clock (the clock of kc_timing). */
+double kc_server_clock(kc_server *s);
+/* Waits for admitted jobs, drops queued ones, frees everything. */
+int kc_server_destroy(kc_server *s);
 
 /* Stage timing.  While enabled (kc_profile(1)), each count queued by this thread records
  * HIP events on its own stream at the boundaries of its stages:

@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 def build() -> str:
     """Compile liboracle.so with g++ (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, _SRC])
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC])
     os.replace(tmp, _LIB)
     return _LIB
 

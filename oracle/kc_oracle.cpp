@@ -192,7 +192,8 @@ uint64_t kco_query(const uint8_t *reads, const uint64_t *offsets, uint64_t n_rea
 }
 
 // Batch form of kco_query: counts for n_q query k-mers in one pass over the reads
-// (queries are looked up by binary search in a sorted copy).
+// (queries are looked up by binary search in a sorted copy).  Reads are split over
+// threads; each thread counts into its own array and the arrays are summed.
 void kco_query_many(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k,
                     const uint64_t *q_words, uint64_t n_q, uint64_t *counts_out) {
   std::vector<std::pair<u128, uint64_t>> q(n_q);
@@ -202,19 +203,26 @@ void kco_query_many(const uint8_t *reads, const uint64_t *offsets, uint64_t n_re
   }
   std::sort(q.begin(), q.end());
   std::vector<uint64_t> cnt(n_q, 0);
-  for (uint64_t r = 0; r < n_reads; ++r) {
-    uint64_t len = offsets[r + 1] - offsets[r];
-    if (len < (uint64_t)k) continue;
-    const uint8_t *read = reads + offsets[r];
-    for (uint64_t i = 0; i + (uint64_t)k <= len; ++i) {
-      u128 v;
-      if (!window_value<u128>(read, i, k, &v)) continue;
-      auto it = std::lower_bound(q.begin(), q.end(), std::make_pair(v, (uint64_t)0));
-      while (it != q.end() && it->first == v) {
-        cnt[it->second] += 1;
-        ++it;
+#pragma omp parallel
+  {
+    std::vector<uint64_t> mine(n_q, 0);
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t r = 0; r < (int64_t)n_reads; ++r) {
+      uint64_t len = offsets[r + 1] - offsets[r];
+      if (len < (uint64_t)k) continue;
+      const uint8_t *read = reads + offsets[r];
+      for (uint64_t i = 0; i + (uint64_t)k <= len; ++i) {
+        u128 v;
+        if (!window_value<u128>(read, i, k, &v)) continue;
+        auto it = std::lower_bound(q.begin(), q.end(), std::make_pair(v, (uint64_t)0));
+        while (it != q.end() && it->first == v) {
+          mine[it->second] += 1;
+          ++it;
+        }
       }
     }
+#pragma omp critical
+    for (uint64_t i = 0; i < n_q; ++i) cnt[i] += mine[i];
   }
   for (uint64_t i = 0; i < n_q; ++i) counts_out[i] = cnt[i];
 }

@@ -11,7 +11,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/kc.h"
@@ -74,10 +77,9 @@ struct Plan {
   u32 span = 0;
   u32 nb_large = 1, nb_surv = 1;        // radix blocks
   // offsets into the workspace
-  u64 o_packed, o_nmask, o_starts, o_recA, o_recB, o_bid, o_bcnt, o_recoff, o_cursor, o_small, o_large,
-      o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_tot_large, o_tot_surv, o_bc, o_hp, o_surv0k, o_surv0c, o_surv1k,
-      o_surv1c, o_spancnt, o_chstart, o_chlen, o_kl0k, o_kl0c, o_kl1k, o_kl1c, o_tiny, o_kall, o_klsc, o_klcnt,
-      o_kloff, o_scnt, o_soff, o_bsum, o_scanbuf, o_ptmp_rec, o_ptmp_bid, o_phist;
+  u64 o_packed, o_nmask, o_starts, o_X, o_Y, o_Z, o_bcnt, o_recoff, o_cursor, o_small, o_large,
+      o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_tot_large, o_tot_surv, o_bc, o_hp, o_spancnt, o_chstart, o_chlen,
+      o_tiny, o_kall, o_klcnt, o_kloff, o_scnt, o_soff, o_bsum, o_scanbuf, o_phist;
   int log_c = 0, log_f = 0;
   u32 part_nblk = 1, part_spb = 1;
   u64 n_packed, n_mask, bytes = 0;
@@ -156,13 +158,22 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
     return r;
   };
   const u64 rb = 4ull * p->rec_words;
+  const u64 N = p->rec_cap;
+  p->chunk_cap = N / p->cap_chunk + p->B + 1;
+  p->kl_cap = N;
   p->o_packed = take(4 * p->n_packed);
   p->o_nmask = take(4 * p->n_mask);
   p->o_starts = take(4 * p->n_mask);
-  // unsorted records; after the scatter the same bytes hold the two large-key arrays
-  p->o_recA = take(std::max(rb * p->slots, 2 * w * p->rec_cap));
-  p->o_recB = take(rb * p->rec_cap);
-  p->o_bid = take(4 * p->slots);
+  // Three large regions whose contents rotate as the stages retire them:
+  //   X: span record slots + bucket ids (extract)  -> records in bucket order (fine
+  //      partition, read by the sorts) -> first buffer of the chunk-list sort
+  //   Y: records grouped by coarse digit + bucket ids (partition) -> large-bucket keys,
+  //      overwritten in place by the chunk lists, + list counts -> second sort buffer
+  //   Z: survivors at their bucket's k-mer slots -> second buffer of the survivor sort
+  // The final dense survivors use whichever of X / Y the chunk-list sort left free.
+  p->o_X = take(std::max(std::max((rb + 4) * p->slots, rb * N), (w + 4) * N));
+  p->o_Y = take(std::max((rb + 4) * N, (w + 4) * N));
+  p->o_Z = take((w + 4) * N);
   p->o_spancnt = take(4 * p->n_span_alloc);
   p->o_bcnt = take(8ull * p->B);
   p->o_recoff = take(4ull * (p->B + 1));
@@ -171,36 +182,22 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_tiny = take(4ull * p->B);
   p->o_large = take(4ull * p->B);
   p->o_lkoff = take(8ull * p->B);
+  p->o_kall = take(8ull * p->B);
   p->o_ctrl = take(8ull * C_WORDS);
   p->o_cnt_large = take(4ull * 256 * p->nb_large);
   p->o_cnt_surv = take(4ull * 256 * p->nb_surv);
   p->o_tot_large = take(4ull * 256);
   p->o_tot_surv = take(4ull * 256);
   p->o_bc = take(4ull * 1024);
-  p->o_hp = take(4 * p->rec_cap);
-  p->o_surv0k = take(w * p->surv_cap);
-  p->o_surv0c = take(4 * p->surv_cap);
-  p->o_surv1k = take(w * p->surv_cap);
-  p->o_surv1c = take(4 * p->surv_cap);
-  // chunks of large buckets and their (k-mer, count) lists
-  p->chunk_cap = p->rec_cap / p->cap_chunk + p->B + 1;
-  p->kl_cap = p->rec_cap;
+  p->o_hp = take(4 * N);
   p->o_chstart = take(8 * p->chunk_cap);
   p->o_chlen = take(4 * p->chunk_cap);
-  p->o_kl0k = take(w * p->kl_cap);
-  p->o_kl0c = take(4 * p->kl_cap);
-  p->o_kl1k = take(w * p->kl_cap);
-  p->o_kl1c = take(4 * p->kl_cap);
-  p->o_kall = take(8ull * p->B);
-  p->o_klsc = take(4 * p->kl_cap);
   p->o_klcnt = take(4 * p->chunk_cap);
   p->o_kloff = take(4 * p->chunk_cap);
   p->o_scnt = take(4ull * (p->B + RUN_BLOCKS));
   p->o_soff = take(4ull * (p->B + RUN_BLOCKS));
   p->o_bsum = take(8ull * PLAN_Q * (p->B / PLAN_BLOCK + 1));
   p->o_scanbuf = take(8ull * 1024);
-  p->o_ptmp_rec = take(rb * p->rec_cap);
-  p->o_ptmp_bid = take(4 * p->rec_cap);
   p->o_phist = take(4ull * ((u64)1 << p->log_c) * p->part_nblk);
   p->bytes = o;
   return true;
@@ -214,10 +211,41 @@ int check_args(int k, int m, uint32_t lo, uint32_t hi, uint64_t hist_len) {
   return KC_OK;
 }
 
+// Device attributes and kernel occupancies are looked up once (host queries stay out of
+// graph capture).
 int device_info(int* n_cu) {
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  HIP_TRY(hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  static std::atomic<int> cached{0};
+  int v = cached.load();
+  if (v <= 0) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
+    cached.store(v);
+  }
+  *n_cu = v;
+  return KC_OK;
+}
+
+std::mutex g_occ_mu;
+std::unordered_map<const void*, int> g_occ;
+
+template <typename F>
+int blocks_per_cu(F kernel, int threads, int* out) {
+  const void* key = reinterpret_cast<const void*>(kernel);
+  {
+    std::lock_guard<std::mutex> g(g_occ_mu);
+    auto it = g_occ.find(key);
+    if (it != g_occ.end()) {
+      *out = it->second;
+      return KC_OK;
+    }
+  }
+  int v = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kernel, threads, 0));
+  v = std::max(1, v);
+  std::lock_guard<std::mutex> g(g_occ_mu);
+  g_occ[key] = v;
+  *out = v;
   return KC_OK;
 }
 
@@ -287,19 +315,32 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   int n_cu = 0;
   int rc = device_info(&n_cu);
   if (rc) return rc;
+  const u64 N = P.rec_cap, RB = 4ull * P.rec_words, WK = sizeof(K);
+  char* X = at<char>(ws, P.o_X);
+  char* Y = at<char>(ws, P.o_Y);
+  char* Z = at<char>(ws, P.o_Z);
   u32* packed = at<u32>(ws, P.o_packed);
   u32* nmask = at<u32>(ws, P.o_nmask);
   u32* starts = at<u32>(ws, P.o_starts);
-  u32* recA = at<u32>(ws, P.o_recA);
-  u32* recB = at<u32>(ws, P.o_recB);
-  u32* bid = at<u32>(ws, P.o_bid);
+  u32* recA = reinterpret_cast<u32*>(X);                       // span slots
+  u32* bid = reinterpret_cast<u32*>(X + RB * P.slots);
+  u32* ptmp_rec = reinterpret_cast<u32*>(Y);                   // coarse partition
+  u32* ptmp_bid = reinterpret_cast<u32*>(Y + RB * N);
+  u32* recB = reinterpret_cast<u32*>(X);                       // bucket order
+  K* lk0 = reinterpret_cast<K*>(Y);                            // large keys -> chunk lists
+  u32* klsc = reinterpret_cast<u32*>(Y + WK * N);
+  K* s0k = reinterpret_cast<K*>(Z);                            // survivors at bucket slots
+  u32* s0c = reinterpret_cast<u32*>(Z + WK * N);
+  K* kl0k = reinterpret_cast<K*>(X);                           // chunk-list sort buffers
+  u32* kl0c = reinterpret_cast<u32*>(X + WK * N);
+  K* kl1k = reinterpret_cast<K*>(Y);
+  u32* kl1c = reinterpret_cast<u32*>(Y + WK * N);
   u64* bcnt = at<u64>(ws, P.o_bcnt);
   u32* recoff = at<u32>(ws, P.o_recoff);
   u32* cursor = at<u32>(ws, P.o_cursor);
   u32* small = at<u32>(ws, P.o_small);
   u32* tiny = at<u32>(ws, P.o_tiny);
   u64* kall = at<u64>(ws, P.o_kall);
-  u32* klsc = at<u32>(ws, P.o_klsc);
   u32* klcnt = at<u32>(ws, P.o_klcnt);
   u32* kloff = at<u32>(ws, P.o_kloff);
   u32* scnt = at<u32>(ws, P.o_scnt);
@@ -316,16 +357,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u32* spancnt = at<u32>(ws, P.o_spancnt);
   u64* chstart = at<u64>(ws, P.o_chstart);
   u32* chlen = at<u32>(ws, P.o_chlen);
-  K* kl0k = at<K>(ws, P.o_kl0k);
-  u32* kl0c = at<u32>(ws, P.o_kl0c);
-  K* kl1k = at<K>(ws, P.o_kl1k);
-  u32* kl1c = at<u32>(ws, P.o_kl1c);
   u32* bc = at<u32>(ws, P.o_bc);
   u32* hp = at<u32>(ws, P.o_hp);
-  K* s0k = at<K>(ws, P.o_surv0k);
-  u32* s0c = at<u32>(ws, P.o_surv0c);
-  K* s1k = at<K>(ws, P.o_surv1k);
-  u32* s1c = at<u32>(ws, P.o_surv1c);
   u64* counters = ctrl + C_COUNTERS;
   u64* meta = ctrl + C_META;
   u32* flags = reinterpret_cast<u32*>(ctrl + C_FLAGS);
@@ -392,8 +425,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     pp.log_f = P.log_f;
     pp.rec_words = P.rec_words;
     pp.hist = at<u32>(ws, P.o_phist);
-    pp.tmp_rec = at<u32>(ws, P.o_ptmp_rec);
-    pp.tmp_bid = at<u32>(ws, P.o_ptmp_bid);
+    pp.tmp_rec = ptmp_rec;
+    pp.tmp_bid = ptmp_bid;
     pp.rec_out = recB;
     pp.bcnt = bcnt;
     pp.n_rec_ptr = counters;
@@ -435,7 +468,6 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ca.surv_k = s0k;           // sparse: bucket b's survivors at kall[b] + i
   ca.surv_c = s0c;
   ca.surv_cnt = scnt;
-  K* lk0 = reinterpret_cast<K*>(recA);   // unsorted records are dead after the scatter
   ca.lkeys = lk0;
   ca.kl_k = lk0;             // a chunk's list overwrites its own keys (read into LDS first)
   ca.kl_c = klsc;
@@ -447,20 +479,19 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   if (P.variant == 2) {
     constexpr int T = 512, IT = WIDE ? 8 : 16;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
+    if ((rc = blocks_per_cu(k_bucket_sort_count<K, T, IT>, T, &per_cu))) return rc;
     hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
   } else {
     constexpr int T = 256, IT = WIDE ? 8 : 16;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_sort_count<K, T, IT>, T, 0));
+    if ((rc = blocks_per_cu(k_bucket_sort_count<K, T, IT>, T, &per_cu))) return rc;
     hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
   }
   stage_mark(5, st);
   {
     constexpr u32 WC = WIDE ? WAVE_CAP_128 : WAVE_CAP_64;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_sort_count<K, WC, WAVES_PER_BLOCK>,
-                                                         WAVES_PER_BLOCK * 64, 0));
+    if ((rc = blocks_per_cu(k_wave_sort_count<K, WC, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &per_cu))) return rc;
     hipLaunchKernelGGL((k_wave_sort_count<K, WC, WAVES_PER_BLOCK>), dim3(std::max(1, per_cu) * n_cu),
                        dim3(WAVES_PER_BLOCK * 64), 0, st, ca, tiny, meta + 5);
   }
@@ -477,6 +508,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u32* lvs = second ? kl1c : kl0c;
   K* fk = second ? kl0k : kl1k;     // the free buffer holds the merged runs' survivors
   u32* fc = second ? kl0c : kl1c;
+  K* s1k = lks;                      // dense survivors go where the sorted lists were
+  u32* s1c = lvs;
   hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc);
   hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, bc, bc, (const u64*)nullptr, (u64)P.nb_large, nruns);
   hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc, hp);
@@ -501,6 +534,22 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   hipLaunchKernelGGL(k_totals_meta, dim3(1), dim3(64), 0, st, d_tot, meta, kl_n, P.B);
   stage_mark(8, st);
   HIP_TRY(hipGetLastError());
+  return KC_OK;
+}
+
+// Resolve the device facts every launch sequence looks up (multiprocessor count and
+// the occupancy of the persistent kernels), so that later launches, e.g. under graph
+// capture, make no host queries.
+int warm_launch_facts() {
+  int v = 0, rc;
+  if ((rc = device_info(&v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<u64, 256, 16>, 256, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<u64, 512, 16>, 512, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 256, 8>, 256, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 512, 8>, 512, &v))) return rc;
+  if ((rc = blocks_per_cu(k_wave_sort_count<u64, WAVE_CAP_64, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v))) return rc;
+  if ((rc = blocks_per_cu(k_wave_sort_count<k128, WAVE_CAP_128, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v)))
+    return rc;
   return KC_OK;
 }
 
@@ -699,3 +748,5 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
 }
 
 }  // extern "C"
+
+#include "kc_runtime.hpp"

@@ -29,8 +29,8 @@ class KCError(RuntimeError):
 
 class kc_config(ctypes.Structure):
     _fields_ = [("log2_buckets", ctypes.c_uint32), ("force_hbm", ctypes.c_uint32),
-                ("small_variant", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("hbm_budget", ctypes.c_uint64)]
+                ("small_variant", ctypes.c_uint32), ("lanes", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64), ("no_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32)]
 
 
 class kc_totals(ctypes.Structure):
@@ -51,6 +51,25 @@ class kc_result(ctypes.Structure):
                 ("hist", ctypes.POINTER(ctypes.c_uint64)), ("hist_len", ctypes.c_uint64), ("totals", kc_totals)]
 
 
+class kc_job(ctypes.Structure):
+    _fields_ = [("reads", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n_reads", ctypes.c_uint64),
+                ("k", ctypes.c_int), ("m", ctypes.c_int), ("min_freq", ctypes.c_uint32),
+                ("max_freq", ctypes.c_uint32), ("hist_len", ctypes.c_uint64)]
+
+
+class kc_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("slots", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("arena_bytes", ctypes.c_uint64), ("count", kc_config)]
+
+
+class kc_timing(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("footprint", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 KC_N_STAGES = 8
 STAGES = ["encode", "extract", "partition", "expand", "block_sort", "wave_sort", "merge", "output"]
 
@@ -62,6 +81,9 @@ class kc_stage_times(ctypes.Structure):
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
+    # torch (which owns device memory and streams here) is loaded first so that the
+    # library binds to the HIP runtime torch already carries: one runtime per process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
     lib.kc_version.restype = ctypes.c_char_p
@@ -77,6 +99,31 @@ def _load() -> ctypes.CDLL:
     lib.kc_count_device.restype = i32
     lib.kc_count_device_async.argtypes = dev_args
     lib.kc_count_device_async.restype = i32
+    P = ctypes.POINTER
+    lib.kc_count_batch.argtypes = [u32, P(kc_job), P(kc_config), P(kc_result)]
+    lib.kc_count_batch.restype = i32
+    lib.kc_batch_create.argtypes = [u32, P(kc_job), P(kc_config), P(vp)]
+    lib.kc_batch_create.restype = i32
+    lib.kc_batch_run.argtypes = [vp, vp]
+    lib.kc_batch_run.restype = i32
+    lib.kc_batch_result.argtypes = [vp, u32, P(kc_result)]
+    lib.kc_batch_result.restype = i32
+    lib.kc_batch_destroy.argtypes = [vp]
+    lib.kc_batch_destroy.restype = i32
+    lib.kc_autotune.argtypes = [P(kc_job), P(kc_config), P(kc_config), P(ctypes.c_double)]
+    lib.kc_autotune.restype = i32
+    lib.kc_server_create.argtypes = [P(kc_server_cfg), P(vp)]
+    lib.kc_server_create.restype = i32
+    lib.kc_server_submit.argtypes = [vp, P(kc_job), P(ctypes.c_uint64)]
+    lib.kc_server_submit.restype = i32
+    lib.kc_server_poll.argtypes = [vp, ctypes.c_uint64, P(kc_result), P(kc_timing)]
+    lib.kc_server_poll.restype = i32
+    lib.kc_server_cancel.argtypes = [vp, ctypes.c_uint64]
+    lib.kc_server_cancel.restype = i32
+    lib.kc_server_clock.argtypes = [vp]
+    lib.kc_server_clock.restype = ctypes.c_double
+    lib.kc_server_destroy.argtypes = [vp]
+    lib.kc_server_destroy.restype = i32
     lib.kc_profile.argtypes = [i32]
     lib.kc_profile.restype = i32
     lib.kc_profile_read.argtypes = [ctypes.POINTER(kc_stage_times)]
@@ -114,8 +161,8 @@ def kc_profile_read() -> dict:
 
 
 def make_config(log2_buckets: int = 0, force_hbm: bool = False, small_variant: int = 0,
-                hbm_budget: int = 0) -> kc_config:
-    return kc_config(log2_buckets, int(force_hbm), small_variant, 0, hbm_budget)
+                hbm_budget: int = 0, lanes: int = 0, no_graph: bool = False, autotune: bool = False) -> kc_config:
+    return kc_config(log2_buckets, int(force_hbm), small_variant, lanes, hbm_budget, int(no_graph), int(autotune))
 
 
 @dataclass
@@ -150,6 +197,131 @@ def kc_count(reads: np.ndarray, offsets: np.ndarray, k: int, m: int, min_freq: i
         return Result(kmers, counts, hist, res.totals.as_dict())
     finally:
         _lib.kc_result_free(ctypes.byref(res))
+
+
+def _take_result(res: kc_result, hist_len: int) -> Result:
+    try:
+        n, kw = int(res.n_pairs), int(res.key_words)
+        kmers = np.ctypeslib.as_array(res.kmers, shape=(max(1, n * kw),))[: n * kw].copy().reshape(n, kw)
+        counts = np.ctypeslib.as_array(res.counts, shape=(max(1, n),))[:n].copy()
+        hist = np.ctypeslib.as_array(res.hist, shape=(hist_len,)).copy()
+        return Result(kmers, counts, hist, res.totals.as_dict())
+    finally:
+        _lib.kc_result_free(ctypes.byref(res))
+
+
+class Job:
+    """One read set of a batch or a server request (host numpy arrays)."""
+
+    def __init__(self, reads, offsets, k: int, m: int, min_freq: int, max_freq: int, hist_len: int = 65536):
+        self.reads = np.ascontiguousarray(reads, dtype=np.uint8)
+        if self.reads.size == 0:
+            self.reads = np.zeros(1, dtype=np.uint8)
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        self.k, self.m, self.min_freq, self.max_freq, self.hist_len = k, m, min_freq, max_freq, hist_len
+
+    def c(self) -> kc_job:
+        return kc_job(self.reads.ctypes.data, self.offsets.ctypes.data, self.offsets.shape[0] - 1, self.k, self.m,
+                      self.min_freq, self.max_freq, self.hist_len)
+
+
+def kc_count_batch(jobs, cfg: Optional[kc_config] = None):
+    """Count a list of Job read sets in one batched call; returns one Result per job."""
+    arr = (kc_job * max(1, len(jobs)))(*[j.c() for j in jobs])
+    outs = (kc_result * max(1, len(jobs)))()
+    _check(_lib.kc_count_batch(len(jobs), arr, ctypes.byref(cfg) if cfg is not None else None, outs))
+    return [_take_result(outs[i], jobs[i].hist_len) for i in range(len(jobs))]
+
+
+class DeviceBatch:
+    """A prepared batch over device-resident read sets (torch tensors): one hipGraph that
+    counts every set; run() launches it, result(i) copies set i's outputs to the host."""
+
+    def __init__(self, sets, cfg: Optional[kc_config] = None):
+        # sets: list of (d_reads uint8, d_offsets int64, k, m, min_freq, max_freq, hist_len)
+        self._keep = sets
+        self.hist = [s[6] for s in sets]
+        arr = (kc_job * max(1, len(sets)))(*[kc_job(_ptr(s[0]), _ptr(s[1]), int(s[1].numel()) - 1, s[2], s[3], s[4],
+                                                    s[5], s[6]) for s in sets])
+        h = ctypes.c_void_p()
+        _check(_lib.kc_batch_create(len(sets), arr, ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(h)))
+        self.h = h
+
+    def run(self, stream=None) -> None:
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(_lib.kc_batch_run(self.h, ctypes.c_void_p(st.cuda_stream)))
+
+    def result(self, i: int) -> Result:
+        res = kc_result()
+        _check(_lib.kc_batch_result(self.h, i, ctypes.byref(res)))
+        return _take_result(res, self.hist[i])
+
+    def close(self) -> None:
+        if self.h:
+            _lib.kc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kc_autotune(d_reads, d_offsets, k: int, m: int, min_freq: int, max_freq: int, hist_len: int = 65536,
+                base: Optional[kc_config] = None):
+    """Tune bucket count and block shape on one device read set; returns (config, ms)."""
+    job = kc_job(_ptr(d_reads), _ptr(d_offsets), int(d_offsets.numel()) - 1, k, m, min_freq, max_freq, hist_len)
+    out = kc_config()
+    ms = ctypes.c_double()
+    _check(_lib.kc_autotune(ctypes.byref(job), ctypes.byref(base) if base is not None else None, ctypes.byref(out),
+                            ctypes.byref(ms)))
+    return out, float(ms.value)
+
+
+class Server:
+    """Request loop on the GPU (kc_server_*): submit() never blocks, poll() returns the
+    Result once done (None while queued or running)."""
+
+    def __init__(self, hbm_budget: int, slots: int = 8, count_cfg: Optional[kc_config] = None, arena_bytes: int = 0):
+        cfg = kc_server_cfg(hbm_budget, slots, 0, arena_bytes, count_cfg if count_cfg is not None else kc_config())
+        h = ctypes.c_void_p()
+        _check(_lib.kc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        self._hist = {}
+
+    def submit(self, job: Job) -> int:
+        t = ctypes.c_uint64()
+        _check(_lib.kc_server_submit(self.h, ctypes.byref(job.c()), ctypes.byref(t)))
+        self._hist[int(t.value)] = job.hist_len
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(Result, timing dict) once done, None while pending; raises KCError on failure."""
+        res, tm = kc_result(), kc_timing()
+        rc = _lib.kc_server_poll(self.h, ticket, ctypes.byref(res), ctypes.byref(tm))
+        if rc == KC_EAGAIN:
+            return None
+        _check(rc)
+        return _take_result(res, self._hist.pop(ticket)), tm.as_dict()
+
+    def cancel(self, ticket: int) -> None:
+        _check(_lib.kc_server_cancel(self.h, ticket))
+
+    def clock(self) -> float:
+        return float(_lib.kc_server_clock(self.h))
+
+    def close(self) -> None:
+        if self.h:
+            _lib.kc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def kc_workspace_size(total_bases: int, n_reads: int, k: int, cfg: Optional[kc_config] = None) -> int:

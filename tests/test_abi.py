@@ -66,3 +66,45 @@ def test_workspace_size_scales():
     assert 0 < a < b and c > a
     assert kc.kc_workspace_size(1000, 10, 0) == 0
     assert kc.kc_workspace_size(1000, 10, 64) == 0
+
+
+def test_header_declares_batch_and_server_entry_points():
+    names = declared_functions()
+    for n in ["kc_count_batch", "kc_batch_create", "kc_batch_run", "kc_batch_result", "kc_batch_destroy",
+              "kc_autotune", "kc_server_create", "kc_server_submit", "kc_server_poll", "kc_server_cancel",
+              "kc_server_clock", "kc_server_destroy", "kc_profile", "kc_profile_read"]:
+        assert n in names
+
+
+def test_struct_sizes_match_header_layout():
+    from paper_2407_07718_amd import kc
+    assert ctypes.sizeof(kc.kc_totals) == 16 * 8
+    assert ctypes.sizeof(kc.kc_config) == 4 * 4 + 8 + 2 * 4
+    assert ctypes.sizeof(kc.kc_job) == 8 * 3 + 4 * 4 + 8
+    assert ctypes.sizeof(kc.kc_server_cfg) == 8 + 2 * 4 + 8 + ctypes.sizeof(kc.kc_config)
+    assert ctypes.sizeof(kc.kc_timing) == 3 * 8 + 8
+
+
+def test_batch_rejects_bad_job_before_device_work():
+    from paper_2407_07718_amd import kc
+    reads = np.frombuffer(b"ACGT" * 20, dtype=np.uint8)
+    good = kc.Job(reads, np.array([0, 80], dtype=np.uint64), 31, 15, 2, 10, 16)
+    bad_m = kc.Job(reads, np.array([0, 80], dtype=np.uint64), 31, 31, 2, 10, 16)
+    bad_off = kc.Job(reads, np.array([0, 50, 40, 80], dtype=np.uint64), 11, 5, 1, 10, 16)
+    for jobs in ([good, bad_m], [bad_off, good]):
+        with pytest.raises(kc.KCError) as e:
+            kc.kc_count_batch(jobs)
+        assert e.value.code == kc.KC_EINVAL
+
+
+def test_server_rejects_bad_arguments_on_host():
+    from paper_2407_07718_amd import kc
+    with pytest.raises(kc.KCError) as e:
+        kc.Server(hbm_budget=1000)
+    assert e.value.code == kc.KC_EINVAL
+    lib = kc._lib
+    t = ctypes.c_uint64()
+    assert lib.kc_server_submit(None, None, ctypes.byref(t)) == kc.KC_EINVAL
+    assert lib.kc_server_poll(None, 1, None, None) == kc.KC_EINVAL
+    assert lib.kc_server_cancel(None, 1) == kc.KC_EINVAL
+    assert lib.kc_server_destroy(None) == kc.KC_OK

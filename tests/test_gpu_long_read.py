@@ -1,0 +1,107 @@
+"""Parity at the long-read configuration's full size (1 Gbp of lognormal reads, k=31 with
+u64 keys and k=51 with 128-bit keys), in the launch configuration bench.py times.
+
+The oracle cannot sort a billion windows in a test, so the check is
+* exact properties at full size: total count = number of valid windows (closed form from
+  the reads' ACGT runs), histogram sums, filtered pairs = histogram mass in the window,
+  strict ascending order;
+* sampled outputs counted one by one by the oracle: 150 reported pairs must have the
+  oracle's count, and 150 random windows must appear with the oracle's count exactly when
+  that count is inside the frequency window.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_07718_amd import synth
+from tests.gpu_util import device_count
+
+pytestmark = pytest.mark.gpu
+
+_CODE = {"A": 0, "C": 1, "G": 2, "T": 3}
+_VALID = np.zeros(256, dtype=bool)
+_VALID[np.frombuffer(b"ACGTacgt", dtype=np.uint8)] = True
+
+
+def _windows_closed_form(reads, offsets, k):
+    total = 0
+    for r in range(len(offsets) - 1):
+        v = _VALID[reads[int(offsets[r]):int(offsets[r + 1])]]
+        if v.size < k:
+            continue
+        edges = np.diff(np.concatenate(([0], v.astype(np.int8), [0])))
+        starts, ends = np.flatnonzero(edges == 1), np.flatnonzero(edges == -1)
+        runs = ends - starts
+        total += int(np.maximum(runs - k + 1, 0).sum())
+    return total
+
+
+def _canonical(window: str) -> int:
+    fwd = 0
+    for ch in window:
+        fwd = fwd * 4 + _CODE[ch]
+    rc = 0
+    for ch in reversed(window):
+        rc = rc * 4 + (3 - _CODE[ch])
+    return min(fwd, rc)
+
+
+def _as_int(row) -> int:
+    return sum(int(x) << (64 * i) for i, x in enumerate(row))
+
+
+@pytest.mark.parametrize("k", [31, 51])
+def test_long_read_full_size(k):
+    rs = synth.config(3, k=k)
+    print(f"case long-read full size: k={k} m={rs.m} bases={rs.n_bases} reads={rs.n_reads}", flush=True)
+    got = device_count(rs.reads, rs.offsets, k, rs.m, rs.min_freq, rs.max_freq, 65536)
+    t = got.totals
+    H = got.hist.shape[0]
+    cs = np.arange(H, dtype=np.uint64)
+    # exact properties
+    n_win = _windows_closed_form(rs.reads, rs.offsets, k)
+    assert t["n_windows"] == n_win
+    assert int((cs[:-1] * got.hist[:-1]).sum()) + t["overflow_sum"] == n_win
+    assert int(got.hist.sum()) == t["n_distinct"] and int(got.hist[0]) == 0
+    assert got.n_pairs == int(got.hist[rs.min_freq:rs.max_freq + 1].sum())
+    assert got.counts.min() >= rs.min_freq and got.counts.max() <= rs.max_freq
+    keys = [_as_int(r) for r in got.kmers[:: max(1, got.n_pairs // 200000)]]
+    assert all(a < b for a, b in zip(keys, keys[1:]))
+    if k <= 31:
+        assert np.all(np.diff(got.kmers[:, 0].astype(np.uint64)) > 0)
+    # sampled outputs, counted by the oracle
+    rng = np.random.Generator(np.random.PCG64(k))
+    idx = rng.choice(got.n_pairs, size=150, replace=False)
+    words = [got.kmers[i] for i in idx]
+    raw = rs.reads
+    picks = []
+    while len(picks) < 150:
+        r = int(rng.integers(0, rs.n_reads))
+        a, b = int(rs.offsets[r]), int(rs.offsets[r + 1])
+        if b - a < k:
+            continue
+        p = int(rng.integers(a, b - k + 1))
+        w = bytes(raw[p:p + k]).decode("latin-1").upper()
+        if all(ch in _CODE for ch in w):
+            picks.append(_canonical(w))
+    pick_words = [[v & ((1 << 64) - 1), v >> 64] for v in picks]
+    q = np.array([[int(x) for x in (list(wd) + [0])[:2]] for wd in words] + pick_words, dtype=np.uint64)
+    oc = oracle.query(rs.reads, rs.offsets, k, q)
+    assert np.array_equal(oc[:150], got.counts[idx].astype(np.uint64))
+    lo_w = got.kmers[:, 0].astype(np.uint64)
+    hi_w = got.kmers[:, 1].astype(np.uint64) if k > 31 else None
+    for v, c in zip(picks, oc[150:]):
+        c = int(c)
+        assert c >= 1
+        vl, vh = np.uint64(v & ((1 << 64) - 1)), np.uint64(v >> 64)
+        if hi_w is None:
+            j = int(np.searchsorted(lo_w, vl))
+        else:
+            a = int(np.searchsorted(hi_w, vh, side="left"))
+            b = int(np.searchsorted(hi_w, vh, side="right"))
+            j = a + int(np.searchsorted(lo_w[a:b], vl))
+        present = j < got.n_pairs and lo_w[j] == vl and (hi_w is None or hi_w[j] == vh)
+        if rs.min_freq <= c <= rs.max_freq:
+            assert present and int(got.counts[j]) == c
+        else:
+            assert not present
