@@ -68,6 +68,11 @@ def parse():
     p.add_argument("--force-hbm", action="store_true")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 1 GiB device copy (calibrates HBM counters)")
+    p.add_argument("--batch-sets", type=int, default=256, help="read sets of the batched workload (0: skip)")
+    p.add_argument("--batch-scale", type=float, default=0.05,
+                   help="size factor of the batched sets (1.0 = genomes of 1-20 Mbp, 1-200 Mbp of reads each)")
+    p.add_argument("--serve-seconds", type=float, default=10.0, help="seconds of Poisson arrivals per rate (0: skip)")
+    p.add_argument("--serve-rates", type=str, default="5,20,50")
     return p.parse_args()
 
 
@@ -91,6 +96,189 @@ def cpu_baseline(rs, frac: float) -> dict:
     return {"value": r.n_windows / dt, "unit": "k-mers/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} of {len(rs.offsets) - 1} reads ({r.n_windows} k-mers), "
                       f"single-threaded std::sort oracle, {dt:.1f} s"}
+
+
+def digest(kmers, counts, hist) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for a in (kmers, counts, hist):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def oracle_digests(sets) -> list:
+    """Oracle result digest of every read set (threads: the oracle call releases the GIL)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(rs):
+        r = oracle.count(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, 65536)
+        return digest(r.kmers, r.counts.view(np.uint32), r.hist)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, sets))
+
+
+def batched_leg(args, torch, kc, synth) -> tuple:
+    """The batched workload: every set counted in one launch of a captured hipGraph (stream
+    lanes, autotuned configuration per set class) against one plain count per set in
+    sequence.  Both sides start from inputs resident in HBM."""
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    sets = [synth.batch_set(i, args.batch_scale) for i in range(args.batch_sets)]
+    gen_s = time.perf_counter() - t0
+    print(f"bench: batched sets generated ({sum(r.n_bases for r in sets) / 1e6:.1f} Mbp, {gen_s:.1f} s)",
+          file=sys.stderr, flush=True)
+    d_sets = [(torch.from_numpy(np.ascontiguousarray(rs.reads)).to(dev),
+               torch.from_numpy(rs.offsets.view(np.int64)).to(dev)) for rs in sets]
+    # plain: one workspace sized for the largest set, one count per set, each waited for
+    ws = max(kc.kc_workspace_size(rs.n_bases, rs.n_reads, rs.k) for rs in sets)
+    cap = max(1, max(rs.n_bases // rs.min_freq for rs in sets))
+    d_ws = torch.empty(ws, dtype=torch.uint8, device=dev)
+    d_k = torch.empty((cap, 1), dtype=torch.int64, device=dev)
+    d_c = torch.empty(cap, dtype=torch.int32, device=dev)
+    d_h = torch.empty(65536, dtype=torch.int64, device=dev)
+    d_t = torch.zeros(ctypes_words(kc), dtype=torch.int64, device=dev)
+    plain_dig, n_kmers, plain_s = [], 0, 0.0
+    for rep in range(2):            # pass 0 warms up, pass 1 is timed
+        for rs, (dr, do) in zip(sets, d_sets):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tot = kc.kc_count_device(dr, do, rs.k, rs.m, rs.min_freq, rs.max_freq, 65536, None, d_ws, d_k, d_c,
+                                     d_h, d_t)
+            dt = time.perf_counter() - t0
+            if rep == 1:
+                plain_s += dt
+                n = int(tot["n_pairs"])
+                n_kmers += int(tot["n_windows"])
+                plain_dig.append(digest(d_k[:n].cpu().numpy().view(np.uint64), d_c[:n].cpu().numpy().view(np.uint32),
+                                        d_h.cpu().numpy().view(np.uint64)))
+    del d_ws, d_k, d_c, d_h, d_t
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    b = kc.DeviceBatch([(dr, do, rs.k, rs.m, rs.min_freq, rs.max_freq, 65536) for rs, (dr, do) in zip(sets, d_sets)],
+                       kc.make_config(autotune=True, lanes=8))
+    setup_s = time.perf_counter() - t0
+    times = []
+    for rep in range(4):            # replay 0 warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run()
+        if rep:
+            times.append(time.perf_counter() - t0)
+    batch_s = float(np.median(times))
+    batch_dig = []
+    for i in range(len(sets)):
+        r = b.result(i)
+        batch_dig.append(digest(r.kmers, r.counts, r.hist))
+    b.close()
+    print("bench: batched oracle digests", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ref = oracle_digests(sets)
+    res = {
+        "sets": len(sets), "scale": args.batch_scale, "bases": int(sum(r.n_bases for r in sets)), "kmers": n_kmers,
+        "k_mix": {str(k): sum(1 for r in sets if r.k == k) for k in (21, 31)},
+        "long_read_sets": sum(1 for r in sets if r.info["long"]),
+        "graph_replay_ms": round(batch_s * 1e3, 3), "sequential_plain_ms": round(plain_s * 1e3, 3),
+        "speedup_vs_plain": round(plain_s / batch_s, 3),
+        "value": n_kmers / batch_s, "plain_value": n_kmers / plain_s, "unit": "k-mers/s",
+        "setup_s": round(setup_s, 3), "lanes": 8, "autotune": True,
+        "bit_exact_batch_vs_plain": batch_dig == plain_dig, "bit_exact_vs_oracle": batch_dig == ref,
+        "oracle_s": round(time.perf_counter() - t0, 2), "gen_s": round(gen_s, 1),
+    }
+    assert res["bit_exact_batch_vs_plain"] and res["bit_exact_vs_oracle"], "batched results differ"
+    return res, sets, ref
+
+
+def ctypes_words(kc) -> int:
+    import ctypes
+    return ctypes.sizeof(kc.kc_totals) // 8
+
+
+def serving_leg(args, kc, sets, ref) -> dict:
+    """Open-loop Poisson arrivals of counting requests drawn uniformly from the batched
+    sets; latency runs from the scheduled arrival to the result in host memory."""
+    import threading
+    jobs = [kc.Job(rs.reads, rs.offsets, rs.k, rs.m, rs.min_freq, rs.max_freq, 65536) for rs in sets]
+    biggest = max(rs.n_bases for rs in sets)
+    # device arena: room for the largest request three times over (at least 8 GiB); the
+    # admission budget on estimated footprints (read bytes x k) is half of it
+    one = kc.kc_workspace_size(biggest, max(rs.n_reads for rs in sets), 31) + 16 * biggest
+    arena = max(8 << 30, 3 * one)
+    budget = arena // 2
+    srv = kc.Server(hbm_budget=budget, slots=8, arena_bytes=arena)
+    out = {"budget_bytes": budget, "arena_bytes": arena, "slots": 8, "seconds_per_rate": args.serve_seconds,
+           "scale": args.batch_scale, "rates": {}}
+    rng = np.random.Generator(np.random.PCG64(5))
+    try:
+        # warm-up: a few requests before the timed rates
+        warm = [srv.submit(jobs[i]) for i in range(min(8, len(jobs)))]
+        while warm:
+            warm = [t for t in warm if srv.poll(t) is None]
+            time.sleep(0.001)
+        all_ok = True
+        for lam in [float(x) for x in args.serve_rates.split(",") if x]:
+            gaps = rng.exponential(1.0 / lam, size=int(lam * args.serve_seconds * 3) + 16)
+            arr = np.cumsum(gaps)
+            arr = arr[arr < args.serve_seconds]
+            pick = rng.integers(0, len(jobs), size=arr.shape[0])
+            pending = {}
+            lock = threading.Lock()
+            c0 = srv.clock()
+            w0 = time.perf_counter()
+
+            def producer():
+                for t, i in zip(arr, pick):
+                    d = w0 + float(t) - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    tk = srv.submit(jobs[int(i)])
+                    with lock:
+                        pending[tk] = (c0 + float(t), int(i))
+
+            th = threading.Thread(target=producer)
+            th.start()
+            lat, kmers, done_last, bad, foot, devb, inflight = [], 0, 0.0, 0, [], [], []
+            n_done = 0
+            while n_done < arr.shape[0]:
+                with lock:
+                    items = list(pending.items())
+                for tk, (t_arr, i) in items:
+                    r = srv.poll(tk)
+                    if r is None:
+                        continue
+                    res, tm = r
+                    with lock:
+                        del pending[tk]
+                    n_done += 1
+                    lat.append(tm["done_s"] - t_arr)
+                    kmers += int(res.totals["n_windows"])
+                    done_last = max(done_last, tm["done_s"])
+                    foot.append(tm["footprint"])
+                    devb.append(tm["device_bytes"])
+                    inflight.append((tm["admit_s"], tm["done_s"]))
+                    if digest(res.kmers, res.counts, res.hist) != ref[i]:
+                        bad += 1
+                time.sleep(0.0005)
+            th.join()
+            span = done_last - c0
+            lat_ms = np.array(lat) * 1e3
+            conc = max(sum(1 for a, d in inflight if a <= x < d) for x, _ in inflight) if inflight else 0
+            out["rates"][str(int(lam))] = {
+                "requests": int(arr.shape[0]), "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "mean_ms": round(float(lat_ms.mean()), 3),
+                "kmers_per_s": kmers / span if span > 0 else 0.0,
+                "offered_bases_per_s": float(sum(sets[int(i)].n_bases for i in pick)) / args.serve_seconds,
+                "max_in_flight": conc, "est_over_actual_bytes": round(float(np.sum(foot)) / float(np.sum(devb)), 3),
+                "bit_exact_vs_oracle": bad == 0,
+            }
+            all_ok &= bad == 0
+            print(f"bench: served {lam} req/s: {out['rates'][str(int(lam))]}", file=sys.stderr, flush=True)
+        out["all_bit_exact"] = all_ok
+    finally:
+        srv.close()
+    assert out["all_bit_exact"], "a served result differs from the oracle"
+    return out
 
 
 def main():
@@ -186,6 +374,12 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(rs, args.cpu_sample_frac)
+    if args.batch_sets > 0:
+        print(f"bench: batched leg ({args.batch_sets} sets, scale {args.batch_scale})", file=sys.stderr, flush=True)
+        out["batched"], sets, ref = batched_leg(args, torch, kc, synth)
+        if args.serve_seconds > 0:
+            print("bench: serving leg", file=sys.stderr, flush=True)
+            out["serving"] = serving_leg(args, kc, sets, ref)
     if args.copy_calib:
         # a plain device copy of 1 GiB, for scaling HBM counters to bytes
         src = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)

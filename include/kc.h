@@ -193,7 +193,9 @@ typedef struct kc_timing {
   double submit_s;         /* seconds on the server clock */
   double admit_s;
   double done_s;
-  uint64_t footprint;      /* estimated bytes used for admission */
+  uint64_t footprint;      /* estimated bytes used for admission (read bytes x k) */
+  uint64_t device_bytes;   /* bytes actually carved from the arena (inputs, workspace,
+                              outputs) */
 } kc_timing;
 
 typedef struct kc_server kc_server;

@@ -776,6 +776,7 @@ int kc_server_submit(kc_server* s, const kc_job* job, uint64_t* ticket) {
   J->ticket = s->next_ticket++;
   J->tm.submit_s = s->now();
   J->tm.footprint = J->est;
+  J->tm.device_bytes = J->bytes;
   *ticket = J->ticket;
   SrvJob* raw = J.release();
   s->jobs[raw->ticket] = raw;
