@@ -49,13 +49,47 @@ struct CountArgs {
   u32* kl_cnt;             // list length per chunk
 };
 
+// ---------------------------------------------------------------------------- key mixing
+// A bucket is sorted only to bring equal keys together, so its keys are sorted as images
+// under a bijection whose low bits depend on every key bit: y = b ^ (b >> 32) with
+// b = a * C mod 2^64 and a = x ^ (x >> 32).  Both xor-shifts are involutions and C is
+// odd, so the map is undone exactly by the same steps in reverse with C^-1.  K-mers that
+// differ in one base (sequencing errors) then differ in their low bits with
+// probability about 1 - 2^-32, so a sort over the low digits alone already separates
+// distinct keys (checked, and completed by the remaining passes when it did not).
+// 128-bit keys mix their low word and fold in a mix of the high word (a Feistel step).
+constexpr u64 MIX_C = 0x9e3779b97f4a7c15ull;
+constexpr u64 mod_inverse64(u64 c) {
+  u64 x = c;                                      // correct to 3 bits for odd c
+  for (int i = 0; i < 5; ++i) x *= 2ull - c * x;  // Newton step doubles the correct bits
+  return x;
+}
+constexpr u64 MIX_CINV = mod_inverse64(MIX_C);
+static_assert(MIX_C * MIX_CINV == 1ull, "modular inverse");
+
+__device__ __forceinline__ u64 mix64(u64 x) {
+  x ^= x >> 32;
+  x *= MIX_C;
+  return x ^ (x >> 32);
+}
+__device__ __forceinline__ u64 unmix64(u64 y) {
+  y ^= y >> 32;
+  y *= MIX_CINV;
+  return y ^ (y >> 32);
+}
+__device__ __forceinline__ u64 mix_key(u64 x) { return mix64(x); }
+__device__ __forceinline__ u64 unmix_key(u64 y) { return unmix64(y); }
+__device__ __forceinline__ k128 mix_key(k128 x) { return k128{mix64(x.lo) ^ mix64(x.hi ^ MIX_C), x.hi}; }
+__device__ __forceinline__ k128 unmix_key(k128 y) { return k128{unmix64(y.lo ^ mix64(y.hi ^ MIX_C)), y.hi}; }
+
 // ---------------------------------------------------------------------------- expand
 __device__ __forceinline__ u32 record_g(const u32* __restrict__ rec, u64 r, int rec_words) {
   return (rec[r * (u64)rec_words + (u64)rec_words - 1] >> 26) + 1u;
 }
 
 // k <= 31: record = 4 words, bases LSB first in 122 bits.
-__device__ __forceinline__ void expand_record(const u32* __restrict__ rec, u64 r, int k, u64* dst, u32 g) {
+__device__ __forceinline__ void expand_record(const u32* __restrict__ rec, u64 r, int k, u64* dst, u32 g,
+                                              bool mix = false) {
   const uint4 v = reinterpret_cast<const uint4*>(rec)[r];
   const u64 lo = (u64)v.x | ((u64)v.y << 32);
   const u64 hi = ((u64)v.z | ((u64)v.w << 32)) & ((1ull << 58) - 1);
@@ -63,18 +97,21 @@ __device__ __forceinline__ void expand_record(const u32* __restrict__ rec, u64 r
   const u64 V = lo & mask;
   u64 F = rev2_64(V) >> (64 - 2 * k);
   u64 RC = ~V & mask;
-  dst[0] = F < RC ? F : RC;
+  u64 cv = F < RC ? F : RC;
+  dst[0] = mix ? mix_key(cv) : cv;
   for (u32 j = 1; j < g; ++j) {
     const u32 p = j + (u32)k - 1;   // index of the base entering the window
     const u64 c = p < 32 ? (lo >> (2 * p)) & 3ull : (hi >> (2 * p - 64)) & 3ull;
     F = ((F << 2) | c) & mask;
     RC = (RC >> 2) | ((3ull - c) << (2 * k - 2));
-    dst[j] = F < RC ? F : RC;
+    cv = F < RC ? F : RC;
+    dst[j] = mix ? mix_key(cv) : cv;
   }
 }
 
 // 32 <= k <= 63: record = 8 words, bases LSB first in 250 bits.
-__device__ __forceinline__ void expand_record(const u32* __restrict__ rec, u64 r, int k, k128* dst, u32 g) {
+__device__ __forceinline__ void expand_record(const u32* __restrict__ rec, u64 r, int k, k128* dst, u32 g,
+                                              bool mix = false) {
   const uint4* p4 = reinterpret_cast<const uint4*>(rec) + 2 * r;
   const uint4 a = p4[0], b = p4[1];
   u64 w[4];
@@ -93,7 +130,8 @@ __device__ __forceinline__ void expand_record(const u32* __restrict__ rec, u64 r
   else { F.lo = (rlo >> s) | (rhi << (64 - s)); F.hi = rhi >> s; }
   RC.lo = ~vlo;
   RC.hi = ~vhi & mhi;
-  dst[0] = key_lt(F, RC) ? F : RC;
+  k128 v = key_lt(F, RC) ? F : RC;
+  dst[0] = mix ? mix_key(v) : v;
   for (u32 j = 1; j < g; ++j) {
     const u32 p = j + (u32)k - 1;
     const u64 wsel = p < 64 ? (p < 32 ? w[0] : w[1]) : (p < 96 ? w[2] : w[3]);   // no dynamic register index
@@ -107,7 +145,8 @@ __device__ __forceinline__ void expand_record(const u32* __restrict__ rec, u64 r
     const int t = 2 * k - 2;                      // 62..124
     if (t >= 64) RC.hi |= (3ull - c) << (t - 64);
     else RC.lo |= (3ull - c) << t;
-    dst[j] = key_lt(F, RC) ? F : RC;
+    v = key_lt(F, RC) ? F : RC;
+    dst[j] = mix ? mix_key(v) : v;
   }
 }
 
@@ -228,18 +267,20 @@ __device__ __forceinline__ u64 digit_peers(u64* tbl, u32 d, bool act) {
 // per-wave offsets -- prefix over waves within a digit, wave scan over 64 digits, and
 // a 4-entry prefix over digit groups applied at the scatter.
 template <typename K, int T, int ITEMS>
-__device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pad, int np) {
+__device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pad, int p_begin, int p_end) {
   constexpr int W = T / 64;
   const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const u64 ge = ~((1ull << lane) - 1ull);
-  for (u32 i = tid; i < W * 256; i += T) {
-    (&S.u.r.tbl[0][0])[i] = 0;
-    (&S.u.r.cnt[0][0][0])[i] = 0;
-    (&S.u.r.cnt[1][0][0])[i] = 0;
+  if (p_begin == 0) {
+    for (u32 i = tid; i < W * 256; i += T) {
+      (&S.u.r.tbl[0][0])[i] = 0;
+      (&S.u.r.cnt[0][0][0])[i] = 0;
+      (&S.u.r.cnt[1][0][0])[i] = 0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int per = (int)(n_pad / (64u * W));
-  for (int p = 0; p < np; ++p) {
+  for (int p = p_begin; p < p_end; ++p) {
     u32(*C)[256] = S.u.r.cnt[p & 1];
     K kr[ITEMS];
     u32 rk[ITEMS];
@@ -293,6 +334,40 @@ __device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pa
   }
 }
 
+// Counting needs equal keys adjacent, not ascending order (the survivors of all buckets
+// are sorted by key at the end).  After the LSD passes over the low `bits` bits the
+// keys are ordered by those bits, so equal keys already share one group of equal low
+// bits; if no two neighbours in [0, n) have equal low bits but different keys, every
+// such group holds one distinct key and each key's copies are contiguous.  Otherwise the
+// remaining passes complete the sort.  (Padding keys follow all real keys after any
+// number of passes: their digits are all 0xFF and the sort is stable.)
+__device__ __forceinline__ bool low_eq(u64 a, u64 b, int bits) { return ((a ^ b) & ((1ull << bits) - 1ull)) == 0; }
+__device__ __forceinline__ bool low_eq(k128 a, k128 b, int bits) { return low_eq(a.lo, b.lo, bits); }
+
+template <typename K>
+__device__ __forceinline__ bool mixed_pair(const K* keys, u32 idx, u32 n, int bits) {
+  if (idx == 0 || idx >= n) return false;
+  const K a = keys[idx], b = keys[idx - 1];
+  return low_eq(a, b, bits) && !key_eq(a, b);
+}
+
+// Block-wide: does any group of equal low bits hold two distinct keys?
+template <typename K, int T, int ITEMS>
+__device__ __forceinline__ bool mixed_groups(BucketSmem<K, T, ITEMS>& S, u32 n, int bits) {
+  bool bad = false;
+  for (u32 idx = threadIdx.x; idx < n; idx += T) bad |= mixed_pair(S.keys, idx, n, bits);
+  return __syncthreads_or(bad) != 0;
+}
+
+// Passes sorted first: 3 digits (24 bits) for up to 1536 keys, else 4 digits (32 bits),
+// so a bucket of D distinct mixed keys needs the remaining passes with probability
+// about D^2 / 2^25 (D <= 1536: under 7%) or D^2 / 2^33 (D <= 4096: 0.2%).  Keys of at
+// most 32 bits are sorted in full without mixing.
+__device__ __forceinline__ int first_passes(u32 n) { return n <= 1536u ? 3 : 4; }
+template <typename K> __device__ __forceinline__ int sort_passes(int k);
+template <> __device__ __forceinline__ int sort_passes<u64>(int k) { return 2 * k <= 32 ? (2 * k + 7) / 8 : 8; }
+template <> __device__ __forceinline__ int sort_passes<k128>(int k) { return (2 * k + 7) / 8; }
+
 // Run heads of the sorted keys[0, n) -> S.u.hp[0, nruns) in order.  Returns nruns.
 template <typename K, int T, int ITEMS>
 __device__ __forceinline__ u32 run_heads(BucketSmem<K, T, ITEMS>& S, u32 n) {
@@ -331,7 +406,8 @@ __device__ __forceinline__ u32 run_heads(BucketSmem<K, T, ITEMS>& S, u32 n) {
 // Block-wide (barriers inside).
 template <typename K>
 __device__ __forceinline__ u32 emit_runs_block(const K* keys, const u16* hp, u32 nruns, u32 n, bool final, u32 lo,
-                                               u32 hi, const RunSink& sink, K* dst_k, u32* dst_c, u64* scr) {
+                                               u32 hi, const RunSink& sink, K* dst_k, u32* dst_c, u64* scr,
+                                               bool mixed) {
   u32 kept = 0;
   for (u32 c0 = 0; c0 < nruns; c0 += blockDim.x) {
     const u32 r = c0 + threadIdx.x;
@@ -350,7 +426,7 @@ __device__ __forceinline__ u32 emit_runs_block(const K* keys, const u16* hp, u32
     u64 tot;
     const u64 ex = block_exclusive_scan<u64>(emit ? 1ull : 0ull, scr, &tot);
     if (emit) {
-      dst_k[kept + ex] = keys[s];
+      dst_k[kept + ex] = mixed ? unmix_key(keys[s]) : keys[s];
       dst_c[kept + ex] = c;
     }
     kept += (u32)tot;
@@ -378,7 +454,8 @@ __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
   }
   RunSink sink{S.hist_s, A.hist_len, A.hist, A.tot, &S.lmax, &lover};
   const u64 n_small = A.meta[0], n_chunks = A.meta[4];
-  const int np = (2 * A.k + 7) / 8;
+  const int np = sort_passes<K>(A.k);
+  const bool mixed = 2 * A.k > 32;
   u64 ndist = 0;
   K* skeys = reinterpret_cast<K*>(A.surv_k);
   const K* lkeys = reinterpret_cast<const K*>(A.lkeys);
@@ -391,7 +468,7 @@ __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
     if (chunk) {
       ks = A.chunk_start[item];
       n = min(A.chunk_len[item], (u32)CAP);
-      for (u32 i = tid; i < n; i += T) S.keys[i] = lkeys[ks + i];
+      for (u32 i = tid; i < n; i += T) S.keys[i] = mixed ? mix_key(lkeys[ks + i]) : lkeys[ks + i];
     } else {
       b = A.small_list[item - n_chunks];
       const u32 r0 = A.rec_off[b], nr = A.rec_off[b + 1] - r0;
@@ -405,7 +482,7 @@ __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
       u64 off = block_exclusive_scan<u64>(gsum, S.scr, &gall);
       for (u32 r = ra; r < rb; ++r) {
         const u32 g = record_g(A.rec, (u64)r0 + r, A.rec_words);
-        if (off + g <= (u64)CAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + off, g);
+        if (off + g <= (u64)CAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + off, g, mixed);
         off += g;
       }
     }
@@ -414,15 +491,18 @@ __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
     const u32 n_pad = (n + WB - 1) / WB * WB;
     for (u32 i = n + tid; i < n_pad; i += T) S.keys[i] = key_pad<K>();
     __syncthreads();
-    bucket_sort<K, T, ITEMS>(S, n_pad, np);
+    const int p0 = mixed ? first_passes(n) : np;
+    bucket_sort<K, T, ITEMS>(S, n_pad, 0, p0);
+    if (p0 < np && mixed_groups<K, T, ITEMS>(S, n, 8 * p0)) bucket_sort<K, T, ITEMS>(S, n_pad, p0, np);
     const u32 nruns = run_heads<K, T, ITEMS>(S, n);
     if (chunk) {
-      const u32 kept = emit_runs_block<K>(S.keys, S.u.hp, nruns, n, false, 0, 0, sink, klk + ks, A.kl_c + ks, S.scr);
+      const u32 kept =
+          emit_runs_block<K>(S.keys, S.u.hp, nruns, n, false, 0, 0, sink, klk + ks, A.kl_c + ks, S.scr, mixed);
       if (tid == 0) A.kl_cnt[item] = kept;
     } else {
       const u64 so = A.kall_off[b];
       const u32 kept = emit_runs_block<K>(S.keys, S.u.hp, nruns, n, true, A.min_freq, A.max_freq, sink, skeys + so,
-                                          A.surv_c + so, S.scr);
+                                          A.surv_c + so, S.scr, mixed);
       if (tid == 0) A.surv_cnt[b] = kept;
       ndist += nruns;
     }
@@ -448,12 +528,12 @@ struct WaveSmem {
 };
 
 template <typename K, int WCAP>
-__device__ __forceinline__ void wave_sort(WaveSmem<K, WCAP>& S, u32 n_pad, int np) {
+__device__ __forceinline__ void wave_sort(WaveSmem<K, WCAP>& S, u32 n_pad, int p_begin, int p_end) {
   constexpr int ITEMS = WCAP / 64;
   const u32 lane = lane_id();
   const u64 ge = ~((1ull << lane) - 1ull);
   const int per = (int)(n_pad / 64);
-  for (int p = 0; p < np; ++p) {
+  for (int p = p_begin; p < p_end; ++p) {
     K kr[ITEMS];
     u32 rk[ITEMS];
 #pragma unroll
@@ -507,7 +587,8 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
   RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax, &lover};
   WaveSmem<K, WCAP>& S = WS[wave];
   const u64 n_tiny = *n_tiny_ptr;
-  const int np = (2 * A.k + 7) / 8;
+  const int np = sort_passes<K>(A.k);
+  const bool mixed = 2 * A.k > 32;
   K* skeys = reinterpret_cast<K*>(A.surv_k);
   u64 ndist = 0;
   const u64 gw = (u64)blockIdx.x * WPB + wave, nw = (u64)gridDim.x * WPB;
@@ -526,12 +607,18 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
       const u32 g = r < nr ? record_g(A.rec, (u64)r0 + r, A.rec_words) : 0u;
       const u32 inc = wave_scan_u32(g);
       const u32 o = off + inc - g;
-      if (g && o + g <= (u32)WCAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + o, g);
+      if (g && o + g <= (u32)WCAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + o, g, mixed);
       off += (u32)__shfl((int)inc, 63, 64);
     }
     const u32 n_pad = (n + 63u) & ~63u;
     for (u32 i = n + lane; i < n_pad; i += 64) S.keys[i] = key_pad<K>();
-    wave_sort<K, WCAP>(S, n_pad, np);
+    const int p0 = mixed ? first_passes(n) : np;
+    wave_sort<K, WCAP>(S, n_pad, 0, p0);
+    if (p0 < np) {
+      bool bad = false;
+      for (u32 idx = lane; idx < n; idx += 64) bad |= mixed_pair(S.keys, idx, n, 8 * p0);
+      if (__ballot(bad) != 0) wave_sort<K, WCAP>(S, n_pad, p0, np);
+    }
     // run heads
     const int per = (int)((n + 63) / 64);
     u32 nruns = 0;
@@ -558,7 +645,7 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
       const u64 m = __ballot(emit);
       if (emit) {
         const u64 dst = so + kept + mbcnt64(m);
-        skeys[dst] = S.keys[s];
+        skeys[dst] = mixed ? unmix_key(S.keys[s]) : S.keys[s];
         A.surv_c[dst] = c;
       }
       kept += (u32)__popcll(m);

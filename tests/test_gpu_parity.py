@@ -63,6 +63,28 @@ def test_paths_and_bucket_counts(cfg, k):
     check(reads, offsets, k, 17, 2, 100, 1024, cfg=kc.make_config(**cfg), label=f"{cfg}")
 
 
+def _shared_low_bits_reads(seed, k, n_distinct, copies):
+    """Reads of exactly k bases 'A' + random + a fixed 12-base tail ending in 'A': the
+    forward value is canonical (first base A < T, the complement of the last), so every
+    key carries the same low 24 bits and only the remaining sort passes separate them."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tail = "CCGTACGTACGA"
+    seqs = []
+    for _ in range(n_distinct):
+        mid = "".join("ACGT"[c] for c in rng.integers(0, 4, k - 13))
+        seqs.extend(["A" + mid + tail] * int(rng.integers(1, copies + 1)))
+    order = rng.permutation(len(seqs))
+    return synth.from_strings([seqs[i] for i in order])
+
+
+@pytest.mark.parametrize("log2_buckets", [0, 2, 9])
+@pytest.mark.parametrize("k", [31, 51])
+def test_keys_sharing_low_bits(k, log2_buckets):
+    reads, offsets = _shared_low_bits_reads(900 + k, k, 6000, 4)
+    cfg = _kc().make_config(log2_buckets=log2_buckets)
+    check(reads, offsets, k, 15, 2, 3, 64, cfg, label=f"shared low bits k{k} log2_b={log2_buckets}")
+
+
 def test_long_reads_cross_spans():
     reads, offsets = _genome_reads(3, 12, 20000, 60000, genome=100000, p_sub=0.001, p_n=0.0, p_indel=0.0005)
     check(reads, offsets, 31, 21, 2, 200, 4096, label="long reads")
