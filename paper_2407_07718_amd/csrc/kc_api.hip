@@ -135,9 +135,9 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->log_c = std::min(9, p->log_b);
   p->log_f = p->log_b - p->log_c;
   p->rec_cap = std::max<u64>(1, n_max);
-  // each wave span of the extract stage owns `span` record slots; the slot region is
-  // sized for any m (span <= 16 * 63)
-  p->span = 16u * (u32)(64 - k + m);
+  // each wave span of the extract stage covers `span` k-mer positions (16 tiles of 64)
+  // and owns as many record slots
+  p->span = 16u * 64u;
   p->slots = R + 16 * 64;
   p->n_span_cap = (std::max<u64>(R, 1) + p->span - 1) / p->span;
   p->n_span_alloc = R / 32 + 2;

@@ -81,16 +81,35 @@ struct ExtractArgs {
   u64 n_span_cap;      // spans the record region holds
 };
 
-// Sliding minimum over `w` consecutive lanes: lane l gets min(v[l..l+w-1]).
-// Lanes with l + w > 64 get a partial minimum and must not be used.
-__device__ __forceinline__ u32 window_min(u32 v, int w) {
-  int len = 1;
+// Minimum of the last `w` scores ending at each lane, over a stream of 64-lane tiles: the
+// log-step doubling takes its lower neighbour from this tile where one exists and from
+// the previous tile otherwise.  `carry[j]` holds step j's rotated values of the previous
+// tile and is updated in place.  Lanes whose window reaches before the first tile of a
+// stream get garbage and must not be used.
+__device__ __forceinline__ u32 rot_up(u32 v, u32 d) {
+  return (u32)__shfl((int)v, (int)((lane_id() - d) & 63u), 64);
+}
+constexpr int WIN_STEPS = 5;   // w <= 63: doubling steps of 1, 2, 4, 8, 16, then the remainder
+
+__device__ __forceinline__ u32 window_min_carry(u32 v, int w, u32 (&carry)[WIN_STEPS], u32& carry_rest) {
+  const u32 lane = lane_id();
   u32 a = v;
-  while (len * 2 <= w) {
-    a = min(a, (u32)__shfl_down((int)a, len, 64));
-    len *= 2;
+  u32 len = 1;
+#pragma unroll
+  for (int j = 0; j < WIN_STEPS; ++j) {   // static indices: the carries stay in registers
+    if (2 * (int)len <= w) {
+      const u32 r = rot_up(a, len);
+      a = min(a, lane >= len ? r : carry[j]);
+      carry[j] = r;
+      len *= 2;
+    }
   }
-  if (w > len) a = min(a, (u32)__shfl_down((int)a, w - len, 64));
+  if ((u32)w > len) {
+    const u32 d = (u32)w - len;
+    const u32 r = rot_up(a, d);
+    a = min(a, lane >= d ? r : carry_rest);
+    carry_rest = r;
+  }
   return a;
 }
 
@@ -125,19 +144,23 @@ __device__ __forceinline__ void write_record(const ExtractArgs& A, u64 slot, u64
   }
 }
 
-// Each wave walks one span of window positions in tiles of 64 lanes.  Lane l of a tile
-// scores the canonical m-mer at position T0+l; the window minimum over w = k-m+1 lanes
-// then gives the minimizer score of the k-mer at T0+l for the first A = 64-w+1 lanes.
-// Runs of consecutive valid k-mers with the same bucket form supermers, cut every gmax
-// k-mers so that a record fits; a run still open at the tile's end is carried into the
-// next tile.  Paper: minimizer by lowest hash score with the destination from the same
-// hash (Section 3.2); the deque of the paper's sliding-window minimum (Section 3.2) is
-// replaced by a log-step minimum across lanes, which returns the same minimum score.
-__global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
+// Each wave walks one span of k-mer positions in tiles of 64 lanes.  Lane l of a tile
+// scores the canonical m-mer at position T0+l; the minimum of the last w = k-m+1 scores
+// (this tile's and, across the tile edge, the previous tile's) is the minimizer score of
+// the k-mer starting at T0+l-(w-1), so every lane of every tile but a span's first
+// yields a k-mer.  Runs of consecutive valid k-mers with the same bucket form
+// supermers, cut every gmax k-mers so that a record fits; a run still open at the
+// tile's end is carried into the next tile.  Paper: minimizer by lowest hash score with
+// the destination from the same hash (Section 3.2); the deque of the paper's
+// sliding-window minimum (Section 3.2) is replaced by a log-step minimum across lanes,
+// which returns the same minimum score.
+// (At most 102 VGPRs: five waves per SIMD measured fastest over k = 31 and 51.)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_extract(ExtractArgs A) {
   const u32 lane = lane_id();
   const u64 wave = (blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6;
   const u64 n_waves = ((u64)gridDim.x * blockDim.x) >> 6;
-  const int k = A.k, m = A.m, w = k - m + 1, adv = 64 - w + 1;
+  const int k = A.k, m = A.m, w = k - m + 1;
+  const u32 back = (u32)(w - 1);                 // k-mer position = m-mer position - back
   const u32 gmax = (u32)A.gmax;
   const u64 lo = A.n_reads ? min(A.offsets[0], A.R) : 0;
   const u64 hi = A.n_reads ? min(A.offsets[A.n_reads], A.R) : 0;
@@ -159,18 +182,22 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
     bool c_open = false;
     u32 c_b = 0, c_pos = 0;
     u64 c_p = 0;
-    for (u64 T0 = S0; T0 < S1; T0 += adv) {
-      const u64 q = T0 + lane;
+    u32 carry[WIN_STEPS], carry_rest = 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < WIN_STEPS; ++j) carry[j] = 0xFFFFFFFFu;
+    for (u64 T0 = S0; T0 < S1 + back; T0 += 64) {
+      const u64 q = T0 + lane;           // m-mer position
+      const u64 p = q - back;            // k-mer position (meaningful when q >= S0 + back)
       // canonical m-mer at q and its score
       u64 V = bases64(A.packed, q) & mmask;
       u64 F = rev2_64(V) >> (64 - 2 * m);
       u64 RC = ~V & mmask;
-      u32 sc = mmer_score(F < RC ? F : RC);
-      u32 mn = window_min(sc, w);
-      bool valid = (lane < (u32)adv) && (q < S1);
+      const u32 sc = mmer_score(F < RC ? F : RC);
+      const u32 mn = window_min_carry(sc, w, carry, carry_rest);
+      bool valid = (q >= S0 + back) && (p < S1);
       if (valid) {
-        u64 nb = bits64(A.nmask, q) & kmask1;
-        u64 sb = bits64(A.starts, q + 1) & kmask2;
+        u64 nb = bits64(A.nmask, p) & kmask1;
+        u64 sb = bits64(A.starts, p + 1) & kmask2;
         valid = (nb == 0) && (sb == 0);
       }
       const u32 b = mn & bmask;   // destination = score mod B (B a power of two)
@@ -190,7 +217,7 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
       const bool head = valid && (pm == 0);
       const int nv = __shfl_down((int)valid, 1, 64);
       const int nh = __shfl_down((int)head, 1, 64);
-      const bool close = valid && (lane < (u32)(adv - 1)) && (!nv || nh);
+      const bool close = valid && (lane < 63u) && (!nv || nh);
       const bool cont0 = __shfl((int)cont, 0, 64);
       const bool head0 = __shfl((int)head, 0, 64);
       const bool carry_close = c_open && !(cont0 && !head0);
@@ -202,17 +229,17 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
           const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
           write_record(A, base, c_p - cm, cm + 1, c_b);
         }
-        if (close) write_record(A, base + (carry_close ? 1 : 0) + mbcnt64(CL), q - pm, pm + 1, b);
+        if (close) write_record(A, base + (carry_close ? 1 : 0) + mbcnt64(CL), p - pm, pm + 1, b);
         written += n_close;
       }
       my_windows += (u64)__popcll(__ballot(valid));
-      // carry the window in the last tile lane
-      const int vl = __shfl((int)valid, adv - 1, 64);
+      // carry the window in the last lane
+      const int vl = __shfl((int)valid, 63, 64);
       c_open = vl != 0;
       if (c_open) {
-        c_b = (u32)__shfl((int)b, adv - 1, 64);
-        c_pos = (u32)__shfl((int)pos, adv - 1, 64);
-        c_p = T0 + (u64)(adv - 1);
+        c_b = (u32)__shfl((int)b, 63, 64);
+        c_pos = (u32)__shfl((int)pos, 63, 64);
+        c_p = T0 + 63 - back;
       }
     }
     if (c_open) {
