@@ -73,12 +73,12 @@ struct Plan {
   u64 chunk_cap = 0, kl_cap = 0;
   u64 R = 0, n_reads = 0, n_max = 0;   // bases, reads, bound on windows
   u64 rec_cap = 0, surv_cap = 0;
-  u64 slots = 0, n_span_cap = 0, n_span_alloc = 0;  // sparse record slots of the extract stage
+  u64 slots = 0, n_span_cap = 0;   // record slots of the extract blocks
   u32 span = 0;
   u32 nb_large = 1, nb_surv = 1;        // radix blocks
   // offsets into the workspace
   u64 o_packed, o_nmask, o_starts, o_X, o_Y, o_Z, o_bcnt, o_recoff, o_cursor, o_small, o_large,
-      o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_tot_large, o_tot_surv, o_bc, o_hp, o_spancnt, o_chstart, o_chlen,
+      o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_tot_large, o_tot_surv, o_bc, o_hp, o_blkcnt, o_chstart, o_chlen,
       o_tiny, o_kall, o_klcnt, o_kloff, o_scnt, o_soff, o_bsum, o_scanbuf, o_phist;
   int log_c = 0, log_f = 0;
   u32 part_nblk = 1, part_spb = 1;
@@ -114,7 +114,7 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->n_max = n_max;
   p->key_words = k <= 31 ? 1 : 2;
   p->rec_words = k <= 31 ? 4 : 8;
-  const int cap_bases = k <= 31 ? 61 : 125;
+  const int cap_bases = k <= 31 ? 51 : 115;   // record bits left after bucket and g
   p->gmax = std::min(64, cap_bases - k + 1);
   p->variant = (cfg && cfg->small_variant) ? cfg->small_variant : default_variant(p->key_words);
   if (p->variant > 2) return false;
@@ -135,14 +135,13 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->log_c = std::min(9, p->log_b);
   p->log_f = p->log_b - p->log_c;
   p->rec_cap = std::max<u64>(1, n_max);
-  // each wave span of the extract stage covers `span` k-mer positions (16 tiles of 64)
-  // and owns as many record slots
+  // each wave span of the extract stage covers `span` k-mer positions (16 tiles of 64);
+  // extract block b covers spans [b*spb, (b+1)*spb) and owns spb*span record slots
   p->span = 16u * 64u;
-  p->slots = R + 16 * 64;
   p->n_span_cap = (std::max<u64>(R, 1) + p->span - 1) / p->span;
-  p->n_span_alloc = R / 32 + 2;
-  p->part_nblk = (u32)std::min<u64>(8192, std::max<u64>(1, p->n_span_cap));
-  p->part_spb = (u32)((p->n_span_cap + p->part_nblk - 1) / p->part_nblk);
+  p->part_spb = (u32)std::max<u64>(1, ceil_div(p->n_span_cap, 2048));
+  p->part_nblk = (u32)ceil_div(p->n_span_cap, p->part_spb);
+  p->slots = (u64)p->part_nblk * p->part_spb * p->span;
   (void)min_freq;
   p->surv_cap = std::max<u64>(1, n_max);   // survivors sit at their bucket's k-mer slots first
   const u64 w = 8ull * p->key_words;
@@ -165,16 +164,16 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_nmask = take(4 * p->n_mask);
   p->o_starts = take(4 * p->n_mask);
   // Three large regions whose contents rotate as the stages retire them:
-  //   X: span record slots + bucket ids (extract)  -> records in bucket order (fine
-  //      partition, read by the sorts) -> first buffer of the chunk-list sort
-  //   Y: records grouped by coarse digit + bucket ids (partition) -> large-bucket keys,
+  //   X: extract block record slots -> records in bucket order (fine partition, read
+  //      by the sorts) -> first buffer of the chunk-list sort
+  //   Y: records grouped by coarse digit (partition) -> large-bucket keys,
   //      overwritten in place by the chunk lists, + list counts -> second sort buffer
   //   Z: survivors at their bucket's k-mer slots -> second buffer of the survivor sort
   // The final dense survivors use whichever of X / Y the chunk-list sort left free.
-  p->o_X = take(std::max(std::max((rb + 4) * p->slots, rb * N), (w + 4) * N));
-  p->o_Y = take(std::max((rb + 4) * N, (w + 4) * N));
+  p->o_X = take(std::max(std::max(rb * p->slots, rb * N), (w + 4) * N));
+  p->o_Y = take(std::max(rb * N, (w + 4) * N));
   p->o_Z = take((w + 4) * N);
-  p->o_spancnt = take(4 * p->n_span_alloc);
+  p->o_blkcnt = take(4ull * p->part_nblk);
   p->o_bcnt = take(8ull * p->B);
   p->o_recoff = take(4ull * (p->B + 1));
   p->o_cursor = take(4ull * p->B);
@@ -322,10 +321,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u32* packed = at<u32>(ws, P.o_packed);
   u32* nmask = at<u32>(ws, P.o_nmask);
   u32* starts = at<u32>(ws, P.o_starts);
-  u32* recA = reinterpret_cast<u32*>(X);                       // span slots
-  u32* bid = reinterpret_cast<u32*>(X + RB * P.slots);
+  u32* recA = reinterpret_cast<u32*>(X);                       // extract block slots
   u32* ptmp_rec = reinterpret_cast<u32*>(Y);                   // coarse partition
-  u32* ptmp_bid = reinterpret_cast<u32*>(Y + RB * N);
   u32* recB = reinterpret_cast<u32*>(X);                       // bucket order
   K* lk0 = reinterpret_cast<K*>(Y);                            // large keys -> chunk lists
   u32* klsc = reinterpret_cast<u32*>(Y + WK * N);
@@ -354,7 +351,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u32* cnt_surv = at<u32>(ws, P.o_cnt_surv);
   u32* tot_large = at<u32>(ws, P.o_tot_large);
   u32* tot_surv = at<u32>(ws, P.o_tot_surv);
-  u32* spancnt = at<u32>(ws, P.o_spancnt);
+  u32* blkcnt = at<u32>(ws, P.o_blkcnt);
   u64* chstart = at<u64>(ws, P.o_chstart);
   u32* chlen = at<u32>(ws, P.o_chlen);
   u32* bc = at<u32>(ws, P.o_bc);
@@ -378,7 +375,6 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   fill(d_hist, 2ull * hist_len);
   fill(d_tot, sizeof(DevTotals) / 4);
   fill(starts, P.n_mask);
-  fill(spancnt, P.n_span_cap);
   fill(scnt, P.B);
   const u64 n32 = ceil_div(P.R, 32);
   fill(packed + 2 * n32, P.n_packed - 2 * n32);
@@ -403,37 +399,38 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ea.gmax_magic = (u32)(((1ull << 32) + (u64)P.gmax - 1) / (u64)P.gmax);
   ea.rec_words = P.rec_words;
   ea.span = P.span;
+  ea.spb = P.part_spb;
+  ea.blk_slots = (u64)P.part_spb * P.span;
   ea.rec = recA;
-  ea.bid = bid;
-  ea.span_cnt = spancnt;
+  ea.blk_cnt = blkcnt;
+  ea.hist = at<u32>(ws, P.o_phist);
+  ea.log_f = P.log_f;
+  ea.C = 1u << P.log_c;
   ea.counters = counters;
   ea.n_span_cap = P.n_span_cap;
-  const u64 n_spans = P.n_span_cap;
   stage_mark(1, st);
-  hipLaunchKernelGGL(k_extract, grid_for(n_spans, 4, 8192), dim3(256), 0, st, ea);
+  hipLaunchKernelGGL(k_extract, dim3(P.part_nblk), dim3(256), 0, st, ea);
   stage_mark(2, st);
   {
     PartArgs pp;
     pp.rec = recA;
-    pp.bid = bid;
-    pp.span_cnt = spancnt;
-    pp.n_span = P.n_span_cap;
-    pp.span = P.span;
-    pp.spb = P.part_spb;
+    pp.blk_cnt = blkcnt;
+    pp.blk_slots = ea.blk_slots;
     pp.nblk = P.part_nblk;
     pp.log_c = P.log_c;
     pp.log_f = P.log_f;
     pp.rec_words = P.rec_words;
-    pp.hist = at<u32>(ws, P.o_phist);
+    pp.hist = ea.hist;
     pp.tmp_rec = ptmp_rec;
-    pp.tmp_bid = ptmp_bid;
     pp.rec_out = recB;
     pp.bcnt = bcnt;
     pp.n_rec_ptr = counters;
     const u64 nh = ((u64)1 << P.log_c) * P.part_nblk;
-    hipLaunchKernelGGL(k_part_coarse<false>, dim3(P.part_nblk), dim3(256), 0, st, pp);
-    scan_u32(pp.hist, pp.hist, (const u64*)nullptr, nh, (u64*)nullptr, scanbuf, st);
-    hipLaunchKernelGGL(k_part_coarse<true>, dim3(P.part_nblk), dim3(256), 0, st, pp);
+    scan_u32(ea.hist, ea.hist, (const u64*)nullptr, nh, (u64*)nullptr, scanbuf, st);
+    if (P.rec_words == 4)
+      hipLaunchKernelGGL(k_part_scatter<4>, dim3(P.part_nblk), dim3(512), 0, st, pp);
+    else
+      hipLaunchKernelGGL(k_part_scatter<8>, dim3(P.part_nblk), dim3(512), 0, st, pp);
     hipLaunchKernelGGL(k_part_fine, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
   }
   {

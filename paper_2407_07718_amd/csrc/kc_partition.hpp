@@ -73,10 +73,14 @@ struct ExtractArgs {
   u64 n_reads, R;
   int k, m, log_b, gmax, rec_words;
   u32 gmax_magic;      // ceil(2^32 / gmax)
-  u32 span;            // k-mer windows per wave span (a multiple of the tile advance)
-  u32* rec;            // records of span s at slots [s*span, s*span + span_cnt[s])
-  u32* bid;            // bucket of each record slot
-  u32* span_cnt;       // records written per span
+  u32 span;            // k-mer positions per wave span (16 tiles of 64)
+  u32 spb;             // spans per block: block b covers spans [b*spb, (b+1)*spb)
+  u64 blk_slots;       // record slots per block (spb * span)
+  u32* rec;            // records of block b at slots [b*blk_slots, b*blk_slots + blk_cnt[b])
+  u32* blk_cnt;        // records written per block
+  u32* hist;           // [C][nblk] records per coarse bucket group and block
+  int log_f;           // coarse group = bucket >> log_f
+  u32 C;               // coarse groups
   u64* counters;       // [0] records written, [1] valid windows
   u64 n_span_cap;      // spans the record region holds
 };
@@ -113,8 +117,13 @@ __device__ __forceinline__ u32 window_min_carry(u32 v, int w, u32 (&carry)[WIN_S
   return a;
 }
 
-// A supermer record holds its bases, two bits each from bit 0, and (g - 1) in the top
-// six bits, g being the number of k-mers it carries.
+// A supermer record (16 bytes for k <= 31, 32 bytes for k >= 32) holds its bases, two
+// bits each from bit 0 (at most 51 / 115 bases), its bucket in 20 bits and (g - 1) in the
+// top six bits, g being the number of k-mers it carries.  In the record's last 32-bit
+// word: bits 26..31 = g - 1, bits 6..25 = bucket, bits 0..5 = bases.
+constexpr int REC_BUCKET_SHIFT = 38;   // within the record's top 64-bit word
+__device__ __forceinline__ u32 rec_last_bucket(u32 last_word) { return (last_word >> 6) & 0xFFFFFu; }
+
 __device__ __forceinline__ void write_record(const ExtractArgs& A, u64 slot, u64 start, u32 g, u32 bucket) {
   {
     const u32 nb2 = 2u * (g + (u32)A.k - 1u);       // bits of bases
@@ -122,7 +131,7 @@ __device__ __forceinline__ void write_record(const ExtractArgs& A, u64 slot, u64
       u64 w0 = bases64(A.packed, start), w1 = bases64(A.packed, start + 32);
       if (nb2 < 64) { w0 &= (1ull << nb2) - 1; w1 = 0; }
       else { u32 r = nb2 - 64; w1 = r ? (w1 & ((1ull << r) - 1)) : 0; }
-      w1 |= (u64)(g - 1) << 58;
+      w1 |= ((u64)(g - 1) << 58) | ((u64)bucket << REC_BUCKET_SHIFT);
       uint4 v = make_uint4((u32)w0, (u32)(w0 >> 32), (u32)w1, (u32)(w1 >> 32));
       reinterpret_cast<uint4*>(A.rec)[slot] = v;
     } else {
@@ -135,12 +144,11 @@ __device__ __forceinline__ void write_record(const ExtractArgs& A, u64 slot, u64
         if (rem <= 0) w[i] = 0;
         else if (rem < 64) w[i] &= (1ull << rem) - 1;
       }
-      w[3] |= (u64)(g - 1) << 58;
+      w[3] |= ((u64)(g - 1) << 58) | ((u64)bucket << REC_BUCKET_SHIFT);
       uint4* dst = reinterpret_cast<uint4*>(A.rec) + 2 * slot;
       dst[0] = make_uint4((u32)w[0], (u32)(w[0] >> 32), (u32)w[1], (u32)(w[1] >> 32));
       dst[1] = make_uint4((u32)w[2], (u32)(w[2] >> 32), (u32)w[3], (u32)(w[3] >> 32));
     }
-    A.bid[slot] = bucket;
   }
 }
 
@@ -154,11 +162,17 @@ __device__ __forceinline__ void write_record(const ExtractArgs& A, u64 slot, u64
 // the destination from the same hash (Section 3.2); the deque of the paper's
 // sliding-window minimum (Section 3.2) is replaced by a log-step minimum across lanes,
 // which returns the same minimum score.
+// Block b covers spans [b*spb, (b+1)*spb), its four waves taking them in turn; its records
+// go densely to the block's slot range through an LDS counter, and an LDS histogram of
+// their coarse bucket groups feeds the partition.
 // (At most 102 VGPRs: five waves per SIMD measured fastest over k = 31 and 51.)
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_extract(ExtractArgs A) {
+  __shared__ u32 h[512];
+  __shared__ u32 blk_n;
   const u32 lane = lane_id();
-  const u64 wave = (blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6;
-  const u64 n_waves = ((u64)gridDim.x * blockDim.x) >> 6;
+  for (u32 i = threadIdx.x; i < 512; i += blockDim.x) h[i] = 0;
+  if (threadIdx.x == 0) blk_n = 0;
+  __syncthreads();
   const int k = A.k, m = A.m, w = k - m + 1;
   const u32 back = (u32)(w - 1);                 // k-mer position = m-mer position - back
   const u32 gmax = (u32)A.gmax;
@@ -173,12 +187,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   u64 my_windows = 0;
 
   const u64 n_sp = min(n_spans, A.n_span_cap);
-  u64 my_records = 0;
-  for (u64 s = wave; s < n_sp; s += n_waves) {
+  const u64 s_end = min(n_sp, (u64)(blockIdx.x + 1) * A.spb);
+  const u64 slot0 = (u64)blockIdx.x * A.blk_slots;   // records of this block: slot0 + [0, blk_n)
+  for (u64 s = (u64)blockIdx.x * A.spb + (threadIdx.x >> 6); s < s_end; s += blockDim.x >> 6) {
     const u64 S0 = lo + s * A.span;
     const u64 S1 = min(S0 + A.span, lo + n_pos);
-    const u64 slot0 = s * (u64)A.span;   // records of this span: slot0 + [0, written)
-    u32 written = 0;
     bool c_open = false;
     u32 c_b = 0, c_pos = 0;
     u64 c_p = 0;
@@ -224,13 +237,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       const u64 CL = __ballot(close);
       const u32 n_close = (u32)__popcll(CL) + (carry_close ? 1u : 0u);
       if (n_close) {
-        const u64 base = slot0 + written;
+        u32 at = 0;
+        if (lane == 0) at = atomicAdd(&blk_n, n_close);
+        const u64 base = slot0 + (u32)__shfl((int)at, 0, 64);
         if (carry_close && lane == 0) {
           const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
           write_record(A, base, c_p - cm, cm + 1, c_b);
+          atomicAdd(&h[c_b >> A.log_f], 1u);
         }
-        if (close) write_record(A, base + (carry_close ? 1 : 0) + mbcnt64(CL), p - pm, pm + 1, b);
-        written += n_close;
+        if (close) {
+          write_record(A, base + (carry_close ? 1 : 0) + mbcnt64(CL), p - pm, pm + 1, b);
+          atomicAdd(&h[b >> A.log_f], 1u);
+        }
       }
       my_windows += (u64)__popcll(__ballot(valid));
       // carry the window in the last lane
@@ -242,18 +260,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         c_p = T0 + 63 - back;
       }
     }
-    if (c_open) {
-      if (lane == 0) {
-        const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
-        write_record(A, slot0 + written, c_p - cm, cm + 1, c_b);
-      }
-      ++written;
+    if (c_open && lane == 0) {
+      const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
+      write_record(A, slot0 + atomicAdd(&blk_n, 1u), c_p - cm, cm + 1, c_b);
+      atomicAdd(&h[c_b >> A.log_f], 1u);
     }
-    if (lane == 0) A.span_cnt[s] = written;
-    my_records += written;
   }
   if (lane == 0 && my_windows) atomicAdd((unsigned long long*)&A.counters[1], (unsigned long long)my_windows);
-  if (lane == 0 && my_records) atomicAdd((unsigned long long*)&A.counters[0], (unsigned long long)my_records);
+  __syncthreads();
+  for (u32 i = threadIdx.x; i < A.C; i += blockDim.x) A.hist[(u64)i * gridDim.x + blockIdx.x] = h[i];
+  if (threadIdx.x == 0) {
+    A.blk_cnt[blockIdx.x] = blk_n;
+    if (blk_n) atomicAdd((unsigned long long*)&A.counters[0], (unsigned long long)blk_n);
+  }
 }
 
 // ---------------------------------------------------------------------------- bucket plan
@@ -391,25 +410,21 @@ __global__ __launch_bounds__(PLAN_T) void k_plan_write(PlanArgs P) {
 }
 
 // ---------------------------------------------------------------------------- partition
-// Records move from their extract-span slots into bucket order in two passes with no
-// global atomics: a coarse pass on the top log_c bits of the bucket (per-block LDS
-// histograms, one device-wide scan, a scatter with LDS cursors) and a fine pass, one
-// block per coarse group, that counts records and k-mers per bucket in LDS, writes the
-// bucket table and places each record in its bucket.  Order inside a bucket is free:
-// the bucket is sorted afterwards.
+// Records move from the extract blocks' slots into bucket order in two passes with no
+// global atomics: a coarse pass on the top log_c bits of the bucket (the extract blocks'
+// LDS histograms, one device-wide scan, a scatter staged through LDS) and a fine pass,
+// one block per coarse group, that counts records and k-mers per bucket in LDS, writes
+// the bucket table and places each record in its bucket.  Order inside a bucket is
+// free: the bucket is sorted afterwards.
 struct PartArgs {
-  const u32* rec;          // span slots
-  const u32* bid;
-  const u32* span_cnt;
-  u64 n_span;              // spans
-  u32 span;                // slots per span
-  u32 spb;                 // spans per coarse-pass block
-  u32 nblk;                // coarse-pass blocks
+  const u32* rec;          // block record slots of the extract stage
+  const u32* blk_cnt;      // records per extract block
+  u64 blk_slots;           // slots per extract block
+  u32 nblk;                // extract blocks
   int log_c, log_f;        // bucket = (coarse << log_f) | fine
   int rec_words;
-  u32* hist;               // [C][nblk] counts -> offsets (digit-major)
-  u32* tmp_rec;            // records grouped by coarse digit
-  u32* tmp_bid;
+  const u32* hist;         // [C][nblk] counts, scanned to offsets (group-major)
+  u32* tmp_rec;            // records grouped by coarse group
   u32* rec_out;            // records in bucket order
   u64* bcnt;               // per bucket: (records << 32) | k-mers
   const u64* n_rec_ptr;    // records in total
@@ -427,37 +442,75 @@ __device__ __forceinline__ void copy_record(const u32* __restrict__ src, u64 i, 
   }
 }
 
-template <bool SCATTER>
-__global__ __launch_bounds__(256) void k_part_coarse(PartArgs P) {
-  __shared__ u32 h[512];
-  const u32 C = 1u << P.log_c;
-  const u32 wave = threadIdx.x >> 6, lane = lane_id();
-  for (u32 i = threadIdx.x; i < C; i += 256) h[i] = SCATTER ? P.hist[(u64)i * P.nblk + blockIdx.x] : 0u;
+// Coarse pass: each block moves one extract block's records into their coarse groups.
+// Rounds of R records are ranked per group in LDS, staged in group order and written
+// out so that consecutive threads write consecutive slots of a group's range (this
+// block's offset in every group comes from the scanned extract histogram).
+template <int RW>
+__global__ __launch_bounds__(512) void k_part_scatter(PartArgs P) {
+  constexpr u32 T = 512, Q = RW / 4;              // uint4 per record
+  constexpr u32 R = RW == 4 ? 4096u : 2048u;      // records staged per round (64 KB)
+  constexpr u32 IT = R / T;
+  __shared__ uint4 stage[R * Q];
+  __shared__ u32 cnt[512], lbase[512], gpos[512];
+  __shared__ u64 scr[17];
+  const u32 C = 1u << P.log_c, tid = threadIdx.x, blk = blockIdx.x;
+  const u32 total = P.blk_cnt[blk];
+  const uint4* src = reinterpret_cast<const uint4*>(P.rec) + (u64)blk * P.blk_slots * Q;
+  uint4* dst = reinterpret_cast<uint4*>(P.tmp_rec);
+  for (u32 c = tid; c < 512; c += T) {
+    cnt[c] = 0;
+    gpos[c] = c < C ? P.hist[(u64)c * P.nblk + blk] : 0u;
+  }
   __syncthreads();
-  const u64 s0 = (u64)blockIdx.x * P.spb;
-  const u64 s1 = min(P.n_span, s0 + P.spb);
-  for (u64 sp = s0 + wave; sp < s1; sp += 4) {
-    const u32 cnt = P.span_cnt[sp];
-    for (u32 j = lane; j < cnt; j += 64) {
-      const u64 i = sp * (u64)P.span + j;
-      const u32 b = P.bid[i];
-      const u32 c = b >> P.log_f;
-      if (SCATTER) {
-        const u32 pos = atomicAdd(&h[c], 1u);
-        copy_record(P.rec, i, P.tmp_rec, pos, P.rec_words);
-        P.tmp_bid[pos] = b;
-      } else {
-        atomicAdd(&h[c], 1u);
+  for (u32 r0 = 0; r0 < total; r0 += R) {
+    const u32 nr = min(R, total - r0);
+    // all loads first (they overlap), then the ranks
+    uint4 rec[IT * Q];
+    u32 cc[IT], rk[IT];
+#pragma unroll
+    for (u32 j = 0; j < IT; ++j) {
+      const u32 i = tid + j * T;
+#pragma unroll
+      for (u32 q = 0; q < Q; ++q)
+        rec[j * Q + q] = i < nr ? src[(u64)(r0 + i) * Q + q] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (u32 j = 0; j < IT; ++j) {
+      if (tid + j * T < nr) {
+        cc[j] = rec_last_bucket(rec[j * Q + Q - 1].w) >> P.log_f;
+        rk[j] = atomicAdd(&cnt[cc[j]], 1u);
       }
     }
-  }
-  if (!SCATTER) {
     __syncthreads();
-    for (u32 i = threadIdx.x; i < C; i += 256) P.hist[(u64)i * P.nblk + blockIdx.x] = h[i];
+    u64 tot;
+    const u32 ex = (u32)block_exclusive_scan<u64>(tid < C ? (u64)cnt[tid] : 0ull, scr, &tot);
+    if (tid < C) lbase[tid] = ex;
+    __syncthreads();
+#pragma unroll
+    for (u32 j = 0; j < IT; ++j) {
+      if (tid + j * T < nr) {
+#pragma unroll
+        for (u32 q = 0; q < Q; ++q) stage[(lbase[cc[j]] + rk[j]) * Q + q] = rec[j * Q + q];
+      }
+    }
+    __syncthreads();
+    for (u32 i = tid; i < nr; i += T) {
+      const u32 c = rec_last_bucket(stage[i * Q + Q - 1].w) >> P.log_f;
+      const u64 d = (u64)gpos[c] + (i - lbase[c]);
+#pragma unroll
+      for (u32 q = 0; q < Q; ++q) dst[d * Q + q] = stage[i * Q + q];
+    }
+    __syncthreads();
+    if (tid < C) {
+      gpos[tid] += cnt[tid];
+      cnt[tid] = 0;
+    }
+    __syncthreads();
   }
 }
 
-// One block per coarse group c: records [start(c), start(c+1)) of tmp.
+// Fine pass: one block per coarse group c, records [start(c), start(c+1)) of tmp.
 __global__ __launch_bounds__(1024) void k_part_fine(PartArgs P) {
   __shared__ u32 cr[2048], ck[2048], cur[2048];
   __shared__ u64 scr[17];
@@ -465,16 +518,17 @@ __global__ __launch_bounds__(1024) void k_part_fine(PartArgs P) {
   const u64 n_rec = *P.n_rec_ptr;
   const u64 g0 = P.hist[(u64)c * P.nblk];
   const u64 g1 = (c + 1 < C) ? (u64)P.hist[(u64)(c + 1) * P.nblk] : n_rec;
+  const int rw = P.rec_words;
   for (u32 i = threadIdx.x; i < F; i += T) {
     cr[i] = 0;
     ck[i] = 0;
   }
   __syncthreads();
   for (u64 i = g0 + threadIdx.x; i < g1; i += T) {
-    const u32 f = P.tmp_bid[i] & (F - 1);
-    const u32 g = (P.tmp_rec[i * (u64)P.rec_words + P.rec_words - 1] >> 26) + 1u;
+    const u32 last = P.tmp_rec[i * (u64)rw + rw - 1];
+    const u32 f = rec_last_bucket(last) & (F - 1);
     atomicAdd(&cr[f], 1u);
-    atomicAdd(&ck[f], g);
+    atomicAdd(&ck[f], (last >> 26) + 1u);
   }
   __syncthreads();
   // exclusive prefix of the record counts over the F buckets of the group
@@ -491,8 +545,8 @@ __global__ __launch_bounds__(1024) void k_part_fine(PartArgs P) {
   }
   __syncthreads();
   for (u64 i = g0 + threadIdx.x; i < g1; i += T) {
-    const u32 f = P.tmp_bid[i] & (F - 1);
+    const u32 f = rec_last_bucket(P.tmp_rec[i * (u64)rw + rw - 1]) & (F - 1);
     const u32 pos = atomicAdd(&cur[f], 1u);
-    copy_record(P.tmp_rec, i, P.rec_out, pos, P.rec_words);
+    copy_record(P.tmp_rec, i, P.rec_out, pos, rw);
   }
 }
