@@ -22,6 +22,7 @@
 #include "kc_count.hpp"
 #include "kc_partition.hpp"
 #include "kc_sort.hpp"
+#include "kc_segsort.hpp"
 
 namespace {
 
@@ -79,7 +80,7 @@ struct Plan {
   // offsets into the workspace
   u64 o_packed, o_nmask, o_starts, o_X, o_Y, o_Z, o_bcnt, o_recoff, o_cursor, o_small, o_large,
       o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_tot_large, o_tot_surv, o_bc, o_hp, o_blkcnt, o_chstart, o_chlen,
-      o_tiny, o_kall, o_klcnt, o_kloff, o_scnt, o_soff, o_bsum, o_scanbuf, o_phist;
+      o_tiny, o_kall, o_klcnt, o_kloff, o_scnt, o_soff, o_bsum, o_scanbuf, o_phist, o_lch0, o_seg, o_mhist;
   int log_c = 0, log_f = 0;
   u32 part_nblk = 1, part_spb = 1;
   u64 n_packed, n_mask, bytes = 0;
@@ -95,7 +96,8 @@ enum Ctrl : int {
   C_SURV_NC = 13,   // survivors, clamped to capacity
   C_KL_N = 14,      // (k-mer, count) list entries
   C_KL_NC = 15,     // ... clamped to capacity
-  C_WORDS = 16
+  C_NSEG = 16,      // key ranges of the survivors
+  C_WORDS = 17
 };
 static_assert(C_META + 8 <= C_FLAGS, "meta overlaps the flags");
 
@@ -198,6 +200,9 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_bsum = take(8ull * PLAN_Q * (p->B / PLAN_BLOCK + 1));
   p->o_scanbuf = take(8ull * 1024);
   p->o_phist = take(4ull * ((u64)1 << p->log_c) * p->part_nblk);
+  p->o_lch0 = take(4ull * p->B);
+  p->o_seg = take(8ull * (std::max<u64>(p->B, (u64)256 << 8) + 2));
+  p->o_mhist = take(4ull * 256 * MSD_NB);
   p->bytes = o;
   return true;
 }
@@ -307,6 +312,31 @@ inline dim3 grid_for(u64 n, u32 block, u32 max_blocks = 1u << 20) {
 }
 
 // Queue one full count on `st`.
+constexpr u32 SEG_CAP_64 = 256 * 16, SEG_CAP_128 = 256 * 8;   // pairs sorted on chip per segment
+
+template <typename K>
+int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64 out_cap, const u64* seg,
+             const u64* n_seg, int nbits, int n_cu, hipStream_t st, int* grid) {
+  constexpr int IT = sizeof(K) == 8 ? 16 : 8;
+  static_assert(256 * IT == (sizeof(K) == 8 ? SEG_CAP_64 : SEG_CAP_128), "segment capacity");
+  int per_cu = 0, rc;
+  if ((rc = blocks_per_cu(k_seg_sort<K, 256, IT>, 256, &per_cu))) return rc;
+  *grid = std::max(1, per_cu) * n_cu;
+  SegArgs a;
+  a.keys = keys;
+  a.vals = vals;
+  a.tmp_k = tmp_k;
+  a.tmp_v = tmp_v;
+  a.out_k = out_k;
+  a.out_v = out_v;
+  a.out_cap = out_cap;
+  a.seg = seg;
+  a.n_seg_ptr = n_seg;
+  a.nbits = nbits;
+  hipLaunchKernelGGL((k_seg_sort<K, 256, IT>), dim3(*grid), dim3(256), 0, st, a);
+  return KC_OK;
+}
+
 template <typename K>
 int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_offsets, uint32_t lo, uint32_t hi,
             uint64_t hist_len, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap, uint64_t* d_hist,
@@ -435,7 +465,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   }
   {
     PlanArgs pa{bcnt, P.B, P.cap_tiny, P.cap, P.cap_chunk, bsum, tiny, recoff, cursor, small, large, lkoff, chstart,
-                chlen, P.chunk_cap, kall, meta};
+                chlen, P.chunk_cap, kall, meta, at<u32>(ws, P.o_lch0)};
     const u32 nbp = (P.B + PLAN_BLOCK - 1) / PLAN_BLOCK;
     hipLaunchKernelGGL(k_plan_reduce, dim3(nbp), dim3(PLAN_T), 0, st, pa);
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, st, pa, nbp);
@@ -498,13 +528,17 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.chunk_cap, 4, 4096), dim3(256), 0, st, lk0, klsc, chstart,
                      (const u64*)nullptr, 0u, klcnt, kloff, meta + 4, P.chunk_cap, kl0k, kl0c);
   hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, kl_n, P.kl_cap, kl_nc);
-  bool second = false;
-  rc = radix_sort<K, true>(kl0k, kl1k, kl0c, kl1c, kl_nc, cnt_large, tot_large, P.nb_large, 2 * P.k, st, &second);
-  if (rc) return rc;
-  K* lks = second ? kl1k : kl0k;
-  u32* lvs = second ? kl1c : kl0c;
-  K* fk = second ? kl0k : kl1k;     // the free buffer holds the merged runs' survivors
-  u32* fc = second ? kl0c : kl1c;
+  // each heavy bucket's lists are one segment, sorted on its own (in place)
+  u64* seg = at<u64>(ws, P.o_seg);
+  hipLaunchKernelGGL(k_merge_segs, grid_for(P.B + 1, 256, 1024), dim3(256), 0, st, kloff, at<u32>(ws, P.o_lch0), meta + 1,
+                     meta + 4, P.chunk_cap, kl_nc, seg);
+  int seg_grid = 0;
+  if ((rc = seg_sort<K>(kl0k, kl0c, kl1k, kl1c, kl0k, kl0c, ~0ull, seg, meta + 1, 2 * P.k, n_cu, st, &seg_grid)))
+    return rc;
+  K* lks = kl0k;
+  u32* lvs = kl0c;
+  K* fk = kl1k;                      // the free buffer holds the merged runs' survivors
+  u32* fc = kl1c;
   K* s1k = lks;                      // dense survivors go where the sorted lists were
   u32* s1c = lvs;
   hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc);
@@ -521,12 +555,29 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   hipLaunchKernelGGL((k_gather_segments<K>), grid_for(RUN_BLOCKS, 4, 4096), dim3(256), 0, st, fk, fc, (const u64*)nullptr,
                      nruns, RUN_BLOCKS, scnt + P.B, soff + P.B, (const u64*)nullptr, (u64)RUN_BLOCKS, s1k, s1c);
   hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, surv_n, P.surv_cap, surv_nc);
-  rc = radix_sort<K, true>(s1k, s0k, s1c, s0c, surv_nc, cnt_surv, tot_surv, P.nb_surv, 2 * P.k, st, &second);
-  if (rc) return rc;
-  K* ok = second ? s0k : s1k;
-  u32* oc = second ? s0c : s1c;
-  hipLaunchKernelGGL((k_copy_pairs<K>), grid_for(P.surv_cap, 256, 4096), dim3(256), 0, st, ok, oc, surv_nc, pair_cap,
-                     reinterpret_cast<K*>(d_kmers), d_counts);
+  // key ranges by the top bits (s1 -> s0 -> s1), then each range sorted into the output
+  {
+    MsdArgs ma;
+    ma.in_k = s1k;
+    ma.in_v = s1c;
+    ma.n_ptr = surv_nc;
+    ma.mid_k = s0k;
+    ma.mid_v = s0c;
+    ma.out_k = s1k;
+    ma.out_v = s1c;
+    ma.hist = at<u32>(ws, P.o_mhist);
+    ma.seg = seg;
+    ma.n_seg = ctrl + C_NSEG;
+    ma.nbits = 2 * P.k;
+    ma.target = (P.key_words == 1 ? SEG_CAP_64 : SEG_CAP_128) / 2;
+    hipLaunchKernelGGL((k_msd_hist<K>), dim3(MSD_NB), dim3(256), 0, st, ma);
+    scan_u32(ma.hist, ma.hist, (const u64*)nullptr, 256ull * MSD_NB, (u64*)nullptr, scanbuf, st);
+    hipLaunchKernelGGL((k_msd_scatter<K>), dim3(MSD_NB), dim3(512), 0, st, ma);
+    hipLaunchKernelGGL((k_msd_fine<K>), dim3(256), dim3(1024), 0, st, ma);
+  }
+  if ((rc = seg_sort<K>(s1k, s1c, s0k, s0c, reinterpret_cast<K*>(d_kmers), d_counts, pair_cap, seg, ctrl + C_NSEG,
+                        2 * P.k, n_cu, st, &seg_grid)))
+    return rc;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags);
   hipLaunchKernelGGL(k_totals_meta, dim3(1), dim3(64), 0, st, d_tot, meta, kl_n, P.B);
   stage_mark(8, st);
@@ -547,6 +598,8 @@ int warm_launch_facts() {
   if ((rc = blocks_per_cu(k_wave_sort_count<u64, WAVE_CAP_64, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v))) return rc;
   if ((rc = blocks_per_cu(k_wave_sort_count<k128, WAVE_CAP_128, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v)))
     return rc;
+  if ((rc = blocks_per_cu(k_seg_sort<u64, 256, 16>, 256, &v))) return rc;
+  if ((rc = blocks_per_cu(k_seg_sort<k128, 256, 8>, 256, &v))) return rc;
   return KC_OK;
 }
 

@@ -261,42 +261,54 @@ __device__ __forceinline__ u64 digit_peers(u64* tbl, u32 d, bool act) {
   return act ? tbl[d] : 0ull;
 }
 
-// LSD radix sort of keys[0, n) over bits [0, 8*np) in LDS.  Per pass: each item is
-// ranked among the equal digits of its wave (digit_peers + mbcnt; the lowest lane adds
-// the group size to the wave's running count); then threads 0..255 turn the counts into
-// per-wave offsets -- prefix over waves within a digit, wave scan over 64 digits, and
-// a 4-entry prefix over digit groups applied at the scatter.
-template <typename K, int T, int ITEMS>
-__device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pad, int p_begin, int p_end) {
+// LSD radix passes [p_begin, p_end) over 8-bit digits of keys[0, n_pad) in LDS (with
+// vals moving alongside when HASV).  Per pass: each item is ranked among the equal
+// digits of its wave (digit_peers_full + mbcnt; the lowest lane adds the group size to
+// the wave's running count); then threads 0..255 turn the counts into per-wave offsets
+// -- prefix over waves within a digit, wave scan over 64 digits, and a 4-entry prefix
+// over digit groups applied at the scatter.  tbl is [W][256], cnt is [2][W][256] (one
+// table per pass parity), gtot has 4 entries.  With `clear` the tables are zeroed first;
+// otherwise they must be as a previous call left them (tbl zero, the table of parity
+// p_begin zero).  n_pad is a multiple of 64 * W.  Block-wide: barriers inside.
+template <typename K, int T, int ITEMS, bool HASV>
+__device__ __forceinline__ void lds_sort_passes(K* keys, u32* vals, u64* tbl, u32* cnt, u32* gtot, u32 n_pad,
+                                                int p_begin, int p_end, bool clear) {
   constexpr int W = T / 64;
   const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const u64 ge = ~((1ull << lane) - 1ull);
-  if (p_begin == 0) {
+  if (clear) {
     for (u32 i = tid; i < W * 256; i += T) {
-      (&S.u.r.tbl[0][0])[i] = 0;
-      (&S.u.r.cnt[0][0][0])[i] = 0;
-      (&S.u.r.cnt[1][0][0])[i] = 0;
+      tbl[i] = 0;
+      cnt[i] = 0;
+      cnt[W * 256 + i] = 0;
     }
     __syncthreads();
   }
   const int per = (int)(n_pad / (64u * W));
+  u64* wtbl = tbl + wave * 256;
   for (int p = p_begin; p < p_end; ++p) {
-    u32(*C)[256] = S.u.r.cnt[p & 1];
+    u32* C = cnt + (p & 1) * (W * 256);
     K kr[ITEMS];
+    u32 vr[HASV ? ITEMS : 1];
     u32 rk[ITEMS];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j)
-      if (j < per) kr[j] = S.keys[(wave * (u32)per + (u32)j) * 64u + lane];
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 at = (wave * (u32)per + (u32)j) * 64u + lane;
+        kr[j] = keys[at];
+        if (HASV) vr[HASV ? j : 0] = vals[at];
+      }
+    }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       if (j < per) {
         const u32 d = key_digit(kr[j], 8 * p);
-        const u64 mask = digit_peers_full(S.u.r.tbl[wave], d, ge);
-        const u32 base = C[wave][d];
+        const u64 mask = digit_peers_full(wtbl, d, ge);
+        const u32 base = C[wave * 256 + d];
         const u32 lr = mbcnt64(mask);
         if (lr == 0) {
-          C[wave][d] = base + (u32)__popcll(mask);
-          S.u.r.tbl[wave][d] = 0;
+          C[wave * 256 + d] = base + (u32)__popcll(mask);
+          wtbl[d] = 0;
         }
         rk[j] = base + lr;
       }
@@ -307,31 +319,39 @@ __device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pa
       u32 col = 0;
 #pragma unroll
       for (int v = 0; v < W; ++v) {
-        const u32 x = C[v][tid];
-        C[v][tid] = col;
+        const u32 x = C[v * 256 + tid];
+        C[v * 256 + tid] = col;
         col += x;
       }
       const u32 inc = wave_scan_u32(col);
       const u32 ex = inc - col;
 #pragma unroll
-      for (int v = 0; v < W; ++v) C[v][tid] += ex;
-      if (lane == 63) S.gtot[wave] = inc;
+      for (int v = 0; v < W; ++v) C[v * 256 + tid] += ex;
+      if (lane == 63) gtot[wave] = inc;
     }
     __syncthreads();
-    const u32 g1 = S.gtot[0], g2 = g1 + S.gtot[1], g3 = g2 + S.gtot[2];
+    const u32 g1 = gtot[0], g2 = g1 + gtot[1], g3 = g2 + gtot[2];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       if (j < per) {
         const u32 d = key_digit(kr[j], 8 * p);
         const u32 gb = d < 128 ? (d < 64 ? 0u : g1) : (d < 192 ? g2 : g3);
-        S.keys[C[wave][d] + gb + rk[j]] = kr[j];
+        const u32 at = C[wave * 256 + d] + gb + rk[j];
+        keys[at] = kr[j];
+        if (HASV) vals[at] = vr[HASV ? j : 0];
       }
     }
     // the other count table is free again: clear it for the next pass
-    u32* nxt = &S.u.r.cnt[(p + 1) & 1][0][0];
+    u32* nxt = cnt + ((p + 1) & 1) * (W * 256);
     for (u32 i = tid; i < W * 256; i += T) nxt[i] = 0;
     __syncthreads();
   }
+}
+
+template <typename K, int T, int ITEMS>
+__device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pad, int p_begin, int p_end) {
+  lds_sort_passes<K, T, ITEMS, false>(S.keys, nullptr, &S.u.r.tbl[0][0], &S.u.r.cnt[0][0][0], S.gtot, n_pad, p_begin,
+                                      p_end, p_begin == 0);
 }
 
 // Counting needs equal keys adjacent, not ascending order (the survivors of all buckets

@@ -303,6 +303,7 @@ struct PlanArgs {
   u64 chunk_cap;
   u64* kall_off;
   u64* meta;
+  u32* large_ch0;        // first chunk of each large bucket (in large-list order)
 };
 
 __device__ __forceinline__ void plan_quantities(const PlanArgs& P, u64 c, u64 q[PLAN_Q]) {
@@ -391,6 +392,7 @@ __global__ __launch_bounds__(PLAN_T) void k_plan_write(PlanArgs P) {
     P.kall_off[b] = pk;
     pk += nk;
     if (nk > P.cap_small) {
+      P.large_ch0[plarge] = (u32)pch;
       P.large_list[plarge++] = b;
       P.large_koff[b] = plk;
       for (u32 o = 0; o < nk; o += P.cap_chunk) {

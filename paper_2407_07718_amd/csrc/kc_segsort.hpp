@@ -1,0 +1,320 @@
+// Segmented sorts of (key, value) pairs, used where a stage needs keys in order but the
+// keys already fall into independent segments:
+//   * the (k-mer, count) lists of one heavy bucket (Section 3.4: lists are sorted and
+//     merged again) -- equal k-mers never span two buckets, so each bucket's lists are
+//     sorted on their own and summed per run;
+//   * the survivors, split by their top key bits into key ranges (two scatter passes),
+//     each range then sorted on its own -- ascending order of the whole output.
+// A segment that fits the block's LDS is sorted there in one read and one write; a
+// longer one is sorted by its block through HBM (stable LSD passes over LDS tiles).
+#pragma once
+#include "kc_common.hpp"
+#include "kc_count.hpp"
+
+// Bits [sh, sh + nb) of a key, nb <= 16 (may straddle the words of a 128-bit key).
+__device__ __forceinline__ u32 key_field(u64 k, int sh, int nb) {
+  return nb ? (u32)(k >> sh) & ((1u << nb) - 1u) : 0u;
+}
+__device__ __forceinline__ u32 key_field(k128 k, int sh, int nb) {
+  if (!nb) return 0u;
+  u64 v;
+  if (sh >= 64) v = k.hi >> (sh - 64);
+  else if (sh == 0) v = k.lo;
+  else v = (k.lo >> sh) | (k.hi << (64 - sh));
+  return (u32)v & ((1u << nb) - 1u);
+}
+
+struct SegArgs {
+  void* keys;              // input pairs; also the first ping-pong buffer of long segments
+  u32* vals;
+  void* tmp_k;             // second ping-pong buffer (same positions)
+  u32* tmp_v;
+  void* out_k;             // sorted output (may equal keys); positions >= out_cap are dropped
+  u32* out_v;
+  u64 out_cap;
+  const u64* seg;          // segment i = [seg[i], seg[i + 1])
+  const u64* n_seg_ptr;    // number of segments
+  int nbits;               // key bits to sort
+};
+
+template <typename K, int T, int ITEMS>
+struct SegSmem {
+  static constexpr int W = T / 64, CAP = T * ITEMS;
+  K keys[CAP];
+  u32 vals[CAP];
+  u64 tbl[W * 256];
+  u32 cnt[2 * W * 256];
+  u32 gtot[4];
+  u32 dcnt[256], dstart[256], drun[256];
+  u64 scr[17];
+};
+
+template <typename K, int T, int ITEMS>
+__global__ __launch_bounds__(T) void k_seg_sort(SegArgs A) {
+  using SM = SegSmem<K, T, ITEMS>;
+  constexpr u32 CAP = SM::CAP, WB = 64u * (T / 64);
+  __shared__ SM S;
+  const u32 tid = threadIdx.x;
+  const u64 n_seg = *A.n_seg_ptr;
+  const int np = (A.nbits + 7) / 8;
+  K* in_k = reinterpret_cast<K*>(A.keys);
+  K* tmp_k = reinterpret_cast<K*>(A.tmp_k);
+  K* out_k = reinterpret_cast<K*>(A.out_k);
+  for (u64 sgi = blockIdx.x; sgi < n_seg; sgi += gridDim.x) {
+    const u64 s0 = A.seg[sgi], s1 = A.seg[sgi + 1];
+    if (s1 <= s0) continue;                      // uniform over the block
+    const u64 n = s1 - s0;
+    __syncthreads();                             // LDS of the previous segment is free
+    if (n <= CAP) {
+      const u32 m = (u32)n, m_pad = (m + WB - 1) / WB * WB;
+      for (u32 i = tid; i < m_pad; i += T) {
+        S.keys[i] = i < m ? in_k[s0 + i] : key_pad<K>();
+        S.vals[i] = i < m ? A.vals[s0 + i] : 0u;
+      }
+      __syncthreads();
+      lds_sort_passes<K, T, ITEMS, true>(S.keys, S.vals, S.tbl, S.cnt, S.gtot, m_pad, 0, np, true);
+      for (u32 i = tid; i < m; i += T) {
+        if (s0 + i < A.out_cap) {
+          out_k[s0 + i] = S.keys[i];
+          A.out_v[s0 + i] = S.vals[i];
+        }
+      }
+      continue;
+    }
+    // Long segment: stable LSD passes through HBM, ping-pong between in and tmp.
+    K* src_k = in_k;
+    u32* src_v = A.vals;
+    K* dst_k = tmp_k;
+    u32* dst_v = A.tmp_v;
+    for (int p = 0; p < np; ++p) {
+      for (u32 d = tid; d < 256; d += T) S.dcnt[d] = 0;
+      __syncthreads();
+      for (u64 i = tid; i < n; i += T) atomicAdd(&S.dcnt[key_digit(src_k[s0 + i], 8 * p)], 1u);
+      __syncthreads();
+      {
+        u64 tot;
+        const u64 v = tid < 256 ? (u64)S.dcnt[tid] : 0ull;
+        const u64 ex = block_exclusive_scan<u64>(v, S.scr, &tot);
+        if (tid < 256) S.drun[tid] = (u32)ex;
+      }
+      __syncthreads();
+      for (u64 t0 = 0; t0 < n; t0 += CAP) {
+        const u32 m = (u32)min((u64)CAP, n - t0), m_pad = (m + WB - 1) / WB * WB;
+        for (u32 i = tid; i < m_pad; i += T) {
+          S.keys[i] = i < m ? src_k[s0 + t0 + i] : key_pad<K>();
+          S.vals[i] = i < m ? src_v[s0 + t0 + i] : 0u;
+        }
+        for (u32 d = tid; d < 256; d += T) S.dcnt[d] = 0;
+        __syncthreads();
+        // one stable pass on digit p orders the tile by that digit (padding last)
+        lds_sort_passes<K, T, ITEMS, true>(S.keys, S.vals, S.tbl, S.cnt, S.gtot, m_pad, p, p + 1, true);
+        for (u32 i = tid; i < m; i += T) {
+          const u32 d = key_digit(S.keys[i], 8 * p);
+          if (i == 0 || key_digit(S.keys[i - 1], 8 * p) != d) S.dstart[d] = i;
+          atomicAdd(&S.dcnt[d], 1u);
+        }
+        __syncthreads();
+        for (u32 i = tid; i < m; i += T) {
+          const u32 d = key_digit(S.keys[i], 8 * p);
+          const u64 at = s0 + S.drun[d] + (i - S.dstart[d]);
+          dst_k[at] = S.keys[i];
+          dst_v[at] = S.vals[i];
+        }
+        __syncthreads();
+        for (u32 d = tid; d < 256; d += T) S.drun[d] += S.dcnt[d];
+        __syncthreads();
+      }
+      K* tk = src_k;
+      src_k = dst_k;
+      dst_k = tk;
+      u32* tv = src_v;
+      src_v = dst_v;
+      dst_v = tv;
+    }
+    if (src_k != out_k) {
+      for (u64 i = tid; i < n; i += T) {
+        if (s0 + i < A.out_cap) {
+          out_k[s0 + i] = src_k[s0 + i];
+          A.out_v[s0 + i] = src_v[s0 + i];
+        }
+      }
+    }
+  }
+}
+
+// Segment table of the heavy buckets' lists: lists are compacted in chunk order and the
+// chunks of one bucket are consecutive, so bucket i spans the scanned list offsets of its
+// first chunk up to those of the next bucket's first chunk.
+__global__ __launch_bounds__(256) void k_merge_segs(const u32* __restrict__ kloff, const u32* __restrict__ large_ch0,
+                                                    const u64* __restrict__ n_large_ptr,
+                                                    const u64* __restrict__ n_chunks_ptr, u64 chunk_cap,
+                                                    const u64* __restrict__ n_entries_ptr, u64* __restrict__ seg) {
+  const u64 n_large = *n_large_ptr, n_chunks = min(*n_chunks_ptr, chunk_cap), n_ent = *n_entries_ptr;
+  for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i <= n_large; i += (u64)gridDim.x * blockDim.x) {
+    const u64 c = i < n_large ? (u64)large_ch0[i] : n_chunks;
+    seg[i] = c < n_chunks ? min((u64)kloff[c], n_ent) : n_ent;
+  }
+}
+
+// ---------------------------------------------------------------------------- key ranges
+// The survivors are split into key ranges by their top bits: a coarse pass on the top 8
+// bits (per-block LDS histograms, one scan, a scatter staged through LDS) and a fine
+// pass, one block per coarse group, on the next g2 bits, g2 chosen from the survivor
+// count so that a range averages about `target` keys.  The fine pass writes the range
+// table in key order.
+constexpr u32 MSD_NB = 1024;   // blocks of the coarse pass
+
+struct MsdArgs {
+  const void* in_k;        // dense survivors
+  const u32* in_v;
+  const u64* n_ptr;        // survivors
+  void* mid_k;             // grouped by the top 8 bits
+  u32* mid_v;
+  void* out_k;             // grouped by the top 8 + g2 bits
+  u32* out_v;
+  u32* hist;               // [256][MSD_NB] counts -> offsets
+  u64* seg;                // [(256 << g2) + 1] range starts
+  u64* n_seg;              // ranges
+  int nbits;               // key bits (2k)
+  u32 target;              // keys per range wanted
+};
+
+__device__ __forceinline__ int msd_shift1(int nbits) { return nbits > 8 ? nbits - 8 : 0; }
+__device__ __forceinline__ int msd_bits1(int nbits) { return nbits < 8 ? nbits : 8; }
+__device__ __forceinline__ int msd_g2(u64 n, int nbits, u32 target) {
+  const int room = msd_shift1(nbits);
+  int g2 = 0;
+  while (g2 < 8 && g2 < room && (n >> (8 + g2)) > (u64)target) ++g2;
+  return g2;
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_msd_hist(MsdArgs A) {
+  __shared__ u32 h[256];
+  const u64 n = *A.n_ptr;
+  const u64 per = (n + MSD_NB - 1) / MSD_NB;
+  const u64 a = min(n, blockIdx.x * per), b = min(n, a + per);
+  const int sh = msd_shift1(A.nbits), nb = msd_bits1(A.nbits);
+  const K* in = reinterpret_cast<const K*>(A.in_k);
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  for (u64 i = a + threadIdx.x; i < b; i += 256) atomicAdd(&h[key_field(in[i], sh, nb)], 1u);
+  __syncthreads();
+  A.hist[(u64)threadIdx.x * MSD_NB + blockIdx.x] = h[threadIdx.x];
+}
+
+// Coarse scatter: the block's range in rounds staged through LDS, written group by group.
+template <typename K>
+__global__ __launch_bounds__(512) void k_msd_scatter(MsdArgs A) {
+  constexpr u32 T = 512, R = sizeof(K) == 8 ? 4096u : 2048u, IT = R / T;
+  __shared__ K sk[R];
+  __shared__ u32 sv[R];
+  __shared__ u32 cnt[256], lbase[256], gpos[256];
+  __shared__ u64 scr[17];
+  const u32 tid = threadIdx.x;
+  const u64 n = *A.n_ptr;
+  const u64 per = (n + MSD_NB - 1) / MSD_NB;
+  const u64 a = min(n, blockIdx.x * per), b = min(n, a + per);
+  const int sh = msd_shift1(A.nbits), nb = msd_bits1(A.nbits);
+  const K* in = reinterpret_cast<const K*>(A.in_k);
+  K* mid = reinterpret_cast<K*>(A.mid_k);
+  if (tid < 256) {
+    cnt[tid] = 0;
+    gpos[tid] = A.hist[(u64)tid * MSD_NB + blockIdx.x];
+  }
+  __syncthreads();
+  for (u64 r0 = a; r0 < b; r0 += R) {
+    const u32 nr = (u32)min((u64)R, b - r0);
+    K kr[IT];
+    u32 vr[IT], cc[IT], rk[IT];
+#pragma unroll
+    for (u32 j = 0; j < IT; ++j) {
+      const u32 i = tid + j * T;
+      if (i < nr) {
+        kr[j] = in[r0 + i];
+        vr[j] = A.in_v[r0 + i];
+      }
+    }
+#pragma unroll
+    for (u32 j = 0; j < IT; ++j) {
+      if (tid + j * T < nr) {
+        cc[j] = key_field(kr[j], sh, nb);
+        rk[j] = atomicAdd(&cnt[cc[j]], 1u);
+      }
+    }
+    __syncthreads();
+    u64 tot;
+    const u32 ex = (u32)block_exclusive_scan<u64>(tid < 256 ? (u64)cnt[tid] : 0ull, scr, &tot);
+    if (tid < 256) lbase[tid] = ex;
+    __syncthreads();
+#pragma unroll
+    for (u32 j = 0; j < IT; ++j) {
+      if (tid + j * T < nr) {
+        const u32 at = lbase[cc[j]] + rk[j];
+        sk[at] = kr[j];
+        sv[at] = vr[j];
+      }
+    }
+    __syncthreads();
+    for (u32 i = tid; i < nr; i += T) {
+      const u32 c = key_field(sk[i], sh, nb);
+      const u64 d = (u64)gpos[c] + (i - lbase[c]);
+      mid[d] = sk[i];
+      A.mid_v[d] = sv[i];
+    }
+    __syncthreads();
+    if (tid < 256) {
+      gpos[tid] += cnt[tid];
+      cnt[tid] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// Fine pass: one block per coarse group; writes the range table.
+template <typename K>
+__global__ __launch_bounds__(1024) void k_msd_fine(MsdArgs A) {
+  __shared__ u32 cr[256], cur[256];
+  const u32 g = blockIdx.x, tid = threadIdx.x;
+  const u64 n = *A.n_ptr;
+  const int sh1 = msd_shift1(A.nbits), g2 = msd_g2(n, A.nbits, A.target), sh2 = sh1 - g2;
+  const u32 F = 1u << g2;
+  const u64 a = A.hist[(u64)g * MSD_NB];
+  const u64 b = g + 1 < 256 ? (u64)A.hist[(u64)(g + 1) * MSD_NB] : n;
+  const K* mid = reinterpret_cast<const K*>(A.mid_k);
+  K* out = reinterpret_cast<K*>(A.out_k);
+  if (tid < 256) cr[tid] = 0;
+  __syncthreads();
+  for (u64 i = a + tid; i < b; i += 1024) atomicAdd(&cr[key_field(mid[i], sh2, g2)], 1u);
+  __syncthreads();
+  if (tid < 64) {
+    // exclusive prefix over the F <= 256 sub-ranges: lane l owns sub-ranges 4l..4l+3
+    u32 c[4], s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c[q] = 4 * tid + q < F ? cr[4 * tid + q] : 0u;
+      s += c[q];
+    }
+    u32 run = wave_scan_u32(s) - s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u32 f = 4 * tid + q;
+      if (f < F) {
+        cur[f] = (u32)a + run;
+        A.seg[((u64)g << g2) + f] = a + run;
+      }
+      run += c[q];
+    }
+  }
+  if (g == 0 && tid == 0) {
+    A.seg[(u64)256 << g2] = n;
+    *A.n_seg = (u64)256 << g2;
+  }
+  __syncthreads();
+  for (u64 i = a + tid; i < b; i += 1024) {
+    const K k = mid[i];
+    const u32 pos = atomicAdd(&cur[key_field(k, sh2, g2)], 1u);
+    out[pos] = k;
+    A.out_v[pos] = A.mid_v[i];
+  }
+}

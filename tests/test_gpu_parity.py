@@ -85,6 +85,20 @@ def test_keys_sharing_low_bits(k, log2_buckets):
     check(reads, offsets, k, 15, 2, 3, 64, cfg, label=f"shared low bits k{k} log2_b={log2_buckets}")
 
 
+@pytest.mark.parametrize("k", [31, 51])
+def test_output_key_range_beyond_chip(k):
+    """Every survivor starts with k-11 A's, so all of them fall into one key range of the
+    output sort, larger than one block's LDS: that range is sorted through HBM."""
+    rng = np.random.Generator(np.random.PCG64(1200 + k))
+    seqs = []
+    for _ in range(6000):
+        tail = "".join("ACG"[c] for c in rng.integers(0, 3, 11))   # no T: forward is canonical
+        seqs.extend(["A" * (k - 11) + tail] * 2)
+    reads, offsets = synth.from_strings([seqs[i] for i in rng.permutation(len(seqs))])
+    got, ref = check(reads, offsets, k, 15, 2, 10, 64, label=f"one output range k{k}")
+    assert ref.n_pairs > 5000
+
+
 def test_long_reads_cross_spans():
     reads, offsets = _genome_reads(3, 12, 20000, 60000, genome=100000, p_sub=0.001, p_n=0.0, p_indel=0.0005)
     check(reads, offsets, 31, 21, 2, 200, 4096, label="long reads")
