@@ -316,7 +316,8 @@ constexpr u32 SEG_CAP_64 = 256 * 16, SEG_CAP_128 = 256 * 8;   // pairs sorted on
 
 template <typename K>
 int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64 out_cap, const u64* seg,
-             const u64* n_seg, int nbits, int n_cu, hipStream_t st, int* grid) {
+             const u64* n_seg, int nbits, bool group_only, const u64* msd_n, u32 msd_target, int n_cu, hipStream_t st,
+             int* grid) {
   constexpr int IT = sizeof(K) == 8 ? 16 : 8;
   static_assert(256 * IT == (sizeof(K) == 8 ? SEG_CAP_64 : SEG_CAP_128), "segment capacity");
   int per_cu = 0, rc;
@@ -333,6 +334,9 @@ int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64
   a.seg = seg;
   a.n_seg_ptr = n_seg;
   a.nbits = nbits;
+  a.group_only = group_only ? 1 : 0;
+  a.msd_n = msd_n;
+  a.msd_target = msd_target;
   hipLaunchKernelGGL((k_seg_sort<K, 256, IT>), dim3(*grid), dim3(256), 0, st, a);
   return KC_OK;
 }
@@ -533,7 +537,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   hipLaunchKernelGGL(k_merge_segs, grid_for(P.B + 1, 256, 1024), dim3(256), 0, st, kloff, at<u32>(ws, P.o_lch0), meta + 1,
                      meta + 4, P.chunk_cap, kl_nc, seg);
   int seg_grid = 0;
-  if ((rc = seg_sort<K>(kl0k, kl0c, kl1k, kl1c, kl0k, kl0c, ~0ull, seg, meta + 1, 2 * P.k, n_cu, st, &seg_grid)))
+  if ((rc = seg_sort<K>(kl0k, kl0c, kl1k, kl1c, kl0k, kl0c, ~0ull, seg, meta + 1, 2 * P.k, true, nullptr, 0, n_cu,
+                        st, &seg_grid)))
     return rc;
   K* lks = kl0k;
   u32* lvs = kl0c;
@@ -576,7 +581,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     hipLaunchKernelGGL((k_msd_fine<K>), dim3(256), dim3(1024), 0, st, ma);
   }
   if ((rc = seg_sort<K>(s1k, s1c, s0k, s0c, reinterpret_cast<K*>(d_kmers), d_counts, pair_cap, seg, ctrl + C_NSEG,
-                        2 * P.k, n_cu, st, &seg_grid)))
+                        2 * P.k, false, surv_nc, (P.key_words == 1 ? SEG_CAP_64 : SEG_CAP_128) / 2, n_cu, st,
+                        &seg_grid)))
     return rc;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags);
   hipLaunchKernelGGL(k_totals_meta, dim3(1), dim3(64), 0, st, d_tot, meta, kl_n, P.B);

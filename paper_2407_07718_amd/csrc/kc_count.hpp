@@ -161,12 +161,22 @@ struct RunSink {
   unsigned long long* lover;   // LDS sum of counts in the last bin
 };
 
-__device__ __forceinline__ void run_stats(const RunSink& S, u64 c) {
-  const u64 bin = c < S.hist_len - 1 ? c : S.hist_len - 1;
-  if (bin < 256) atomicAdd(&S.hist_s[bin], 1u);
-  else atomicAdd((unsigned long long*)&S.hist[bin], 1ull);
-  if (c >= S.hist_len - 1) atomicAdd(S.lover, (unsigned long long)c);
-  atomicMax(S.lmax, (u32)min(c, (u64)0xFFFFFFFFu));
+// Runs held by the lanes with `act` set; every lane of the wave calls it (converged).
+// Runs seen once -- most error k-mers -- are counted with one ballot, and the running
+// maximum is only raised by lanes above the value already recorded, so that the LDS
+// atomics of a wave rarely pile up on one address.
+__device__ __forceinline__ void run_stats_lanes(const RunSink& S, u64 c, bool act) {
+  const u64 last = S.hist_len - 1;
+  const u64 bin = c < last ? c : last;
+  const u64 ones = __ballot(act && bin == 1);
+  if (ones && lane_id() == 0) atomicAdd(&S.hist_s[1], (u32)__popcll(ones));
+  if (act && bin != 1) {
+    if (bin < 256) atomicAdd(&S.hist_s[bin], 1u);
+    else atomicAdd((unsigned long long*)&S.hist[bin], 1ull);
+  }
+  if (act && c >= last) atomicAdd(S.lover, (unsigned long long)c);
+  const u32 c32 = (u32)min(c, (u64)0xFFFFFFFFu);
+  if (act && c32 > *(volatile u32*)S.lmax) atomicMax(S.lmax, c32);
 }
 
 __device__ __forceinline__ void flush_stats(const RunSink& S, u64 ndist) {
@@ -436,13 +446,9 @@ __device__ __forceinline__ u32 emit_runs_block(const K* keys, const u16* hp, u32
     if (r < nruns) {
       s = hp[r];
       c = ((r + 1 < nruns) ? (u32)hp[r + 1] : n) - s;
-      if (final) {
-        run_stats(sink, c);
-        emit = c >= lo && c <= hi;
-      } else {
-        emit = true;
-      }
+      emit = final ? (c >= lo && c <= hi) : true;
     }
+    if (final) run_stats_lanes(sink, c, r < nruns);
     u64 tot;
     const u64 ex = block_exclusive_scan<u64>(emit ? 1ull : 0ull, scr, &tot);
     if (emit) {
@@ -659,9 +665,9 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
       if (r < nruns) {
         s = S.u.hp[r];
         c = ((r + 1 < nruns) ? (u32)S.u.hp[r + 1] : n) - s;
-        run_stats(sink, c);
         emit = c >= A.min_freq && c <= A.max_freq;
       }
+      run_stats_lanes(sink, c, r < nruns);
       const u64 m = __ballot(emit);
       if (emit) {
         const u64 dst = so + kept + mbcnt64(m);
@@ -761,9 +767,9 @@ __global__ __launch_bounds__(256) void k_rle_runs(CountArgs A, const K* __restri
       s = hp[r];
       const u64 e = (r + 1 < nruns) ? hp[r + 1] : n;
       for (u64 i = s; i < e; ++i) c += vals[i];
-      run_stats(sink, c);
       surv = c >= A.min_freq && c <= A.max_freq;
     }
+    run_stats_lanes(sink, c, r < re);
     u64 tot;
     const u64 ex = block_exclusive_scan<u64>(surv ? 1ull : 0ull, scr, &tot);
     if (surv) {

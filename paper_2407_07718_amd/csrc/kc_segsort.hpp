@@ -24,6 +24,32 @@ __device__ __forceinline__ u32 key_field(k128 k, int sh, int nb) {
   return (u32)v & ((1u << nb) - 1u);
 }
 
+constexpr u32 MSD_NB = 1024;   // blocks of the coarse pass
+
+struct MsdArgs {
+  const void* in_k;        // dense survivors
+  const u32* in_v;
+  const u64* n_ptr;        // survivors
+  void* mid_k;             // grouped by the top 8 bits
+  u32* mid_v;
+  void* out_k;             // grouped by the top 8 + g2 bits
+  u32* out_v;
+  u32* hist;               // [256][MSD_NB] counts -> offsets
+  u64* seg;                // [(256 << g2) + 1] range starts
+  u64* n_seg;              // ranges
+  int nbits;               // key bits (2k)
+  u32 target;              // keys per range wanted
+};
+
+__device__ __forceinline__ int msd_shift1(int nbits) { return nbits > 8 ? nbits - 8 : 0; }
+__device__ __forceinline__ int msd_bits1(int nbits) { return nbits < 8 ? nbits : 8; }
+__device__ __forceinline__ int msd_g2(u64 n, int nbits, u32 target) {
+  const int room = msd_shift1(nbits);
+  int g2 = 0;
+  while (g2 < 8 && g2 < room && (n >> (8 + g2)) > (u64)target) ++g2;
+  return g2;
+}
+
 struct SegArgs {
   void* keys;              // input pairs; also the first ping-pong buffer of long segments
   u32* vals;
@@ -34,7 +60,10 @@ struct SegArgs {
   u64 out_cap;
   const u64* seg;          // segment i = [seg[i], seg[i + 1])
   const u64* n_seg_ptr;    // number of segments
-  int nbits;               // key bits to sort
+  int nbits;               // key bits (2k)
+  int group_only;          // equal keys adjacent suffices (segments of a count's lists)
+  const u64* msd_n;        // when set: segments are key ranges of k_msd_fine over *msd_n keys,
+  u32 msd_target;          //   so only the bits below the range fields are sorted
 };
 
 template <typename K, int T, int ITEMS>
@@ -56,7 +85,13 @@ __global__ __launch_bounds__(T) void k_seg_sort(SegArgs A) {
   __shared__ SM S;
   const u32 tid = threadIdx.x;
   const u64 n_seg = *A.n_seg_ptr;
-  const int np = (A.nbits + 7) / 8;
+  // bits to order: all, or those below the key-range fields
+  const int sort_bits =
+      A.msd_n ? msd_shift1(A.nbits) - msd_g2(*A.msd_n, A.nbits, A.msd_target) : A.nbits;
+  const int np = (sort_bits + 7) / 8;
+  // grouping only: mixed keys, early exit as in the bucket kernels
+  const bool mixed = A.group_only && A.nbits > 32;
+  const int np_mixed = sort_passes<K>(A.nbits / 2);
   K* in_k = reinterpret_cast<K*>(A.keys);
   K* tmp_k = reinterpret_cast<K*>(A.tmp_k);
   K* out_k = reinterpret_cast<K*>(A.out_k);
@@ -68,14 +103,25 @@ __global__ __launch_bounds__(T) void k_seg_sort(SegArgs A) {
     if (n <= CAP) {
       const u32 m = (u32)n, m_pad = (m + WB - 1) / WB * WB;
       for (u32 i = tid; i < m_pad; i += T) {
-        S.keys[i] = i < m ? in_k[s0 + i] : key_pad<K>();
+        K key = key_pad<K>();
+        if (i < m) key = mixed ? mix_key(in_k[s0 + i]) : in_k[s0 + i];
+        S.keys[i] = key;
         S.vals[i] = i < m ? A.vals[s0 + i] : 0u;
       }
       __syncthreads();
-      lds_sort_passes<K, T, ITEMS, true>(S.keys, S.vals, S.tbl, S.cnt, S.gtot, m_pad, 0, np, true);
+      if (mixed) {
+        const int p0 = first_passes(m);
+        lds_sort_passes<K, T, ITEMS, true>(S.keys, S.vals, S.tbl, S.cnt, S.gtot, m_pad, 0, p0, true);
+        bool bad = false;
+        for (u32 i = tid; i < m; i += T) bad |= mixed_pair(S.keys, i, m, 8 * p0);
+        if (__syncthreads_or(bad))
+          lds_sort_passes<K, T, ITEMS, true>(S.keys, S.vals, S.tbl, S.cnt, S.gtot, m_pad, p0, np_mixed, false);
+      } else {
+        lds_sort_passes<K, T, ITEMS, true>(S.keys, S.vals, S.tbl, S.cnt, S.gtot, m_pad, 0, np, true);
+      }
       for (u32 i = tid; i < m; i += T) {
         if (s0 + i < A.out_cap) {
-          out_k[s0 + i] = S.keys[i];
+          out_k[s0 + i] = mixed ? unmix_key(S.keys[i]) : S.keys[i];
           A.out_v[s0 + i] = S.vals[i];
         }
       }
@@ -162,32 +208,6 @@ __global__ __launch_bounds__(256) void k_merge_segs(const u32* __restrict__ klof
 // pass, one block per coarse group, on the next g2 bits, g2 chosen from the survivor
 // count so that a range averages about `target` keys.  The fine pass writes the range
 // table in key order.
-constexpr u32 MSD_NB = 1024;   // blocks of the coarse pass
-
-struct MsdArgs {
-  const void* in_k;        // dense survivors
-  const u32* in_v;
-  const u64* n_ptr;        // survivors
-  void* mid_k;             // grouped by the top 8 bits
-  u32* mid_v;
-  void* out_k;             // grouped by the top 8 + g2 bits
-  u32* out_v;
-  u32* hist;               // [256][MSD_NB] counts -> offsets
-  u64* seg;                // [(256 << g2) + 1] range starts
-  u64* n_seg;              // ranges
-  int nbits;               // key bits (2k)
-  u32 target;              // keys per range wanted
-};
-
-__device__ __forceinline__ int msd_shift1(int nbits) { return nbits > 8 ? nbits - 8 : 0; }
-__device__ __forceinline__ int msd_bits1(int nbits) { return nbits < 8 ? nbits : 8; }
-__device__ __forceinline__ int msd_g2(u64 n, int nbits, u32 target) {
-  const int room = msd_shift1(nbits);
-  int g2 = 0;
-  while (g2 < 8 && g2 < room && (n >> (8 + g2)) > (u64)target) ++g2;
-  return g2;
-}
-
 template <typename K>
 __global__ __launch_bounds__(256) void k_msd_hist(MsdArgs A) {
   __shared__ u32 h[256];
