@@ -69,6 +69,23 @@ __device__ __forceinline__ u32 mbcnt64(u64 m) {
   return __builtin_amdgcn_mbcnt_hi((u32)(m >> 32), __builtin_amdgcn_mbcnt_lo((u32)m, 0u));
 }
 
+// Cross-lane moves that stay in the VALU (DPP) or go to a scalar register (readlane),
+// for a fully active wave.
+// v of lane l-1 (lane 0 gets `fill`): DPP wave_shr:1.
+__device__ __forceinline__ u32 lane_prev(u32 v, u32 fill) {
+  return (u32)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xF, 0xF, false);
+}
+// v of lane l+1 (lane 63 gets `fill`): DPP wave_shl:1.
+__device__ __forceinline__ u32 lane_next(u32 v, u32 fill) {
+  return (u32)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x130, 0xF, 0xF, false);
+}
+// v of lane (l-1) mod 64: DPP wave_ror:1.
+__device__ __forceinline__ u32 lane_rot1(u32 v) {
+  return (u32)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x13C, 0xF, 0xF, false);
+}
+// v of lane `src` (a constant), as a wave-uniform value.
+__device__ __forceinline__ u32 lane_read(u32 v, int src) { return (u32)__builtin_amdgcn_readlane((int)v, src); }
+
 // Inclusive prefix sum over the 64 lanes of a wave.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {

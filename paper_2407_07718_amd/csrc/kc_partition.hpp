@@ -91,7 +91,7 @@ struct ExtractArgs {
 // tile and is updated in place.  Lanes whose window reaches before the first tile of a
 // stream get garbage and must not be used.
 __device__ __forceinline__ u32 rot_up(u32 v, u32 d) {
-  return (u32)__shfl((int)v, (int)((lane_id() - d) & 63u), 64);
+  return d == 1 ? lane_rot1(v) : (u32)__shfl((int)v, (int)((lane_id() - d) & 63u), 64);
 }
 constexpr int WIN_STEPS = 5;   // w <= 63: doubling steps of 1, 2, 4, 8, 16, then the remainder
 
@@ -215,8 +215,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       }
       const u32 b = mn & bmask;   // destination = score mod B (B a power of two)
       // runs of valid windows with one bucket
-      const u32 b_prev = (u32)__shfl_up((int)b, 1, 64);
-      const int v_prev = __shfl_up((int)valid, 1, 64);
+      const u32 b_prev = lane_prev(b, 0u);
+      const u32 v_prev = lane_prev(valid ? 1u : 0u, 0u);
       bool cont;
       if (lane == 0) cont = valid && c_open && (c_b == b);
       else cont = valid && v_prev && (b_prev == b);
@@ -228,18 +228,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       else pos = c_pos + 1 + lane;
       const u32 pm = pos - div_small(pos, A.gmax_magic) * gmax;   // pos % gmax
       const bool head = valid && (pm == 0);
-      const int nv = __shfl_down((int)valid, 1, 64);
-      const int nh = __shfl_down((int)head, 1, 64);
+      const u32 nv = lane_next(valid ? 1u : 0u, 0u);
+      const u32 nh = lane_next(head ? 1u : 0u, 0u);
       const bool close = valid && (lane < 63u) && (!nv || nh);
-      const bool cont0 = __shfl((int)cont, 0, 64);
-      const bool head0 = __shfl((int)head, 0, 64);
+      const bool cont0 = lane_read(cont ? 1u : 0u, 0) != 0;
+      const bool head0 = lane_read(head ? 1u : 0u, 0) != 0;
       const bool carry_close = c_open && !(cont0 && !head0);
       const u64 CL = __ballot(close);
       const u32 n_close = (u32)__popcll(CL) + (carry_close ? 1u : 0u);
       if (n_close) {
         u32 at = 0;
         if (lane == 0) at = atomicAdd(&blk_n, n_close);
-        const u64 base = slot0 + (u32)__shfl((int)at, 0, 64);
+        const u64 base = slot0 + lane_read(at, 0);
         if (carry_close && lane == 0) {
           const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
           write_record(A, base, c_p - cm, cm + 1, c_b);
@@ -252,11 +252,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       }
       my_windows += (u64)__popcll(__ballot(valid));
       // carry the window in the last lane
-      const int vl = __shfl((int)valid, 63, 64);
-      c_open = vl != 0;
+      c_open = lane_read(valid ? 1u : 0u, 63) != 0;
       if (c_open) {
-        c_b = (u32)__shfl((int)b, 63, 64);
-        c_pos = (u32)__shfl((int)pos, 63, 64);
+        c_b = lane_read(b, 63);
+        c_pos = lane_read(pos, 63);
         c_p = T0 + 63 - back;
       }
     }
