@@ -43,6 +43,15 @@ class _Result(ctypes.Structure):
     ]
 
 
+class _Occ(ctypes.Structure):
+    _fields_ = [
+        ("n_occ", ctypes.c_uint64),
+        ("off", ctypes.POINTER(ctypes.c_uint64)),
+        ("read", ctypes.POINTER(ctypes.c_uint32)),
+        ("pos", ctypes.POINTER(ctypes.c_uint32)),
+    ]
+
+
 _lib = None
 
 
@@ -60,6 +69,11 @@ def _load():
         lib.kco_query.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                   ctypes.c_uint64, ctypes.c_uint64]
         lib.kco_query.restype = ctypes.c_uint64
+        lib.kco_count_ext.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                      ctypes.POINTER(_Result), ctypes.POINTER(_Occ)]
+        lib.kco_count_ext.restype = ctypes.c_int
+        lib.kco_occ_free.argtypes = [ctypes.POINTER(_Occ)]
         lib.kco_query_many.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
         _lib = lib
@@ -124,3 +138,44 @@ def query(reads, offsets, k: int, kmer_words) -> np.ndarray:
     lib.kco_query_many(reads.ctypes.data, offsets.ctypes.data,
                        offsets.shape[0] - 1, k, qq.ctypes.data, q.shape[0], out.ctypes.data)
     return out
+
+
+@dataclass
+class OracleExtResult:
+    """Counts as ``count`` plus the extension information of every reported k-mer:
+    occurrences of pair j are rows ``occ_off[j]:occ_off[j+1]`` of ``occ_read`` /
+    ``occ_pos``, ascending by (read, pos)."""
+    base: OracleResult
+    occ_off: np.ndarray      # uint64 [n_pairs + 1]
+    occ_read: np.ndarray     # uint32 [n_occ]
+    occ_pos: np.ndarray      # uint32 [n_occ]
+
+
+def count_ext(reads, offsets, k: int, min_freq: int = 1, max_freq: int = 0xFFFFFFFF,
+              hist_len: int = 65536) -> OracleExtResult:
+    """Extension version: every window is kept with (read index, position in read)."""
+    lib = _load()
+    reads, offsets = _arrays(reads, offsets)
+    n_reads = offsets.shape[0] - 1
+    res, occ = _Result(), _Occ()
+    rc = lib.kco_count_ext(reads.ctypes.data, offsets.ctypes.data, n_reads, k,
+                           min_freq, max_freq, hist_len, ctypes.byref(res), ctypes.byref(occ))
+    if rc != 0:
+        lib.kco_free(ctypes.byref(res))
+        lib.kco_occ_free(ctypes.byref(occ))
+        raise ValueError(f"oracle rejected arguments (k={k}, lo={min_freq}, hi={max_freq}, H={hist_len})")
+    try:
+        n, kw = int(res.n_pairs), int(res.key_words)
+        kmers = np.ctypeslib.as_array(res.kmers, shape=(max(1, n * kw),))[: n * kw].copy().reshape(n, kw)
+        counts = np.ctypeslib.as_array(res.counts, shape=(max(1, n),))[:n].copy()
+        hist = np.ctypeslib.as_array(res.hist, shape=(hist_len,)).copy()
+        base = OracleResult(kmers, counts, hist, int(res.n_windows), int(res.n_distinct),
+                            int(res.overflow_sum), int(res.max_count))
+        no = int(occ.n_occ)
+        off = np.ctypeslib.as_array(occ.off, shape=(n + 1,)).copy()
+        rd = np.ctypeslib.as_array(occ.read, shape=(max(1, no),))[:no].copy()
+        ps = np.ctypeslib.as_array(occ.pos, shape=(max(1, no),))[:no].copy()
+        return OracleExtResult(base, off, rd, ps)
+    finally:
+        lib.kco_free(ctypes.byref(res))
+        lib.kco_occ_free(ctypes.byref(occ))

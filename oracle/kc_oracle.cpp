@@ -28,6 +28,11 @@
 //   * pairs are reported in ascending canonical value; values of k > 31 are emitted as
 //     two little-endian 64-bit words {low, high}.
 //
+// The extension version (kco_count_ext) keeps, for every reported k-mer, where each
+// of its windows was found: the read's index and the window's first base inside it
+// (Section 2.2, extension information; Section 3.3, its compression in transit).  The
+// occurrences of one k-mer are listed in ascending (read, position) order.
+//
 // Steps are written the slow, obvious way: every window is re-read base by base.
 #include <algorithm>
 #include <cstdint>
@@ -51,6 +56,15 @@ typedef struct {
   uint64_t overflow_sum;
   uint64_t max_count;
 } kco_result;
+
+// Extension information of the reported k-mers: occurrence i of pair j is
+// (read[off[j] + i], pos[off[j] + i]), ascending by (read, pos) within the pair.
+typedef struct {
+  uint64_t n_occ;
+  uint64_t *off;       // n_pairs + 1
+  uint32_t *read;      // n_occ: index of the read holding the window
+  uint32_t *pos;       // n_occ: offset of the window's first base inside that read
+} kco_occ;
 
 }  // extern "C"
 
@@ -147,6 +161,81 @@ int count_all(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, i
   return 0;
 }
 
+// Extension version (Section 2.2: a k-mer may travel with the index of its read and
+// its position in that read): every window is kept as (canonical value, read, pos),
+// the triples are sorted, and each run of equal values is one distinct k-mer whose
+// occurrences are the run's (read, pos) in ascending order.
+template <typename V>
+struct Occ {
+  V v;
+  uint32_t read, pos;
+  bool operator<(const Occ &o) const {
+    if (v != o.v) return v < o.v;
+    if (read != o.read) return read < o.read;
+    return pos < o.pos;
+  }
+};
+
+template <typename V>
+int count_ext(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k,
+              uint32_t lo, uint32_t hi, uint64_t hist_len, uint32_t key_words,
+              kco_result *out, kco_occ *occ) {
+  std::vector<Occ<V>> all;
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    uint64_t len = offsets[r + 1] - offsets[r];
+    if (len < (uint64_t)k) continue;
+    const uint8_t *read = reads + offsets[r];
+    for (uint64_t i = 0; i + (uint64_t)k <= len; ++i) {
+      V v;
+      if (window_value<V>(read, i, k, &v)) all.push_back(Occ<V>{v, (uint32_t)r, (uint32_t)i});
+    }
+  }
+  std::sort(all.begin(), all.end());
+  out->hist = (uint64_t *)calloc(hist_len, sizeof(uint64_t));
+  std::vector<uint64_t> keys, offs{0};
+  std::vector<uint32_t> cnts, rd, ps;
+  size_t i = 0;
+  while (i < all.size()) {
+    size_t j = i;
+    while (j < all.size() && all[j].v == all[i].v) ++j;
+    uint64_t c = j - i;
+    out->n_distinct += 1;
+    out->n_windows += c;
+    if (c > out->max_count) out->max_count = c;
+    if (c >= hist_len - 1) {
+      out->hist[hist_len - 1] += 1;
+      out->overflow_sum += c;
+    } else {
+      out->hist[c] += 1;
+    }
+    if (c >= lo && c <= hi) {
+      uint64_t w[2];
+      put_key(w, all[i].v);
+      for (uint32_t q = 0; q < key_words; ++q) keys.push_back(w[q]);
+      cnts.push_back((uint32_t)c);
+      for (size_t t = i; t < j; ++t) {
+        rd.push_back(all[t].read);
+        ps.push_back(all[t].pos);
+      }
+      offs.push_back(rd.size());
+    }
+    i = j;
+  }
+  out->n_pairs = cnts.size();
+  out->kmers = (uint64_t *)malloc(std::max<size_t>(1, keys.size()) * sizeof(uint64_t));
+  out->counts = (uint32_t *)malloc(std::max<size_t>(1, cnts.size()) * sizeof(uint32_t));
+  if (!keys.empty()) memcpy(out->kmers, keys.data(), keys.size() * sizeof(uint64_t));
+  if (!cnts.empty()) memcpy(out->counts, cnts.data(), cnts.size() * sizeof(uint32_t));
+  occ->n_occ = rd.size();
+  occ->off = (uint64_t *)malloc(offs.size() * sizeof(uint64_t));
+  occ->read = (uint32_t *)malloc(std::max<size_t>(1, rd.size()) * sizeof(uint32_t));
+  occ->pos = (uint32_t *)malloc(std::max<size_t>(1, ps.size()) * sizeof(uint32_t));
+  memcpy(occ->off, offs.data(), offs.size() * sizeof(uint64_t));
+  if (!rd.empty()) memcpy(occ->read, rd.data(), rd.size() * sizeof(uint32_t));
+  if (!ps.empty()) memcpy(occ->pos, ps.data(), ps.size() * sizeof(uint32_t));
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -163,6 +252,33 @@ int kco_count(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, i
   out->key_words = k <= 31 ? 1 : 2;
   if (k <= 31) return count_all<uint64_t>(reads, offsets, n_reads, k, lo, hi, hist_len, 1, out);
   return count_all<u128>(reads, offsets, n_reads, k, lo, hi, hist_len, 2, out);
+}
+
+// Extension version of kco_count: the same result, plus the occurrences of every
+// reported k-mer in *occ (free with kco_occ_free).  Read indices and positions must fit
+// 32 bits.
+int kco_count_ext(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k,
+                  uint32_t lo, uint32_t hi, uint64_t hist_len, kco_result *out, kco_occ *occ) {
+  if (!out || !occ) return -1;
+  memset(out, 0, sizeof(*out));
+  memset(occ, 0, sizeof(*occ));
+  if (k < 1 || k > 63 || hist_len < 2 || lo > hi) return -1;
+  if (n_reads > 0 && (!offsets || !reads)) return -1;
+  if (n_reads >= (1ull << 32)) return -1;
+  for (uint64_t r = 0; r < n_reads; ++r)
+    if (offsets[r + 1] - offsets[r] >= (1ull << 32)) return -1;
+  out->hist_len = hist_len;
+  out->key_words = k <= 31 ? 1 : 2;
+  if (k <= 31) return count_ext<uint64_t>(reads, offsets, n_reads, k, lo, hi, hist_len, 1, out, occ);
+  return count_ext<u128>(reads, offsets, n_reads, k, lo, hi, hist_len, 2, out, occ);
+}
+
+void kco_occ_free(kco_occ *o) {
+  if (!o) return;
+  free(o->off);
+  free(o->read);
+  free(o->pos);
+  memset(o, 0, sizeof(*o));
 }
 
 void kco_free(kco_result *r) {

@@ -25,6 +25,26 @@ def brute_count(seqs: Iterable[str], k: int) -> Dict[str, int]:
     return d
 
 
+def brute_occurrences(seqs: Iterable[str], k: int) -> Dict[str, List[Tuple[int, int]]]:
+    """Canonical k-mer string -> list of (read index, window start), in read order."""
+    d: Dict[str, List[Tuple[int, int]]] = {}
+    for r, s in enumerate(seqs):
+        for i in range(len(s) - k + 1):
+            w = s[i:i + k]
+            if not all(ch in _VALID for ch in w):
+                continue
+            w = w.upper()
+            rc = "".join(_COMP[ch] for ch in reversed(w))
+            d.setdefault(w if w <= rc else rc, []).append((r, i))
+    return d
+
+
+def canonical_str(w: str) -> str:
+    w = w.upper()
+    rc = "".join(_COMP[ch] for ch in reversed(w))
+    return w if w <= rc else rc
+
+
 def decode(words, k: int) -> str:
     """Integer k-mer (first base in the most significant two bits) -> string."""
     v = int(words[0])

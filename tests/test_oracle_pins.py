@@ -249,3 +249,100 @@ def test_query_matches_count():
         idx = np.arange(0, full.n_pairs, max(1, full.n_pairs // 50))
         q = oracle.query(reads, offsets, k, full.kmers[idx])
         assert np.array_equal(q, full.counts[idx].astype(np.uint64))
+
+
+# ---------------------------------------------------------------------------- extension version
+from tests.brute import brute_occurrences, canonical_str  # noqa: E402
+
+GOLDEN_OCC = os.path.join(os.path.dirname(__file__), "golden", "hand_occurrences.tsv")
+
+
+def _ext_lists(res, k):
+    out = []
+    for j in range(res.base.n_pairs):
+        a, b = int(res.occ_off[j]), int(res.occ_off[j + 1])
+        out.append((decode(res.base.kmers[j], k),
+                    [(int(r), int(p)) for r, p in zip(res.occ_read[a:b], res.occ_pos[a:b])]))
+    return out
+
+
+def _check_ext_against_brute(reads, offsets, k, lo=1, hi=0xFFFFFFFF, H=64):
+    res = oracle.count_ext(reads, offsets, k, lo, hi, H)
+    ref = brute_occurrences(split_reads(reads, offsets), k)
+    exp = sorted((s, sorted(v)) for s, v in ref.items() if lo <= len(v) <= hi)
+    assert _ext_lists(res, k) == exp
+    assert [c for _, c in pairs_of(res.base, k)] == [len(v) for _, v in exp]
+    exp_hist = np.zeros(H, dtype=np.uint64)
+    for v in ref.values():
+        exp_hist[min(len(v), H - 1)] += 1
+    assert np.array_equal(res.base.hist, exp_hist)
+    assert res.base.n_windows == sum(len(v) for v in ref.values())
+    assert int(res.occ_off[-1]) == int(res.base.counts.astype(np.uint64).sum())
+    return res
+
+
+def test_ext_hand_strings():
+    n = 0
+    with open(GOLDEN_OCC) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, seqs, spec = line.rstrip("\n").split("\t")
+            k = int(k)
+            exp = []
+            for item in spec.split(","):
+                kmer, occ = item.split("=")
+                exp.append((kmer, [tuple(int(x) for x in o.split("/")) for o in occ.split(";")]))
+            reads, offsets = synth.from_strings(seqs.split(","))
+            res = oracle.count_ext(reads, offsets, k, 1, 0xFFFFFFFF, 16)
+            assert _ext_lists(res, k) == exp, line
+            n += 1
+    assert n >= 6
+
+
+def test_ext_brute_force_random_tiny():
+    rng = np.random.Generator(np.random.PCG64(4242))
+    for case in range(3000):
+        k = int(rng.integers(1, 10))
+        reads, offsets = synth.random_small(rng, int(rng.integers(0, 5)), 40, p_bad=0.1)
+        lo = int(rng.integers(1, 4))
+        hi = int(rng.integers(lo, 6))
+        _check_ext_against_brute(reads, offsets, k, lo, hi, int(rng.integers(2, 8)))
+
+
+@pytest.mark.parametrize("k", [17, 31, 32, 51, 63])
+def test_ext_brute_force_long_k(k):
+    rng = np.random.Generator(np.random.PCG64(2000 + k))
+    genome = "".join("ACGT"[i] for i in rng.integers(0, 4, 300))
+    seqs = []
+    for _ in range(50):
+        s = int(rng.integers(0, 220))
+        r = genome[s:s + int(rng.integers(k - 2, 90))]
+        if rng.random() < 0.5:
+            r = r.encode().translate(_RC)[::-1].decode()
+        seqs.append(r.lower() if rng.random() < 0.2 else r)
+    reads, offsets = synth.from_strings(seqs)
+    res = _check_ext_against_brute(reads, offsets, k, 2, 0xFFFFFFFF, 8)
+    assert res.base.n_pairs > 0
+
+
+@pytest.mark.parametrize("k", [5, 31, 51])
+def test_ext_properties(k):
+    reads, offsets = _rand_medium(300 + k, n_reads=400)
+    seqs = split_reads(reads, offsets)
+    for lo, hi in [(1, 0xFFFFFFFF), (2, 9)]:
+        ext = oracle.count_ext(reads, offsets, k, lo, hi, 32)
+        plain = oracle.count(reads, offsets, k, lo, hi, 32)
+        # the counts are those of the plain version ...
+        assert np.array_equal(ext.base.kmers, plain.kmers) and np.array_equal(ext.base.counts, plain.counts)
+        assert np.array_equal(ext.base.hist, plain.hist)
+        # ... each count is the length of the k-mer's occurrence list ...
+        assert np.array_equal(np.diff(ext.occ_off), ext.base.counts.astype(np.uint64))
+        # ... and every occurrence is a window of its read whose canonical form is the k-mer
+        for j in range(0, ext.base.n_pairs, max(1, ext.base.n_pairs // 200)):
+            want = decode(ext.base.kmers[j], k)
+            a, b = int(ext.occ_off[j]), int(ext.occ_off[j + 1])
+            occ = list(zip(ext.occ_read[a:b].tolist(), ext.occ_pos[a:b].tolist()))
+            assert occ == sorted(set(occ))
+            for r, p in occ:
+                assert canonical_str(seqs[r][p:p + k]) == want
