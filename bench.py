@@ -73,6 +73,8 @@ def parse():
                    help="size factor of the batched sets (1.0 = genomes of 1-20 Mbp, 1-200 Mbp of reads each)")
     p.add_argument("--serve-seconds", type=float, default=10.0, help="seconds of Poisson arrivals per rate (0: skip)")
     p.add_argument("--serve-rates", type=str, default="5,20,50")
+    p.add_argument("--ext-steps", type=int, default=10,
+                   help="timed counts of the extension version on the same workload (0: skip)")
     return p.parse_args()
 
 
@@ -188,6 +190,49 @@ def batched_leg(args, torch, kc, synth) -> tuple:
     }
     assert res["bit_exact_batch_vs_plain"] and res["bit_exact_vs_oracle"], "batched results differ"
     return res, sets, ref
+
+
+EXT_STAGES = ["encode", "windows", "sort", "runs", "emit"]
+
+
+def ext_leg(args, torch, kc, rs, d_reads, d_offsets, plain_digest) -> dict:
+    """The extension version on the same workload: every reported k-mer with the list of
+    its occurrences (read, position).  Same timing discipline as the main leg; the radix
+    sort of (key, base offset) pairs is HBM-bound and reported against the HBM peak."""
+    ctr = kc.DeviceExtCounter(rs.n_bases, rs.n_reads, rs.k, rs.min_freq, rs.max_freq, 65536)
+    tot = None
+    for _ in range(max(1, args.warmup)):
+        tot = ctr.count(d_reads, d_offsets)
+    res = ctr.result(tot)
+    same = digest(res.pairs.kmers, res.pairs.counts, res.pairs.hist) == plain_digest
+    st = torch.cuda.current_stream()
+    kc.kc_profile(True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.ext_steps):
+        ctr.count(d_reads, d_offsets, stream=st, sync=False)
+    e1.record(st)
+    torch.cuda.synchronize()
+    kc.kc_profile(False)
+    stages = kc.kc_profile_read()
+    ms = e0.elapsed_time(e1) / args.ext_steps
+    per = {name: stages[s] / max(1, stages["n_counts"]) for name, s in zip(EXT_STAGES, kc.STAGES)}
+    n_win, w = int(tot["n_windows"]), 8 * (1 if rs.k <= 31 else 2)
+    passes = (2 * rs.k + 7) // 8
+    # per 8-bit pass: the upsweep reads every key, the downsweep reads and writes every
+    # (key, 32-bit offset) pair
+    sort_bytes = passes * n_win * (w + 2 * (w + 4))
+    gbs = sort_bytes / (per["sort"] * 1e-3) / 1e9
+    return {
+        "value": n_win / (ms * 1e-3), "unit": "k-mers/s", "ms_per_step": round(ms, 4), "steps": args.ext_steps,
+        "n_pairs": int(tot["n_pairs"]), "n_occ": int(tot["n_occ"]),
+        "stage_ms": {k: round(v, 4) for k, v in per.items()},
+        "pairs_equal_plain_count": same,
+        "sort_roofline": {"bound": "hbm", "kernels": "k_radix_upsweep/rowscan/downsweep x %d passes" % passes,
+                          "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(gbs / HBM_PEAK_GBS, 4), "algo_bytes": int(sort_bytes)},
+    }
 
 
 def ctypes_words(kc) -> int:
@@ -371,6 +416,14 @@ def main():
         "wall_s": round(wall, 3),
         "roofline": roofline,
     }
+    if args.ext_steps > 0:
+        print("bench: extension version", file=sys.stderr, flush=True)
+        pres = ctr.result(final)
+        pd = digest(pres.kmers, pres.counts, pres.hist)
+        del ctr
+        torch.cuda.empty_cache()
+        out["extension"] = ext_leg(args, torch, kc, rs, d_reads, d_offsets, pd)
+        assert out["extension"]["pairs_equal_plain_count"], "extension pairs differ from the plain count"
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(rs, args.cpu_sample_frac)

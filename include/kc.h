@@ -73,6 +73,8 @@ typedef struct kc_totals {
   uint64_t chunks;         /* on-chip chunks of the large buckets */
   uint64_t list_entries;   /* (k-mer, count) entries the chunks produced */
   uint64_t buckets;        /* B */
+  uint64_t n_occ;          /* extension version: occurrences listed for the reported k-mers
+                              (0 for the plain count) */
 } kc_totals;
 
 typedef struct kc_result {
@@ -132,6 +134,62 @@ int kc_count_device_async(const uint8_t *d_reads, uint64_t total_bases, const ui
                           uint64_t hist_len, const kc_config *cfg, void *d_workspace,
                           size_t workspace_bytes, uint64_t *d_kmers, uint32_t *d_counts,
                           uint64_t pair_capacity, uint64_t *d_hist, kc_totals *d_totals, void *stream);
+
+/* ---------------------------------------------------------------- extension version
+ * The count with extension information (Section 2.2: a k-mer may carry the ID of the read
+ * it came from and its position in that read; Section 3.3 compresses that information
+ * in transit).  Every reported k-mer also lists all of its occurrences as (read index,
+ * offset of the window's first base inside the read), ascending by (read, offset).
+ * Pairs, counts, histogram and totals are exactly those of kc_count; m plays no part.
+ * Internally each window travels as (canonical key, 32-bit base offset) through one
+ * stable LSD radix sort; the offset is decoded into (read, position) only for the
+ * reported k-mers.  Read indices and in-read offsets are 32-bit: n_reads < 2^32. */
+typedef struct kc_ext_result {
+  kc_result pairs;         /* k-mers, counts, histogram, totals (totals.n_occ = n_occ) */
+  uint64_t n_occ;          /* sum of the reported counts */
+  uint64_t *occ_off;       /* pairs.n_pairs + 1 entries: pair i's occurrences are
+                              [occ_off[i], occ_off[i+1]) of the two arrays below */
+  uint32_t *occ_read;      /* n_occ read indices */
+  uint32_t *occ_pos;       /* n_occ offsets of the window inside its read */
+} kc_ext_result;
+
+/* Host API of the extension version.  Arguments and errors as kc_count (no m); on KC_OK
+ * *out owns host arrays that kc_ext_result_free releases.  cfg->hbm_budget (if set)
+ * bounds the device workspace: KC_ENOMEM when it does not fit. */
+int kc_count_ext(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k,
+                 uint32_t min_freq, uint32_t max_freq, uint64_t hist_len, const kc_config *cfg,
+                 kc_ext_result *out);
+
+/* Release the arrays of a kc_ext_result filled by kc_count_ext (safe on a zeroed one). */
+void kc_ext_result_free(kc_ext_result *res);
+
+/* Bytes of device workspace kc_count_ext_device needs (0 on bad arguments). */
+size_t kc_ext_workspace_size(uint64_t total_bases, uint64_t n_reads, int k);
+
+/* Device API of the extension version; every buffer is caller-owned device memory:
+ *   d_kmers (pair_capacity * key_words words), d_counts (pair_capacity), d_occ_off
+ *   (pair_capacity + 1 entries), d_occ_read and d_occ_pos (occ_capacity each), d_hist
+ *   (hist_len), d_totals (one kc_totals; n_occ gives the occurrences needed).
+ *   Work is queued on `stream`; the call waits, copies the totals to *totals_out (may
+ *   be NULL) and returns KC_ETRUNC when n_pairs > pair_capacity or n_occ >
+ *   occ_capacity (outputs are then cut at the capacities). */
+int kc_count_ext_device(const uint8_t *d_reads, uint64_t total_bases, const uint64_t *d_offsets,
+                        uint64_t n_reads, int k, uint32_t min_freq, uint32_t max_freq,
+                        uint64_t hist_len, const kc_config *cfg, void *d_workspace,
+                        size_t workspace_bytes, uint64_t *d_kmers, uint32_t *d_counts,
+                        uint64_t pair_capacity, uint64_t *d_occ_off, uint32_t *d_occ_read,
+                        uint32_t *d_occ_pos, uint64_t occ_capacity, uint64_t *d_hist,
+                        kc_totals *d_totals, void *stream, kc_totals *totals_out);
+
+/* As kc_count_ext_device but returns right after queueing (no wait, no KC_ETRUNC): read
+ * *d_totals after synchronizing the stream. */
+int kc_count_ext_device_async(const uint8_t *d_reads, uint64_t total_bases, const uint64_t *d_offsets,
+                              uint64_t n_reads, int k, uint32_t min_freq, uint32_t max_freq,
+                              uint64_t hist_len, const kc_config *cfg, void *d_workspace,
+                              size_t workspace_bytes, uint64_t *d_kmers, uint32_t *d_counts,
+                              uint64_t pair_capacity, uint64_t *d_occ_off, uint32_t *d_occ_read,
+                              uint32_t *d_occ_pos, uint64_t occ_capacity, uint64_t *d_hist,
+                              kc_totals *d_totals, void *stream);
 
 /* ---------------------------------------------------------------- batched counting
  * One read set of a batch (or a server request).  reads/offsets are host pointers for

@@ -23,6 +23,7 @@
 #include "kc_partition.hpp"
 #include "kc_sort.hpp"
 #include "kc_segsort.hpp"
+#include "kc_ext.hpp"
 
 namespace {
 
@@ -648,6 +649,201 @@ int device_common(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* 
                      reinterpret_cast<DevTotals*>(d_tot), reinterpret_cast<hipStream_t>(stream));
 }
 
+// ---------------------------------------------------------------------------- extension version
+// Workspace of one extension count: the packed reads and masks, two (key, offset)
+// buffers for the out-of-place sort, run heads, per-block counts and the read table.
+struct ExtPlan {
+  int k = 0, key_words = 0;
+  u64 R = 0, n_reads = 0, N = 0;   // bases, reads, window positions (upper bound)
+  u64 n_tiles = 1, n_packed = 0, n_mask = 0, n_blk = 0;
+  u32 nb = 1;                      // radix blocks
+  u64 o_packed, o_nmask, o_starts, o_k0, o_k1, o_v0, o_v1, o_hp, o_blk, o_bp, o_bo, o_rid, o_ctrl, o_cnt, o_tot,
+      o_scan, bytes = 0;
+};
+
+enum ExtCtrl : int { X_NWIN = 0, X_NRUNS = 1, X_NPAIRS = 2, X_NOCC = 3, X_FLAGS = 4, X_WORDS = 5 };
+
+bool make_ext_plan(u64 R, u64 n_reads, int k, ExtPlan* p) {
+  p->k = k;
+  p->key_words = k <= 31 ? 1 : 2;
+  p->R = R;
+  p->n_reads = n_reads;
+  p->N = std::max<u64>(1, R);
+  p->n_tiles = std::max<u64>(1, ceil_div(p->N, EXT_TILE));
+  if (p->n_tiles > 1024ull * SCAN_BLOCK) return false;
+  p->n_packed = R / 16 + 16;
+  p->n_mask = R / 32 + 16;
+  p->n_blk = R / 64 + 2;
+  const u64 w = 8ull * p->key_words;
+  const u64 tile = (u64)RADIX_T * (p->key_words == 1 ? RADIX_ITEMS_64 : RADIX_ITEMS_128);
+  p->nb = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(p->N, tile * 2)));
+  u64 o = 0;
+  auto take = [&](u64 bytes) {
+    u64 r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  p->o_packed = take(4 * p->n_packed);
+  p->o_nmask = take(4 * p->n_mask);
+  p->o_starts = take(4 * p->n_mask);
+  p->o_k0 = take(w * p->N);
+  p->o_k1 = take(w * p->N);
+  p->o_v0 = take(4 * p->N);
+  p->o_v1 = take(4 * p->N);
+  p->o_hp = take(4 * p->N);
+  p->o_blk = take(4 * p->n_tiles);
+  p->o_bp = take(4 * p->n_tiles);
+  p->o_bo = take(4 * p->n_tiles);
+  p->o_rid = take(4 * p->n_blk);
+  p->o_ctrl = take(8ull * X_WORDS);
+  p->o_cnt = take(4ull * 256 * p->nb);
+  p->o_tot = take(4ull * 256);
+  p->o_scan = take(8ull * 1024);
+  p->bytes = o;
+  return true;
+}
+
+template <typename K>
+int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_offsets, uint32_t lo,
+                uint32_t hi, uint64_t hist_len, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap,
+                uint64_t* d_occ_off, uint32_t* d_occ_read, uint32_t* d_occ_pos, uint64_t occ_cap, uint64_t* d_hist,
+                DevTotals* d_tot, hipStream_t st) {
+  u32* packed = at<u32>(ws, P.o_packed);
+  u32* nmask = at<u32>(ws, P.o_nmask);
+  u32* starts = at<u32>(ws, P.o_starts);
+  K* k0 = at<K>(ws, P.o_k0);
+  K* k1 = at<K>(ws, P.o_k1);
+  u32* v0 = at<u32>(ws, P.o_v0);
+  u32* v1 = at<u32>(ws, P.o_v1);
+  u32* hp = at<u32>(ws, P.o_hp);
+  u32* blk = at<u32>(ws, P.o_blk);
+  u32* bp = at<u32>(ws, P.o_bp);
+  u32* bo = at<u32>(ws, P.o_bo);
+  u32* rid = at<u32>(ws, P.o_rid);
+  u64* ctrl = at<u64>(ws, P.o_ctrl);
+  u64* scanbuf = at<u64>(ws, P.o_scan);
+  u32* flags = reinterpret_cast<u32*>(ctrl + X_FLAGS);
+  auto fill = [&](void* p, u64 n_words, u32 v) {
+    if (n_words)
+      hipLaunchKernelGGL(k_fill_u32, grid_for(n_words, 256, 4096), dim3(256), 0, st, (u32*)p, n_words, v);
+  };
+  stage_mark(0, st);
+  fill(ctrl, 2ull * X_WORDS, 0u);
+  fill(d_hist, 2ull * hist_len, 0u);
+  fill(d_tot, sizeof(DevTotals) / 4, 0u);
+  fill(starts, P.n_mask, 0u);
+  fill(rid, P.n_blk, 0xFFFFFFFFu);
+  const u64 n32 = ceil_div(P.R, 32);
+  fill(packed + 2 * n32, P.n_packed - 2 * n32, 0u);
+  fill(nmask + n32, P.n_mask - n32, 0u);
+  if (P.R) hipLaunchKernelGGL(k_pack, grid_for(n32, 256), dim3(256), 0, st, d_reads, P.R, packed, nmask);
+  if (P.n_reads) {
+    hipLaunchKernelGGL(k_read_starts, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, starts,
+                       flags);
+    hipLaunchKernelGGL(k_ext_read_blocks, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, rid,
+                       P.n_blk);
+  }
+  stage_mark(1, st);
+  // window positions: every base of the buffer; the kernel keeps the windows inside
+  // [offsets[0], offsets[n_reads]) that hold k valid bases of one read
+  ExtWinArgs wa;
+  wa.packed = packed;
+  wa.nmask = nmask;
+  wa.starts = starts;
+  wa.offsets = d_offsets;
+  wa.n_reads = P.n_reads;
+  wa.R = P.R;
+  wa.n_pos = P.R >= (u64)P.k ? P.R - (u64)P.k + 1 : 0;
+  wa.k = P.k;
+  wa.blk = blk;
+  wa.keys = k0;
+  wa.vals = v0;
+  const dim3 gw((u32)P.n_tiles);
+  hipLaunchKernelGGL((k_ext_windows<K, false>), gw, dim3(EXT_T), 0, st, wa);
+  scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles, ctrl + X_NWIN, scanbuf, st);
+  hipLaunchKernelGGL((k_ext_windows<K, true>), gw, dim3(EXT_T), 0, st, wa);
+  stage_mark(2, st);
+  bool second = false;
+  int rc = radix_sort<K, true>(k0, k1, v0, v1, ctrl + X_NWIN, at<u32>(ws, P.o_cnt), at<u32>(ws, P.o_tot), P.nb,
+                               2 * P.k, st, &second);
+  if (rc) return rc;
+  const K* sk = second ? k1 : k0;
+  const u32* sv = second ? v1 : v0;
+  stage_mark(3, st);
+  hipLaunchKernelGGL((k_ext_heads<K, false>), gw, dim3(EXT_T), 0, st, sk, ctrl + X_NWIN, blk, hp);
+  scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles, ctrl + X_NRUNS, scanbuf, st);
+  hipLaunchKernelGGL((k_ext_heads<K, true>), gw, dim3(EXT_T), 0, st, sk, ctrl + X_NWIN, blk, hp);
+  ExtRunArgs ra;
+  ra.keys = sk;
+  ra.vals = sv;
+  ra.hp = hp;
+  ra.n_ptr = ctrl + X_NWIN;
+  ra.nruns_ptr = ctrl + X_NRUNS;
+  ra.min_freq = lo;
+  ra.max_freq = hi;
+  ra.hist_len = hist_len;
+  ra.hist = d_hist;
+  ra.tot = d_tot;
+  ra.blk_pairs = bp;
+  ra.blk_occ = bo;
+  ra.offsets = d_offsets;
+  ra.n_reads = P.n_reads;
+  ra.rid = rid;
+  ra.n_blk = P.n_blk;
+  ra.out_k = d_kmers;
+  ra.out_c = d_counts;
+  ra.occ_off = d_occ_off;
+  ra.pair_cap = pair_cap;
+  ra.occ_read = d_occ_read;
+  ra.occ_pos = d_occ_pos;
+  ra.occ_cap = occ_cap;
+  hipLaunchKernelGGL((k_ext_runs<K, false>), gw, dim3(EXT_T), 0, st, ra);
+  scan_u32(bp, bp, (const u64*)nullptr, P.n_tiles, ctrl + X_NPAIRS, scanbuf, st);
+  scan_u32(bo, bo, (const u64*)nullptr, P.n_tiles, ctrl + X_NOCC, scanbuf, st);
+  stage_mark(4, st);
+  hipLaunchKernelGGL((k_ext_runs<K, true>), gw, dim3(EXT_T), 0, st, ra);
+  hipLaunchKernelGGL(k_ext_finalize, dim3(1), dim3(64), 0, st, d_tot, ctrl + X_NWIN, ctrl + X_NPAIRS, ctrl + X_NOCC,
+                     flags, d_occ_off, pair_cap);
+  stage_mark(5, st);
+  HIP_TRY(hipGetLastError());
+  return KC_OK;
+}
+
+int ext_check(int k, uint32_t lo, uint32_t hi, uint64_t hist_len, uint64_t total_bases, uint64_t n_reads) {
+  if (k < 1 || k > 63) return fail(KC_EINVAL, "k=%d outside [1, 63]", k);
+  if (lo < 1 || lo > hi) return fail(KC_EINVAL, "frequency bounds [%u, %u] invalid", lo, hi);
+  if (hist_len < 2) return fail(KC_EINVAL, "hist_len=%llu < 2", (unsigned long long)hist_len);
+  if (total_bases >= (1ull << 32)) return fail(KC_EINVAL, "total_bases=%llu >= 2^32", (unsigned long long)total_bases);
+  if (n_reads >= (1ull << 32)) return fail(KC_EINVAL, "n_reads=%llu >= 2^32", (unsigned long long)n_reads);
+  return KC_OK;
+}
+
+int enqueue_ext_any(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_offsets, uint32_t lo,
+                    uint32_t hi, uint64_t hist_len, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap,
+                    uint64_t* d_occ_off, uint32_t* d_occ_read, uint32_t* d_occ_pos, uint64_t occ_cap,
+                    uint64_t* d_hist, DevTotals* d_tot, hipStream_t st) {
+  g_ev_cur = nullptr;
+  if (g_profile) {
+    if (g_ev_used == g_ev_pool.size()) {
+      StageEvents e;
+      for (int i = 0; i <= KC_N_STAGES; ++i) HIP_TRY(hipEventCreate(&e.ev[i]));
+      g_ev_pool.push_back(e);
+    }
+    g_ev_cur = &g_ev_pool[g_ev_used++];
+  }
+  int rc;
+  if (P.key_words == 1)
+    rc = enqueue_ext<u64>(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_occ_off,
+                          d_occ_read, d_occ_pos, occ_cap, d_hist, d_tot, st);
+  else
+    rc = enqueue_ext<k128>(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_occ_off,
+                           d_occ_read, d_occ_pos, occ_cap, d_hist, d_tot, st);
+  if (rc) return rc;
+  // the unused stage marks close at the end so that the stage table stays well formed
+  for (int i = 6; i <= KC_N_STAGES; ++i) stage_mark(i, st);
+  return KC_OK;
+}
+
 }  // namespace
 
 static_assert(sizeof(DevTotals) == sizeof(kc_totals), "device and ABI totals differ");
@@ -799,6 +995,168 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
   if ((t.n_pairs && (hipMemcpy(out->kmers, d_kmers, t.n_pairs * w, hipMemcpyDeviceToHost) != hipSuccess ||
                      hipMemcpy(out->counts, d_counts, t.n_pairs * 4, hipMemcpyDeviceToHost) != hipSuccess)) ||
       hipMemcpy(out->hist, d_hist, hist_len * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "D2H failed"));
+  return cleanup(KC_OK);
+}
+
+// ---------------------------------------------------------------- extension version
+size_t kc_ext_workspace_size(uint64_t total_bases, uint64_t n_reads, int k) {
+  if (k < 1 || k > 63) return 0;
+  ExtPlan P;
+  if (!make_ext_plan(total_bases, n_reads, k, &P)) return 0;
+  return (size_t)P.bytes;
+}
+
+static int ext_device_common(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* d_offsets, uint64_t n_reads,
+                             int k, uint32_t lo, uint32_t hi, uint64_t hist_len, const kc_config* cfg, void* ws,
+                             size_t ws_bytes, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap,
+                             uint64_t* d_occ_off, uint32_t* d_occ_read, uint32_t* d_occ_pos, uint64_t occ_cap,
+                             uint64_t* d_hist, kc_totals* d_tot, void* stream) {
+  int rc = ext_check(k, lo, hi, hist_len, total_bases, n_reads);
+  if (rc) return rc;
+  if ((total_bases && !d_reads) || !d_offsets || !ws || !d_hist || !d_tot || !d_occ_off ||
+      (pair_cap && (!d_kmers || !d_counts)) || (occ_cap && (!d_occ_read || !d_occ_pos)))
+    return fail(KC_EINVAL, "NULL device pointer");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(KC_EINVAL, "workspace not 256-byte aligned");
+  ExtPlan P;
+  if (!make_ext_plan(total_bases, n_reads, k, &P)) return fail(KC_EINVAL, "input too large");
+  if (ws_bytes < P.bytes)
+    return fail(KC_EINVAL, "workspace of %zu bytes < %llu needed", ws_bytes, (unsigned long long)P.bytes);
+  if (cfg && cfg->hbm_budget && P.bytes > cfg->hbm_budget)
+    return fail(KC_ENOMEM, "workspace %llu bytes > budget %llu", (unsigned long long)P.bytes,
+                (unsigned long long)cfg->hbm_budget);
+  return enqueue_ext_any(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_occ_off,
+                         d_occ_read, d_occ_pos, occ_cap, d_hist, reinterpret_cast<DevTotals*>(d_tot),
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+int kc_count_ext_device_async(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* d_offsets,
+                              uint64_t n_reads, int k, uint32_t min_freq, uint32_t max_freq, uint64_t hist_len,
+                              const kc_config* cfg, void* d_workspace, size_t workspace_bytes, uint64_t* d_kmers,
+                              uint32_t* d_counts, uint64_t pair_capacity, uint64_t* d_occ_off, uint32_t* d_occ_read,
+                              uint32_t* d_occ_pos, uint64_t occ_capacity, uint64_t* d_hist, kc_totals* d_totals,
+                              void* stream) {
+  g_err.clear();
+  return ext_device_common(d_reads, total_bases, d_offsets, n_reads, k, min_freq, max_freq, hist_len, cfg,
+                           d_workspace, workspace_bytes, d_kmers, d_counts, pair_capacity, d_occ_off, d_occ_read,
+                           d_occ_pos, occ_capacity, d_hist, d_totals, stream);
+}
+
+int kc_count_ext_device(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* d_offsets, uint64_t n_reads,
+                        int k, uint32_t min_freq, uint32_t max_freq, uint64_t hist_len, const kc_config* cfg,
+                        void* d_workspace, size_t workspace_bytes, uint64_t* d_kmers, uint32_t* d_counts,
+                        uint64_t pair_capacity, uint64_t* d_occ_off, uint32_t* d_occ_read, uint32_t* d_occ_pos,
+                        uint64_t occ_capacity, uint64_t* d_hist, kc_totals* d_totals, void* stream,
+                        kc_totals* totals_out) {
+  g_err.clear();
+  int rc = ext_device_common(d_reads, total_bases, d_offsets, n_reads, k, min_freq, max_freq, hist_len, cfg,
+                             d_workspace, workspace_bytes, d_kmers, d_counts, pair_capacity, d_occ_off, d_occ_read,
+                             d_occ_pos, occ_capacity, d_hist, d_totals, stream);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  kc_totals t;
+  HIP_TRY(hipMemcpyAsync(&t, d_totals, sizeof(t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (totals_out) *totals_out = t;
+  if (t.flags & 1) return fail(KC_EINVAL, "offsets are not non-decreasing or exceed total_bases");
+  if (t.flags) return fail(KC_EDEVICE, "internal status flags=%llu", (unsigned long long)t.flags);
+  if (t.n_pairs > pair_capacity || t.n_occ > occ_capacity)
+    return fail(KC_ETRUNC, "%llu pairs / %llu occurrences > capacities %llu / %llu", (unsigned long long)t.n_pairs,
+                (unsigned long long)t.n_occ, (unsigned long long)pair_capacity, (unsigned long long)occ_capacity);
+  return KC_OK;
+}
+
+void kc_ext_result_free(kc_ext_result* r) {
+  if (!r) return;
+  kc_result_free(&r->pairs);
+  free(r->occ_off);
+  free(r->occ_read);
+  free(r->occ_pos);
+  memset(r, 0, sizeof(*r));
+}
+
+int kc_count_ext(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, uint32_t min_freq,
+                 uint32_t max_freq, uint64_t hist_len, const kc_config* cfg, kc_ext_result* out) {
+  g_err.clear();
+  if (!out) return fail(KC_EINVAL, "out is NULL");
+  memset(out, 0, sizeof(*out));
+  if (!offsets || (n_reads && !reads)) return fail(KC_EINVAL, "NULL host pointer");
+  u64 n_max = 0;
+  for (u64 r = 0; r < n_reads; ++r) {
+    if (offsets[r + 1] < offsets[r]) return fail(KC_EINVAL, "offsets decrease at read %llu", (unsigned long long)r);
+    const u64 L = offsets[r + 1] - offsets[r];
+    if (L >= (u64)k) n_max += L - (u64)k + 1;
+  }
+  const u64 R = n_reads ? offsets[n_reads] : 0;
+  int rc = ext_check(k, min_freq, max_freq, hist_len, R, n_reads);
+  if (rc) return rc;
+  ExtPlan P;
+  if (!make_ext_plan(R, n_reads, k, &P)) return fail(KC_EINVAL, "input too large");
+  if (cfg && cfg->hbm_budget && P.bytes > cfg->hbm_budget)
+    return fail(KC_ENOMEM, "workspace %llu bytes > budget %llu", (unsigned long long)P.bytes,
+                (unsigned long long)cfg->hbm_budget);
+  const u64 w = 8ull * P.key_words, cap = std::max<u64>(1, n_max);
+  const u64 in_bytes = align_up(R + 16, 256) + align_up(8 * (n_reads + 1), 256);
+  const u64 o_k = 0, o_c = o_k + align_up(w * cap, 256), o_off = o_c + align_up(4 * cap, 256),
+            o_rd = o_off + align_up(8 * (cap + 1), 256), o_ps = o_rd + align_up(4 * cap, 256),
+            o_tot = o_ps + align_up(4 * cap, 256), o_h = o_tot + align_up(sizeof(kc_totals), 256),
+            out_bytes = o_h + align_up(8 * hist_len, 256);
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  if (P.bytes + in_bytes + out_bytes > free_b)
+    return fail(KC_ENOMEM, "needs %llu bytes of HBM, %zu free", (unsigned long long)(P.bytes + in_bytes + out_bytes),
+                free_b);
+  char* dmem = nullptr;
+  HIP_TRY(hipMalloc(&dmem, P.bytes + in_bytes + out_bytes));
+  void* ws = dmem;
+  uint8_t* d_reads = reinterpret_cast<uint8_t*>(dmem + P.bytes);
+  uint64_t* d_offsets = reinterpret_cast<uint64_t*>(dmem + P.bytes + align_up(R + 16, 256));
+  char* ob = dmem + P.bytes + in_bytes;
+  uint64_t* d_kmers = reinterpret_cast<uint64_t*>(ob + o_k);
+  uint32_t* d_counts = reinterpret_cast<uint32_t*>(ob + o_c);
+  uint64_t* d_occ_off = reinterpret_cast<uint64_t*>(ob + o_off);
+  uint32_t* d_occ_read = reinterpret_cast<uint32_t*>(ob + o_rd);
+  uint32_t* d_occ_pos = reinterpret_cast<uint32_t*>(ob + o_ps);
+  kc_totals* d_tot = reinterpret_cast<kc_totals*>(ob + o_tot);
+  uint64_t* d_hist = reinterpret_cast<uint64_t*>(ob + o_h);
+  hipStream_t st = nullptr;
+  auto cleanup = [&](int code) {
+    (void)hipFree(dmem);
+    if (code) kc_ext_result_free(out);
+    return code;
+  };
+  if (R && hipMemcpyAsync(d_reads, reads, R, hipMemcpyHostToDevice, st) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "H2D reads failed"));
+  if (hipMemcpyAsync(d_offsets, offsets, 8 * (n_reads + 1), hipMemcpyHostToDevice, st) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "H2D offsets failed"));
+  rc = enqueue_ext_any(P, ws, d_reads, d_offsets, min_freq, max_freq, hist_len, d_kmers, d_counts, cap, d_occ_off,
+                       d_occ_read, d_occ_pos, cap, d_hist, reinterpret_cast<DevTotals*>(d_tot), st);
+  if (rc) return cleanup(rc);
+  kc_totals t;
+  if (hipMemcpyAsync(&t, d_tot, sizeof(t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "count failed: %s", hipGetErrorString(hipGetLastError())));
+  if (t.flags) return cleanup(fail(KC_EDEVICE, "internal status flags=%llu", (unsigned long long)t.flags));
+  kc_result& pr = out->pairs;
+  pr.n_pairs = t.n_pairs;
+  pr.key_words = (uint32_t)P.key_words;
+  pr.hist_len = hist_len;
+  pr.totals = t;
+  out->n_occ = t.n_occ;
+  pr.kmers = (uint64_t*)malloc(std::max<u64>(1, t.n_pairs * P.key_words) * 8);
+  pr.counts = (uint32_t*)malloc(std::max<u64>(1, t.n_pairs) * 4);
+  pr.hist = (uint64_t*)malloc(hist_len * 8);
+  out->occ_off = (uint64_t*)malloc((t.n_pairs + 1) * 8);
+  out->occ_read = (uint32_t*)malloc(std::max<u64>(1, t.n_occ) * 4);
+  out->occ_pos = (uint32_t*)malloc(std::max<u64>(1, t.n_occ) * 4);
+  if (!pr.kmers || !pr.counts || !pr.hist || !out->occ_off || !out->occ_read || !out->occ_pos)
+    return cleanup(fail(KC_ENOMEM, "host allocation failed"));
+  if ((t.n_pairs && (hipMemcpy(pr.kmers, d_kmers, t.n_pairs * w, hipMemcpyDeviceToHost) != hipSuccess ||
+                     hipMemcpy(pr.counts, d_counts, t.n_pairs * 4, hipMemcpyDeviceToHost) != hipSuccess)) ||
+      hipMemcpy(out->occ_off, d_occ_off, (t.n_pairs + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      (t.n_occ && (hipMemcpy(out->occ_read, d_occ_read, t.n_occ * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                   hipMemcpy(out->occ_pos, d_occ_pos, t.n_occ * 4, hipMemcpyDeviceToHost) != hipSuccess)) ||
+      hipMemcpy(pr.hist, d_hist, hist_len * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return cleanup(fail(KC_EDEVICE, "D2H failed"));
   return cleanup(KC_OK);
 }

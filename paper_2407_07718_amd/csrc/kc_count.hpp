@@ -21,6 +21,7 @@ struct DevTotals {
   u64 flags;          // bit 0: bad offsets, bit 1: record buffer overflow, bit 2: survivor overflow
   u64 large_keys;     // k-mers of large buckets
   u64 tiny_buckets, tiny_kmers, small_buckets, small_kmers, large_buckets, chunks, list_entries, buckets;
+  u64 n_occ;          // extension version: occurrences of the reported k-mers
 };
 
 struct CountArgs {

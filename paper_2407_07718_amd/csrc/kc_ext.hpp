@@ -1,0 +1,326 @@
+// Extension version of the count: every reported k-mer also lists where it occurs --
+// the index of the read and the offset of the window's first base inside it.
+//
+// Paper mapping: a k-mer may travel with extension information, its read's ID and its
+// position in that read (Section 2.2); the paper compresses that information in transit
+// (Section 3.3, data compression) because it outweighs the k-mer itself.  Here each
+// window carries one 32-bit global base offset (the read and the in-read position are
+// both functions of it), and it is decoded into (read, position) only for the k-mers
+// that are reported.  The windows are sorted by canonical value as (key, offset) pairs
+// with a stable LSD radix sort (Section 3.1), whose input is in offset order, so each
+// run of equal keys holds its occurrences in ascending (read, position) order, and one
+// scan over the runs counts them (Section 3.1).
+#pragma once
+#include "kc_common.hpp"
+#include "kc_count.hpp"
+
+constexpr u32 EXT_T = 256, EXT_PER = 16, EXT_TILE = EXT_T * EXT_PER;
+// Wave w of block b takes elements [b*EXT_TILE + w*EXT_WAVE, +EXT_WAVE) in EXT_PER steps of
+// 64 lanes, so the elements of a block are in (wave, step, lane) order.
+constexpr u32 EXT_WAVE = EXT_PER * 64;
+
+// ---------------------------------------------------------------------------- windows
+// Window at base p holds k valid bases of one read: no invalid byte in [p, p+k) and no
+// read start in (p, p+k).
+__device__ __forceinline__ bool ext_window_valid(const u32* __restrict__ nmask, const u32* __restrict__ starts, u64 p,
+                                                 int k) {
+  const u64 m1 = (k >= 64) ? ~0ull : ((1ull << k) - 1);
+  const u64 m2 = (1ull << (k - 1)) - 1;
+  return ((bits64(nmask, p) & m1) == 0) && ((bits64(starts, p + 1) & m2) == 0);
+}
+
+// Canonical value of the k bases at p (k <= 31): forward value with the first base most
+// significant, against the complement read backwards.
+__device__ __forceinline__ void ext_canon(const u32* __restrict__ packed, u64 p, int k, u64* out) {
+  const u64 mask = (1ull << (2 * k)) - 1;
+  const u64 V = bases64(packed, p) & mask;   // base j at bits 2j
+  const u64 F = rev2_64(V) >> (64 - 2 * k);
+  const u64 RC = ~V & mask;
+  *out = F < RC ? F : RC;
+}
+
+// 32 <= k <= 63: the window spans two 64-bit views; the forward value is the 2-bit
+// reversal of the 128-bit window shifted down by 128 - 2k.
+__device__ __forceinline__ void ext_canon(const u32* __restrict__ packed, u64 p, int k, k128* out) {
+  const int hb = 2 * k - 64;
+  const u64 mhi = hb ? ((1ull << hb) - 1) : 0ull;
+  const u64 vlo = bases64(packed, p), vhi = bases64(packed, p + 32) & mhi;
+  const u64 rlo = rev2_64(vhi), rhi = rev2_64(vlo);
+  const int s = 128 - 2 * k;
+  k128 F, RC;
+  if (s == 64) {
+    F.lo = rhi;
+    F.hi = 0;
+  } else {
+    F.lo = (rlo >> s) | (rhi << (64 - s));
+    F.hi = rhi >> s;
+  }
+  RC.lo = ~vlo;
+  RC.hi = ~vhi & mhi;
+  *out = key_lt(F, RC) ? F : RC;
+}
+
+struct ExtWinArgs {
+  const u32* packed;
+  const u32* nmask;
+  const u32* starts;
+  const u64* offsets;   // windows lie inside [offsets[0], offsets[n_reads])
+  u64 n_reads, R;
+  u64 n_pos;            // window positions [0, n_pos) of the read buffer
+  int k;
+  u32* blk;          // valid windows per block, then (scanned) the block's first output slot
+  void* keys;        // valid windows in position order: canonical key ...
+  u32* vals;         // ... and base offset
+};
+
+// Pass 1 (WRITE = false): valid windows per block.  Pass 2: the same windows written
+// densely in position order to keys/vals from the block's scanned offset.
+template <typename K, bool WRITE>
+__global__ __launch_bounds__(EXT_T) void k_ext_windows(ExtWinArgs A) {
+  __shared__ u32 wtot[EXT_T / 64];
+  const u32 lane = lane_id(), wave = threadIdx.x >> 6;
+  const u64 e0 = (u64)blockIdx.x * EXT_TILE + (u64)wave * EXT_WAVE;
+  const u64 lo = A.n_reads ? min(A.offsets[0], A.R) : 0;
+  const u64 hi = A.n_reads ? min(A.offsets[A.n_reads], A.R) : 0;
+  u64 bal[EXT_PER];
+  u32 cnt = 0;
+#pragma unroll
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    const u64 i = e0 + (u64)j * 64 + lane;
+    const bool v = i < A.n_pos && i >= lo && i + (u64)A.k <= hi && ext_window_valid(A.nmask, A.starts, i, A.k);
+    bal[j] = __ballot(v);
+    cnt += (u32)__popcll(bal[j]);
+  }
+  if (lane == 0) wtot[wave] = cnt;
+  __syncthreads();
+  if (!WRITE) {
+    if (threadIdx.x == 0) {
+      u32 s = 0;
+      for (u32 w = 0; w < EXT_T / 64; ++w) s += wtot[w];
+      A.blk[blockIdx.x] = s;
+    }
+    return;
+  }
+  u64 base = A.blk[blockIdx.x];
+  for (u32 w = 0; w < wave; ++w) base += wtot[w];
+  K* keys = reinterpret_cast<K*>(A.keys);
+#pragma unroll
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    const u64 i = e0 + (u64)j * 64 + lane;
+    if ((bal[j] >> lane) & 1ull) {
+      const u64 p = i;
+      K key;
+      ext_canon(A.packed, p, A.k, &key);
+      const u64 at = base + mbcnt64(bal[j]);
+      keys[at] = key;
+      A.vals[at] = (u32)p;
+    }
+    base += (u32)__popcll(bal[j]);
+  }
+}
+
+// rid[b] = the read holding base 64*b, for every 64-base block that starts inside a
+// read; other entries keep the fill value ~0.  Reads whose offsets are out of order or
+// out of range are skipped (the count reports them through its flags).
+__global__ __launch_bounds__(256) void k_ext_read_blocks(const u64* __restrict__ offsets, u64 n_reads, u64 R,
+                                                         u32* __restrict__ rid, u64 n_blk) {
+  const u64 r = blockIdx.x * (u64)blockDim.x + threadIdx.x;
+  if (r >= n_reads) return;
+  const u64 a = offsets[r], b = offsets[r + 1];
+  if (b <= a || b > R) return;
+  for (u64 q = (a + 63) >> 6; (q << 6) < b && q < n_blk; ++q) rid[q] = (u32)r;
+}
+
+// Index of the read holding base g (g inside [offsets[0], offsets[n_reads]) and inside a
+// read): the largest r with offsets[r] <= g, searched between the reads holding the
+// starts of g's 64-base block and of the next block.
+__device__ __forceinline__ u32 ext_find_read(const u64* __restrict__ offsets, u64 n_reads, const u32* __restrict__ rid,
+                                             u64 n_blk, u64 g) {
+  const u64 q = g >> 6;
+  u32 a = rid[q];
+  if (a == 0xFFFFFFFFu) a = 0;
+  u32 b = (q + 1 < n_blk) ? rid[q + 1] : 0xFFFFFFFFu;
+  if (b == 0xFFFFFFFFu) b = (u32)(n_reads - 1);
+  while (a < b) {   // invariant: offsets[a] <= g, answer in [a, b]
+    const u32 mid = a + (b - a + 1) / 2;
+    if (offsets[mid] <= g) a = mid;
+    else b = mid - 1;
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------------------- runs
+// Run heads of the sorted keys[0, n): position i starts a run when i == 0 or its key
+// differs from key i-1.  Pass 1 counts heads per block, pass 2 writes their positions
+// to hp in order from the block's scanned offset.
+template <typename K, bool WRITE>
+__global__ __launch_bounds__(EXT_T) void k_ext_heads(const K* __restrict__ keys, const u64* __restrict__ n_ptr,
+                                                     u32* __restrict__ blk, u32* __restrict__ hp) {
+  __shared__ u32 wtot[EXT_T / 64];
+  const u64 n = *n_ptr;
+  const u32 lane = lane_id(), wave = threadIdx.x >> 6;
+  const u64 e0 = (u64)blockIdx.x * EXT_TILE + (u64)wave * EXT_WAVE;
+  u64 bal[EXT_PER];
+  u32 cnt = 0;
+#pragma unroll
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    const u64 i = e0 + (u64)j * 64 + lane;
+    const bool h = i < n && (i == 0 || !key_eq(keys[i], keys[i - 1]));
+    bal[j] = __ballot(h);
+    cnt += (u32)__popcll(bal[j]);
+  }
+  if (lane == 0) wtot[wave] = cnt;
+  __syncthreads();
+  if (!WRITE) {
+    if (threadIdx.x == 0) {
+      u32 s = 0;
+      for (u32 w = 0; w < EXT_T / 64; ++w) s += wtot[w];
+      blk[blockIdx.x] = s;
+    }
+    return;
+  }
+  u64 base = blk[blockIdx.x];
+  for (u32 w = 0; w < wave; ++w) base += wtot[w];
+#pragma unroll
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    if ((bal[j] >> lane) & 1ull) hp[base + mbcnt64(bal[j])] = (u32)(e0 + (u64)j * 64 + lane);
+    base += (u32)__popcll(bal[j]);
+  }
+}
+
+struct ExtRunArgs {
+  const void* keys;        // sorted keys
+  const u32* vals;         // their base offsets
+  const u32* hp;           // run heads [0, nruns)
+  const u64* n_ptr;        // sorted elements
+  const u64* nruns_ptr;
+  u32 min_freq, max_freq;
+  u64 hist_len;
+  u64* hist;
+  DevTotals* tot;
+  u32* blk_pairs;          // reported runs per block (pass 1), then scanned
+  u32* blk_occ;            // their summed counts (pass 1), then scanned
+  const u64* offsets;      // the reads' offsets, for decoding
+  u64 n_reads;
+  const u32* rid;
+  u64 n_blk;
+  void* out_k;             // pairs [0, pair_cap) ...
+  u32* out_c;
+  u64* occ_off;            // ... the first occurrence of each pair
+  u64 pair_cap;
+  u32* occ_read;           // occurrences [0, occ_cap)
+  u32* occ_pos;
+  u64 occ_cap;
+};
+
+// Run r of the sorted array: [hp[r], hp[r+1]) (the last run ends at n).
+__device__ __forceinline__ void ext_run(const ExtRunArgs& A, u64 r, u64 nruns, u64 n, u32* s, u32* c) {
+  const u32 a = A.hp[r];
+  const u64 b = (r + 1 < nruns) ? (u64)A.hp[r + 1] : n;
+  *s = a;
+  *c = (u32)(b - a);
+}
+
+// Pass 1 (WRITE = false): histogram, extremes and distinct count of every run, and per
+// block the reported runs and their summed counts.  Pass 2: reported runs written as
+// (k-mer, count, first occurrence) from the block's scanned offsets, with their
+// occurrences decoded into (read, position).
+template <typename K, bool WRITE>
+__global__ __launch_bounds__(EXT_T) void k_ext_runs(ExtRunArgs A) {
+  __shared__ u32 hist_s[256];
+  __shared__ u32 lmax;
+  __shared__ unsigned long long lover;
+  __shared__ u32 wp[EXT_T / 64], wo[EXT_T / 64];
+  const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const u64 nruns = *A.nruns_ptr, n = *A.n_ptr;
+  const u64 e0 = (u64)blockIdx.x * EXT_TILE + (u64)wave * EXT_WAVE;
+  if (!WRITE) {
+    for (u32 i = tid; i < 256; i += EXT_T) hist_s[i] = 0;
+    if (tid == 0) {
+      lmax = 0;
+      lover = 0;
+    }
+    __syncthreads();
+  }
+  RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax, &lover};
+  u32 np = 0, osum = 0;
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    const u64 r = e0 + (u64)j * 64 + lane;
+    const bool act = r < nruns;
+    u32 s = 0, c = 0;
+    if (act) ext_run(A, r, nruns, n, &s, &c);
+    const bool emit = act && c >= A.min_freq && c <= A.max_freq;
+    if (!WRITE) run_stats_lanes(sink, c, act);
+    np += (u32)__popcll(__ballot(emit));
+    osum += emit ? c : 0u;
+  }
+  // wave totals: lanes' sums reduced through the DPP scan, read from lane 63
+  const u32 otot = lane_read(wave_scan_u32(osum), 63);
+  if (lane == 0) {
+    wp[wave] = np;
+    wo[wave] = otot;
+  }
+  __syncthreads();
+  if (!WRITE) {
+    if (tid == 0) {
+      u32 a = 0, b = 0;
+      for (u32 w = 0; w < EXT_T / 64; ++w) {
+        a += wp[w];
+        b += wo[w];
+      }
+      A.blk_pairs[blockIdx.x] = a;
+      A.blk_occ[blockIdx.x] = b;
+    }
+    flush_stats(sink, 0);
+    if (tid == 0) {
+      const u64 b0 = (u64)blockIdx.x * EXT_TILE;
+      const u64 d = nruns > b0 ? min((u64)EXT_TILE, nruns - b0) : 0ull;
+      if (d) atomicAdd((unsigned long long*)&A.tot->n_distinct, (unsigned long long)d);
+    }
+    return;
+  }
+  u64 pbase = A.blk_pairs[blockIdx.x], obase = A.blk_occ[blockIdx.x];
+  for (u32 w = 0; w < wave; ++w) {
+    pbase += wp[w];
+    obase += wo[w];
+  }
+  K* ok = reinterpret_cast<K*>(A.out_k);
+  const K* keys = reinterpret_cast<const K*>(A.keys);
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    const u64 r = e0 + (u64)j * 64 + lane;
+    u32 s = 0, c = 0;
+    if (r < nruns) ext_run(A, r, nruns, n, &s, &c);
+    const bool emit = r < nruns && c >= A.min_freq && c <= A.max_freq;
+    const u64 EB = __ballot(emit);
+    const u32 ci = emit ? c : 0u;
+    const u32 incl = wave_scan_u32(ci);
+    if (emit) {
+      const u64 pi = pbase + mbcnt64(EB);
+      const u64 oi = obase + (incl - ci);
+      if (pi < A.pair_cap) {
+        ok[pi] = keys[s];
+        A.out_c[pi] = c;
+        A.occ_off[pi] = oi;
+      }
+      for (u32 t = 0; t < c && oi + t < A.occ_cap; ++t) {
+        const u64 g = A.vals[s + t];
+        const u32 rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, g);
+        A.occ_read[oi + t] = rd;
+        A.occ_pos[oi + t] = (u32)(g - A.offsets[rd]);
+      }
+    }
+    pbase += (u32)__popcll(EB);
+    obase += lane_read(incl, 63);
+  }
+}
+
+// Totals of an extension count; occ_off[n_pairs] closes the last pair's list.
+__global__ void k_ext_finalize(DevTotals* tot, const u64* n_win, const u64* n_pairs, const u64* n_occ, const u32* flags,
+                               u64* occ_off, u64 pair_cap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  tot->n_windows = *n_win;
+  tot->n_pairs = *n_pairs;
+  tot->n_occ = *n_occ;
+  tot->flags = *flags & 1u;
+  if (*n_pairs <= pair_cap && occ_off) occ_off[*n_pairs] = *n_occ;
+}

@@ -39,7 +39,7 @@ class kc_totals(ctypes.Structure):
                 ("flags", ctypes.c_uint64), ("large_keys", ctypes.c_uint64), ("tiny_buckets", ctypes.c_uint64),
                 ("tiny_kmers", ctypes.c_uint64), ("small_buckets", ctypes.c_uint64), ("small_kmers", ctypes.c_uint64),
                 ("large_buckets", ctypes.c_uint64), ("chunks", ctypes.c_uint64), ("list_entries", ctypes.c_uint64),
-                ("buckets", ctypes.c_uint64)]
+                ("buckets", ctypes.c_uint64), ("n_occ", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -49,6 +49,11 @@ class kc_result(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_uint64), ("key_words", ctypes.c_uint32),
                 ("kmers", ctypes.POINTER(ctypes.c_uint64)), ("counts", ctypes.POINTER(ctypes.c_uint32)),
                 ("hist", ctypes.POINTER(ctypes.c_uint64)), ("hist_len", ctypes.c_uint64), ("totals", kc_totals)]
+
+
+class kc_ext_result(ctypes.Structure):
+    _fields_ = [("pairs", kc_result), ("n_occ", ctypes.c_uint64), ("occ_off", ctypes.POINTER(ctypes.c_uint64)),
+                ("occ_read", ctypes.POINTER(ctypes.c_uint32)), ("occ_pos", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class kc_job(ctypes.Structure):
@@ -124,6 +129,17 @@ def _load() -> ctypes.CDLL:
     lib.kc_server_clock.restype = ctypes.c_double
     lib.kc_server_destroy.argtypes = [vp]
     lib.kc_server_destroy.restype = i32
+    lib.kc_count_ext.argtypes = [vp, vp, u64, i32, u32, u32, u64, P(kc_config), P(kc_ext_result)]
+    lib.kc_count_ext.restype = i32
+    lib.kc_ext_result_free.argtypes = [P(kc_ext_result)]
+    lib.kc_ext_workspace_size.argtypes = [u64, u64, i32]
+    lib.kc_ext_workspace_size.restype = ctypes.c_size_t
+    ext_args = [vp, u64, vp, u64, i32, u32, u32, u64, P(kc_config), vp, ctypes.c_size_t, vp, vp, u64, vp, vp, vp,
+                u64, vp, vp, vp]
+    lib.kc_count_ext_device.argtypes = ext_args + [P(kc_totals)]
+    lib.kc_count_ext_device.restype = i32
+    lib.kc_count_ext_device_async.argtypes = ext_args
+    lib.kc_count_ext_device_async.restype = i32
     lib.kc_profile.argtypes = [i32]
     lib.kc_profile.restype = i32
     lib.kc_profile_read.argtypes = [ctypes.POINTER(kc_stage_times)]
@@ -385,3 +401,93 @@ class DeviceCounter:
         counts = self.counts[:n].cpu().numpy().view(np.uint32)
         hist = self.hist.cpu().numpy().view(np.uint64)
         return Result(kmers, counts, hist, totals)
+
+
+# ---------------------------------------------------------------------------- extension version
+@dataclass
+class ExtResult:
+    """Counts plus the occurrences of every reported k-mer: pair j's occurrences are
+    rows occ_off[j]:occ_off[j+1] of occ_read / occ_pos, ascending by (read, pos)."""
+    pairs: Result
+    occ_off: np.ndarray      # uint64 [n_pairs + 1]
+    occ_read: np.ndarray     # uint32 [n_occ]
+    occ_pos: np.ndarray      # uint32 [n_occ]
+
+
+def kc_count_ext(reads: np.ndarray, offsets: np.ndarray, k: int, min_freq: int, max_freq: int,
+                 hist_len: int = 65536, cfg: Optional[kc_config] = None) -> ExtResult:
+    """Host API of the extension version (kc_count_ext)."""
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if reads.size == 0:
+        reads = np.zeros(1, dtype=np.uint8)
+    res = kc_ext_result()
+    rc = _lib.kc_count_ext(reads.ctypes.data, offsets.ctypes.data, offsets.shape[0] - 1, k, min_freq, max_freq,
+                           hist_len, ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(res))
+    _check(rc)
+    try:
+        p = res.pairs
+        n, kw, no = int(p.n_pairs), int(p.key_words), int(res.n_occ)
+        kmers = np.ctypeslib.as_array(p.kmers, shape=(max(1, n * kw),))[: n * kw].copy().reshape(n, kw)
+        counts = np.ctypeslib.as_array(p.counts, shape=(max(1, n),))[:n].copy()
+        hist = np.ctypeslib.as_array(p.hist, shape=(hist_len,)).copy()
+        off = np.ctypeslib.as_array(res.occ_off, shape=(n + 1,)).copy()
+        rd = np.ctypeslib.as_array(res.occ_read, shape=(max(1, no),))[:no].copy()
+        ps = np.ctypeslib.as_array(res.occ_pos, shape=(max(1, no),))[:no].copy()
+        return ExtResult(Result(kmers, counts, hist, p.totals.as_dict()), off, rd, ps)
+    finally:
+        _lib.kc_ext_result_free(ctypes.byref(res))
+
+
+def kc_ext_workspace_size(total_bases: int, n_reads: int, k: int) -> int:
+    return int(_lib.kc_ext_workspace_size(total_bases, n_reads, k))
+
+
+class DeviceExtCounter:
+    """Workspace and output buffers on the GPU for repeated extension counts of read sets
+    up to ``max_bases`` bases / ``max_reads`` reads at one k."""
+
+    def __init__(self, max_bases: int, max_reads: int, k: int, min_freq: int, max_freq: int,
+                 hist_len: int = 65536, cfg: Optional[kc_config] = None, pair_capacity: Optional[int] = None,
+                 occ_capacity: Optional[int] = None, device: str = "cuda"):
+        import torch
+        self.k, self.lo, self.hi, self.H, self.cfg = k, min_freq, max_freq, hist_len, cfg
+        self.key_words = 1 if k <= 31 else 2
+        ws = kc_ext_workspace_size(max_bases, max_reads, k)
+        if ws == 0:
+            raise KCError(KC_EINVAL, "kc_ext_workspace_size rejected the arguments")
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=device)
+        cap = pair_capacity if pair_capacity is not None else max(1, max_bases // max(1, min_freq))
+        ocap = occ_capacity if occ_capacity is not None else max(1, max_bases)
+        self.kmers = torch.empty((cap, self.key_words), dtype=torch.int64, device=device)
+        self.counts = torch.empty(cap, dtype=torch.int32, device=device)
+        self.occ_off = torch.empty(cap + 1, dtype=torch.int64, device=device)
+        self.occ_read = torch.empty(ocap, dtype=torch.int32, device=device)
+        self.occ_pos = torch.empty(ocap, dtype=torch.int32, device=device)
+        self.hist = torch.empty(hist_len, dtype=torch.int64, device=device)
+        self.totals = torch.zeros(ctypes.sizeof(kc_totals) // 8, dtype=torch.int64, device=device)
+
+    def count(self, d_reads, d_offsets, stream=None, sync: bool = True):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        args = (_ptr(d_reads), int(d_reads.numel()), _ptr(d_offsets), int(d_offsets.numel()) - 1, self.k, self.lo,
+                self.hi, self.H, ctypes.byref(self.cfg) if self.cfg is not None else None, _ptr(self.workspace),
+                int(self.workspace.numel()), _ptr(self.kmers), _ptr(self.counts), int(self.counts.shape[0]),
+                _ptr(self.occ_off), _ptr(self.occ_read), _ptr(self.occ_pos), int(self.occ_read.shape[0]),
+                _ptr(self.hist), _ptr(self.totals), ctypes.c_void_p(st.cuda_stream))
+        if sync:
+            tot = kc_totals()
+            _check(_lib.kc_count_ext_device(*args, ctypes.byref(tot)))
+            return tot.as_dict()
+        _check(_lib.kc_count_ext_device_async(*args))
+        return None
+
+    def result(self, totals: dict) -> ExtResult:
+        n, no = int(totals["n_pairs"]), int(totals["n_occ"])
+        kmers = self.kmers[:n].cpu().numpy().view(np.uint64).reshape(n, self.key_words)
+        counts = self.counts[:n].cpu().numpy().view(np.uint32)
+        hist = self.hist.cpu().numpy().view(np.uint64)
+        off = self.occ_off[: n + 1].cpu().numpy().view(np.uint64)
+        rd = self.occ_read[:no].cpu().numpy().view(np.uint32)
+        ps = self.occ_pos[:no].cpu().numpy().view(np.uint32)
+        return ExtResult(Result(kmers, counts, hist, totals), off, rd, ps)

@@ -78,7 +78,7 @@ def test_header_declares_batch_and_server_entry_points():
 
 def test_struct_sizes_match_header_layout():
     from paper_2407_07718_amd import kc
-    assert ctypes.sizeof(kc.kc_totals) == 16 * 8
+    assert ctypes.sizeof(kc.kc_totals) == 17 * 8
     assert ctypes.sizeof(kc.kc_config) == 4 * 4 + 8 + 2 * 4
     assert ctypes.sizeof(kc.kc_job) == 8 * 3 + 4 * 4 + 8
     assert ctypes.sizeof(kc.kc_server_cfg) == 8 + 2 * 4 + 8 + ctypes.sizeof(kc.kc_config)
@@ -108,3 +108,37 @@ def test_server_rejects_bad_arguments_on_host():
     assert lib.kc_server_poll(None, 1, None, None) == kc.KC_EINVAL
     assert lib.kc_server_cancel(None, 1) == kc.KC_EINVAL
     assert lib.kc_server_destroy(None) == kc.KC_OK
+
+
+def test_header_declares_extension_entry_points():
+    names = declared_functions()
+    for n in ["kc_count_ext", "kc_ext_result_free", "kc_ext_workspace_size", "kc_count_ext_device",
+              "kc_count_ext_device_async"]:
+        assert n in names
+
+
+def test_extension_struct_layout():
+    from paper_2407_07718_amd import kc
+    assert ctypes.sizeof(kc.kc_ext_result) == ctypes.sizeof(kc.kc_result) + 8 + 3 * 8
+
+
+@pytest.mark.parametrize("k,lo,hi,H", [(0, 2, 3, 16), (64, 2, 3, 16), (31, 0, 3, 16), (31, 5, 3, 16),
+                                      (31, 2, 3, 1)])
+def test_extension_host_api_rejects_bad_arguments(k, lo, hi, H):
+    from paper_2407_07718_amd import kc
+    reads = np.frombuffer(b"ACGT" * 20, dtype=np.uint8)
+    with pytest.raises(kc.KCError) as e:
+        kc.kc_count_ext(reads, np.array([0, 80], dtype=np.uint64), k, lo, hi, H)
+    assert e.value.code == kc.KC_EINVAL
+    with pytest.raises(kc.KCError) as e:
+        kc.kc_count_ext(reads, np.array([0, 50, 40, 80], dtype=np.uint64), 11, 1, 10, 16)
+    assert e.value.code == kc.KC_EINVAL and "decrease" in str(e.value)
+
+
+def test_extension_workspace_size_scales():
+    from paper_2407_07718_amd import kc
+    a = kc.kc_ext_workspace_size(1_000_000, 10_000, 31)
+    b = kc.kc_ext_workspace_size(2_000_000, 20_000, 31)
+    c = kc.kc_ext_workspace_size(1_000_000, 10_000, 51)
+    assert 0 < a < b and c > a
+    assert kc.kc_ext_workspace_size(1000, 10, 0) == 0 and kc.kc_ext_workspace_size(1000, 10, 64) == 0

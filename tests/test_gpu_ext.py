@@ -1,0 +1,134 @@
+"""Parity of the extension version on the GPU (through the C ABI) with the CPU oracle:
+the pairs, histogram and totals of the plain count plus, for every reported k-mer, the
+exact list of its occurrences (read index, position in the read) in ascending order.
+Bit-exact on seeded inputs spanning many tiles and radix blocks with ragged tails, on
+the method's edge cases, and at the short-read configuration's full size."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_07718_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _kc():
+    from paper_2407_07718_amd import kc
+    return kc
+
+
+def _genome_reads(seed, n_reads, lo_len, hi_len, genome=4000, p_sub=0.01, p_n=0.002):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = synth.uniform_genome(rng, genome)
+    lens = rng.integers(lo_len, hi_len + 1, n_reads)
+    return synth.sample_reads(rng, g, lens, p_sub=p_sub, p_n=p_n)
+
+
+def device_ext(reads, offsets, k, lo, hi, H=65536, pair_capacity=None, occ_capacity=None):
+    import torch
+    kc = _kc()
+    dev = torch.device("cuda:0")
+    d_reads = torch.from_numpy(np.ascontiguousarray(reads, dtype=np.uint8)).to(dev)
+    d_offsets = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.uint64).view(np.int64)).to(dev)
+    ctr = kc.DeviceExtCounter(int(len(reads)), int(len(offsets) - 1), k, lo, hi, H, pair_capacity=pair_capacity,
+                              occ_capacity=occ_capacity)
+    tot = ctr.count(d_reads, d_offsets)
+    return ctr.result(tot)
+
+
+def assert_same_ext(got, ref, label=""):
+    g, r = got.pairs, ref.base
+    assert g.kmers.shape == r.kmers.shape, f"{label}: {g.kmers.shape} vs {r.kmers.shape}"
+    assert np.array_equal(g.kmers, r.kmers), f"{label}: k-mers differ"
+    assert np.array_equal(g.counts, r.counts), f"{label}: counts differ"
+    assert np.array_equal(g.hist, r.hist), f"{label}: histogram differs"
+    t = g.totals
+    assert t["n_windows"] == r.n_windows and t["n_distinct"] == r.n_distinct, label
+    assert t["overflow_sum"] == r.overflow_sum and t["max_count"] == r.max_count, label
+    assert t["n_occ"] == int(ref.occ_off[-1]), f"{label}: n_occ"
+    assert np.array_equal(got.occ_off, ref.occ_off), f"{label}: occurrence offsets differ"
+    assert np.array_equal(got.occ_read, ref.occ_read), f"{label}: occurrence reads differ"
+    assert np.array_equal(got.occ_pos, ref.occ_pos), f"{label}: occurrence positions differ"
+
+
+def check_ext(reads, offsets, k, lo, hi, H=65536, label=""):
+    print(f"case ext {label}: k={k} [{lo},{hi}] H={H} bases={len(reads)} reads={len(offsets) - 1}", flush=True)
+    got = device_ext(reads, offsets, k, lo, hi, H)
+    ref = oracle.count_ext(reads, offsets, k, lo, hi, H)
+    assert_same_ext(got, ref, label)
+    return got, ref
+
+
+def test_ext_tiny_config():
+    rs = synth.tiny_config()
+    got, ref = check_ext(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, label="tiny")
+    assert ref.base.n_pairs > 100
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 11, 17, 21, 30, 31, 32, 33, 47, 51, 63])
+def test_ext_random_keys(k):
+    rng = np.random.Generator(np.random.PCG64(700 + k))
+    reads, offsets = _genome_reads(k, 500, 0, 400)
+    lo = int(rng.integers(1, 4))
+    check_ext(reads, offsets, k, lo, lo + int(rng.integers(0, 60)), int(rng.integers(2, 300)), label=f"k{k}")
+
+
+def test_ext_many_tiles_and_radix_blocks():
+    # ~2.4 Mbp: hundreds of 4096-element tiles, many radix blocks, heavy repeats
+    rng = np.random.Generator(np.random.PCG64(31337))
+    g = synth.uniform_genome(rng, 200_000)
+    synth.add_repeat_families(rng, g, families=20)   # in place
+    reads, offsets = synth.sample_reads(rng, g, rng.integers(100, 200, 16000), p_sub=0.005, p_n=0.001)
+    check_ext(reads, offsets, 31, 2, 200, 1024, label="many tiles")
+    check_ext(reads, offsets, 51, 1, 0xFFFFFFFF, 64, label="many tiles k51")
+
+
+def test_ext_edge_cases():
+    cases = [
+        (["ACGTACGTAC"], 31), ([], 5), (["", "", ""], 3), (["NNNNNNNN", "acgtNacgt"], 3),
+        (["A" * 300, "T" * 200], 21), (["ACGT" * 30, "", "CG", "ACGT" * 25], 4),
+        (["GATTACA"], 7), (["GATTACA"], 8),
+    ]
+    for seqs, k in cases:
+        reads, offsets = synth.from_strings(seqs)
+        check_ext(reads, offsets, k, 1, 0xFFFFFFFF, 16, label=f"edge {seqs[:2]} k{k}")
+    # bytes before the first read and after the last belong to no read
+    reads = np.frombuffer(b"ACGTACGTAC" + b"GGGCCCAAATTT" * 3 + b"ACGTAC", dtype=np.uint8).copy()
+    offsets = np.array([10, 22, 22, 46], dtype=np.uint64)
+    check_ext(reads, offsets, 5, 1, 0xFFFFFFFF, 16, label="offset window")
+    # homopolymer heavy hitter above the filter and a frequency window of one value
+    reads, offsets = synth.from_strings(["A" * 5000, "ACGTTGCA" * 50])
+    check_ext(reads, offsets, 11, 2, 2, 8, label="homopolymer")
+
+
+def test_ext_matches_plain_count():
+    from tests.gpu_util import device_count
+    reads, offsets = _genome_reads(99, 800, 100, 300, genome=30000)
+    for k in (21, 45):
+        ext = device_ext(reads, offsets, k, 2, 40, 500)
+        plain = device_count(reads, offsets, k, 11, 2, 40, 500)
+        assert np.array_equal(ext.pairs.kmers, plain.kmers) and np.array_equal(ext.pairs.counts, plain.counts)
+        assert np.array_equal(ext.pairs.hist, plain.hist)
+
+
+def test_ext_truncation_and_host_api():
+    kc = _kc()
+    rs = synth.tiny_config()
+    ref = oracle.count_ext(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, 65536)
+    with pytest.raises(kc.KCError) as e:
+        device_ext(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, pair_capacity=10)
+    assert e.value.code == kc.KC_ETRUNC
+    with pytest.raises(kc.KCError) as e:
+        device_ext(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, occ_capacity=50)
+    assert e.value.code == kc.KC_ETRUNC
+    got = kc.kc_count_ext(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, 65536)
+    assert_same_ext(got, ref, "host api")
+
+
+def test_ext_short_read_config_full_size():
+    rs = synth.config(2)
+    print(f"case ext short-read full size: bases={rs.n_bases} reads={rs.n_reads}", flush=True)
+    got = device_ext(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq)
+    print("case ext short-read full size: GPU done, oracle next", flush=True)
+    ref = oracle.count_ext(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, 65536)
+    assert_same_ext(got, ref, "ext short-read full size")
