@@ -58,12 +58,27 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(KC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int RADIX_T = 256;
+#ifndef KC_RADIX_T
+#define KC_RADIX_T 512
+#endif
+#ifndef KC_RADIX_SHARED
+#define KC_RADIX_SHARED 1
+#endif
+#ifndef KC_RADIX_NB_MAX
+#define KC_RADIX_NB_MAX 1024
+#endif
+constexpr int RADIX_T = KC_RADIX_T;   // HBM radix passes: threads per block ...
 constexpr u32 WAVE_CAP_64 = 1024, WAVE_CAP_128 = 512;   // k-mers of a bucket sorted by one wave
 constexpr int WAVES_PER_BLOCK = 4;
 constexpr u32 RUN_BLOCKS = 1024;   // blocks of the merged-run kernel
-constexpr int RADIX_ITEMS_64 = 16;
-constexpr int RADIX_ITEMS_128 = 8;
+#ifndef KC_RADIX_ITEMS_64
+#define KC_RADIX_ITEMS_64 16
+#endif
+#ifndef KC_RADIX_ITEMS_128
+#define KC_RADIX_ITEMS_128 8
+#endif
+constexpr int RADIX_ITEMS_64 = KC_RADIX_ITEMS_64;    // ... keys per thread of a tile (u64, 128-bit keys)
+constexpr int RADIX_ITEMS_128 = KC_RADIX_ITEMS_128;
 
 inline u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
 inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
@@ -271,7 +286,8 @@ int radix_sort(K* k0, K* k1, u32* v0, u32* v1, const u64* n_ptr, u32* counts, u3
   for (int sh = 0; sh < nbits; sh += 8) {
     hipLaunchKernelGGL((k_radix_upsweep<K>), dim3(nb), dim3(256), 0, st, src, n_ptr, counts, sh);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, st, counts, nb, totals);
-    hipLaunchKernelGGL((k_radix_downsweep<K, HASV, RADIX_T, ITEMS>), dim3(nb), dim3(RADIX_T), 0, st, src, dst, vs,
+    hipLaunchKernelGGL((k_radix_downsweep<K, HASV, RADIX_T, ITEMS, KC_RADIX_SHARED != 0>), dim3(nb), dim3(RADIX_T), 0,
+                       st, src, dst, vs,
                        vd, n_ptr, counts, totals, sh);
     std::swap(src, dst);
     std::swap(vs, vd);
@@ -661,7 +677,14 @@ struct ExtPlan {
       o_scan, bytes = 0;
 };
 
-enum ExtCtrl : int { X_NWIN = 0, X_NRUNS = 1, X_NPAIRS = 2, X_NOCC = 3, X_FLAGS = 4, X_WORDS = 5 };
+enum ExtCtrl : int { X_NWIN = 0, X_NRUNS = 1, X_NPAIRS = 2, X_NOCC = 3, X_FLAGS = 4, X_MAXLEN = 5, X_WORDS = 6 };
+
+// bits of a read index (indices 0 .. n_reads - 1)
+u32 read_bits(u64 n_reads) {
+  u32 b = 0;
+  while (b < 64 && n_reads > 1 && ((n_reads - 1) >> b)) ++b;
+  return b;
+}
 
 bool make_ext_plan(u64 R, u64 n_reads, int k, ExtPlan* p) {
   p->k = k;
@@ -676,7 +699,7 @@ bool make_ext_plan(u64 R, u64 n_reads, int k, ExtPlan* p) {
   p->n_blk = R / 64 + 2;
   const u64 w = 8ull * p->key_words;
   const u64 tile = (u64)RADIX_T * (p->key_words == 1 ? RADIX_ITEMS_64 : RADIX_ITEMS_128);
-  p->nb = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(p->N, tile * 2)));
+  p->nb = (u32)std::min<u64>(KC_RADIX_NB_MAX, std::max<u64>(1, ceil_div(p->N, tile * 2)));
   u64 o = 0;
   auto take = [&](u64 bytes) {
     u64 r = o;
@@ -686,11 +709,14 @@ bool make_ext_plan(u64 R, u64 n_reads, int k, ExtPlan* p) {
   p->o_packed = take(4 * p->n_packed);
   p->o_nmask = take(4 * p->n_mask);
   p->o_starts = take(4 * p->n_mask);
-  p->o_k0 = take(w * p->N);
-  p->o_k1 = take(w * p->N);
-  p->o_v0 = take(4 * p->N);
-  p->o_v1 = take(4 * p->N);
-  p->o_hp = take(4 * p->N);
+  // whole tiles, so that the run-start bits of every tile (one u64 per 64 positions,
+  // kept in a free key buffer) fit as well
+  const u64 NT = p->n_tiles * EXT_TILE;
+  p->o_k0 = take(w * NT);
+  p->o_k1 = take(w * NT);
+  p->o_v0 = take(4 * NT);
+  p->o_v1 = take(4 * NT);
+  p->o_hp = take(4 * NT);
   p->o_blk = take(4 * p->n_tiles);
   p->o_bp = take(4 * p->n_tiles);
   p->o_bo = take(4 * p->n_tiles);
@@ -741,7 +767,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
     hipLaunchKernelGGL(k_read_starts, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, starts,
                        flags);
     hipLaunchKernelGGL(k_ext_read_blocks, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, rid,
-                       P.n_blk);
+                       P.n_blk, ctrl + X_MAXLEN);
   }
   stage_mark(1, st);
   // window positions: every base of the buffer; the kernel keeps the windows inside
@@ -758,6 +784,10 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   wa.blk = blk;
   wa.keys = k0;
   wa.vals = v0;
+  wa.rid = rid;
+  wa.n_blk = P.n_blk;
+  wa.rbits = read_bits(P.n_reads);
+  wa.max_len = ctrl + X_MAXLEN;
   const dim3 gw((u32)P.n_tiles);
   hipLaunchKernelGGL((k_ext_windows<K, false>), gw, dim3(EXT_T), 0, st, wa);
   scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles, ctrl + X_NWIN, scanbuf, st);
@@ -769,10 +799,13 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   if (rc) return rc;
   const K* sk = second ? k1 : k0;
   const u32* sv = second ? v1 : v0;
+  // the other (key, offset) buffer is free now: run-start bits and per-run slots go there
+  u64* hbits = reinterpret_cast<u64*>(second ? k0 : k1);
+  u32* odst = second ? v0 : v1;
   stage_mark(3, st);
-  hipLaunchKernelGGL((k_ext_heads<K, false>), gw, dim3(EXT_T), 0, st, sk, ctrl + X_NWIN, blk, hp);
+  hipLaunchKernelGGL((k_ext_heads<K, false>), gw, dim3(EXT_T), 0, st, sk, ctrl + X_NWIN, blk, hp, hbits);
   scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles, ctrl + X_NRUNS, scanbuf, st);
-  hipLaunchKernelGGL((k_ext_heads<K, true>), gw, dim3(EXT_T), 0, st, sk, ctrl + X_NWIN, blk, hp);
+  hipLaunchKernelGGL((k_ext_heads<K, true>), gw, dim3(EXT_T), 0, st, sk, ctrl + X_NWIN, blk, hp, hbits);
   ExtRunArgs ra;
   ra.keys = sk;
   ra.vals = sv;
@@ -797,11 +830,17 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   ra.occ_read = d_occ_read;
   ra.occ_pos = d_occ_pos;
   ra.occ_cap = occ_cap;
+  ra.odst = odst;
+  ra.hbits = hbits;
+  ra.blk_heads = blk;
+  ra.rbits = wa.rbits;
+  ra.max_len = ctrl + X_MAXLEN;
   hipLaunchKernelGGL((k_ext_runs<K, false>), gw, dim3(EXT_T), 0, st, ra);
   scan_u32(bp, bp, (const u64*)nullptr, P.n_tiles, ctrl + X_NPAIRS, scanbuf, st);
   scan_u32(bo, bo, (const u64*)nullptr, P.n_tiles, ctrl + X_NOCC, scanbuf, st);
   stage_mark(4, st);
   hipLaunchKernelGGL((k_ext_runs<K, true>), gw, dim3(EXT_T), 0, st, ra);
+  hipLaunchKernelGGL((k_ext_occ<K>), gw, dim3(EXT_T), 0, st, ra);
   hipLaunchKernelGGL(k_ext_finalize, dim3(1), dim3(64), 0, st, d_tot, ctrl + X_NWIN, ctrl + X_NPAIRS, ctrl + X_NOCC,
                      flags, d_occ_off, pair_cap);
   stage_mark(5, st);

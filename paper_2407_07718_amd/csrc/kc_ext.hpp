@@ -60,6 +60,48 @@ __device__ __forceinline__ void ext_canon(const u32* __restrict__ packed, u64 p,
   *out = key_lt(F, RC) ? F : RC;
 }
 
+// rid[b] = the read holding base 64*b, for every 64-base block that starts inside a
+// read; other entries keep the fill value ~0.  Reads whose offsets are out of order or
+// out of range are skipped (the count reports them through its flags).
+// Also raises *max_len to the longest read.
+__global__ __launch_bounds__(256) void k_ext_read_blocks(const u64* __restrict__ offsets, u64 n_reads, u64 R,
+                                                         u32* __restrict__ rid, u64 n_blk, u64* __restrict__ max_len) {
+  for (u64 r = blockIdx.x * (u64)blockDim.x + threadIdx.x; r < n_reads; r += (u64)gridDim.x * blockDim.x) {
+    const u64 a = offsets[r], b = offsets[r + 1];
+    if (b <= a || b > R) continue;
+    for (u64 q = (a + 63) >> 6; (q << 6) < b && q < n_blk; ++q) rid[q] = (u32)r;
+    if (b - a > *(volatile u64*)max_len) atomicMax((unsigned long long*)max_len, (unsigned long long)(b - a));
+  }
+}
+
+// Index of the read holding base g (g inside [offsets[0], offsets[n_reads]) and inside a
+// read): the largest r with offsets[r] <= g, searched between the reads holding the
+// starts of g's 64-base block and of the next block.
+__device__ __forceinline__ u32 ext_find_read(const u64* __restrict__ offsets, u64 n_reads, const u32* __restrict__ rid,
+                                             u64 n_blk, u64 g) {
+  const u64 q = g >> 6;
+  u32 a = rid[q];
+  if (a == 0xFFFFFFFFu) a = 0;
+  u32 b = (q + 1 < n_blk) ? rid[q + 1] : 0xFFFFFFFFu;
+  if (b == 0xFFFFFFFFu) b = (u32)(n_reads - 1);
+  while (a < b) {   // invariant: offsets[a] <= g, answer in [a, b]
+    const u32 mid = a + (b - a + 1) / 2;
+    if (offsets[mid] <= g) a = mid;
+    else b = mid - 1;
+  }
+  return a;
+}
+
+// The 32-bit value a window carries through the sort, in one of two encodings chosen per
+// count on the device: (read << pb) | position when the read index and the in-read
+// position fit together (pb = bits of the longest read's positions), else the global
+// base offset, decoded later by a search over the offsets.  Both grow with (read,
+// position), so the sort orders occurrences the same way under either.
+__device__ __forceinline__ u32 ext_pos_bits(u64 max_len) {
+  return max_len > 1 ? 64u - (u32)__clzll(max_len - 1) : 0u;
+}
+__device__ __forceinline__ bool ext_packed(u32 rbits, u64 max_len) { return rbits + ext_pos_bits(max_len) <= 32u; }
+
 struct ExtWinArgs {
   const u32* packed;
   const u32* nmask;
@@ -70,7 +112,11 @@ struct ExtWinArgs {
   int k;
   u32* blk;          // valid windows per block, then (scanned) the block's first output slot
   void* keys;        // valid windows in position order: canonical key ...
-  u32* vals;         // ... and base offset
+  u32* vals;         // ... and its (read, position) value
+  const u32* rid;    // read table of 64-base blocks (k_ext_read_blocks)
+  u64 n_blk;
+  u32 rbits;         // bits of a read index
+  const u64* max_len;   // longest read
 };
 
 // Pass 1 (WRITE = false): valid windows per block.  Pass 2: the same windows written
@@ -104,6 +150,9 @@ __global__ __launch_bounds__(EXT_T) void k_ext_windows(ExtWinArgs A) {
   u64 base = A.blk[blockIdx.x];
   for (u32 w = 0; w < wave; ++w) base += wtot[w];
   K* keys = reinterpret_cast<K*>(A.keys);
+  const u64 ml = *A.max_len;
+  const bool pk = ext_packed(A.rbits, ml);
+  const u32 pb = ext_pos_bits(ml);
 #pragma unroll
   for (int j = 0; j < (int)EXT_PER; ++j) {
     const u64 i = e0 + (u64)j * 64 + lane;
@@ -113,40 +162,15 @@ __global__ __launch_bounds__(EXT_T) void k_ext_windows(ExtWinArgs A) {
       ext_canon(A.packed, p, A.k, &key);
       const u64 at = base + mbcnt64(bal[j]);
       keys[at] = key;
-      A.vals[at] = (u32)p;
+      u32 v = (u32)p;
+      if (pk) {   // neighbouring lanes share the table entries and offsets they search
+        const u32 rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, p);
+        v = (pb < 32 ? (rd << pb) : 0u) | (u32)(p - A.offsets[rd]);
+      }
+      A.vals[at] = v;
     }
     base += (u32)__popcll(bal[j]);
   }
-}
-
-// rid[b] = the read holding base 64*b, for every 64-base block that starts inside a
-// read; other entries keep the fill value ~0.  Reads whose offsets are out of order or
-// out of range are skipped (the count reports them through its flags).
-__global__ __launch_bounds__(256) void k_ext_read_blocks(const u64* __restrict__ offsets, u64 n_reads, u64 R,
-                                                         u32* __restrict__ rid, u64 n_blk) {
-  const u64 r = blockIdx.x * (u64)blockDim.x + threadIdx.x;
-  if (r >= n_reads) return;
-  const u64 a = offsets[r], b = offsets[r + 1];
-  if (b <= a || b > R) return;
-  for (u64 q = (a + 63) >> 6; (q << 6) < b && q < n_blk; ++q) rid[q] = (u32)r;
-}
-
-// Index of the read holding base g (g inside [offsets[0], offsets[n_reads]) and inside a
-// read): the largest r with offsets[r] <= g, searched between the reads holding the
-// starts of g's 64-base block and of the next block.
-__device__ __forceinline__ u32 ext_find_read(const u64* __restrict__ offsets, u64 n_reads, const u32* __restrict__ rid,
-                                             u64 n_blk, u64 g) {
-  const u64 q = g >> 6;
-  u32 a = rid[q];
-  if (a == 0xFFFFFFFFu) a = 0;
-  u32 b = (q + 1 < n_blk) ? rid[q + 1] : 0xFFFFFFFFu;
-  if (b == 0xFFFFFFFFu) b = (u32)(n_reads - 1);
-  while (a < b) {   // invariant: offsets[a] <= g, answer in [a, b]
-    const u32 mid = a + (b - a + 1) / 2;
-    if (offsets[mid] <= g) a = mid;
-    else b = mid - 1;
-  }
-  return a;
 }
 
 // ---------------------------------------------------------------------------- runs
@@ -155,7 +179,8 @@ __device__ __forceinline__ u32 ext_find_read(const u64* __restrict__ offsets, u6
 // to hp in order from the block's scanned offset.
 template <typename K, bool WRITE>
 __global__ __launch_bounds__(EXT_T) void k_ext_heads(const K* __restrict__ keys, const u64* __restrict__ n_ptr,
-                                                     u32* __restrict__ blk, u32* __restrict__ hp) {
+                                                     u32* __restrict__ blk, u32* __restrict__ hp,
+                                                     u64* __restrict__ hbits) {
   __shared__ u32 wtot[EXT_T / 64];
   const u64 n = *n_ptr;
   const u32 lane = lane_id(), wave = threadIdx.x >> 6;
@@ -184,6 +209,7 @@ __global__ __launch_bounds__(EXT_T) void k_ext_heads(const K* __restrict__ keys,
 #pragma unroll
   for (int j = 0; j < (int)EXT_PER; ++j) {
     if ((bal[j] >> lane) & 1ull) hp[base + mbcnt64(bal[j])] = (u32)(e0 + (u64)j * 64 + lane);
+    if (lane == (u32)j) hbits[(e0 >> 6) + (u64)j] = bal[j];   // one bit per position: run starts
     base += (u32)__popcll(bal[j]);
   }
 }
@@ -211,6 +237,11 @@ struct ExtRunArgs {
   u32* occ_read;           // occurrences [0, occ_cap)
   u32* occ_pos;
   u64 occ_cap;
+  u32* odst;               // per run: its first occurrence slot if reported, else ~0
+  const u64* hbits;        // run starts, one bit per sorted position
+  const u32* blk_heads;    // runs starting before each block of positions
+  u32 rbits;               // value encoding (see ext_packed)
+  const u64* max_len;
 };
 
 // Run r of the sorted array: [hp[r], hp[r+1]) (the last run ends at n).
@@ -294,23 +325,70 @@ __global__ __launch_bounds__(EXT_T) void k_ext_runs(ExtRunArgs A) {
     const u64 EB = __ballot(emit);
     const u32 ci = emit ? c : 0u;
     const u32 incl = wave_scan_u32(ci);
+    const u64 oi = obase + (incl - ci);
     if (emit) {
       const u64 pi = pbase + mbcnt64(EB);
-      const u64 oi = obase + (incl - ci);
       if (pi < A.pair_cap) {
         ok[pi] = keys[s];
         A.out_c[pi] = c;
         A.occ_off[pi] = oi;
       }
-      for (u32 t = 0; t < c && oi + t < A.occ_cap; ++t) {
-        const u64 g = A.vals[s + t];
-        const u32 rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, g);
-        A.occ_read[oi + t] = rd;
-        A.occ_pos[oi + t] = (u32)(g - A.offsets[rd]);
-      }
     }
+    if (r < nruns) A.odst[r] = emit ? (u32)oi : 0xFFFFFFFFu;
     pbase += (u32)__popcll(EB);
     obase += lane_read(incl, 63);
+  }
+}
+
+// Occurrences: sorted position i belongs to run rid = (run starts at positions <= i) - 1;
+// when that run is reported, its offset is decoded and written to occurrence slot
+// odst[rid] + (i - hp[rid]).  Runs occupy consecutive positions and consecutive slots,
+// so the writes of a wave are contiguous.
+template <typename K>
+__global__ __launch_bounds__(EXT_T) void k_ext_occ(ExtRunArgs A) {
+  __shared__ u32 wtot[EXT_T / 64];
+  const u64 n = *A.n_ptr;
+  const u32 lane = lane_id(), wave = threadIdx.x >> 6;
+  const u64 e0 = (u64)blockIdx.x * EXT_TILE + (u64)wave * EXT_WAVE;
+  const u64 le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);   // lanes <= this one
+  u64 hw[EXT_PER];
+  u32 cnt = 0;
+#pragma unroll
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    hw[j] = (e0 + (u64)j * 64 < n) ? A.hbits[(e0 >> 6) + (u64)j] : 0ull;
+    cnt += (u32)__popcll(hw[j]);
+  }
+  if (lane == 0) wtot[wave] = cnt;
+  __syncthreads();
+  u64 run = A.blk_heads[blockIdx.x];   // runs starting before this block
+  for (u32 w = 0; w < wave; ++w) run += wtot[w];
+  const u64 ml = *A.max_len;
+  const bool pk = ext_packed(A.rbits, ml);
+  const u32 pb = ext_pos_bits(ml);
+#pragma unroll
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    const u64 i = e0 + (u64)j * 64 + lane;
+    if (i < n) {
+      const u64 rid = run + (u64)__popcll(hw[j] & le) - 1;
+      const u32 d = A.odst[rid];
+      if (d != 0xFFFFFFFFu) {
+        const u64 o = (u64)d + (i - A.hp[rid]);
+        if (o < A.occ_cap) {
+          const u32 v = A.vals[i];
+          u32 rd, ps;
+          if (pk) {
+            rd = pb < 32 ? (v >> pb) : 0u;
+            ps = v & (u32)((1ull << pb) - 1);
+          } else {
+            rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, v);
+            ps = (u32)(v - A.offsets[rd]);
+          }
+          A.occ_read[o] = rd;
+          A.occ_pos[o] = ps;
+        }
+      }
+    }
+    run += (u32)__popcll(hw[j]);
   }
 }
 

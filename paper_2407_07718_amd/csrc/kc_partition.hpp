@@ -57,11 +57,11 @@ __global__ __launch_bounds__(256) void k_pack(const u8* __restrict__ reads, u64 
 // the buffer (flag bit 0).
 __global__ __launch_bounds__(256) void k_read_starts(const u64* __restrict__ offsets, u64 n_reads, u64 R,
                                                      u32* __restrict__ starts, u32* __restrict__ flags) {
-  const u64 r = blockIdx.x * (u64)blockDim.x + threadIdx.x;
-  if (r >= n_reads) return;
-  const u64 a = offsets[r], b = offsets[r + 1];
-  if (b < a || b > R) atomicOr(flags, 1u);
-  if (a < R) atomicOr(&starts[a >> 5], 1u << (a & 31));
+  for (u64 r = blockIdx.x * (u64)blockDim.x + threadIdx.x; r < n_reads; r += (u64)gridDim.x * blockDim.x) {
+    const u64 a = offsets[r], b = offsets[r + 1];
+    if (b < a || b > R) atomicOr(flags, 1u);
+    if (a < R) atomicOr(&starts[a >> 5], 1u << (a & 31));
+  }
 }
 
 // ---------------------------------------------------------------------------- extract

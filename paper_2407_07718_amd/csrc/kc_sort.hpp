@@ -132,7 +132,19 @@ __global__ __launch_bounds__(256) void k_radix_upsweep(const K* __restrict__ key
   __syncthreads();
   u64 s, e;
   block_range(*n_ptr, nb, &s, &e);
-  for (u64 i = s + tid; i < e; i += 256) atomicAdd(&h[wave][key_digit(keys[i], sh)], 1u);
+  // eight independent loads in flight per thread before their counts
+  constexpr u32 U = 8;
+  for (u64 i0 = s + tid; i0 < e; i0 += 256 * U) {
+    K kx[U];
+#pragma unroll
+    for (u32 u = 0; u < U; ++u) {
+      const u64 i = i0 + (u64)u * 256;
+      if (i < e) kx[u] = keys[i];
+    }
+#pragma unroll
+    for (u32 u = 0; u < U; ++u)
+      if (i0 + (u64)u * 256 < e) atomicAdd(&h[wave][key_digit(kx[u], sh)], 1u);
+  }
   __syncthreads();
   counts[(u64)tid * nb + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
 }
@@ -228,8 +240,9 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(u32* __restrict__ counts,
 }
 
 // Stable scatter of one pass.  Each tile of T*ITEMS keys is ranked by digit, staged in
-// LDS in digit order and written out as one run per digit.
-template <typename K, bool HASV, int T, int ITEMS>
+// LDS in digit order and written out as one run per digit.  With SHARED the values are
+// staged after the keys in the same LDS buffer (less LDS per block, one more barrier).
+template <typename K, bool HASV, int T, int ITEMS, bool SHARED = false>
 __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin, K* __restrict__ kout,
                                                        const u32* __restrict__ vin, u32* __restrict__ vout,
                                                        const u64* __restrict__ n_ptr, const u32* __restrict__ counts,
@@ -237,7 +250,7 @@ __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin
   constexpr int W = T / 64, TILE = T * ITEMS;
   __shared__ RankSmem<W> S;
   __shared__ K stage_k[TILE];
-  __shared__ u32 stage_v[HASV ? TILE : 1];
+  __shared__ u32 stage_v[(HASV && !SHARED) ? TILE : 1];
   __shared__ u32 run_base[256];
   const u32 nb = gridDim.x, tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   for (u32 i = tid; i < W * 256; i += T) (&S.tbl[0][0])[i] = 0;
@@ -251,6 +264,28 @@ __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin
   __syncthreads();
   u64 s, e;
   block_range(*n_ptr, nb, &s, &e);
+  // Tiles are loaded one ahead into registers: the next tile's loads stay in flight
+  // while this tile is ranked, staged and written (barriers wait on LDS only).
+  K kn[ITEMS];
+  u32 vn[ITEMS];
+  auto load_tile = [&](u64 t0) {
+    const u32 nt = (u32)min((u64)TILE, e - t0);
+    const int per = (int)((nt + 64u * W - 1) / (64u * W));
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+        if (idx < nt) {
+          kn[j] = kin[t0 + idx];
+          if (HASV) vn[j] = vin[t0 + idx];
+        } else {
+          kn[j] = key_zero<K>();
+          vn[j] = 0;
+        }
+      }
+    }
+  };
+  if (s < e) load_tile(s);
   for (u64 t0 = s; t0 < e; t0 += TILE) {
     const u32 nt = (u32)min((u64)TILE, e - t0);
     const int per = (int)((nt + 64u * W - 1) / (64u * W));
@@ -258,17 +293,13 @@ __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin
     u32 vr[ITEMS], dg[ITEMS], rk[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      if (j < per) {
-        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
-        if (idx < nt) {
-          kr[j] = kin[t0 + idx];
-          if (HASV) vr[j] = vin[t0 + idx];
-        } else {
-          kr[j] = key_zero<K>();
-          vr[j] = 0;
-        }
-        dg[j] = key_digit(kr[j], sh);
-      }
+      kr[j] = kn[j];
+      vr[j] = vn[j];
+    }
+    if (t0 + TILE < e) load_tile(t0 + TILE);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) dg[j] = key_digit(kr[j], sh);
     }
     rank_by_digit<T, ITEMS>(dg, rk, per, nt, S);
 #pragma unroll
@@ -277,17 +308,47 @@ __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin
         const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
         if (idx < nt) {
           stage_k[rk[j]] = kr[j];
-          if (HASV) stage_v[rk[j]] = vr[j];
+          if (HASV && !SHARED) stage_v[rk[j]] = vr[j];
         }
       }
     }
     __syncthreads();
-    for (u32 i = tid; i < nt; i += T) {
-      const K key = stage_k[i];
-      const u32 d = key_digit(key, sh);
-      const u64 dst = (u64)run_base[d] + (i - S.dstart[d]);
-      kout[dst] = key;
-      if (HASV) vout[dst] = stage_v[i];
+    if (HASV && SHARED) {
+      // keys out, remembering each staged slot's destination; then the values
+      u32 dsts[ITEMS];
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const u32 i = tid + (u32)j * T;
+        if (i < nt) {
+          const K key = stage_k[i];
+          const u32 d = key_digit(key, sh);
+          dsts[j] = run_base[d] + (i - S.dstart[d]);
+          kout[dsts[j]] = key;
+        }
+      }
+      __syncthreads();
+      u32* sv = reinterpret_cast<u32*>(stage_k);
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        if (j < per) {
+          const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+          if (idx < nt) sv[rk[j]] = vr[j];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const u32 i = tid + (u32)j * T;
+        if (i < nt) vout[dsts[j]] = sv[i];
+      }
+    } else {
+      for (u32 i = tid; i < nt; i += T) {
+        const K key = stage_k[i];
+        const u32 d = key_digit(key, sh);
+        const u64 dst = (u64)run_base[d] + (i - S.dstart[d]);
+        kout[dst] = key;
+        if (HASV) vout[dst] = stage_v[i];
+      }
     }
     __syncthreads();
     if (tid < 256) run_base[tid] += S.dstart[tid + 1] - S.dstart[tid];

@@ -132,3 +132,18 @@ def test_ext_short_read_config_full_size():
     print("case ext short-read full size: GPU done, oracle next", flush=True)
     ref = oracle.count_ext(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, 65536)
     assert_same_ext(got, ref, "ext short-read full size")
+
+
+def test_ext_both_value_encodings():
+    # 2^20 + 1 reads with one 9 kb read: read index (21 bits) and position (14 bits) no
+    # longer fit one 32-bit value together, so the windows carry global base offsets
+    rng = np.random.Generator(np.random.PCG64(4711))
+    short = ["".join("ACGT"[c] for c in rng.integers(0, 4, 6)) for _ in range(64)]
+    seqs = [short[i % 64] for i in range((1 << 20))]
+    seqs.insert(1000, "".join("ACGT"[c] for c in rng.integers(0, 4, 9000)))
+    reads, offsets = synth.from_strings(seqs)
+    check_ext(reads, offsets, 5, 1, 0xFFFFFFFF, 64, label="offset encoding")
+    # the same reads without the long one: packed (read, position) values
+    del seqs[1000]
+    reads, offsets = synth.from_strings(seqs)
+    check_ext(reads, offsets, 5, 1, 0xFFFFFFFF, 64, label="packed encoding")
