@@ -155,7 +155,7 @@ typedef struct kc_ext_result {
 
 /* Host API of the extension version.  Arguments and errors as kc_count (no m); on KC_OK
  * *out owns host arrays that kc_ext_result_free releases.  cfg->hbm_budget (if set)
- * bounds the device workspace: KC_ENOMEM when it does not fit. */
+ * bounds the device workspace (see kc_ext_workspace_size): KC_ENOMEM when no plan fits. */
 int kc_count_ext(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k,
                  uint32_t min_freq, uint32_t max_freq, uint64_t hist_len, const kc_config *cfg,
                  kc_ext_result *out);
@@ -163,8 +163,20 @@ int kc_count_ext(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads
 /* Release the arrays of a kc_ext_result filled by kc_count_ext (safe on a zeroed one). */
 void kc_ext_result_free(kc_ext_result *res);
 
-/* Bytes of device workspace kc_count_ext_device needs (0 on bad arguments). */
-size_t kc_ext_workspace_size(uint64_t total_bases, uint64_t n_reads, int k);
+/* Bytes of device workspace kc_count_ext_device needs (0 on bad arguments, or when
+ * cfg->hbm_budget is set and no plan fits it).
+ *
+ * Memory-bounded counting (Section 3.1: with too little memory for an out-of-place sort
+ * the paper switches to an in-place one; Section 3.3: the exchange runs in rounds of
+ * bounded size).  When cfg->hbm_budget is smaller than the workspace of a one-pass
+ * count, the plan sizes the sort buffers from the budget and counts in rounds of
+ * consecutive key ranges: a histogram of the top 12 key bits splits the canonical
+ * values into ranges of at most a buffer's worth of windows, and each round regenerates
+ * the windows of its range from the 2-bit reads, sorts and counts them, and appends its
+ * pairs and occurrences (ranges ascend, so the output stays in key order).  Results are
+ * identical to a one-pass count.  KC_ENOMEM when a single 12-bit key prefix holds more
+ * windows than a round (reported by the count). */
+size_t kc_ext_workspace_size(uint64_t total_bases, uint64_t n_reads, int k, const kc_config *cfg);
 
 /* Device API of the extension version; every buffer is caller-owned device memory:
  *   d_kmers (pair_capacity * key_words words), d_counts (pair_capacity), d_occ_off

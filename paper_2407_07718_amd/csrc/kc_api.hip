@@ -666,18 +666,34 @@ int device_common(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* 
 }
 
 // ---------------------------------------------------------------------------- extension version
-// Workspace of one extension count: the packed reads and masks, two (key, offset)
-// buffers for the out-of-place sort, run heads, per-block counts and the read table.
+// Workspace of one extension count: the packed reads and masks, two (key, value) buffers
+// for the out-of-place sort, run heads, per-block counts and the read table.  With an HBM
+// budget too small for all windows at once, the windows are counted in rounds of
+// consecutive key ranges: the sort buffers then hold `cap` windows, one round's worth.
 struct ExtPlan {
   int k = 0, key_words = 0;
   u64 R = 0, n_reads = 0, N = 0;   // bases, reads, window positions (upper bound)
-  u64 n_tiles = 1, n_packed = 0, n_mask = 0, n_blk = 0;
+  u64 cap = 0;                     // windows sorted per round
+  u32 rounds = 1;                  // rounds enqueued (1: all windows at once)
+  u64 n_tiles = 1, n_tiles_cap = 1, n_packed = 0, n_mask = 0, n_blk = 0;
   u32 nb = 1;                      // radix blocks
   u64 o_packed, o_nmask, o_starts, o_k0, o_k1, o_v0, o_v1, o_hp, o_blk, o_bp, o_bo, o_rid, o_ctrl, o_cnt, o_tot,
-      o_scan, bytes = 0;
+      o_scan, o_bins, o_rb, bytes = 0;
 };
 
-enum ExtCtrl : int { X_NWIN = 0, X_NRUNS = 1, X_NPAIRS = 2, X_NOCC = 3, X_FLAGS = 4, X_MAXLEN = 5, X_WORDS = 6 };
+enum ExtCtrl : int {
+  X_NWIN = 0,     // windows of the current round
+  X_NRUNS = 1,
+  X_NPAIRS = 2,   // pairs / occurrences of the current round
+  X_NOCC = 3,
+  X_FLAGS = 4,
+  X_MAXLEN = 5,
+  X_NWINC = 6,    // windows of the round, clamped to cap
+  X_PBASE = 7,    // pairs / occurrences / windows of all rounds so far
+  X_OBASE = 8,
+  X_WTOT = 9,
+  X_WORDS = 10
+};
 
 // bits of a read index (indices 0 .. n_reads - 1)
 u32 read_bits(u64 n_reads) {
@@ -686,20 +702,12 @@ u32 read_bits(u64 n_reads) {
   return b;
 }
 
-bool make_ext_plan(u64 R, u64 n_reads, int k, ExtPlan* p) {
-  p->k = k;
-  p->key_words = k <= 31 ? 1 : 2;
-  p->R = R;
-  p->n_reads = n_reads;
-  p->N = std::max<u64>(1, R);
-  p->n_tiles = std::max<u64>(1, ceil_div(p->N, EXT_TILE));
-  if (p->n_tiles > 1024ull * SCAN_BLOCK) return false;
-  p->n_packed = R / 16 + 16;
-  p->n_mask = R / 32 + 16;
-  p->n_blk = R / 64 + 2;
+void ext_layout(ExtPlan* p, u64 cap) {
+  p->cap = cap;
+  p->n_tiles_cap = std::max<u64>(1, ceil_div(cap, EXT_TILE));
   const u64 w = 8ull * p->key_words;
   const u64 tile = (u64)RADIX_T * (p->key_words == 1 ? RADIX_ITEMS_64 : RADIX_ITEMS_128);
-  p->nb = (u32)std::min<u64>(KC_RADIX_NB_MAX, std::max<u64>(1, ceil_div(p->N, tile * 2)));
+  p->nb = (u32)std::min<u64>(KC_RADIX_NB_MAX, std::max<u64>(1, ceil_div(cap, tile * 2)));
   u64 o = 0;
   auto take = [&](u64 bytes) {
     u64 r = o;
@@ -711,22 +719,54 @@ bool make_ext_plan(u64 R, u64 n_reads, int k, ExtPlan* p) {
   p->o_starts = take(4 * p->n_mask);
   // whole tiles, so that the run-start bits of every tile (one u64 per 64 positions,
   // kept in a free key buffer) fit as well
-  const u64 NT = p->n_tiles * EXT_TILE;
+  const u64 NT = p->n_tiles_cap * EXT_TILE;
   p->o_k0 = take(w * NT);
   p->o_k1 = take(w * NT);
   p->o_v0 = take(4 * NT);
   p->o_v1 = take(4 * NT);
   p->o_hp = take(4 * NT);
-  p->o_blk = take(4 * p->n_tiles);
-  p->o_bp = take(4 * p->n_tiles);
-  p->o_bo = take(4 * p->n_tiles);
+  p->o_blk = take(4 * std::max(p->n_tiles, p->n_tiles_cap));
+  p->o_bp = take(4 * p->n_tiles_cap);
+  p->o_bo = take(4 * p->n_tiles_cap);
   p->o_rid = take(4 * p->n_blk);
   p->o_ctrl = take(8ull * X_WORDS);
   p->o_cnt = take(4ull * 256 * p->nb);
   p->o_tot = take(4ull * 256);
   p->o_scan = take(8ull * 1024);
+  p->o_bins = take(4ull * EXT_NBINS);
+  p->o_rb = take(4ull * (p->rounds + 1));
   p->bytes = o;
-  return true;
+}
+
+// budget 0: no limit.  Returns false when the input is too large or the budget cannot
+// hold even small rounds.
+bool make_ext_plan(u64 R, u64 n_reads, int k, u64 budget, ExtPlan* p) {
+  p->k = k;
+  p->key_words = k <= 31 ? 1 : 2;
+  p->R = R;
+  p->n_reads = n_reads;
+  p->N = std::max<u64>(1, R);
+  p->n_tiles = std::max<u64>(1, ceil_div(p->N, EXT_TILE));
+  if (p->n_tiles > 1024ull * SCAN_BLOCK) return false;
+  p->n_packed = R / 16 + 16;
+  p->n_mask = R / 32 + 16;
+  p->n_blk = R / 64 + 2;
+  p->rounds = 1;
+  ext_layout(p, p->N);
+  if (!budget || p->bytes <= budget) return true;
+  // rounds: sort buffers sized from what the budget leaves after the fixed part
+  ExtPlan q = *p;
+  ext_layout(&q, 0);
+  const u64 per = 2 * 8ull * p->key_words + 12;   // two keys, two values, one head per window
+  if (budget <= q.bytes) return false;
+  u64 cap = (budget - q.bytes) / per / EXT_TILE * EXT_TILE;
+  for (; cap >= 16 * EXT_TILE; cap -= EXT_TILE) {
+    // a round of the greedy split holds more than cap - (largest prefix) >= cap / 2 windows
+    p->rounds = (u32)std::min<u64>(EXT_NBINS, ceil_div(2 * p->N, cap) + 1);
+    ext_layout(p, cap);
+    if (p->bytes <= budget) return true;
+  }
+  return false;
 }
 
 template <typename K>
@@ -746,6 +786,8 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   u32* bp = at<u32>(ws, P.o_bp);
   u32* bo = at<u32>(ws, P.o_bo);
   u32* rid = at<u32>(ws, P.o_rid);
+  u32* bins = at<u32>(ws, P.o_bins);
+  u32* rb = at<u32>(ws, P.o_rb);
   u64* ctrl = at<u64>(ws, P.o_ctrl);
   u64* scanbuf = at<u64>(ws, P.o_scan);
   u32* flags = reinterpret_cast<u32*>(ctrl + X_FLAGS);
@@ -753,6 +795,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
     if (n_words)
       hipLaunchKernelGGL(k_fill_u32, grid_for(n_words, 256, 4096), dim3(256), 0, st, (u32*)p, n_words, v);
   };
+  const bool rounds = P.rounds > 1;
   stage_mark(0, st);
   fill(ctrl, 2ull * X_WORDS, 0u);
   fill(d_hist, 2ull * hist_len, 0u);
@@ -769,8 +812,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
     hipLaunchKernelGGL(k_ext_read_blocks, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, rid,
                        P.n_blk, ctrl + X_MAXLEN);
   }
-  stage_mark(1, st);
-  // window positions: every base of the buffer; the kernel keeps the windows inside
+  // window positions: every base of the buffer; the kernels keep the windows inside
   // [offsets[0], offsets[n_reads]) that hold k valid bases of one read
   ExtWinArgs wa;
   wa.packed = packed;
@@ -788,29 +830,22 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   wa.n_blk = P.n_blk;
   wa.rbits = read_bits(P.n_reads);
   wa.max_len = ctrl + X_MAXLEN;
-  const dim3 gw((u32)P.n_tiles);
-  hipLaunchKernelGGL((k_ext_windows<K, false>), gw, dim3(EXT_T), 0, st, wa);
-  scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles, ctrl + X_NWIN, scanbuf, st);
-  hipLaunchKernelGGL((k_ext_windows<K, true>), gw, dim3(EXT_T), 0, st, wa);
-  stage_mark(2, st);
-  bool second = false;
-  int rc = radix_sort<K, true>(k0, k1, v0, v1, ctrl + X_NWIN, at<u32>(ws, P.o_cnt), at<u32>(ws, P.o_tot), P.nb,
-                               2 * P.k, st, &second);
-  if (rc) return rc;
-  const K* sk = second ? k1 : k0;
-  const u32* sv = second ? v1 : v0;
-  // the other (key, offset) buffer is free now: run-start bits and per-run slots go there
-  u64* hbits = reinterpret_cast<u64*>(second ? k0 : k1);
-  u32* odst = second ? v0 : v1;
-  stage_mark(3, st);
-  hipLaunchKernelGGL((k_ext_heads<K, false>), gw, dim3(EXT_T), 0, st, sk, ctrl + X_NWIN, blk, hp, hbits);
-  scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles, ctrl + X_NRUNS, scanbuf, st);
-  hipLaunchKernelGGL((k_ext_heads<K, true>), gw, dim3(EXT_T), 0, st, sk, ctrl + X_NWIN, blk, hp, hbits);
+  wa.range = rb;
+  wa.cap = P.cap;
+  const dim3 gw((u32)P.n_tiles), gc((u32)P.n_tiles_cap);
+  stage_mark(1, st);
+  if (rounds) {
+    // key ranges of the rounds from the windows per key prefix
+    fill(bins, EXT_NBINS, 0u);
+    hipLaunchKernelGGL((k_ext_prefix_hist<K>), gw, dim3(EXT_T), 0, st, wa, bins);
+    hipLaunchKernelGGL(k_ext_plan_rounds, dim3(1), dim3(64), 0, st, bins, P.cap, P.rounds, rb, flags);
+  } else {
+    fill(rb, 1, 0u);
+    fill(rb + 1, 1, EXT_NBINS);
+  }
   ExtRunArgs ra;
-  ra.keys = sk;
-  ra.vals = sv;
   ra.hp = hp;
-  ra.n_ptr = ctrl + X_NWIN;
+  ra.n_ptr = ctrl + X_NWINC;
   ra.nruns_ptr = ctrl + X_NRUNS;
   ra.min_freq = lo;
   ra.max_freq = hi;
@@ -830,18 +865,50 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   ra.occ_read = d_occ_read;
   ra.occ_pos = d_occ_pos;
   ra.occ_cap = occ_cap;
-  ra.odst = odst;
-  ra.hbits = hbits;
   ra.blk_heads = blk;
   ra.rbits = wa.rbits;
   ra.max_len = ctrl + X_MAXLEN;
-  hipLaunchKernelGGL((k_ext_runs<K, false>), gw, dim3(EXT_T), 0, st, ra);
-  scan_u32(bp, bp, (const u64*)nullptr, P.n_tiles, ctrl + X_NPAIRS, scanbuf, st);
-  scan_u32(bo, bo, (const u64*)nullptr, P.n_tiles, ctrl + X_NOCC, scanbuf, st);
-  stage_mark(4, st);
-  hipLaunchKernelGGL((k_ext_runs<K, true>), gw, dim3(EXT_T), 0, st, ra);
-  hipLaunchKernelGGL((k_ext_occ<K>), gw, dim3(EXT_T), 0, st, ra);
-  hipLaunchKernelGGL(k_ext_finalize, dim3(1), dim3(64), 0, st, d_tot, ctrl + X_NWIN, ctrl + X_NPAIRS, ctrl + X_NOCC,
+  ra.pair_base = ctrl + X_PBASE;
+  ra.occ_base = ctrl + X_OBASE;
+  for (u32 q = 0; q < P.rounds; ++q) {
+    wa.range = rb + q;
+    hipLaunchKernelGGL((k_ext_windows<K, false>), gw, dim3(EXT_T), 0, st, wa);
+    scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles, ctrl + X_NWIN, scanbuf, st);
+    hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, ctrl + X_NWIN, P.cap, ctrl + X_NWINC);
+    hipLaunchKernelGGL((k_ext_windows<K, true>), gw, dim3(EXT_T), 0, st, wa);
+    if (!rounds) stage_mark(2, st);
+    bool second = false;
+    int rc = radix_sort<K, true>(k0, k1, v0, v1, ctrl + X_NWINC, at<u32>(ws, P.o_cnt), at<u32>(ws, P.o_tot), P.nb,
+                                 2 * P.k, st, &second);
+    if (rc) return rc;
+    const K* sk = second ? k1 : k0;
+    const u32* sv = second ? v1 : v0;
+    // the other (key, value) buffer is free now: run-start bits and per-run slots go there
+    u64* hbits = reinterpret_cast<u64*>(second ? k0 : k1);
+    u32* odst = second ? v0 : v1;
+    if (!rounds) stage_mark(3, st);
+    hipLaunchKernelGGL((k_ext_heads<K, false>), gc, dim3(EXT_T), 0, st, sk, ctrl + X_NWINC, blk, hp, hbits);
+    scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles_cap, ctrl + X_NRUNS, scanbuf, st);
+    hipLaunchKernelGGL((k_ext_heads<K, true>), gc, dim3(EXT_T), 0, st, sk, ctrl + X_NWINC, blk, hp, hbits);
+    ra.keys = sk;
+    ra.vals = sv;
+    ra.odst = odst;
+    ra.hbits = hbits;
+    hipLaunchKernelGGL((k_ext_runs<K, false>), gc, dim3(EXT_T), 0, st, ra);
+    scan_u32(bp, bp, (const u64*)nullptr, P.n_tiles_cap, ctrl + X_NPAIRS, scanbuf, st);
+    scan_u32(bo, bo, (const u64*)nullptr, P.n_tiles_cap, ctrl + X_NOCC, scanbuf, st);
+    if (!rounds) stage_mark(4, st);
+    hipLaunchKernelGGL((k_ext_runs<K, true>), gc, dim3(EXT_T), 0, st, ra);
+    hipLaunchKernelGGL((k_ext_occ<K>), gc, dim3(EXT_T), 0, st, ra);
+    hipLaunchKernelGGL(k_ext_round_end, dim3(1), dim3(64), 0, st, ctrl + X_NPAIRS, ctrl + X_NOCC, ctrl + X_PBASE,
+                       ctrl + X_OBASE, ctrl + X_NWIN, ctrl + X_WTOT, P.cap, flags);
+  }
+  if (rounds) {
+    stage_mark(2, st);
+    stage_mark(3, st);
+    stage_mark(4, st);
+  }
+  hipLaunchKernelGGL(k_ext_finalize, dim3(1), dim3(64), 0, st, d_tot, ctrl + X_WTOT, ctrl + X_PBASE, ctrl + X_OBASE,
                      flags, d_occ_off, pair_cap);
   stage_mark(5, st);
   HIP_TRY(hipGetLastError());
@@ -1039,10 +1106,10 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
 }
 
 // ---------------------------------------------------------------- extension version
-size_t kc_ext_workspace_size(uint64_t total_bases, uint64_t n_reads, int k) {
+size_t kc_ext_workspace_size(uint64_t total_bases, uint64_t n_reads, int k, const kc_config* cfg) {
   if (k < 1 || k > 63) return 0;
   ExtPlan P;
-  if (!make_ext_plan(total_bases, n_reads, k, &P)) return 0;
+  if (!make_ext_plan(total_bases, n_reads, k, cfg ? cfg->hbm_budget : 0, &P)) return 0;
   return (size_t)P.bytes;
 }
 
@@ -1058,12 +1125,12 @@ static int ext_device_common(const uint8_t* d_reads, uint64_t total_bases, const
     return fail(KC_EINVAL, "NULL device pointer");
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(KC_EINVAL, "workspace not 256-byte aligned");
   ExtPlan P;
-  if (!make_ext_plan(total_bases, n_reads, k, &P)) return fail(KC_EINVAL, "input too large");
+  const u64 budget = cfg ? cfg->hbm_budget : 0;
+  if (!make_ext_plan(total_bases, n_reads, k, budget, &P))
+    return budget ? fail(KC_ENOMEM, "no plan fits a workspace budget of %llu bytes", (unsigned long long)budget)
+                  : fail(KC_EINVAL, "input too large");
   if (ws_bytes < P.bytes)
     return fail(KC_EINVAL, "workspace of %zu bytes < %llu needed", ws_bytes, (unsigned long long)P.bytes);
-  if (cfg && cfg->hbm_budget && P.bytes > cfg->hbm_budget)
-    return fail(KC_ENOMEM, "workspace %llu bytes > budget %llu", (unsigned long long)P.bytes,
-                (unsigned long long)cfg->hbm_budget);
   return enqueue_ext_any(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_occ_off,
                          d_occ_read, d_occ_pos, occ_cap, d_hist, reinterpret_cast<DevTotals*>(d_tot),
                          reinterpret_cast<hipStream_t>(stream));
@@ -1098,6 +1165,7 @@ int kc_count_ext_device(const uint8_t* d_reads, uint64_t total_bases, const uint
   HIP_TRY(hipStreamSynchronize(st));
   if (totals_out) *totals_out = t;
   if (t.flags & 1) return fail(KC_EINVAL, "offsets are not non-decreasing or exceed total_bases");
+  if (t.flags & 8) return fail(KC_ENOMEM, "a key range holds more windows than a round of the budget");
   if (t.flags) return fail(KC_EDEVICE, "internal status flags=%llu", (unsigned long long)t.flags);
   if (t.n_pairs > pair_capacity || t.n_occ > occ_capacity)
     return fail(KC_ETRUNC, "%llu pairs / %llu occurrences > capacities %llu / %llu", (unsigned long long)t.n_pairs,
@@ -1130,10 +1198,10 @@ int kc_count_ext(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads
   int rc = ext_check(k, min_freq, max_freq, hist_len, R, n_reads);
   if (rc) return rc;
   ExtPlan P;
-  if (!make_ext_plan(R, n_reads, k, &P)) return fail(KC_EINVAL, "input too large");
-  if (cfg && cfg->hbm_budget && P.bytes > cfg->hbm_budget)
-    return fail(KC_ENOMEM, "workspace %llu bytes > budget %llu", (unsigned long long)P.bytes,
-                (unsigned long long)cfg->hbm_budget);
+  const u64 budget = cfg ? cfg->hbm_budget : 0;
+  if (!make_ext_plan(R, n_reads, k, budget, &P))
+    return budget ? fail(KC_ENOMEM, "no plan fits a workspace budget of %llu bytes", (unsigned long long)budget)
+                  : fail(KC_EINVAL, "input too large");
   const u64 w = 8ull * P.key_words, cap = std::max<u64>(1, n_max);
   const u64 in_bytes = align_up(R + 16, 256) + align_up(8 * (n_reads + 1), 256);
   const u64 o_k = 0, o_c = o_k + align_up(w * cap, 256), o_off = o_c + align_up(4 * cap, 256),
@@ -1175,6 +1243,8 @@ int kc_count_ext(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads
   if (hipMemcpyAsync(&t, d_tot, sizeof(t), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return cleanup(fail(KC_EDEVICE, "count failed: %s", hipGetErrorString(hipGetLastError())));
+  if (t.flags & 1) return cleanup(fail(KC_EINVAL, "offsets exceed the reads"));
+  if (t.flags & 8) return cleanup(fail(KC_ENOMEM, "a key range holds more windows than a round of the budget"));
   if (t.flags) return cleanup(fail(KC_EDEVICE, "internal status flags=%llu", (unsigned long long)t.flags));
   kc_result& pr = out->pairs;
   pr.n_pairs = t.n_pairs;

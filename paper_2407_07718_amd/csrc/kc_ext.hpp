@@ -102,6 +102,19 @@ __device__ __forceinline__ u32 ext_pos_bits(u64 max_len) {
 }
 __device__ __forceinline__ bool ext_packed(u32 rbits, u64 max_len) { return rbits + ext_pos_bits(max_len) <= 32u; }
 
+// Key ranges for counting in rounds: a canonical key's prefix is its top EXT_PBITS bits
+// of 2k (the whole key when 2k <= EXT_PBITS), so prefix order is key order.
+constexpr u32 EXT_PBITS = 12, EXT_NBINS = 1u << EXT_PBITS;
+__device__ __forceinline__ u32 ext_prefix(u64 key, int k) {
+  const int sh = 2 * k - (int)EXT_PBITS;
+  return sh > 0 ? (u32)(key >> sh) : (u32)key;
+}
+__device__ __forceinline__ u32 ext_prefix(k128 key, int k) {
+  const int sh = 2 * k - (int)EXT_PBITS;   // >= 52 for k >= 32
+  if (sh >= 64) return (u32)(key.hi >> (sh - 64));
+  return (u32)((key.lo >> sh) | (key.hi << (64 - sh))) & (EXT_NBINS - 1);
+}
+
 struct ExtWinArgs {
   const u32* packed;
   const u32* nmask;
@@ -117,6 +130,8 @@ struct ExtWinArgs {
   u64 n_blk;
   u32 rbits;         // bits of a read index
   const u64* max_len;   // longest read
+  const u32* range;  // this round's key prefixes [range[0], range[1])
+  u64 cap;           // windows a round can hold; writes beyond it are dropped (and flagged)
 };
 
 // Pass 1 (WRITE = false): valid windows per block.  Pass 2: the same windows written
@@ -128,12 +143,20 @@ __global__ __launch_bounds__(EXT_T) void k_ext_windows(ExtWinArgs A) {
   const u64 e0 = (u64)blockIdx.x * EXT_TILE + (u64)wave * EXT_WAVE;
   const u64 lo = A.n_reads ? min(A.offsets[0], A.R) : 0;
   const u64 hi = A.n_reads ? min(A.offsets[A.n_reads], A.R) : 0;
+  const u32 r0 = A.range[0], r1 = A.range[1];
+  const bool all = r0 == 0 && r1 >= EXT_NBINS;
   u64 bal[EXT_PER];
   u32 cnt = 0;
 #pragma unroll
   for (int j = 0; j < (int)EXT_PER; ++j) {
     const u64 i = e0 + (u64)j * 64 + lane;
-    const bool v = i < A.n_pos && i >= lo && i + (u64)A.k <= hi && ext_window_valid(A.nmask, A.starts, i, A.k);
+    bool v = i < A.n_pos && i >= lo && i + (u64)A.k <= hi && ext_window_valid(A.nmask, A.starts, i, A.k);
+    if (v && !all) {
+      K key;
+      ext_canon(A.packed, i, A.k, &key);
+      const u32 pf = ext_prefix(key, A.k);
+      v = pf >= r0 && pf < r1;
+    }
     bal[j] = __ballot(v);
     cnt += (u32)__popcll(bal[j]);
   }
@@ -161,13 +184,15 @@ __global__ __launch_bounds__(EXT_T) void k_ext_windows(ExtWinArgs A) {
       K key;
       ext_canon(A.packed, p, A.k, &key);
       const u64 at = base + mbcnt64(bal[j]);
-      keys[at] = key;
       u32 v = (u32)p;
       if (pk) {   // neighbouring lanes share the table entries and offsets they search
         const u32 rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, p);
         v = (pb < 32 ? (rd << pb) : 0u) | (u32)(p - A.offsets[rd]);
       }
-      A.vals[at] = v;
+      if (at < A.cap) {
+        keys[at] = key;
+        A.vals[at] = v;
+      }
     }
     base += (u32)__popcll(bal[j]);
   }
@@ -242,6 +267,8 @@ struct ExtRunArgs {
   const u32* blk_heads;    // runs starting before each block of positions
   u32 rbits;               // value encoding (see ext_packed)
   const u64* max_len;
+  const u64* pair_base;    // pairs and occurrences of earlier rounds
+  const u64* occ_base;
 };
 
 // Run r of the sorted array: [hp[r], hp[r+1]) (the last run ends at n).
@@ -310,7 +337,7 @@ __global__ __launch_bounds__(EXT_T) void k_ext_runs(ExtRunArgs A) {
     }
     return;
   }
-  u64 pbase = A.blk_pairs[blockIdx.x], obase = A.blk_occ[blockIdx.x];
+  u64 pbase = *A.pair_base + A.blk_pairs[blockIdx.x], obase = *A.occ_base + A.blk_occ[blockIdx.x];
   for (u32 w = 0; w < wave; ++w) {
     pbase += wp[w];
     obase += wo[w];
@@ -392,6 +419,68 @@ __global__ __launch_bounds__(EXT_T) void k_ext_occ(ExtRunArgs A) {
   }
 }
 
+// Windows per key prefix, over all valid windows (per-block LDS bins, then one global
+// add per non-empty bin).
+template <typename K>
+__global__ __launch_bounds__(EXT_T) void k_ext_prefix_hist(ExtWinArgs A, u32* __restrict__ bins) {
+  __shared__ u32 h[EXT_NBINS];
+  for (u32 i = threadIdx.x; i < EXT_NBINS; i += EXT_T) h[i] = 0;
+  __syncthreads();
+  const u64 lo = A.n_reads ? min(A.offsets[0], A.R) : 0;
+  const u64 hi = A.n_reads ? min(A.offsets[A.n_reads], A.R) : 0;
+  const u64 e0 = (u64)blockIdx.x * EXT_TILE;
+  for (u32 j = 0; j < EXT_PER; ++j) {
+    const u64 i = e0 + (u64)j * EXT_T + threadIdx.x;
+    if (i < A.n_pos && i >= lo && i + (u64)A.k <= hi && ext_window_valid(A.nmask, A.starts, i, A.k)) {
+      K key;
+      ext_canon(A.packed, i, A.k, &key);
+      atomicAdd(&h[ext_prefix(key, A.k)], 1u);
+    }
+  }
+  __syncthreads();
+  for (u32 i = threadIdx.x; i < EXT_NBINS; i += EXT_T)
+    if (h[i]) atomicAdd(&bins[i], h[i]);
+}
+
+// Rounds: consecutive prefix ranges holding at most `cap` windows each, taken greedily;
+// range q is [rb[q], rb[q+1]), unused rounds are empty.  Flag bit 3 when a single prefix
+// or the rounds available cannot hold the windows.
+__global__ void k_ext_plan_rounds(const u32* __restrict__ bins, u64 cap, u32 r_max, u32* __restrict__ rb,
+                                  u32* __restrict__ flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  u32 r = 0;
+  u64 acc = 0;
+  rb[0] = 0;
+  bool bad = false;
+  for (u32 b = 0; b < EXT_NBINS; ++b) {
+    const u64 c = bins[b];
+    if (c > cap) bad = true;
+    if (acc + c > cap && acc > 0) {
+      if (r + 1 < r_max) {
+        ++r;
+        rb[r] = b;
+        acc = 0;
+      } else {
+        bad = true;
+      }
+    }
+    acc += c;
+  }
+  for (u32 q = r + 1; q <= r_max; ++q) rb[q] = EXT_NBINS;
+  if (bad) atomicOr(flags, 8u);
+}
+
+// After a round: its pairs, occurrences and windows are added to the running totals;
+// flag bit 3 when the round held more windows than fit.
+__global__ void k_ext_round_end(u64* ctrl_pairs, u64* ctrl_occ, u64* pair_base, u64* occ_base, const u64* n_win,
+                                u64* win_total, u64 cap, u32* flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  *pair_base += *ctrl_pairs;
+  *occ_base += *ctrl_occ;
+  *win_total += *n_win;
+  if (*n_win > cap) atomicOr(flags, 8u);
+}
+
 // Totals of an extension count; occ_off[n_pairs] closes the last pair's list.
 __global__ void k_ext_finalize(DevTotals* tot, const u64* n_win, const u64* n_pairs, const u64* n_occ, const u32* flags,
                                u64* occ_off, u64 pair_cap) {
@@ -399,6 +488,6 @@ __global__ void k_ext_finalize(DevTotals* tot, const u64* n_win, const u64* n_pa
   tot->n_windows = *n_win;
   tot->n_pairs = *n_pairs;
   tot->n_occ = *n_occ;
-  tot->flags = *flags & 1u;
+  tot->flags = *flags & 9u;
   if (*n_pairs <= pair_cap && occ_off) occ_off[*n_pairs] = *n_occ;
 }

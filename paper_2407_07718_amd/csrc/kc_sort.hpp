@@ -132,18 +132,25 @@ __global__ __launch_bounds__(256) void k_radix_upsweep(const K* __restrict__ key
   __syncthreads();
   u64 s, e;
   block_range(*n_ptr, nb, &s, &e);
-  // eight independent loads in flight per thread before their counts
+  // batches of eight keys per thread, the next batch's loads issued before this
+  // batch's counts
   constexpr u32 U = 8;
-  for (u64 i0 = s + tid; i0 < e; i0 += 256 * U) {
-    K kx[U];
+  K ka[U], kb[U];
+  auto load = [&](K (&kx)[U], u64 i0) {
 #pragma unroll
     for (u32 u = 0; u < U; ++u) {
       const u64 i = i0 + (u64)u * 256;
       if (i < e) kx[u] = keys[i];
     }
+  };
+  load(ka, s + tid);
+  for (u64 i0 = s + tid; i0 < e; i0 += 256 * U) {
+    if (i0 + 256 * U < e) load(kb, i0 + 256 * U);
 #pragma unroll
     for (u32 u = 0; u < U; ++u)
-      if (i0 + (u64)u * 256 < e) atomicAdd(&h[wave][key_digit(kx[u], sh)], 1u);
+      if (i0 + (u64)u * 256 < e) atomicAdd(&h[wave][key_digit(ka[u], sh)], 1u);
+#pragma unroll
+    for (u32 u = 0; u < U; ++u) ka[u] = kb[u];
   }
   __syncthreads();
   counts[(u64)tid * nb + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];

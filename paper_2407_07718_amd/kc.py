@@ -132,7 +132,7 @@ def _load() -> ctypes.CDLL:
     lib.kc_count_ext.argtypes = [vp, vp, u64, i32, u32, u32, u64, P(kc_config), P(kc_ext_result)]
     lib.kc_count_ext.restype = i32
     lib.kc_ext_result_free.argtypes = [P(kc_ext_result)]
-    lib.kc_ext_workspace_size.argtypes = [u64, u64, i32]
+    lib.kc_ext_workspace_size.argtypes = [u64, u64, i32, P(kc_config)]
     lib.kc_ext_workspace_size.restype = ctypes.c_size_t
     ext_args = [vp, u64, vp, u64, i32, u32, u32, u64, P(kc_config), vp, ctypes.c_size_t, vp, vp, u64, vp, vp, vp,
                 u64, vp, vp, vp]
@@ -439,8 +439,8 @@ def kc_count_ext(reads: np.ndarray, offsets: np.ndarray, k: int, min_freq: int, 
         _lib.kc_ext_result_free(ctypes.byref(res))
 
 
-def kc_ext_workspace_size(total_bases: int, n_reads: int, k: int) -> int:
-    return int(_lib.kc_ext_workspace_size(total_bases, n_reads, k))
+def kc_ext_workspace_size(total_bases: int, n_reads: int, k: int, cfg: Optional[kc_config] = None) -> int:
+    return int(_lib.kc_ext_workspace_size(total_bases, n_reads, k, ctypes.byref(cfg) if cfg is not None else None))
 
 
 class DeviceExtCounter:
@@ -453,7 +453,7 @@ class DeviceExtCounter:
         import torch
         self.k, self.lo, self.hi, self.H, self.cfg = k, min_freq, max_freq, hist_len, cfg
         self.key_words = 1 if k <= 31 else 2
-        ws = kc_ext_workspace_size(max_bases, max_reads, k)
+        ws = kc_ext_workspace_size(max_bases, max_reads, k, cfg)
         if ws == 0:
             raise KCError(KC_EINVAL, "kc_ext_workspace_size rejected the arguments")
         self.workspace = torch.empty(ws, dtype=torch.uint8, device=device)

@@ -147,3 +147,63 @@ def test_ext_both_value_encodings():
     del seqs[1000]
     reads, offsets = synth.from_strings(seqs)
     check_ext(reads, offsets, 5, 1, 0xFFFFFFFF, 64, label="packed encoding")
+
+
+# ---------------------------------------------------------------------------- memory-bounded rounds
+def _repeat_reads(seed=31337, n_reads=16000, genome=200_000):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = synth.uniform_genome(rng, genome)
+    synth.add_repeat_families(rng, g, families=20)   # in place
+    return synth.sample_reads(rng, g, rng.integers(100, 200, n_reads), p_sub=0.005, p_n=0.001)
+
+
+def device_ext_budget(reads, offsets, k, lo, hi, H, budget):
+    import torch
+    kc = _kc()
+    dev = torch.device("cuda:0")
+    cfg = kc.make_config(hbm_budget=budget)
+    d_reads = torch.from_numpy(np.ascontiguousarray(reads, dtype=np.uint8)).to(dev)
+    d_offsets = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.uint64).view(np.int64)).to(dev)
+    ctr = kc.DeviceExtCounter(int(len(reads)), int(len(offsets) - 1), k, lo, hi, H, cfg=cfg)
+    assert ctr.workspace.numel() <= budget
+    return ctr.result(ctr.count(d_reads, d_offsets))
+
+
+@pytest.mark.parametrize("k", [31, 51])
+def test_ext_rounds_match_oracle(k):
+    kc = _kc()
+    reads, offsets = _repeat_reads()
+    full = kc.kc_ext_workspace_size(len(reads), len(offsets) - 1, k)
+    ref = oracle.count_ext(reads, offsets, k, 2, 200, 1024)
+    for frac in (0.5, 0.2, 0.08):
+        budget = int(full * frac)
+        print(f"case ext rounds k={k} budget={budget} of {full}", flush=True)
+        got = device_ext_budget(reads, offsets, k, 2, 200, 1024, budget)
+        assert_same_ext(got, ref, f"rounds k{k} budget {frac}")
+
+
+def test_ext_rounds_limits():
+    kc = _kc()
+    reads, offsets = _repeat_reads(n_reads=2000)
+    # a budget below the fixed part plus the smallest round: no plan
+    assert kc.kc_ext_workspace_size(len(reads), len(offsets) - 1, 31, kc.make_config(hbm_budget=100_000)) == 0
+    # one k-mer (a homopolymer) with more windows than a round holds
+    reads, offsets = synth.from_strings(["A" * 300_000, "ACGT" * 1000])
+    full = kc.kc_ext_workspace_size(len(reads), len(offsets) - 1, 21)
+    budget = int(full * 0.5)
+    with pytest.raises(kc.KCError) as e:
+        device_ext_budget(reads, offsets, 21, 1, 0xFFFFFFFF, 16, budget)
+    assert e.value.code == kc.KC_ENOMEM
+
+
+def test_ext_rounds_short_read_full_size():
+    kc = _kc()
+    rs = synth.config(2)
+    full = kc.kc_ext_workspace_size(rs.n_bases, rs.n_reads, rs.k)
+    print(f"case ext rounds short-read full size: workspace {full}", flush=True)
+    one = device_ext(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq)
+    got = device_ext_budget(rs.reads, rs.offsets, rs.k, rs.min_freq, rs.max_freq, 65536, full // 4)
+    for a, b in [(got.pairs.kmers, one.pairs.kmers), (got.pairs.counts, one.pairs.counts),
+                 (got.pairs.hist, one.pairs.hist), (got.occ_off, one.occ_off), (got.occ_read, one.occ_read),
+                 (got.occ_pos, one.occ_pos)]:
+        assert np.array_equal(a, b)
