@@ -676,6 +676,7 @@ struct ExtPlan {
   u64 cap = 0;                     // windows sorted per round
   u32 rounds = 1;                  // rounds enqueued (1: all windows at once)
   u64 n_tiles = 1, n_tiles_cap = 1, n_packed = 0, n_mask = 0, n_blk = 0;
+  u32 blk_sh = 6;                  // read table: one entry per 2^blk_sh bases
   u32 nb = 1;                      // radix blocks
   u64 o_packed, o_nmask, o_starts, o_k0, o_k1, o_v0, o_v1, o_hp, o_blk, o_bp, o_bo, o_rid, o_ctrl, o_cnt, o_tot,
       o_scan, o_bins, o_rb, bytes = 0;
@@ -750,7 +751,10 @@ bool make_ext_plan(u64 R, u64 n_reads, int k, u64 budget, ExtPlan* p) {
   if (p->n_tiles > 1024ull * SCAN_BLOCK) return false;
   p->n_packed = R / 16 + 16;
   p->n_mask = R / 32 + 16;
-  p->n_blk = R / 64 + 2;
+  // read table blocks of about the mean read length (64 .. 65536 bases)
+  p->blk_sh = 6;
+  while (p->blk_sh < 16 && n_reads && (R / n_reads) >> (p->blk_sh + 1)) ++p->blk_sh;
+  p->n_blk = (R >> p->blk_sh) + 2;
   p->rounds = 1;
   ext_layout(p, p->N);
   if (!budget || p->bytes <= budget) return true;
@@ -810,7 +814,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
     hipLaunchKernelGGL(k_read_starts, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, starts,
                        flags);
     hipLaunchKernelGGL(k_ext_read_blocks, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, rid,
-                       P.n_blk, ctrl + X_MAXLEN);
+                       P.n_blk, P.blk_sh, ctrl + X_MAXLEN);
   }
   // window positions: every base of the buffer; the kernels keep the windows inside
   // [offsets[0], offsets[n_reads]) that hold k valid bases of one read
@@ -828,6 +832,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   wa.vals = v0;
   wa.rid = rid;
   wa.n_blk = P.n_blk;
+  wa.blk_sh = P.blk_sh;
   wa.rbits = read_bits(P.n_reads);
   wa.max_len = ctrl + X_MAXLEN;
   wa.range = rb;
@@ -837,8 +842,12 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   if (rounds) {
     // key ranges of the rounds from the windows per key prefix
     fill(bins, EXT_NBINS, 0u);
-    hipLaunchKernelGGL((k_ext_prefix_hist<K>), gw, dim3(EXT_T), 0, st, wa, bins);
-    hipLaunchKernelGGL(k_ext_plan_rounds, dim3(1), dim3(64), 0, st, bins, P.cap, P.rounds, rb, flags);
+    int n_cu = 0;
+    int rc0 = device_info(&n_cu);
+    if (rc0) return rc0;
+    hipLaunchKernelGGL((k_ext_prefix_hist<K>), dim3((u32)std::min<u64>(P.n_tiles, 4ull * n_cu)), dim3(EXT_T), 0, st, wa,
+                       bins);
+    hipLaunchKernelGGL(k_ext_plan_rounds, dim3(1), dim3(1024), 0, st, bins, P.cap, P.rounds, rb, flags);
   } else {
     fill(rb, 1, 0u);
     fill(rb + 1, 1, EXT_NBINS);
@@ -858,6 +867,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   ra.n_reads = P.n_reads;
   ra.rid = rid;
   ra.n_blk = P.n_blk;
+  ra.blk_sh = P.blk_sh;
   ra.out_k = d_kmers;
   ra.out_c = d_counts;
   ra.occ_off = d_occ_off;

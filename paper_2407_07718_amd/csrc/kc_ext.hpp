@@ -60,26 +60,28 @@ __device__ __forceinline__ void ext_canon(const u32* __restrict__ packed, u64 p,
   *out = key_lt(F, RC) ? F : RC;
 }
 
-// rid[b] = the read holding base 64*b, for every 64-base block that starts inside a
-// read; other entries keep the fill value ~0.  Reads whose offsets are out of order or
-// out of range are skipped (the count reports them through its flags).
-// Also raises *max_len to the longest read.
+// rid[q] = the read holding base q << sh, for every block of 2^sh bases that starts
+// inside a read; other entries keep the fill value ~0.  The block size follows the mean
+// read length, so that a block spans few reads and the table stays small for long reads.
+// Reads whose offsets are out of order or out of range are skipped (the count reports
+// them through its flags).  Also raises *max_len to the longest read.
 __global__ __launch_bounds__(256) void k_ext_read_blocks(const u64* __restrict__ offsets, u64 n_reads, u64 R,
-                                                         u32* __restrict__ rid, u64 n_blk, u64* __restrict__ max_len) {
+                                                         u32* __restrict__ rid, u64 n_blk, u32 sh,
+                                                         u64* __restrict__ max_len) {
   for (u64 r = blockIdx.x * (u64)blockDim.x + threadIdx.x; r < n_reads; r += (u64)gridDim.x * blockDim.x) {
     const u64 a = offsets[r], b = offsets[r + 1];
     if (b <= a || b > R) continue;
-    for (u64 q = (a + 63) >> 6; (q << 6) < b && q < n_blk; ++q) rid[q] = (u32)r;
+    for (u64 q = (a + ((1ull << sh) - 1)) >> sh; (q << sh) < b && q < n_blk; ++q) rid[q] = (u32)r;
     if (b - a > *(volatile u64*)max_len) atomicMax((unsigned long long*)max_len, (unsigned long long)(b - a));
   }
 }
 
 // Index of the read holding base g (g inside [offsets[0], offsets[n_reads]) and inside a
 // read): the largest r with offsets[r] <= g, searched between the reads holding the
-// starts of g's 64-base block and of the next block.
+// starts of g's block and of the next block.
 __device__ __forceinline__ u32 ext_find_read(const u64* __restrict__ offsets, u64 n_reads, const u32* __restrict__ rid,
-                                             u64 n_blk, u64 g) {
-  const u64 q = g >> 6;
+                                             u64 n_blk, u32 sh, u64 g) {
+  const u64 q = g >> sh;
   u32 a = rid[q];
   if (a == 0xFFFFFFFFu) a = 0;
   u32 b = (q + 1 < n_blk) ? rid[q + 1] : 0xFFFFFFFFu;
@@ -126,8 +128,9 @@ struct ExtWinArgs {
   u32* blk;          // valid windows per block, then (scanned) the block's first output slot
   void* keys;        // valid windows in position order: canonical key ...
   u32* vals;         // ... and its (read, position) value
-  const u32* rid;    // read table of 64-base blocks (k_ext_read_blocks)
+  const u32* rid;    // read table (k_ext_read_blocks)
   u64 n_blk;
+  u32 blk_sh;        // log2 of the table's block size
   u32 rbits;         // bits of a read index
   const u64* max_len;   // longest read
   const u32* range;  // this round's key prefixes [range[0], range[1])
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(EXT_T) void k_ext_windows(ExtWinArgs A) {
       const u64 at = base + mbcnt64(bal[j]);
       u32 v = (u32)p;
       if (pk) {   // neighbouring lanes share the table entries and offsets they search
-        const u32 rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, p);
+        const u32 rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, A.blk_sh, p);
         v = (pb < 32 ? (rd << pb) : 0u) | (u32)(p - A.offsets[rd]);
       }
       if (at < A.cap) {
@@ -255,6 +258,7 @@ struct ExtRunArgs {
   u64 n_reads;
   const u32* rid;
   u64 n_blk;
+  u32 blk_sh;
   void* out_k;             // pairs [0, pair_cap) ...
   u32* out_c;
   u64* occ_off;            // ... the first occurrence of each pair
@@ -392,35 +396,50 @@ __global__ __launch_bounds__(EXT_T) void k_ext_occ(ExtRunArgs A) {
   const u64 ml = *A.max_len;
   const bool pk = ext_packed(A.rbits, ml);
   const u32 pb = ext_pos_bits(ml);
+  // the loads of all steps first (slots and run starts, then the values of reported
+  // runs), so that they are in flight together; then decode and write
+  u32 dd[EXT_PER], hh[EXT_PER], vv[EXT_PER];
 #pragma unroll
   for (int j = 0; j < (int)EXT_PER; ++j) {
     const u64 i = e0 + (u64)j * 64 + lane;
+    dd[j] = 0xFFFFFFFFu;
+    hh[j] = 0;
     if (i < n) {
       const u64 rid = run + (u64)__popcll(hw[j] & le) - 1;
-      const u32 d = A.odst[rid];
-      if (d != 0xFFFFFFFFu) {
-        const u64 o = (u64)d + (i - A.hp[rid]);
-        if (o < A.occ_cap) {
-          const u32 v = A.vals[i];
-          u32 rd, ps;
-          if (pk) {
-            rd = pb < 32 ? (v >> pb) : 0u;
-            ps = v & (u32)((1ull << pb) - 1);
-          } else {
-            rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, v);
-            ps = (u32)(v - A.offsets[rd]);
-          }
-          A.occ_read[o] = rd;
-          A.occ_pos[o] = ps;
-        }
-      }
+      dd[j] = A.odst[rid];
+      hh[j] = A.hp[rid];
     }
     run += (u32)__popcll(hw[j]);
   }
+#pragma unroll
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    const u64 i = e0 + (u64)j * 64 + lane;
+    vv[j] = dd[j] != 0xFFFFFFFFu ? A.vals[i] : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < (int)EXT_PER; ++j) {
+    const u64 i = e0 + (u64)j * 64 + lane;
+    if (dd[j] != 0xFFFFFFFFu) {
+      const u64 o = (u64)dd[j] + (i - hh[j]);
+      if (o < A.occ_cap) {
+        const u32 v = vv[j];
+        u32 rd, ps;
+        if (pk) {
+          rd = pb < 32 ? (v >> pb) : 0u;
+          ps = v & (u32)((1ull << pb) - 1);
+        } else {
+          rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, A.blk_sh, v);
+          ps = (u32)(v - A.offsets[rd]);
+        }
+        A.occ_read[o] = rd;
+        A.occ_pos[o] = ps;
+      }
+    }
+  }
 }
 
-// Windows per key prefix, over all valid windows (per-block LDS bins, then one global
-// add per non-empty bin).
+// Windows per key prefix, over all valid windows: persistent blocks stride over the
+// positions with LDS bins and add them to the global bins once at the end.
 template <typename K>
 __global__ __launch_bounds__(EXT_T) void k_ext_prefix_hist(ExtWinArgs A, u32* __restrict__ bins) {
   __shared__ u32 h[EXT_NBINS];
@@ -428,10 +447,8 @@ __global__ __launch_bounds__(EXT_T) void k_ext_prefix_hist(ExtWinArgs A, u32* __
   __syncthreads();
   const u64 lo = A.n_reads ? min(A.offsets[0], A.R) : 0;
   const u64 hi = A.n_reads ? min(A.offsets[A.n_reads], A.R) : 0;
-  const u64 e0 = (u64)blockIdx.x * EXT_TILE;
-  for (u32 j = 0; j < EXT_PER; ++j) {
-    const u64 i = e0 + (u64)j * EXT_T + threadIdx.x;
-    if (i < A.n_pos && i >= lo && i + (u64)A.k <= hi && ext_window_valid(A.nmask, A.starts, i, A.k)) {
+  for (u64 i = blockIdx.x * (u64)EXT_T + threadIdx.x; i < A.n_pos; i += (u64)gridDim.x * EXT_T) {
+    if (i >= lo && i + (u64)A.k <= hi && ext_window_valid(A.nmask, A.starts, i, A.k)) {
       K key;
       ext_canon(A.packed, i, A.k, &key);
       atomicAdd(&h[ext_prefix(key, A.k)], 1u);
@@ -445,15 +462,19 @@ __global__ __launch_bounds__(EXT_T) void k_ext_prefix_hist(ExtWinArgs A, u32* __
 // Rounds: consecutive prefix ranges holding at most `cap` windows each, taken greedily;
 // range q is [rb[q], rb[q+1]), unused rounds are empty.  Flag bit 3 when a single prefix
 // or the rounds available cannot hold the windows.
-__global__ void k_ext_plan_rounds(const u32* __restrict__ bins, u64 cap, u32 r_max, u32* __restrict__ rb,
-                                  u32* __restrict__ flags) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// (One block: the bins are staged in LDS, then one thread walks them.)
+__global__ __launch_bounds__(1024) void k_ext_plan_rounds(const u32* __restrict__ bins, u64 cap, u32 r_max,
+                                                          u32* __restrict__ rb, u32* __restrict__ flags) {
+  __shared__ u32 h[EXT_NBINS];
+  for (u32 i = threadIdx.x; i < EXT_NBINS; i += blockDim.x) h[i] = bins[i];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   u32 r = 0;
   u64 acc = 0;
   rb[0] = 0;
   bool bad = false;
   for (u32 b = 0; b < EXT_NBINS; ++b) {
-    const u64 c = bins[b];
+    const u64 c = h[b];
     if (c > cap) bad = true;
     if (acc + c > cap && acc > 0) {
       if (r + 1 < r_max) {

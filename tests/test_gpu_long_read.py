@@ -105,3 +105,39 @@ def test_long_read_full_size(k):
             assert present and int(got.counts[j]) == c
         else:
             assert not present
+
+
+@pytest.mark.parametrize("k", [31, 51])
+def test_long_read_extension_full_size(k):
+    """Extension version at full long-read size: the read index and in-read position do
+    not fit one 32-bit value together here (66.6 K reads of up to ~60 kb), so every
+    occurrence is decoded from a global base offset.  Pairs and histogram must equal the
+    plain count; every occurrence of 200 sampled reported k-mers is re-read from the reads
+    and must be a window whose canonical value is the k-mer, in ascending order, as many
+    as the count says."""
+    import torch
+    from paper_2407_07718_amd import kc
+    rs = synth.config(3, k=k)
+    print(f"case long-read extension full size: k={k} bases={rs.n_bases} reads={rs.n_reads}", flush=True)
+    dev = torch.device("cuda:0")
+    d_reads = torch.from_numpy(np.ascontiguousarray(rs.reads)).to(dev)
+    d_offsets = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
+    ctr = kc.DeviceExtCounter(rs.n_bases, rs.n_reads, k, rs.min_freq, rs.max_freq, 65536)
+    ext = ctr.result(ctr.count(d_reads, d_offsets))
+    del ctr
+    torch.cuda.empty_cache()
+    plain = device_count(rs.reads, rs.offsets, k, rs.m, rs.min_freq, rs.max_freq, 65536)
+    assert np.array_equal(ext.pairs.kmers, plain.kmers) and np.array_equal(ext.pairs.counts, plain.counts)
+    assert np.array_equal(ext.pairs.hist, plain.hist)
+    assert np.array_equal(np.diff(ext.occ_off), ext.pairs.counts.astype(np.uint64))
+    rng = np.random.Generator(np.random.PCG64(100 + k))
+    for j in rng.choice(ext.pairs.n_pairs, size=200, replace=False):
+        want = _as_int(ext.pairs.kmers[j])
+        a, b = int(ext.occ_off[j]), int(ext.occ_off[j + 1])
+        occ = list(zip(ext.occ_read[a:b].tolist(), ext.occ_pos[a:b].tolist()))
+        assert occ == sorted(set(occ))
+        for r, p in occ:
+            start = int(rs.offsets[r]) + p
+            assert start + k <= int(rs.offsets[r + 1])
+            w = bytes(rs.reads[start:start + k]).decode("latin-1").upper()
+            assert _canonical(w) == want
