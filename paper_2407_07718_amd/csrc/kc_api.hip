@@ -482,7 +482,10 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
       hipLaunchKernelGGL(k_part_scatter<4>, dim3(P.part_nblk), dim3(512), 0, st, pp);
     else
       hipLaunchKernelGGL(k_part_scatter<8>, dim3(P.part_nblk), dim3(512), 0, st, pp);
-    hipLaunchKernelGGL(k_part_fine, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
+    if (P.rec_words == 4)
+      hipLaunchKernelGGL(k_part_fine<4>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
+    else
+      hipLaunchKernelGGL(k_part_fine<8>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
   }
   {
     PlanArgs pa{bcnt, P.B, P.cap_tiny, P.cap, P.cap_chunk, bsum, tiny, recoff, cursor, small, large, lkoff, chstart,

@@ -431,17 +431,6 @@ struct PartArgs {
   const u64* n_rec_ptr;    // records in total
 };
 
-__device__ __forceinline__ void copy_record(const u32* __restrict__ src, u64 i, u32* __restrict__ dst, u64 j,
-                                            int rec_words) {
-  if (rec_words == 4) {
-    reinterpret_cast<uint4*>(dst)[j] = reinterpret_cast<const uint4*>(src)[i];
-  } else {
-    const uint4* s = reinterpret_cast<const uint4*>(src) + 2 * i;
-    uint4* d = reinterpret_cast<uint4*>(dst) + 2 * j;
-    d[0] = s[0];
-    d[1] = s[1];
-  }
-}
 
 // Coarse pass: each block moves one extract block's records into their coarse groups.
 // Rounds of R records are ranked per group in LDS, staged in group order and written
@@ -512,42 +501,101 @@ __global__ __launch_bounds__(512) void k_part_scatter(PartArgs P) {
 }
 
 // Fine pass: one block per coarse group c, records [start(c), start(c+1)) of tmp.
+template <int RW>
 __global__ __launch_bounds__(1024) void k_part_fine(PartArgs P) {
-  __shared__ u32 cr[2048], ck[2048], cur[2048];
+  constexpr u32 T = 1024, Q = RW / 4;             // uint4 per record
+  constexpr u32 R = RW == 4 ? 2048u : 1024u;      // records staged per round (32 KB)
+  constexpr u32 IT = R / T;
+  __shared__ uint4 stage[R * Q];
+  __shared__ u32 cr[2048], ck[2048], cur[2048], lbase[2048];
   __shared__ u64 scr[17];
-  const u32 F = 1u << P.log_f, C = 1u << P.log_c, c = blockIdx.x, T = blockDim.x;
+  const u32 F = 1u << P.log_f, C = 1u << P.log_c, c = blockIdx.x, tid = threadIdx.x;
   const u64 n_rec = *P.n_rec_ptr;
   const u64 g0 = P.hist[(u64)c * P.nblk];
   const u64 g1 = (c + 1 < C) ? (u64)P.hist[(u64)(c + 1) * P.nblk] : n_rec;
-  const int rw = P.rec_words;
-  for (u32 i = threadIdx.x; i < F; i += T) {
+  const uint4* src = reinterpret_cast<const uint4*>(P.tmp_rec);
+  uint4* dst = reinterpret_cast<uint4*>(P.rec_out);
+  for (u32 i = tid; i < F; i += T) {
     cr[i] = 0;
     ck[i] = 0;
   }
   __syncthreads();
-  for (u64 i = g0 + threadIdx.x; i < g1; i += T) {
-    const u32 last = P.tmp_rec[i * (u64)rw + rw - 1];
+  for (u64 i = g0 + tid; i < g1; i += T) {
+    const u32 last = P.tmp_rec[i * (u64)RW + RW - 1];
     const u32 f = rec_last_bucket(last) & (F - 1);
     atomicAdd(&cr[f], 1u);
     atomicAdd(&ck[f], (last >> 26) + 1u);
   }
   __syncthreads();
   // exclusive prefix of the record counts over the F buckets of the group
-  const u32 per = (F + T - 1) / T;
-  const u32 fa = min(F, threadIdx.x * per), fb = min(F, fa + per);
-  u64 sum = 0;
-  for (u32 f = fa; f < fb; ++f) sum += cr[f];
-  u64 tot;
-  u64 run = block_exclusive_scan<u64>(sum, scr, &tot) + g0;
-  for (u32 f = fa; f < fb; ++f) {
-    cur[f] = (u32)run;
-    P.bcnt[((u64)c << P.log_f) + f] = ((u64)cr[f] << 32) | ck[f];
-    run += cr[f];
+  {
+    const u32 per = (F + T - 1) / T;
+    const u32 fa = min(F, tid * per), fb = min(F, fa + per);
+    u64 sum = 0;
+    for (u32 f = fa; f < fb; ++f) sum += cr[f];
+    u64 tot;
+    u64 run = block_exclusive_scan<u64>(sum, scr, &tot) + g0;
+    for (u32 f = fa; f < fb; ++f) {
+      cur[f] = (u32)run;
+      P.bcnt[((u64)c << P.log_f) + f] = ((u64)cr[f] << 32) | ck[f];
+      run += cr[f];
+    }
   }
+  // Rounds of R records: ranked per bucket in LDS, staged in bucket order and written as
+  // one run per bucket, so that consecutive threads write consecutive slots.
   __syncthreads();
-  for (u64 i = g0 + threadIdx.x; i < g1; i += T) {
-    const u32 f = rec_last_bucket(P.tmp_rec[i * (u64)rw + rw - 1]) & (F - 1);
-    const u32 pos = atomicAdd(&cur[f], 1u);
-    copy_record(P.tmp_rec, i, P.rec_out, pos, rw);
+  for (u32 i = tid; i < F; i += T) cr[i] = 0;   // per-round counts from here on
+  __syncthreads();
+  for (u64 r0 = g0; r0 < g1; r0 += R) {
+    const u32 nr = (u32)min((u64)R, g1 - r0);
+    uint4 rec[IT * Q];
+    u32 ff[IT], rk[IT];
+#pragma unroll
+    for (u32 j = 0; j < IT; ++j) {
+      const u32 i = tid + j * T;
+#pragma unroll
+      for (u32 q = 0; q < Q; ++q) rec[j * Q + q] = i < nr ? src[(r0 + i) * Q + q] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (u32 j = 0; j < IT; ++j) {
+      if (tid + j * T < nr) {
+        ff[j] = rec_last_bucket(rec[j * Q + Q - 1].w) & (F - 1);
+        rk[j] = atomicAdd(&cr[ff[j]], 1u);
+      }
+    }
+    __syncthreads();
+    {
+      const u32 per = (F + T - 1) / T;
+      const u32 fa = min(F, tid * per), fb = min(F, fa + per);
+      u64 sum = 0;
+      for (u32 f = fa; f < fb; ++f) sum += cr[f];
+      u64 tot;
+      u64 run = block_exclusive_scan<u64>(sum, scr, &tot);
+      for (u32 f = fa; f < fb; ++f) {
+        lbase[f] = (u32)run;
+        run += cr[f];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (u32 j = 0; j < IT; ++j) {
+      if (tid + j * T < nr) {
+#pragma unroll
+        for (u32 q = 0; q < Q; ++q) stage[(lbase[ff[j]] + rk[j]) * Q + q] = rec[j * Q + q];
+      }
+    }
+    __syncthreads();
+    for (u32 i = tid; i < nr; i += T) {
+      const u32 f = rec_last_bucket(stage[i * Q + Q - 1].w) & (F - 1);
+      const u64 d = (u64)cur[f] + (i - lbase[f]);
+#pragma unroll
+      for (u32 q = 0; q < Q; ++q) dst[d * Q + q] = stage[i * Q + q];
+    }
+    __syncthreads();
+    for (u32 f = tid; f < F; f += T) {
+      cur[f] += cr[f];
+      cr[f] = 0;
+    }
+    __syncthreads();
   }
 }
