@@ -292,6 +292,9 @@ int kc_server_destroy(kc_server *s);
  *   5 wave_sort   (tiny buckets: one wave each)                     -- one kernel
  *   6 merge       (chunk lists: compact, HBM radix sort, summed runs)
  *   7 output      (survivor compaction, sort by key, copy, totals)
+ * An extension count (kc_count_ext*) uses the slots as 0 encode, 1 windows, 2 sort,
+ * 3 runs, 4 emit (5-7 empty); under a memory budget its rounds are timed as one: slot 1
+ * holds the key-range planning and slot 2 all rounds.
  * kc_profile_read waits for those events and returns, per stage, the summed
  * milliseconds over all counts recorded since the last read (then resets). */
 #define KC_N_STAGES 8
