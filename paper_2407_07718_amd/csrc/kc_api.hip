@@ -851,6 +851,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
     hipLaunchKernelGGL((k_ext_prefix_hist<K>), dim3((u32)std::min<u64>(P.n_tiles, 4ull * n_cu)), dim3(EXT_T), 0, st, wa,
                        bins);
     hipLaunchKernelGGL(k_ext_plan_rounds, dim3(1), dim3(1024), 0, st, bins, P.cap, P.rounds, rb, flags);
+    stage_mark(2, st);
   } else {
     fill(rb, 1, 0u);
     fill(rb + 1, 1, EXT_NBINS);
@@ -917,7 +918,6 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
                        ctrl + X_OBASE, ctrl + X_NWIN, ctrl + X_WTOT, P.cap, flags);
   }
   if (rounds) {
-    stage_mark(2, st);
     stage_mark(3, st);
     stage_mark(4, st);
   }
