@@ -4,12 +4,14 @@
 // Paper mapping: a k-mer may travel with extension information, its read's ID and its
 // position in that read (Section 2.2); the paper compresses that information in transit
 // (Section 3.3, data compression) because it outweighs the k-mer itself.  Here each
-// window carries one 32-bit global base offset (the read and the in-read position are
-// both functions of it), and it is decoded into (read, position) only for the k-mers
-// that are reported.  The windows are sorted by canonical value as (key, offset) pairs
-// with a stable LSD radix sort (Section 3.1), whose input is in offset order, so each
+// window carries one 32-bit value: (read, position) packed together when both fit, else
+// the global base offset, which is decoded into (read, position) only for the k-mers
+// that are reported.  The windows are sorted by canonical value as (key, value) pairs
+// with a stable LSD radix sort (Section 3.1), whose input is in position order, so each
 // run of equal keys holds its occurrences in ascending (read, position) order, and one
-// scan over the runs counts them (Section 3.1).
+// scan over the runs counts them (Section 3.1).  Under an HBM budget the same steps run
+// in rounds over consecutive key ranges (Section 3.1: the paper's memory-tight sort;
+// Section 3.3: exchange rounds of bounded size).
 #pragma once
 #include "kc_common.hpp"
 #include "kc_count.hpp"
