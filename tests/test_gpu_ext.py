@@ -207,3 +207,27 @@ def test_ext_rounds_short_read_full_size():
                  (got.pairs.hist, one.pairs.hist), (got.occ_off, one.occ_off), (got.occ_read, one.occ_read),
                  (got.occ_pos, one.occ_pos)]:
         assert np.array_equal(a, b)
+
+
+def test_ext_random_budgets():
+    """Random read sets, k and frequency windows, each counted under a random fraction of
+    its one-pass workspace (from one round up to dozens, some of them empty) and compared
+    with the oracle."""
+    kc = _kc()
+    rng = np.random.Generator(np.random.PCG64(2718))
+    for case in range(24):
+        k = int(rng.choice([5, 13, 21, 31, 32, 45, 63]))
+        genome = int(rng.integers(2000, 60000))
+        reads, offsets = _genome_reads(9000 + case, int(rng.integers(200, 3000)), 0, int(rng.integers(80, 600)),
+                                       genome=genome)
+        lo = int(rng.integers(1, 3))
+        hi = lo + int(rng.integers(0, 30))
+        full = kc.kc_ext_workspace_size(len(reads), len(offsets) - 1, k)
+        frac = float(rng.choice([1.0, 0.6, 0.3, 0.12]))
+        budget = int(full * frac)
+        if kc.kc_ext_workspace_size(len(reads), len(offsets) - 1, k, kc.make_config(hbm_budget=budget)) == 0:
+            continue   # below the smallest plan for this input
+        print(f"case ext budget {case}: k={k} bases={len(reads)} frac={frac}", flush=True)
+        ref = oracle.count_ext(reads, offsets, k, lo, hi, 64)
+        got = device_ext_budget(reads, offsets, k, lo, hi, 64, budget)
+        assert_same_ext(got, ref, f"budget case {case}")
