@@ -302,22 +302,14 @@ __global__ void k_clamp(const u64* src, u64 cap, u64* dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = min(*src, cap);
 }
 
-__global__ void k_totals_meta(DevTotals* tot, const u64* meta, const u64* kl_n, u32 B) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    tot->large_keys = meta[2];
-    tot->tiny_buckets = meta[5];
-    tot->tiny_kmers = meta[6];
-    tot->small_buckets = meta[0];
-    tot->small_kmers = meta[7];
-    tot->large_buckets = meta[1];
-    tot->chunks = meta[4];
-    tot->list_entries = *kl_n;
-    tot->buckets = B;
-  }
-}
-
 // Device-wide exclusive scan (see k_scan_reduce); n_max must be <= 1024 * SCAN_BLOCK.
+// Short inputs take one single-block launch instead of three.
+constexpr u64 SCAN_ONE_BLOCK_MAX = 32768;
 void scan_u32(const u32* in, u32* out, const u64* n_ptr, u64 n_max, u64* total, u64* bsum, hipStream_t st) {
+  if (n_max <= SCAN_ONE_BLOCK_MAX) {
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, in, out, n_ptr, n_max, total);
+    return;
+  }
   const u32 nb = (u32)std::max<u64>(1, (n_max + SCAN_BLOCK - 1) / SCAN_BLOCK);
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_T), 0, st, in, n_ptr, n_max, bsum);
   hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, bsum, nb, total);
@@ -416,20 +408,28 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   u64* kl_n = ctrl + C_KL_N;
   u64* kl_nc = ctrl + C_KL_NC;
 
-  // zero everything that accumulates
-  auto fill = [&](void* p, u64 n_words) {
-    if (n_words)
-      hipLaunchKernelGGL(k_fill_u32, grid_for(n_words, 256, 4096), dim3(256), 0, st, (u32*)p, n_words, 0u);
-  };
+  // zero everything that accumulates (one launch)
   stage_mark(0, st);
-  fill(ctrl, 2ull * C_WORDS);
-  fill(d_hist, 2ull * hist_len);
-  fill(d_tot, sizeof(DevTotals) / 4);
-  fill(starts, P.n_mask);
-  fill(scnt, P.B);
   const u64 n32 = ceil_div(P.R, 32);
-  fill(packed + 2 * n32, P.n_packed - 2 * n32);
-  fill(nmask + n32, P.n_mask - n32);
+  {
+    FillList fl{};
+    u64 most = 0;
+    auto add = [&](void* p, u64 n_words) {
+      fl.p[fl.cnt] = (u32*)p;
+      fl.n[fl.cnt] = n_words;
+      fl.v[fl.cnt] = 0u;
+      ++fl.cnt;
+      most = std::max(most, n_words);
+    };
+    add(ctrl, 2ull * C_WORDS);
+    add(d_hist, 2ull * hist_len);
+    add(d_tot, sizeof(DevTotals) / 4);
+    add(starts, P.n_mask);
+    add(scnt, P.B);
+    add(packed + 2 * n32, P.n_packed - 2 * n32);
+    add(nmask + n32, P.n_mask - n32);
+    hipLaunchKernelGGL(k_fill_multi, grid_for(most, 256, 4096), dim3(256), 0, st, fl);
+  }
 
   // ---- stage 1: encode, read starts, minimizers and supermers, bucket partition
   if (P.R) hipLaunchKernelGGL(k_pack, grid_for(n32, 256), dim3(256), 0, st, d_reads, P.R, packed, nmask);
@@ -604,8 +604,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
                         2 * P.k, false, surv_nc, (P.key_words == 1 ? SEG_CAP_64 : SEG_CAP_128) / 2, n_cu, st,
                         &seg_grid)))
     return rc;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags);
-  hipLaunchKernelGGL(k_totals_meta, dim3(1), dim3(64), 0, st, d_tot, meta, kl_n, P.B);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags,
+                     meta, kl_n, P.B);
   stage_mark(8, st);
   HIP_TRY(hipGetLastError());
   return KC_OK;
@@ -804,14 +804,26 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   };
   const bool rounds = P.rounds > 1;
   stage_mark(0, st);
-  fill(ctrl, 2ull * X_WORDS, 0u);
-  fill(d_hist, 2ull * hist_len, 0u);
-  fill(d_tot, sizeof(DevTotals) / 4, 0u);
-  fill(starts, P.n_mask, 0u);
-  fill(rid, P.n_blk, 0xFFFFFFFFu);
   const u64 n32 = ceil_div(P.R, 32);
-  fill(packed + 2 * n32, P.n_packed - 2 * n32, 0u);
-  fill(nmask + n32, P.n_mask - n32, 0u);
+  {
+    FillList fl{};
+    u64 most = 0;
+    auto add = [&](void* p, u64 n_words, u32 v) {
+      fl.p[fl.cnt] = (u32*)p;
+      fl.n[fl.cnt] = n_words;
+      fl.v[fl.cnt] = v;
+      ++fl.cnt;
+      most = std::max(most, n_words);
+    };
+    add(ctrl, 2ull * X_WORDS, 0u);
+    add(d_hist, 2ull * hist_len, 0u);
+    add(d_tot, sizeof(DevTotals) / 4, 0u);
+    add(starts, P.n_mask, 0u);
+    add(rid, P.n_blk, 0xFFFFFFFFu);
+    add(packed + 2 * n32, P.n_packed - 2 * n32, 0u);
+    add(nmask + n32, P.n_mask - n32, 0u);
+    hipLaunchKernelGGL(k_fill_multi, grid_for(most, 256, 4096), dim3(256), 0, st, fl);
+  }
   if (P.R) hipLaunchKernelGGL(k_pack, grid_for(n32, 256), dim3(256), 0, st, d_reads, P.R, packed, nmask);
   if (P.n_reads) {
     hipLaunchKernelGGL(k_read_starts, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, starts,

@@ -142,3 +142,17 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* scratch, T* total) {
 __global__ void k_fill_u32(u32* __restrict__ p, u64 n, u32 v) {
   for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
 }
+
+// Up to eight fills in one launch (a count starts with several small ones; each launch
+// costs more than the work of most of them).
+struct FillList {
+  u32* p[8];
+  u64 n[8];
+  u32 v[8];
+  int cnt;
+};
+__global__ void k_fill_multi(FillList L) {
+  const u64 t0 = blockIdx.x * (u64)blockDim.x + threadIdx.x, stride = (u64)gridDim.x * blockDim.x;
+  for (int r = 0; r < L.cnt; ++r)
+    for (u64 i = t0; i < L.n[r]; i += stride) L.p[r][i] = L.v[r];
+}

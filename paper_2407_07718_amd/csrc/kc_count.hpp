@@ -830,8 +830,10 @@ __global__ __launch_bounds__(256) void k_copy_pairs(const K* __restrict__ sk, co
   }
 }
 
+// Totals of a count, with the bucket-plan figures (meta: small, large, large k-mers,
+// records, chunks, tiny, tiny k-mers, small k-mers).
 __global__ void k_finalize(DevTotals* tot, const u64* counters, const u64* surv_n, u64 rec_cap, u64 surv_cap,
-                           const u32* flags) {
+                           const u32* flags, const u64* meta, const u64* kl_n, u32 B) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   tot->n_windows = counters[1];
   tot->n_records = counters[0];
@@ -840,4 +842,13 @@ __global__ void k_finalize(DevTotals* tot, const u64* counters, const u64* surv_
   if (counters[0] > rec_cap) f |= 2u;
   if (*surv_n > surv_cap) f |= 4u;
   tot->flags = f;
+  tot->large_keys = meta[2];
+  tot->tiny_buckets = meta[5];
+  tot->tiny_kmers = meta[6];
+  tot->small_buckets = meta[0];
+  tot->small_kmers = meta[7];
+  tot->large_buckets = meta[1];
+  tot->chunks = meta[4];
+  tot->list_entries = *kl_n;
+  tot->buckets = B;
 }
