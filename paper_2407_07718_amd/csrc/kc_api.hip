@@ -595,9 +595,11 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     ma.n_seg = ctrl + C_NSEG;
     ma.nbits = 2 * P.k;
     ma.target = (P.key_words == 1 ? SEG_CAP_64 : SEG_CAP_128) / 2;
-    hipLaunchKernelGGL((k_msd_hist<K>), dim3(MSD_NB), dim3(256), 0, st, ma);
-    scan_u32(ma.hist, ma.hist, (const u64*)nullptr, 256ull * MSD_NB, (u64*)nullptr, scanbuf, st);
-    hipLaunchKernelGGL((k_msd_scatter<K>), dim3(MSD_NB), dim3(512), 0, st, ma);
+    // blocks of the coarse pass: about 16K survivors each at most, up to MSD_NB
+    ma.nb = (u32)std::min<u64>(MSD_NB, std::max<u64>(1, ceil_div(P.surv_cap, 16384)));
+    hipLaunchKernelGGL((k_msd_hist<K>), dim3(ma.nb), dim3(256), 0, st, ma);
+    scan_u32(ma.hist, ma.hist, (const u64*)nullptr, 256ull * ma.nb, (u64*)nullptr, scanbuf, st);
+    hipLaunchKernelGGL((k_msd_scatter<K>), dim3(ma.nb), dim3(512), 0, st, ma);
     hipLaunchKernelGGL((k_msd_fine<K>), dim3(256), dim3(1024), 0, st, ma);
   }
   if ((rc = seg_sort<K>(s1k, s1c, s0k, s0c, reinterpret_cast<K*>(d_kmers), d_counts, pair_cap, seg, ctrl + C_NSEG,

@@ -24,7 +24,7 @@ __device__ __forceinline__ u32 key_field(k128 k, int sh, int nb) {
   return (u32)v & ((1u << nb) - 1u);
 }
 
-constexpr u32 MSD_NB = 1024;   // blocks of the coarse pass
+constexpr u32 MSD_NB = 1024;   // blocks of the coarse pass at most
 
 struct MsdArgs {
   const void* in_k;        // dense survivors
@@ -34,7 +34,8 @@ struct MsdArgs {
   u32* mid_v;
   void* out_k;             // grouped by the top 8 + g2 bits
   u32* out_v;
-  u32* hist;               // [256][MSD_NB] counts -> offsets
+  u32* hist;               // [256][nb] counts -> offsets
+  u32 nb;                  // blocks of the coarse pass (<= MSD_NB)
   u64* seg;                // [(256 << g2) + 1] range starts
   u64* n_seg;              // ranges
   int nbits;               // key bits (2k)
@@ -212,7 +213,7 @@ template <typename K>
 __global__ __launch_bounds__(256) void k_msd_hist(MsdArgs A) {
   __shared__ u32 h[256];
   const u64 n = *A.n_ptr;
-  const u64 per = (n + MSD_NB - 1) / MSD_NB;
+  const u64 per = (n + A.nb - 1) / A.nb;
   const u64 a = min(n, blockIdx.x * per), b = min(n, a + per);
   const int sh = msd_shift1(A.nbits), nb = msd_bits1(A.nbits);
   const K* in = reinterpret_cast<const K*>(A.in_k);
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) void k_msd_hist(MsdArgs A) {
   __syncthreads();
   for (u64 i = a + threadIdx.x; i < b; i += 256) atomicAdd(&h[key_field(in[i], sh, nb)], 1u);
   __syncthreads();
-  A.hist[(u64)threadIdx.x * MSD_NB + blockIdx.x] = h[threadIdx.x];
+  A.hist[(u64)threadIdx.x * A.nb + blockIdx.x] = h[threadIdx.x];
 }
 
 // Coarse scatter: the block's range in rounds staged through LDS, written group by group.
@@ -233,14 +234,14 @@ __global__ __launch_bounds__(512) void k_msd_scatter(MsdArgs A) {
   __shared__ u64 scr[17];
   const u32 tid = threadIdx.x;
   const u64 n = *A.n_ptr;
-  const u64 per = (n + MSD_NB - 1) / MSD_NB;
+  const u64 per = (n + A.nb - 1) / A.nb;
   const u64 a = min(n, blockIdx.x * per), b = min(n, a + per);
   const int sh = msd_shift1(A.nbits), nb = msd_bits1(A.nbits);
   const K* in = reinterpret_cast<const K*>(A.in_k);
   K* mid = reinterpret_cast<K*>(A.mid_k);
   if (tid < 256) {
     cnt[tid] = 0;
-    gpos[tid] = A.hist[(u64)tid * MSD_NB + blockIdx.x];
+    gpos[tid] = A.hist[(u64)tid * A.nb + blockIdx.x];
   }
   __syncthreads();
   for (u64 r0 = a; r0 < b; r0 += R) {
@@ -299,8 +300,8 @@ __global__ __launch_bounds__(1024) void k_msd_fine(MsdArgs A) {
   const u64 n = *A.n_ptr;
   const int sh1 = msd_shift1(A.nbits), g2 = msd_g2(n, A.nbits, A.target), sh2 = sh1 - g2;
   const u32 F = 1u << g2;
-  const u64 a = A.hist[(u64)g * MSD_NB];
-  const u64 b = g + 1 < 256 ? (u64)A.hist[(u64)(g + 1) * MSD_NB] : n;
+  const u64 a = A.hist[(u64)g * A.nb];
+  const u64 b = g + 1 < 256 ? (u64)A.hist[(u64)(g + 1) * A.nb] : n;
   const K* mid = reinterpret_cast<const K*>(A.mid_k);
   K* out = reinterpret_cast<K*>(A.out_k);
   if (tid < 256) cr[tid] = 0;
