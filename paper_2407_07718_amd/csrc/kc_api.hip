@@ -491,9 +491,13 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     PlanArgs pa{bcnt, P.B, P.cap_tiny, P.cap, P.cap_chunk, bsum, tiny, recoff, cursor, small, large, lkoff, chstart,
                 chlen, P.chunk_cap, kall, meta, at<u32>(ws, P.o_lch0)};
     const u32 nbp = (P.B + PLAN_BLOCK - 1) / PLAN_BLOCK;
-    hipLaunchKernelGGL(k_plan_reduce, dim3(nbp), dim3(PLAN_T), 0, st, pa);
-    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, st, pa, nbp);
-    hipLaunchKernelGGL(k_plan_write, dim3(nbp), dim3(PLAN_T), 0, st, pa);
+    if (nbp == 1) {
+      hipLaunchKernelGGL(k_plan_write<true>, dim3(1), dim3(PLAN_T), 0, st, pa);
+    } else {
+      hipLaunchKernelGGL(k_plan_reduce, dim3(nbp), dim3(PLAN_T), 0, st, pa);
+      hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, st, pa, nbp);
+      hipLaunchKernelGGL(k_plan_write<false>, dim3(nbp), dim3(PLAN_T), 0, st, pa);
+    }
   }
 
   stage_mark(3, st);

@@ -278,7 +278,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // The plan classifies buckets by k-mer count n: tiny (n <= cap_tiny, one wave each),
 // small (n <= cap_small, one block each) -- both sorted on chip from their records --
 // and large (cut into chunks of at most cap_chunk k-mers, see the counting stage).  It
-// is three kernels: per-block sums, one scan of the block sums, then the writes.
+// is three kernels: per-block sums, one scan of the block sums, then the writes (one
+// kernel when the buckets fit one block).
 // Quantities per bucket: q0 records, q1 k-mers, q2 classes packed (tiny | small << 21 |
 // large << 42), q3 k-mers of large buckets, q4 chunks, q5 k-mers of tiny buckets, q6
 // k-mers of small buckets.
@@ -334,6 +335,19 @@ __global__ __launch_bounds__(PLAN_T) void k_plan_reduce(PlanArgs P) {
   }
 }
 
+// Plan totals -> meta (and the records' end offset).
+__device__ __forceinline__ void plan_meta(const PlanArgs& P, const u64 (&tot)[PLAN_Q]) {
+  P.rec_off[P.B] = (u32)tot[0];
+  P.meta[0] = (tot[2] >> 21) & ((1ull << 21) - 1);
+  P.meta[1] = tot[2] >> 42;
+  P.meta[2] = tot[3];
+  P.meta[3] = tot[0];
+  P.meta[4] = min(tot[4], P.chunk_cap);
+  P.meta[5] = tot[2] & ((1ull << 21) - 1);
+  P.meta[6] = tot[5];
+  P.meta[7] = tot[6];
+}
+
 // One block: exclusive scan of the block sums (in place) and the totals.
 __global__ __launch_bounds__(1024) void k_plan_scan(PlanArgs P, u32 nblocks) {
   __shared__ u64 scr[17];
@@ -350,19 +364,12 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanArgs P, u32 nblocks) {
       run += v;
     }
   }
-  if (threadIdx.x == 0) {
-    P.rec_off[P.B] = (u32)tot[0];
-    P.meta[0] = (tot[2] >> 21) & ((1ull << 21) - 1);
-    P.meta[1] = tot[2] >> 42;
-    P.meta[2] = tot[3];
-    P.meta[3] = tot[0];
-    P.meta[4] = min(tot[4], P.chunk_cap);
-    P.meta[5] = tot[2] & ((1ull << 21) - 1);
-    P.meta[6] = tot[5];
-    P.meta[7] = tot[6];
-  }
+  if (threadIdx.x == 0) plan_meta(P, tot);
 }
 
+// With ONE (B <= PLAN_BLOCK, a single block) the block's own sums are the totals: the
+// reduce and scan kernels are not needed.
+template <bool ONE>
 __global__ __launch_bounds__(PLAN_T) void k_plan_write(PlanArgs P) {
   __shared__ u64 scr[17];
   const u32 b0 = blockIdx.x * PLAN_BLOCK + threadIdx.x * PLAN_PER_THREAD;
@@ -374,11 +381,10 @@ __global__ __launch_bounds__(PLAN_T) void k_plan_write(PlanArgs P) {
     plan_quantities(P, c[i], q);
     for (int j = 0; j < PLAN_Q; ++j) sum[j] += q[j];
   }
-  u64 off[PLAN_Q];
-  for (int j = 0; j < PLAN_Q; ++j) {
-    u64 tot;
-    off[j] = block_exclusive_scan<u64>(sum[j], scr, &tot) + P.bsum[(u64)blockIdx.x * PLAN_Q + j];
-  }
+  u64 off[PLAN_Q], tot[PLAN_Q];
+  for (int j = 0; j < PLAN_Q; ++j)
+    off[j] = block_exclusive_scan<u64>(sum[j], scr, &tot[j]) + (ONE ? 0ull : P.bsum[(u64)blockIdx.x * PLAN_Q + j]);
+  if (ONE && threadIdx.x == 0) plan_meta(P, tot);
   u64 prec = off[0], pk = off[1], plk = off[3], pch = off[4];
   u64 ptiny = off[2] & ((1ull << 21) - 1), psmall = (off[2] >> 21) & ((1ull << 21) - 1), plarge = off[2] >> 42;
   for (u32 i = 0; i < PLAN_PER_THREAD; ++i) {
