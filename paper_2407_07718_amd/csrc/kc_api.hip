@@ -298,21 +298,19 @@ int radix_sort(K* k0, K* k1, u32* v0, u32* v1, const u64* n_ptr, u32* counts, u3
   return KC_OK;
 }
 
-__global__ void k_clamp(const u64* src, u64 cap, u64* dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = min(*src, cap);
-}
-
 // Device-wide exclusive scan (see k_scan_reduce); n_max must be <= 1024 * SCAN_BLOCK.
 // Short inputs take one single-block launch instead of three.
 constexpr u64 SCAN_ONE_BLOCK_MAX = 32768;
-void scan_u32(const u32* in, u32* out, const u64* n_ptr, u64 n_max, u64* total, u64* bsum, hipStream_t st) {
+// With `clamped`, min(total, cap) is also written there.
+void scan_u32(const u32* in, u32* out, const u64* n_ptr, u64 n_max, u64* total, u64* bsum, hipStream_t st,
+              u64* clamped = nullptr, u64 cap = 0) {
   if (n_max <= SCAN_ONE_BLOCK_MAX) {
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, in, out, n_ptr, n_max, total);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, in, out, n_ptr, n_max, total, clamped, cap);
     return;
   }
   const u32 nb = (u32)std::max<u64>(1, (n_max + SCAN_BLOCK - 1) / SCAN_BLOCK);
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_T), 0, st, in, n_ptr, n_max, bsum);
-  hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, bsum, nb, total);
+  hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(1024), 0, st, bsum, nb, total, clamped, cap);
   hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_T), 0, st, in, out, n_ptr, n_max, bsum);
 }
 
@@ -552,10 +550,9 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   }
   stage_mark(6, st);
   // merge the chunks' (k-mer, count) lists: compact, sort by k-mer, sum each run's counts
-  scan_u32(klcnt, kloff, meta + 4, P.chunk_cap, kl_n, scanbuf, st);
+  scan_u32(klcnt, kloff, meta + 4, P.chunk_cap, kl_n, scanbuf, st, kl_nc, P.kl_cap);
   hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.chunk_cap, 4, 4096), dim3(256), 0, st, lk0, klsc, chstart,
                      (const u64*)nullptr, 0u, klcnt, kloff, meta + 4, P.chunk_cap, kl0k, kl0c);
-  hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, kl_n, P.kl_cap, kl_nc);
   // each heavy bucket's lists are one segment, sorted on its own (in place)
   u64* seg = at<u64>(ws, P.o_seg);
   hipLaunchKernelGGL(k_merge_segs, grid_for(P.B + 1, 256, 1024), dim3(256), 0, st, kloff, at<u32>(ws, P.o_lch0), meta + 1,
@@ -571,19 +568,19 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   K* s1k = lks;                      // dense survivors go where the sorted lists were
   u32* s1c = lvs;
   hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc);
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, bc, bc, (const u64*)nullptr, (u64)P.nb_large, nruns);
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, bc, bc, (const u64*)nullptr, (u64)P.nb_large, nruns,
+                     (u64*)nullptr, 0ull);
   hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc, hp);
   hipLaunchKernelGGL((k_rle_runs<K>), dim3(RUN_BLOCKS), dim3(256), 0, st, ca, lks, lvs, kl_nc, hp, nruns, fk, fc,
                      scnt + P.B);
 
   stage_mark(7, st);
   // ---- output: compact the survivors (buckets, then merged runs), sort them by key
-  scan_u32(scnt, soff, (const u64*)nullptr, (u64)P.B + RUN_BLOCKS, surv_n, scanbuf, st);
+  scan_u32(scnt, soff, (const u64*)nullptr, (u64)P.B + RUN_BLOCKS, surv_n, scanbuf, st, surv_nc, P.surv_cap);
   hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.B, 4, 4096), dim3(256), 0, st, s0k, s0c, kall, (const u64*)nullptr,
                      0u, scnt, soff, (const u64*)nullptr, (u64)P.B, s1k, s1c);
   hipLaunchKernelGGL((k_gather_segments<K>), grid_for(RUN_BLOCKS, 4, 4096), dim3(256), 0, st, fk, fc, (const u64*)nullptr,
                      nruns, RUN_BLOCKS, scnt + P.B, soff + P.B, (const u64*)nullptr, (u64)RUN_BLOCKS, s1k, s1c);
-  hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, surv_n, P.surv_cap, surv_nc);
   // key ranges by the top bits (s1 -> s0 -> s1), then each range sorted into the output
   {
     MsdArgs ma;
@@ -905,8 +902,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   for (u32 q = 0; q < P.rounds; ++q) {
     wa.range = rb + q;
     hipLaunchKernelGGL((k_ext_windows<K, false>), gw, dim3(EXT_T), 0, st, wa);
-    scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles, ctrl + X_NWIN, scanbuf, st);
-    hipLaunchKernelGGL(k_clamp, dim3(1), dim3(64), 0, st, ctrl + X_NWIN, P.cap, ctrl + X_NWINC);
+    scan_u32(blk, blk, (const u64*)nullptr, P.n_tiles, ctrl + X_NWIN, scanbuf, st, ctrl + X_NWINC, P.cap);
     hipLaunchKernelGGL((k_ext_windows<K, true>), gw, dim3(EXT_T), 0, st, wa);
     if (!rounds) stage_mark(2, st);
     bool second = false;

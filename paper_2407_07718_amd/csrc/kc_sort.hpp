@@ -159,7 +159,8 @@ __global__ __launch_bounds__(256) void k_radix_upsweep(const K* __restrict__ key
 // Exclusive scan out[i] = sum of in[0, i) for i < n by one block; n = min(*n_ptr, n_max)
 // when n_ptr is given, else n_max; *total = sum (if non-null).  in and out may alias.
 __global__ __launch_bounds__(1024) void k_scan_u32(const u32* __restrict__ in, u32* __restrict__ out,
-                                                   const u64* __restrict__ n_ptr, u64 n_max, u64* __restrict__ total) {
+                                                   const u64* __restrict__ n_ptr, u64 n_max, u64* __restrict__ total,
+                                                   u64* __restrict__ clamped = nullptr, u64 cap = 0) {
   __shared__ u64 scr[17];
   const u64 n = n_ptr ? min(*n_ptr, n_max) : n_max;
   const u32 T = blockDim.x, t = threadIdx.x;
@@ -175,12 +176,14 @@ __global__ __launch_bounds__(1024) void k_scan_u32(const u32* __restrict__ in, u
     run += v;
   }
   if (t == 0 && total) *total = all;
+  if (t == 0 && clamped) *clamped = min(all, cap);
 }
 
 // Device-wide exclusive scan of u32 counts in three kernels (block sums, scan of the
 // block sums, apply): n = min(*n_ptr, n_max) (n_max alone if n_ptr is null); blocks of
 // SCAN_T threads take SCAN_BLOCK consecutive elements.  bsum holds ceil(n_max /
-// SCAN_BLOCK) <= 1024 entries.  *total = sum.  in and out may alias.
+// SCAN_BLOCK) <= 1024 entries.  *total = sum (and *clamped = min(sum, cap) when given).
+// in and out may alias.
 constexpr u32 SCAN_T = 256, SCAN_PER = 16, SCAN_BLOCK = SCAN_T * SCAN_PER;
 
 __global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const u32* __restrict__ in, const u64* __restrict__ n_ptr,
@@ -196,13 +199,15 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const u32* __restrict__ 
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_mid(u64* __restrict__ bsum, u32 nb, u64* __restrict__ total) {
+__global__ __launch_bounds__(1024) void k_scan_mid(u64* __restrict__ bsum, u32 nb, u64* __restrict__ total,
+                                                   u64* __restrict__ clamped, u64 cap) {
   __shared__ u64 scr[17];
   const u64 v = threadIdx.x < nb ? bsum[threadIdx.x] : 0ull;
   u64 tot;
   const u64 ex = block_exclusive_scan<u64>(v, scr, &tot);
   if (threadIdx.x < nb) bsum[threadIdx.x] = ex;
   if (threadIdx.x == 0 && total) *total = tot;
+  if (threadIdx.x == 0 && clamped) *clamped = min(tot, cap);
 }
 
 __global__ __launch_bounds__(SCAN_T) void k_scan_apply(const u32* __restrict__ in, u32* __restrict__ out,
