@@ -90,7 +90,7 @@ struct Plan {
   u64 chunk_cap = 0, kl_cap = 0;
   u64 R = 0, n_reads = 0, n_max = 0;   // bases, reads, bound on windows
   u64 rec_cap = 0, surv_cap = 0;
-  u64 slots = 0, n_span_cap = 0;   // record slots of the extract blocks
+  u64 slots = 0, n_span_cap = 0;   // record slots of the extract blocks (a bound over m), spans
   u32 span = 0;
   u32 nb_large = 1, nb_surv = 1;        // radix blocks
   // offsets into the workspace
@@ -98,7 +98,7 @@ struct Plan {
       o_lkoff, o_ctrl, o_cnt_large, o_cnt_surv, o_tot_large, o_tot_surv, o_bc, o_hp, o_blkcnt, o_chstart, o_chlen,
       o_tiny, o_kall, o_klcnt, o_kloff, o_scnt, o_soff, o_bsum, o_scanbuf, o_phist, o_lch0, o_seg, o_mhist;
   int log_c = 0, log_f = 0;
-  u32 part_nblk = 1, part_spb = 1;
+  u32 part_nblk = 1, part_spb = 1, nblk_cap = 1;   // extract blocks: this count's, and the bound over m
   u64 n_packed, n_mask, bytes = 0;
 };
 
@@ -155,11 +155,22 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->rec_cap = std::max<u64>(1, n_max);
   // each wave span of the extract stage covers `span` k-mer positions (16 tiles of 64);
   // extract block b covers spans [b*spb, (b+1)*spb) and owns spb*span record slots
-  p->span = 16u * 64u;
+  p->span = EX_SPAN_MAX - (u32)(k - m);   // 16 tiles of 64 m-mer positions per span
   p->n_span_cap = (std::max<u64>(R, 1) + p->span - 1) / p->span;
-  p->part_spb = (u32)std::max<u64>(1, ceil_div(p->n_span_cap, 2048));
+  // at most 4096 extract blocks: about two rounds of the 2048 blocks of 256 threads the
+  // chip holds at eight waves per SIMD (more blocks enlarge the partition's histogram)
+  p->part_spb = (u32)std::max<u64>(1, ceil_div(p->n_span_cap, 4096));
   p->part_nblk = (u32)ceil_div(p->n_span_cap, p->part_spb);
-  p->slots = (u64)p->part_nblk * p->part_spb * p->span;
+  // The workspace may not depend on m (its size query has no m), so the extract regions
+  // take bounds over every m for this k: spans are at least 1024 - (k - 1) positions, so
+  // there are at most nsc_max of them; blocks number at most min(4096, nsc_max); and
+  // nblk * spb * span < (n_span_cap + spb) * span <= R + 1024 * (1 + spb_max).
+  {
+    const u64 nsc_max = ceil_div(std::max<u64>(R, 1), EX_SPAN_MAX - (u64)(k - 1));
+    const u64 spb_max = std::max<u64>(1, ceil_div(nsc_max, 4096));
+    p->nblk_cap = (u32)std::min<u64>(4096, nsc_max);
+    p->slots = std::max<u64>(R, 1) + (u64)EX_SPAN_MAX * (1 + spb_max);
+  }
   (void)min_freq;
   p->surv_cap = std::max<u64>(1, n_max);   // survivors sit at their bucket's k-mer slots first
   const u64 w = 8ull * p->key_words;
@@ -191,7 +202,7 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_X = take(std::max(std::max(rb * p->slots, rb * N), (w + 4) * N));
   p->o_Y = take(std::max(rb * N, (w + 4) * N));
   p->o_Z = take((w + 4) * N);
-  p->o_blkcnt = take(4ull * p->part_nblk);
+  p->o_blkcnt = take(4ull * p->nblk_cap);
   p->o_bcnt = take(8ull * p->B);
   p->o_recoff = take(4ull * (p->B + 1));
   p->o_cursor = take(4ull * p->B);
@@ -215,7 +226,7 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_soff = take(4ull * (p->B + RUN_BLOCKS));
   p->o_bsum = take(8ull * PLAN_Q * (p->B / PLAN_BLOCK + 1));
   p->o_scanbuf = take(8ull * 1024);
-  p->o_phist = take(4ull * ((u64)1 << p->log_c) * p->part_nblk);
+  p->o_phist = take(4ull * ((u64)1 << p->log_c) * p->nblk_cap);
   p->o_lch0 = take(4ull * p->B);
   p->o_seg = take(8ull * (std::max<u64>(p->B, (u64)256 << 8) + 2));
   p->o_mhist = take(4ull * 256 * MSD_NB);
@@ -457,8 +468,13 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ea.C = 1u << P.log_c;
   ea.counters = counters;
   ea.n_span_cap = P.n_span_cap;
+  ea.n_packed = P.n_packed;
+  ea.n_mask = P.n_mask;
   stage_mark(1, st);
-  hipLaunchKernelGGL(k_extract, dim3(P.part_nblk), dim3(256), 0, st, ea);
+  if (P.rec_words == 4)
+    hipLaunchKernelGGL(k_extract<4>, dim3(P.part_nblk), dim3(256), 0, st, ea);
+  else
+    hipLaunchKernelGGL(k_extract<8>, dim3(P.part_nblk), dim3(256), 0, st, ea);
   stage_mark(2, st);
   {
     PartArgs pp;

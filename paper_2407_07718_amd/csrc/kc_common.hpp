@@ -29,9 +29,13 @@ template <> __device__ __forceinline__ u64 key_zero<u64>() { return 0; }
 template <> __device__ __forceinline__ k128 key_zero<k128>() { return k128{0, 0}; }
 
 // Reverse the order of the 32 two-bit groups of x (base j <-> base 31-j).
+// Bit reversal of each 32-bit half, then the two bits of every group swapped back, per
+// half (one bitfield insert).
+__device__ __forceinline__ u32 swap_bit_pairs(u32 v) { return ((v >> 1) & 0x55555555u) | ((v << 1) & 0xAAAAAAAAu); }
 __device__ __forceinline__ u64 rev2_64(u64 x) {
-  x = __builtin_bitreverse64(x);
-  return ((x >> 1) & 0x5555555555555555ull) | ((x & 0x5555555555555555ull) << 1);
+  const u32 lo = swap_bit_pairs(__builtin_bitreverse32((u32)(x >> 32)));
+  const u32 hi = swap_bit_pairs(__builtin_bitreverse32((u32)x));
+  return ((u64)hi << 32) | lo;
 }
 
 // Score of a canonical m-mer: the upper half of MurmurHash3's 64-bit finalizer
@@ -61,6 +65,19 @@ __device__ __forceinline__ u64 bits64(const u32* __restrict__ p, u64 q) {
   u64 a = (u64)p[w] | ((u64)p[w + 1] << 32);
   u64 b = p[w + 2];
   return sh ? (a >> sh) | (b << (64 - sh)) : a;
+}
+
+// bases64 / bits64 on a copy in LDS, q relative to the copy's first base: each 32-bit
+// half is one funnel shift (v_alignbit) of two neighbouring words.
+__device__ __forceinline__ u64 lds_bases64(const u32* p, u32 q) {
+  const u32 w = q >> 4, sh = (q & 15) * 2;
+  const u32 a = p[w], b = p[w + 1], c = p[w + 2];
+  return ((u64)__builtin_amdgcn_alignbit(c, b, sh) << 32) | __builtin_amdgcn_alignbit(b, a, sh);
+}
+__device__ __forceinline__ u64 lds_bits64(const u32* p, u32 q) {
+  const u32 w = q >> 5, sh = q & 31;
+  const u32 a = p[w], b = p[w + 1], c = p[w + 2];
+  return ((u64)__builtin_amdgcn_alignbit(c, b, sh) << 32) | __builtin_amdgcn_alignbit(b, a, sh);
 }
 
 __device__ __forceinline__ u32 lane_id() { return threadIdx.x & 63u; }

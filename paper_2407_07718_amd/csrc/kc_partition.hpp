@@ -83,39 +83,8 @@ struct ExtractArgs {
   u32 C;               // coarse groups
   u64* counters;       // [0] records written, [1] valid windows
   u64 n_span_cap;      // spans the record region holds
+  u64 n_packed, n_mask;   // words in `packed` and in `nmask` / `starts`
 };
-
-// Minimum of the last `w` scores ending at each lane, over a stream of 64-lane tiles: the
-// log-step doubling takes its lower neighbour from this tile where one exists and from
-// the previous tile otherwise.  `carry[j]` holds step j's rotated values of the previous
-// tile and is updated in place.  Lanes whose window reaches before the first tile of a
-// stream get garbage and must not be used.
-__device__ __forceinline__ u32 rot_up(u32 v, u32 d) {
-  return d == 1 ? lane_rot1(v) : (u32)__shfl((int)v, (int)((lane_id() - d) & 63u), 64);
-}
-constexpr int WIN_STEPS = 5;   // w <= 63: doubling steps of 1, 2, 4, 8, 16, then the remainder
-
-__device__ __forceinline__ u32 window_min_carry(u32 v, int w, u32 (&carry)[WIN_STEPS], u32& carry_rest) {
-  const u32 lane = lane_id();
-  u32 a = v;
-  u32 len = 1;
-#pragma unroll
-  for (int j = 0; j < WIN_STEPS; ++j) {   // static indices: the carries stay in registers
-    if (2 * (int)len <= w) {
-      const u32 r = rot_up(a, len);
-      a = min(a, lane >= len ? r : carry[j]);
-      carry[j] = r;
-      len *= 2;
-    }
-  }
-  if ((u32)w > len) {
-    const u32 d = (u32)w - len;
-    const u32 r = rot_up(a, d);
-    a = min(a, lane >= d ? r : carry_rest);
-    carry_rest = r;
-  }
-  return a;
-}
 
 // A supermer record (16 bytes for k <= 31, 32 bytes for k >= 32) holds its bases, two
 // bits each from bit 0 (at most 51 / 115 bases), its bucket in 20 bits and (g - 1) in the
@@ -124,32 +93,80 @@ __device__ __forceinline__ u32 window_min_carry(u32 v, int w, u32 (&carry)[WIN_S
 constexpr int REC_BUCKET_SHIFT = 38;   // within the record's top 64-bit word
 __device__ __forceinline__ u32 rec_last_bucket(u32 last_word) { return (last_word >> 6) & 0xFFFFFu; }
 
-__device__ __forceinline__ void write_record(const ExtractArgs& A, u64 slot, u64 start, u32 g, u32 bucket) {
-  {
-    const u32 nb2 = 2u * (g + (u32)A.k - 1u);       // bits of bases
-    if (A.rec_words == 4) {
-      u64 w0 = bases64(A.packed, start), w1 = bases64(A.packed, start + 32);
-      if (nb2 < 64) { w0 &= (1ull << nb2) - 1; w1 = 0; }
-      else { u32 r = nb2 - 64; w1 = r ? (w1 & ((1ull << r) - 1)) : 0; }
-      w1 |= ((u64)(g - 1) << 58) | ((u64)bucket << REC_BUCKET_SHIFT);
-      uint4 v = make_uint4((u32)w0, (u32)(w0 >> 32), (u32)w1, (u32)(w1 >> 32));
-      reinterpret_cast<uint4*>(A.rec)[slot] = v;
-    } else {
-      u64 w[4];
+// `pk` is the wave's LDS copy of the packed bases, `start` relative to its first base.
+template <int RW>
+__device__ __forceinline__ void write_record(u32* __restrict__ rec, int k, const u32* pk, u64 slot, u32 start, u32 g,
+                                             u32 bucket) {
+  const u32 nb2 = 2u * (g + (u32)k - 1u);       // bits of bases, at least 2k
+  const u64 top = ((u64)(g - 1) << 58) | ((u64)bucket << REC_BUCKET_SHIFT);
+  // word i keeps min(64, max(0, nb2 - 64 i)) low bits of bases
+  if constexpr (RW == 4) {   // masks without branches
+    const u32 r0 = min(nb2, 64u), r1 = max(nb2, 64u) - 64u;   // r0 in [2, 64], r1 in [0, 38]
+    const u64 w0 = lds_bases64(pk, start) & (~0ull >> (64u - r0));
+    const u64 w1 = (lds_bases64(pk, start + 32) & ((1ull << r1) - 1)) | top;
+    reinterpret_cast<uint4*>(rec)[slot] = make_uint4((u32)w0, (u32)(w0 >> 32), (u32)w1, (u32)(w1 >> 32));
+  } else {
+    u64 w[4];   // (branches measured faster than masks here: most words are whole or empty)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        w[i] = bases64(A.packed, start + 32 * i);
-        int lo_bit = 64 * i;
-        int rem = (int)nb2 - lo_bit;
-        if (rem <= 0) w[i] = 0;
-        else if (rem < 64) w[i] &= (1ull << rem) - 1;
-      }
-      w[3] |= ((u64)(g - 1) << 58) | ((u64)bucket << REC_BUCKET_SHIFT);
-      uint4* dst = reinterpret_cast<uint4*>(A.rec) + 2 * slot;
-      dst[0] = make_uint4((u32)w[0], (u32)(w[0] >> 32), (u32)w[1], (u32)(w[1] >> 32));
-      dst[1] = make_uint4((u32)w[2], (u32)(w[2] >> 32), (u32)w[3], (u32)(w[3] >> 32));
+    for (int i = 0; i < 4; ++i) {
+      w[i] = lds_bases64(pk, start + 32 * i);
+      const int rem = (int)nb2 - 64 * i;
+      if (rem <= 0) w[i] = 0;
+      else if (rem < 64) w[i] &= (1ull << rem) - 1;
+    }
+    w[3] |= top;
+    uint4* dst = reinterpret_cast<uint4*>(rec) + 2 * slot;
+    dst[0] = make_uint4((u32)w[0], (u32)(w[0] >> 32), (u32)w[1], (u32)(w[1] >> 32));
+    dst[1] = make_uint4((u32)w[2], (u32)(w[2] >> 32), (u32)w[3], (u32)(w[3] >> 32));
+  }
+}
+
+// LDS words per wave for one span's window of the packed bases and of each bit mask.
+// A span of at most 1024 k-mer positions reads bases [S0, S0 + 1024 + 62 + 63] in its
+// tiles and at most [S0, S0 + 1023 + 127] in its records: at most 75 words from word
+// S0 / 16; the masks are read at positions [S0, S0 + 1023 + 63]: at most 36 words from
+// word S0 / 32.  A span of 1024 - (w - 1) positions fills its 16 tiles exactly (the
+// first w - 1 lanes of a span only start the window minimum).
+constexpr u32 EX_PK = 128, EX_MK = 64, EX_SPAN_MAX = 1024;
+
+// The words a span starting at base S0 reads, one lane's share: two words of packed
+// bases, one of the non-base mask and one of the "cut" mask (non-base or read start).
+__device__ __forceinline__ void ex_stage_load(const ExtractArgs& A, u64 S0, u32 lane, u32& a0, u32& a1, u32& nmw,
+                                              u32& cut) {
+  const u64 pw0 = S0 >> 4, mw0 = S0 >> 5;
+  const u64 i0 = pw0 + lane, i1 = pw0 + 64 + lane, j = mw0 + lane;
+  a0 = i0 < A.n_packed ? A.packed[i0] : 0u;
+  a1 = i1 < A.n_packed ? A.packed[i1] : 0u;
+  nmw = j < A.n_mask ? A.nmask[j] : 0u;
+  cut = nmw | (j < A.n_mask ? A.starts[j] : 0u);
+}
+
+// Sliding minimum of the last w scores ending at each lane over a stream of 64-lane tiles
+// (w = 2^nst + rest, rest < 2^nst, w <= 63): nst doubling steps whose lower neighbour
+// comes from this tile where one exists and from the previous tile otherwise, then one
+// step of `rest`.  `carry[j]` holds step j's rotated values of the previous tile and is
+// updated in place.  Lanes whose window reaches before the first tile of a stream get
+// garbage and must not be used.  `ix[j]` / `ixr` are the ds_bpermute byte indices of
+// lane l - 2^j / l - rest (mod 64).
+constexpr int WIN_STEPS = 5;
+__device__ __forceinline__ u32 window_min_carry(u32 v, int nst, u32 rest, const int (&ix)[WIN_STEPS], int ixr,
+                                                u32 (&carry)[WIN_STEPS + 1]) {
+  const u32 lane = lane_id();
+  u32 a = v;
+#pragma unroll
+  for (int j = 0; j < WIN_STEPS; ++j) {   // static distances; the step count is wave-uniform
+    if (j < nst) {
+      const u32 r = j == 0 ? lane_rot1(a) : (u32)__builtin_amdgcn_ds_bpermute(ix[j], (int)a);
+      a = min(a, lane >= (1u << j) ? r : carry[j]);
+      carry[j] = r;
     }
   }
+  if (rest) {
+    const u32 r = (u32)__builtin_amdgcn_ds_bpermute(ixr, (int)a);
+    a = min(a, lane >= rest ? r : carry[WIN_STEPS]);
+    carry[WIN_STEPS] = r;
+  }
+  return a;
 }
 
 // Each wave walks one span of k-mer positions in tiles of 64 lanes.  Lane l of a tile
@@ -162,79 +179,97 @@ __device__ __forceinline__ void write_record(const ExtractArgs& A, u64 slot, u64
 // the destination from the same hash (Section 3.2); the deque of the paper's
 // sliding-window minimum (Section 3.2) is replaced by a log-step minimum across lanes,
 // which returns the same minimum score.
+// A wave stages its span's window of the packed bases and masks in its LDS slice and
+// works on span-relative 32-bit positions.
 // Block b covers spans [b*spb, (b+1)*spb), its four waves taking them in turn; its records
 // go densely to the block's slot range through an LDS counter, and an LDS histogram of
-// their coarse bucket groups feeds the partition.
-// (At most 102 VGPRs: five waves per SIMD measured fastest over k = 31 and 51.)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_extract(ExtractArgs A) {
+// their coarse bucket groups feeds the partition.  RW = record words (4 or 8).
+template <int RW>
+__global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
   __shared__ u32 h[512];
   __shared__ u32 blk_n;
+  __shared__ u32 s_pk[4][EX_PK], s_nm[4][EX_MK], s_ct[4][EX_MK];
   const u32 lane = lane_id();
+  u32* const pk = s_pk[threadIdx.x >> 6];
+  u32* const nm = s_nm[threadIdx.x >> 6];
+  u32* const ct = s_ct[threadIdx.x >> 6];
   for (u32 i = threadIdx.x; i < 512; i += blockDim.x) h[i] = 0;
   if (threadIdx.x == 0) blk_n = 0;
   __syncthreads();
   const int k = A.k, m = A.m, w = k - m + 1;
   const u32 back = (u32)(w - 1);                 // k-mer position = m-mer position - back
   const u32 gmax = (u32)A.gmax;
+  const int nst = 31 - __builtin_clz((u32)w);    // doubling steps of the window minimum
+  const u32 rest = (u32)w - (1u << nst);
+  int ix[WIN_STEPS];
+#pragma unroll
+  for (int j = 0; j < WIN_STEPS; ++j) ix[j] = (int)(((lane - (1u << j)) & 63u) << 2);
+  const int ixr = (int)(((lane - rest) & 63u) << 2);
+  const u64 lemask = lane == 63 ? ~0ull : ((2ull << lane) - 1);   // lanes <= this lane
   const u64 lo = A.n_reads ? min(A.offsets[0], A.R) : 0;
   const u64 hi = A.n_reads ? min(A.offsets[A.n_reads], A.R) : 0;
   const u64 n_pos = (hi >= lo + (u64)k) ? hi - lo - (u64)k + 1 : 0;
   const u64 n_spans = (n_pos + A.span - 1) / A.span;
   const u64 mmask = (m >= 32) ? ~0ull : ((1ull << (2 * m)) - 1);
-  const u64 kmask1 = (1ull << k) - 1;
-  const u64 kmask2 = (1ull << (k - 1)) - 1;
+  const u64 kmask1 = (1ull << k) - 1;            // bases [p, p + k) of a k-mer at p
+  const u64 kmask_cut = kmask1 & ~1ull;          // no read may start inside (p, p + k)
   const u32 bmask = (1u << A.log_b) - 1u;
   u64 my_windows = 0;
 
   const u64 n_sp = min(n_spans, A.n_span_cap);
   const u64 s_end = min(n_sp, (u64)(blockIdx.x + 1) * A.spb);
   const u64 slot0 = (u64)blockIdx.x * A.blk_slots;   // records of this block: slot0 + [0, blk_n)
-  for (u64 s = (u64)blockIdx.x * A.spb + (threadIdx.x >> 6); s < s_end; s += blockDim.x >> 6) {
+  const u32 nwv = blockDim.x >> 6;
+  const u64 s_first = (u64)blockIdx.x * A.spb + (threadIdx.x >> 6);
+  for (u64 s = s_first; s < s_end; s += nwv) {
     const u64 S0 = lo + s * A.span;
-    const u64 S1 = min(S0 + A.span, lo + n_pos);
+    const u32 len = (u32)(min(S0 + A.span, lo + n_pos) - S0);   // k-mer positions of the span
+    // stage the span's words in this wave's LDS slice (the previous span's reads of it are
+    // done: LDS operations of one wave run in order)
+    const u32 offp = (u32)(S0 & 15), offm = (u32)(S0 & 31);       // S0 within the first words
+    {
+      u32 a0, a1, b0, c0;
+      ex_stage_load(A, S0, lane, a0, a1, b0, c0);
+      __builtin_amdgcn_wave_barrier();
+      pk[lane] = a0;
+      pk[64 + lane] = a1;
+      nm[lane] = b0;
+      ct[lane] = c0;
+      __builtin_amdgcn_wave_barrier();
+    }
     bool c_open = false;
-    u32 c_b = 0, c_pos = 0;
-    u64 c_p = 0;
-    u32 carry[WIN_STEPS], carry_rest = 0xFFFFFFFFu;
+    u32 c_b = 0, c_pos = 0, c_p = 0;
+    u32 carry[WIN_STEPS + 1];
 #pragma unroll
-    for (int j = 0; j < WIN_STEPS; ++j) carry[j] = 0xFFFFFFFFu;
-    for (u64 T0 = S0; T0 < S1 + back; T0 += 64) {
-      const u64 q = T0 + lane;           // m-mer position
-      const u64 p = q - back;            // k-mer position (meaningful when q >= S0 + back)
+    for (int j = 0; j <= WIN_STEPS; ++j) carry[j] = 0xFFFFFFFFu;
+    for (u32 t0 = 0; t0 < len + back; t0 += 64) {
+      const u32 q = t0 + lane;           // m-mer position (span-relative)
+      const u32 p = q - back;            // k-mer position; wraps (and is invalid) for q < back
       // canonical m-mer at q and its score
-      u64 V = bases64(A.packed, q) & mmask;
-      u64 F = rev2_64(V) >> (64 - 2 * m);
-      u64 RC = ~V & mmask;
+      const u64 V = lds_bases64(pk, q + offp) & mmask;
+      const u64 F = rev2_64(V) >> (64 - 2 * m);
+      const u64 RC = ~V & mmask;
       const u32 sc = mmer_score(F < RC ? F : RC);
-      const u32 mn = window_min_carry(sc, w, carry, carry_rest);
-      bool valid = (q >= S0 + back) && (p < S1);
-      if (valid) {
-        u64 nb = bits64(A.nmask, p) & kmask1;
-        u64 sb = bits64(A.starts, p + 1) & kmask2;
-        valid = (nb == 0) && (sb == 0);
-      }
+      const u32 mn = window_min_carry(sc, nst, rest, ix, ixr, carry);
+      // a k-mer is valid if it has no non-base and no read starts inside it
+      const bool in_span = p < len;
+      const u32 x = in_span ? p + offm : 0u;
+      const u64 cb = lds_bits64(ct, x) & kmask_cut;
+      const u64 VM = __ballot(in_span && cb == 0 && ((nm[x >> 5] >> (x & 31)) & 1u) == 0);
       const u32 b = mn & bmask;   // destination = score mod B (B a power of two)
-      // runs of valid windows with one bucket
-      const u32 b_prev = lane_prev(b, 0u);
-      const u32 v_prev = lane_prev(valid ? 1u : 0u, 0u);
-      bool cont;
-      if (lane == 0) cont = valid && c_open && (c_b == b);
-      else cont = valid && v_prev && (b_prev == b);
-      const bool brk = valid && !cont;
-      const u64 BRK = __ballot(brk);
-      const u64 le = BRK & ((lane == 63) ? ~0ull : ((2ull << lane) - 1));
-      u32 pos;
-      if (le) pos = lane - (63u - (u32)__clzll(le));
-      else pos = c_pos + 1 + lane;
+      // Runs of valid k-mers with one bucket, as wave masks: lane l continues the run of
+      // lane l-1 (lane 0: of the run carried from the previous tile) if both are valid and
+      // their buckets agree.
+      const u32 b_prev = (u32)__builtin_amdgcn_update_dpp((int)c_b, (int)b, 0x138, 0xF, 0xF, false);
+      const u64 EQ = __ballot(b_prev == b);
+      const u64 CONT = VM & ((VM << 1) | (c_open ? 1ull : 0ull)) & EQ;
+      const u64 le = (VM & ~CONT) & lemask;      // run starts at or below this lane
+      const u32 pos = le ? lane - (63u - (u32)__clzll(le)) : c_pos + 1 + lane;
       const u32 pm = pos - div_small(pos, A.gmax_magic) * gmax;   // pos % gmax
-      const bool head = valid && (pm == 0);
-      const u32 nv = lane_next(valid ? 1u : 0u, 0u);
-      const u32 nh = lane_next(head ? 1u : 0u, 0u);
-      const bool close = valid && (lane < 63u) && (!nv || nh);
-      const bool cont0 = lane_read(cont ? 1u : 0u, 0) != 0;
-      const bool head0 = lane_read(head ? 1u : 0u, 0) != 0;
-      const bool carry_close = c_open && !(cont0 && !head0);
-      const u64 CL = __ballot(close);
+      const u64 HD = VM & __ballot(pm == 0);     // a record starts here (runs cut every gmax)
+      // a record ends at a valid lane whose successor in this tile is invalid or starts one
+      const u64 CL = VM & (~(VM >> 1) | (HD >> 1)) & ~(1ull << 63);
+      const bool carry_close = c_open && !((CONT & 1) && !(HD & 1));
       const u32 n_close = (u32)__popcll(CL) + (carry_close ? 1u : 0u);
       if (n_close) {
         u32 at = 0;
@@ -242,26 +277,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         const u64 base = slot0 + lane_read(at, 0);
         if (carry_close && lane == 0) {
           const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
-          write_record(A, base, c_p - cm, cm + 1, c_b);
+          write_record<RW>(A.rec, k, pk, base, c_p - cm + offp, cm + 1, c_b);
           atomicAdd(&h[c_b >> A.log_f], 1u);
         }
-        if (close) {
-          write_record(A, base + (carry_close ? 1 : 0) + mbcnt64(CL), p - pm, pm + 1, b);
+        if ((CL >> lane) & 1) {
+          write_record<RW>(A.rec, k, pk, base + (carry_close ? 1 : 0) + mbcnt64(CL), p - pm + offp, pm + 1, b);
           atomicAdd(&h[b >> A.log_f], 1u);
         }
       }
-      my_windows += (u64)__popcll(__ballot(valid));
-      // carry the window in the last lane
-      c_open = lane_read(valid ? 1u : 0u, 63) != 0;
+      my_windows += (u64)__popcll(VM);
+      // carry the run of the last lane
+      c_open = (VM >> 63) != 0;
       if (c_open) {
         c_b = lane_read(b, 63);
         c_pos = lane_read(pos, 63);
-        c_p = T0 + 63 - back;
+        c_p = t0 + 63 - back;
       }
     }
     if (c_open && lane == 0) {
       const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
-      write_record(A, slot0 + atomicAdd(&blk_n, 1u), c_p - cm, cm + 1, c_b);
+      write_record<RW>(A.rec, k, pk, slot0 + atomicAdd(&blk_n, 1u), c_p - cm + offp, cm + 1, c_b);
       atomicAdd(&h[c_b >> A.log_f], 1u);
     }
   }
