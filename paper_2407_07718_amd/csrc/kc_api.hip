@@ -331,6 +331,13 @@ inline dim3 grid_for(u64 n, u32 block, u32 max_blocks = 1u << 20) {
 
 // Queue one full count on `st`.
 constexpr u32 SEG_CAP_64 = 256 * 16, SEG_CAP_128 = 256 * 8;   // pairs sorted on chip per segment
+// Segments of at most seg_wave_cap pairs are sorted by one wave each (k_seg_wave); the
+// survivors' key ranges aim at half that so that most of them are.
+#ifndef KC_SEG_WAVE_CAP64
+#define KC_SEG_WAVE_CAP64 1024
+#endif
+template <typename K> constexpr u32 seg_wave_cap() { return sizeof(K) == 8 ? KC_SEG_WAVE_CAP64 : 512u; }
+template <typename K> constexpr u32 seg_range_target() { return seg_wave_cap<K>() / 2; }
 
 template <typename K>
 int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64 out_cap, const u64* seg,
@@ -338,8 +345,10 @@ int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64
              int* grid) {
   constexpr int IT = sizeof(K) == 8 ? 16 : 8;
   static_assert(256 * IT == (sizeof(K) == 8 ? SEG_CAP_64 : SEG_CAP_128), "segment capacity");
-  int per_cu = 0, rc;
+  int per_cu = 0, per_cu_w = 0, rc;
   if ((rc = blocks_per_cu(k_seg_sort<K, 256, IT>, 256, &per_cu))) return rc;
+  if ((rc = blocks_per_cu(k_seg_wave<K, seg_wave_cap<K>(), WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &per_cu_w)))
+    return rc;
   *grid = std::max(1, per_cu) * n_cu;
   SegArgs a;
   a.keys = keys;
@@ -355,6 +364,9 @@ int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64
   a.group_only = group_only ? 1 : 0;
   a.msd_n = msd_n;
   a.msd_target = msd_target;
+  a.wave_cap = seg_wave_cap<K>();
+  hipLaunchKernelGGL((k_seg_wave<K, seg_wave_cap<K>(), WAVES_PER_BLOCK>), dim3(std::max(1, per_cu_w) * n_cu),
+                     dim3(WAVES_PER_BLOCK * 64), 0, st, a);
   hipLaunchKernelGGL((k_seg_sort<K, 256, IT>), dim3(*grid), dim3(256), 0, st, a);
   return KC_OK;
 }
@@ -611,7 +623,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     ma.seg = seg;
     ma.n_seg = ctrl + C_NSEG;
     ma.nbits = 2 * P.k;
-    ma.target = (P.key_words == 1 ? SEG_CAP_64 : SEG_CAP_128) / 2;
+    ma.target = seg_range_target<K>();
     // blocks of the coarse pass: about 16K survivors each at most, up to MSD_NB
     ma.nb = (u32)std::min<u64>(MSD_NB, std::max<u64>(1, ceil_div(P.surv_cap, 16384)));
     hipLaunchKernelGGL((k_msd_hist<K>), dim3(ma.nb), dim3(256), 0, st, ma);
@@ -620,7 +632,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     hipLaunchKernelGGL((k_msd_fine<K>), dim3(256), dim3(1024), 0, st, ma);
   }
   if ((rc = seg_sort<K>(s1k, s1c, s0k, s0c, reinterpret_cast<K*>(d_kmers), d_counts, pair_cap, seg, ctrl + C_NSEG,
-                        2 * P.k, false, surv_nc, (P.key_words == 1 ? SEG_CAP_64 : SEG_CAP_128) / 2, n_cu, st,
+                        2 * P.k, false, surv_nc, seg_range_target<K>(), n_cu, st,
                         &seg_grid)))
     return rc;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags,
@@ -645,6 +657,9 @@ int warm_launch_facts() {
     return rc;
   if ((rc = blocks_per_cu(k_seg_sort<u64, 256, 16>, 256, &v))) return rc;
   if ((rc = blocks_per_cu(k_seg_sort<k128, 256, 8>, 256, &v))) return rc;
+  if ((rc = blocks_per_cu(k_seg_wave<u64, seg_wave_cap<u64>(), WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v))) return rc;
+  if ((rc = blocks_per_cu(k_seg_wave<k128, seg_wave_cap<k128>(), WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v)))
+    return rc;
   return KC_OK;
 }
 

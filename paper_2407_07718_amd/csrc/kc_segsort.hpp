@@ -42,12 +42,16 @@ struct MsdArgs {
   u32 target;              // keys per range wanted
 };
 
-__device__ __forceinline__ int msd_shift1(int nbits) { return nbits > 8 ? nbits - 8 : 0; }
+__host__ __device__ __forceinline__ int msd_shift1(int nbits) { return nbits > 8 ? nbits - 8 : 0; }
 __device__ __forceinline__ int msd_bits1(int nbits) { return nbits < 8 ? nbits : 8; }
-__device__ __forceinline__ int msd_g2(u64 n, int nbits, u32 target) {
+// Fine field width: the fewest bits that bring a range to about `target` keys, then
+// rounded up (within 8 and the key) until the bits left below the fields are a whole
+// number of 8-bit passes -- the extra bits cost no pass and make the ranges smaller.
+__host__ __device__ __forceinline__ int msd_g2(u64 n, int nbits, u32 target) {
   const int room = msd_shift1(nbits);
   int g2 = 0;
   while (g2 < 8 && g2 < room && (n >> (8 + g2)) > (u64)target) ++g2;
+  while (g2 < 8 && g2 < room && (room - g2) % 8 != 0) ++g2;
   return g2;
 }
 
@@ -65,7 +69,15 @@ struct SegArgs {
   int group_only;          // equal keys adjacent suffices (segments of a count's lists)
   const u64* msd_n;        // when set: segments are key ranges of k_msd_fine over *msd_n keys,
   u32 msd_target;          //   so only the bits below the range fields are sorted
+  u32 wave_cap;            // segments of at most this many pairs are left to k_seg_wave
 };
+
+// Passes of a segment sort: the bits to order are all 2k, or those below the key-range
+// fields when the segments are key ranges.  Grouping only (a count's lists): mixed keys,
+// early exit as in the bucket kernels.
+__device__ __forceinline__ int seg_sort_bits(const SegArgs& A) {
+  return A.msd_n ? msd_shift1(A.nbits) - msd_g2(*A.msd_n, A.nbits, A.msd_target) : A.nbits;
+}
 
 template <typename K, int T, int ITEMS>
 struct SegSmem {
@@ -86,10 +98,7 @@ __global__ __launch_bounds__(T) void k_seg_sort(SegArgs A) {
   __shared__ SM S;
   const u32 tid = threadIdx.x;
   const u64 n_seg = *A.n_seg_ptr;
-  // bits to order: all, or those below the key-range fields
-  const int sort_bits =
-      A.msd_n ? msd_shift1(A.nbits) - msd_g2(*A.msd_n, A.nbits, A.msd_target) : A.nbits;
-  const int np = (sort_bits + 7) / 8;
+  const int np = (seg_sort_bits(A) + 7) / 8;
   // grouping only: mixed keys, early exit as in the bucket kernels
   const bool mixed = A.group_only && A.nbits > 32;
   const int np_mixed = sort_passes<K>(A.nbits / 2);
@@ -98,7 +107,7 @@ __global__ __launch_bounds__(T) void k_seg_sort(SegArgs A) {
   K* out_k = reinterpret_cast<K*>(A.out_k);
   for (u64 sgi = blockIdx.x; sgi < n_seg; sgi += gridDim.x) {
     const u64 s0 = A.seg[sgi], s1 = A.seg[sgi + 1];
-    if (s1 <= s0) continue;                      // uniform over the block
+    if (s1 <= s0 || s1 - s0 <= A.wave_cap) continue;   // uniform over the block
     const u64 n = s1 - s0;
     __syncthreads();                             // LDS of the previous segment is free
     if (n <= CAP) {
@@ -184,6 +193,116 @@ __global__ __launch_bounds__(T) void k_seg_sort(SegArgs A) {
           out_k[s0 + i] = src_k[s0 + i];
           A.out_v[s0 + i] = src_v[s0 + i];
         }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- short segments
+// Segments of at most WCAP pairs are sorted by one wave each in its own slice of LDS, with
+// no block barriers (the waves of a block are independent), by the same stable LSD
+// passes as the block sort: each item ranked among the equal digits of its row
+// (lane-mask table + mbcnt), rows in order, then the digit counts turned into offsets by
+// one wave scan.
+template <typename K, int WCAP>
+struct SegWaveSmem {
+  K keys[WCAP];
+  u32 vals[WCAP];
+  u64 tbl[256];                     // lane masks per digit; all zero between uses
+  u32 cnt[256];                     // digit counts -> digit offsets; zero between passes
+};
+
+template <typename K, int WCAP>
+__device__ __forceinline__ void wave_sort_pairs(SegWaveSmem<K, WCAP>& S, u32 n_pad, int p_begin, int p_end) {
+  constexpr int ITEMS = WCAP / 64;
+  const u32 lane = lane_id();
+  const u64 ge = ~((1ull << lane) - 1ull);
+  const int per = (int)(n_pad / 64);
+  for (int p = p_begin; p < p_end; ++p) {
+    K kr[ITEMS];
+    u32 vr[ITEMS], rk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        kr[j] = S.keys[(u32)j * 64u + lane];
+        vr[j] = S.vals[(u32)j * 64u + lane];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 d = key_digit(kr[j], 8 * p);
+        const u64 mask = digit_peers_full(S.tbl, d, ge);
+        const u32 base = S.cnt[d];
+        const u32 lr = mbcnt64(mask);
+        if (lr == 0) {
+          S.cnt[d] = base + (u32)__popcll(mask);
+          S.tbl[d] = 0;
+        }
+        rk[j] = base + lr;
+      }
+    }
+    // counts -> exclusive digit offsets; lane l owns digits 4l..4l+3
+    const u32 c0 = S.cnt[4 * lane], c1 = S.cnt[4 * lane + 1], c2 = S.cnt[4 * lane + 2], c3 = S.cnt[4 * lane + 3];
+    const u32 s4 = c0 + c1 + c2 + c3;
+    const u32 ex = wave_scan_u32(s4) - s4;
+    S.cnt[4 * lane] = ex;
+    S.cnt[4 * lane + 1] = ex + c0;
+    S.cnt[4 * lane + 2] = ex + c0 + c1;
+    S.cnt[4 * lane + 3] = ex + c0 + c1 + c2;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 at = S.cnt[key_digit(kr[j], 8 * p)] + rk[j];
+        S.keys[at] = kr[j];
+        S.vals[at] = vr[j];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S.cnt[4 * lane + i] = 0;
+  }
+}
+
+// Waves take segments in turn (segment = global wave index, + all waves of the grid, ...);
+// a segment longer than WCAP is left to k_seg_sort.
+template <typename K, int WCAP, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_seg_wave(SegArgs A) {
+  __shared__ SegWaveSmem<K, WCAP> WS[WPB];
+  const u32 lane = lane_id(), wave = threadIdx.x >> 6;
+  SegWaveSmem<K, WCAP>& S = WS[wave];
+  for (u32 i = lane; i < 256; i += 64) {
+    S.tbl[i] = 0;
+    S.cnt[i] = 0;
+  }
+  const u64 n_seg = *A.n_seg_ptr;
+  const int np = (seg_sort_bits(A) + 7) / 8;
+  const bool mixed = A.group_only && A.nbits > 32;
+  const int np_mixed = sort_passes<K>(A.nbits / 2);
+  const K* in_k = reinterpret_cast<const K*>(A.keys);
+  K* out_k = reinterpret_cast<K*>(A.out_k);
+  for (u64 sgi = (u64)blockIdx.x * WPB + wave; sgi < n_seg; sgi += (u64)gridDim.x * WPB) {
+    const u64 s0 = A.seg[sgi], s1 = A.seg[sgi + 1];
+    if (s1 <= s0 || s1 - s0 > WCAP) continue;    // uniform over the wave
+    const u32 m = (u32)(s1 - s0), m_pad = (m + 63u) & ~63u;
+    for (u32 i = lane; i < m_pad; i += 64) {
+      K key = key_pad<K>();
+      if (i < m) key = mixed ? mix_key(in_k[s0 + i]) : in_k[s0 + i];
+      S.keys[i] = key;
+      S.vals[i] = i < m ? A.vals[s0 + i] : 0u;
+    }
+    if (mixed) {
+      const int p0 = first_passes(m);
+      wave_sort_pairs<K, WCAP>(S, m_pad, 0, p0);
+      bool bad = false;
+      for (u32 i = lane; i < m; i += 64) bad |= mixed_pair(S.keys, i, m, 8 * p0);
+      if (__ballot(bad)) wave_sort_pairs<K, WCAP>(S, m_pad, p0, np_mixed);
+    } else {
+      wave_sort_pairs<K, WCAP>(S, m_pad, 0, np);
+    }
+    for (u32 i = lane; i < m; i += 64) {
+      if (s0 + i < A.out_cap) {
+        out_k[s0 + i] = mixed ? unmix_key(S.keys[i]) : S.keys[i];
+        A.out_v[s0 + i] = S.vals[i];
       }
     }
   }
