@@ -688,21 +688,86 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
 // ---------------------------------------------------------------------------- large buckets
 // Expand the records of every large bucket into one HBM key array.  Equal k-mers share
 // a bucket, so sorting that array as a whole still groups each k-mer's copies.
+// Key-parallel: after the block scan of record sizes, each wave writes the keys
+// of its 64 records as consecutive 64-key rows.  The wave's records and their offsets go
+// to its LDS slice with a map from output position to record; each lane then takes one
+// output position and computes that k-mer directly from its record's bases (funnel
+// shifts, a 2-bit reversal, the smaller of the two strands), so the stores are coalesced
+// and no lane waits for a longer record of its wave.  RW = record words (4: k <= 31,
+// u64 keys; 8: k >= 32, 128-bit keys).
+__device__ __forceinline__ u64 rec_bits64(const u32* p, u32 q) {   // 64 bits from bit q of p
+  const u32 w = q >> 5, sh = q & 31;
+  return ((u64)__builtin_amdgcn_alignbit(p[w + 2], p[w + 1], sh) << 32) | __builtin_amdgcn_alignbit(p[w + 1], p[w], sh);
+}
+template <typename K> __device__ __forceinline__ K canon_at(const u32* rec, u32 q, int k);
+template <> __device__ __forceinline__ u64 canon_at<u64>(const u32* rec, u32 q, int k) {
+  const u64 kmask = (1ull << (2 * k)) - 1;
+  const u64 V = rec_bits64(rec, q) & kmask;
+  const u64 F = rev2_64(V) >> (64 - 2 * k);
+  const u64 RC = ~V & kmask;
+  return F < RC ? F : RC;
+}
+template <> __device__ __forceinline__ k128 canon_at<k128>(const u32* rec, u32 q, int k) {
+  const int hb = 2 * k - 64;                      // bits in the high word, 0..62
+  const u64 mhi = hb ? ((1ull << hb) - 1) : 0ull;
+  const u64 vlo = rec_bits64(rec, q), vhi = rec_bits64(rec, q + 64) & mhi;
+  const u64 rlo = rev2_64(vhi), rhi = rev2_64(vlo);
+  const int s = 128 - 2 * k;                      // 2..64
+  k128 F, RC;
+  if (s == 64) { F.lo = rhi; F.hi = 0; }
+  else { F.lo = (rlo >> s) | (rhi << (64 - s)); F.hi = rhi >> s; }
+  RC.lo = ~vlo;
+  RC.hi = ~vhi & mhi;
+  return key_lt(F, RC) ? F : RC;
+}
+
 template <typename K, int T>
 __global__ __launch_bounds__(T) void k_expand_large(CountArgs A, K* __restrict__ lkeys) {
+  constexpr int W = T / 64, RW = sizeof(K) == 8 ? 4 : 8;
   __shared__ u64 scr[17];
+  __shared__ u32 s_rec[W][64 * RW + 4];  // the wave's records (+ words read past the last one)
+  __shared__ u16 s_ex[W][64];            // each record's first key, relative to the wave's first
+  __shared__ u8 s_rid[W][64 * 64];       // record of each output position (g <= 64)
   const u64 n_large = A.meta[1];
-  const u32 tid = threadIdx.x;
+  const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const int k = A.k;
+  u32* const rec_w = s_rec[wave];
+  u16* const ex_w = s_ex[wave];
+  u8* const rid_w = s_rid[wave];
+  if (lane < 4) rec_w[64 * RW + lane] = 0;
   for (u64 item = blockIdx.x; item < n_large; item += gridDim.x) {
     const u32 b = A.large_list[item];
     const u32 r0 = A.rec_off[b], nr = A.rec_off[b + 1] - r0;
     u64 base = A.large_koff[b];
     for (u32 c0 = 0; c0 < nr; c0 += T) {
       const u32 r = c0 + tid;
-      const u32 g = r < nr ? record_g(A.rec, (u64)r0 + r, A.rec_words) : 0u;
+      uint4 v[RW / 4];
+#pragma unroll
+      for (int i = 0; i < RW / 4; ++i)
+        v[i] = r < nr ? reinterpret_cast<const uint4*>(A.rec)[((u64)r0 + r) * (RW / 4) + i] : make_uint4(0u, 0u, 0u, 0u);
+      const u32 g = r < nr ? (v[RW / 4 - 1].w >> 26) + 1u : 0u;
       u64 tot;
       const u64 ex = block_exclusive_scan<u64>((u64)g, scr, &tot);
-      if (g) expand_record(A.rec, (u64)r0 + r, A.k, lkeys + base + ex, g);
+      // the wave's keys are [wb, wb + G) of this round's keys
+      const u64 wb = ((u64)lane_read((u32)(ex >> 32), 0) << 32) | lane_read((u32)ex, 0);
+      const u32 rel = (u32)(ex - wb);
+      const u32 G = lane_read(rel + g, 63);
+#pragma unroll
+      for (int i = 0; i < RW / 4; ++i) {
+        rec_w[RW * lane + 4 * i] = v[i].x;
+        rec_w[RW * lane + 4 * i + 1] = v[i].y;
+        rec_w[RW * lane + 4 * i + 2] = v[i].z;
+        rec_w[RW * lane + 4 * i + 3] = v[i].w;
+      }
+      ex_w[lane] = (u16)rel;
+      for (u32 t = 0; t < g; ++t) rid_w[rel + t] = (u8)lane;
+      for (u32 o0 = 0; o0 < G; o0 += 64) {
+        const u32 o = o0 + lane;
+        if (o < G) {
+          const u32 rr = rid_w[o];
+          lkeys[base + wb + o] = canon_at<K>(rec_w + RW * rr, 2u * (o - ex_w[rr]), k);
+        }
+      }
       base += tot;
     }
   }
