@@ -154,21 +154,24 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->log_c = std::min(9, p->log_b);
   p->log_f = p->log_b - p->log_c;
   p->rec_cap = std::max<u64>(1, n_max);
-  // each wave span of the extract stage covers `span` k-mer positions (16 tiles of 64);
-  // extract block b covers spans [b*spb, (b+1)*spb) and owns spb*span record slots
-  p->span = EX_SPAN_MAX - (u32)(k - m);   // 16 tiles of 64 m-mer positions per span
+  // each wave span of the extract stage covers `span` k-mer positions, 64 * tiles - (w - 1):
+  // 16 tiles of 64 m-mer positions, or fewer (at least 4) for small inputs so that there
+  // are still about 8192 spans to spread over the waves; extract block b covers spans
+  // [b*spb, (b+1)*spb), at least one per wave, and owns spb*span record slots
+  const u64 tiles = std::min<u64>(EX_SPAN_MAX / 64, std::max<u64>(4, ceil_div(std::max<u64>(R, 1), 64ull * 8192)));
+  p->span = (u32)(tiles * 64) - (u32)(k - m);
   p->n_span_cap = (std::max<u64>(R, 1) + p->span - 1) / p->span;
   // at most 4096 extract blocks: about two rounds of the 2048 blocks of 256 threads the
   // chip holds at eight waves per SIMD (more blocks enlarge the partition's histogram)
-  p->part_spb = (u32)std::max<u64>(1, ceil_div(p->n_span_cap, 4096));
+  p->part_spb = (u32)std::max<u64>(4, ceil_div(p->n_span_cap, 4096));
   p->part_nblk = (u32)ceil_div(p->n_span_cap, p->part_spb);
   // The workspace may not depend on m (its size query has no m), so the extract regions
-  // take bounds over every m for this k: spans are at least 1024 - (k - 1) positions, so
-  // there are at most nsc_max of them; blocks number at most min(4096, nsc_max); and
+  // take bounds over every m for this k: spans are at least 64 * tiles - (k - 1) positions,
+  // so there are at most nsc_max of them; blocks number at most min(4096, nsc_max); and
   // nblk * spb * span < (n_span_cap + spb) * span <= R + 1024 * (1 + spb_max).
   {
-    const u64 nsc_max = ceil_div(std::max<u64>(R, 1), EX_SPAN_MAX - (u64)(k - 1));
-    const u64 spb_max = std::max<u64>(1, ceil_div(nsc_max, 4096));
+    const u64 nsc_max = ceil_div(std::max<u64>(R, 1), tiles * 64 - (u64)(k - 1));
+    const u64 spb_max = std::max<u64>(4, ceil_div(nsc_max, 4096));
     p->nblk_cap = (u32)std::min<u64>(4096, nsc_max);
     p->slots = std::max<u64>(R, 1) + (u64)EX_SPAN_MAX * (1 + spb_max);
   }
@@ -337,10 +340,11 @@ constexpr u32 SEG_CAP_64 = 256 * 16, SEG_CAP_128 = 256 * 8;   // pairs sorted on
 template <typename K> constexpr u32 seg_wave_cap() { return sizeof(K) == 8 ? 1024u : 512u; }
 template <typename K> constexpr u32 seg_range_target() { return seg_wave_cap<K>() / 2; }
 
+// max_seg: a host-side bound on the number of segments (the grids need no more blocks).
 template <typename K>
 int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64 out_cap, const u64* seg,
-             const u64* n_seg, int nbits, bool group_only, const u64* msd_n, u32 msd_target, int n_cu, hipStream_t st,
-             int* grid) {
+             const u64* n_seg, u64 max_seg, int nbits, bool group_only, const u64* msd_n, u32 msd_target, int n_cu,
+             hipStream_t st, int* grid) {
   constexpr int IT = sizeof(K) == 8 ? 16 : 8;
   static_assert(256 * IT == (sizeof(K) == 8 ? SEG_CAP_64 : SEG_CAP_128), "segment capacity");
   int per_cu = 0, per_cu_w = 0, rc;
@@ -348,7 +352,9 @@ int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64
   if ((rc = blocks_per_cu(k_seg_wave<K, seg_wave_cap<K>(), SEG_WAVES_PER_BLOCK>, SEG_WAVES_PER_BLOCK * 64,
                           &per_cu_w)))
     return rc;
-  *grid = std::max(1, per_cu) * n_cu;
+  *grid = (int)std::min<u64>((u64)std::max(1, per_cu) * n_cu, std::max<u64>(1, max_seg));
+  const int grid_w = (int)std::min<u64>((u64)std::max(1, per_cu_w) * n_cu,
+                                        std::max<u64>(1, ceil_div(max_seg, SEG_WAVES_PER_BLOCK)));
   SegArgs a;
   a.keys = keys;
   a.vals = vals;
@@ -364,7 +370,7 @@ int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64
   a.msd_n = msd_n;
   a.msd_target = msd_target;
   a.wave_cap = seg_wave_cap<K>();
-  hipLaunchKernelGGL((k_seg_wave<K, seg_wave_cap<K>(), SEG_WAVES_PER_BLOCK>), dim3(std::max(1, per_cu_w) * n_cu),
+  hipLaunchKernelGGL((k_seg_wave<K, seg_wave_cap<K>(), SEG_WAVES_PER_BLOCK>), dim3(grid_w),
                      dim3(SEG_WAVES_PER_BLOCK * 64), 0, st, a);
   hipLaunchKernelGGL((k_seg_sort<K, 256, IT>), dim3(*grid), dim3(256), 0, st, a);
   return KC_OK;
@@ -477,7 +483,6 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ea.hist = at<u32>(ws, P.o_phist);
   ea.log_f = P.log_f;
   ea.C = 1u << P.log_c;
-  ea.counters = counters;
   ea.n_span_cap = P.n_span_cap;
   ea.n_packed = P.n_packed;
   ea.n_mask = P.n_mask;
@@ -502,7 +507,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     pp.bcnt = bcnt;
     pp.n_rec_ptr = counters;
     const u64 nh = ((u64)1 << P.log_c) * P.part_nblk;
-    scan_u32(ea.hist, ea.hist, (const u64*)nullptr, nh, (u64*)nullptr, scanbuf, st);
+    scan_u32(ea.hist, ea.hist, (const u64*)nullptr, nh, counters, scanbuf, st);   // counters[0] = records
     if (P.rec_words == 4)
       hipLaunchKernelGGL(k_part_scatter<4>, dim3(P.part_nblk), dim3(512), 0, st, pp);
     else
@@ -585,8 +590,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   hipLaunchKernelGGL(k_merge_segs, grid_for(P.B + 1, 256, 1024), dim3(256), 0, st, kloff, at<u32>(ws, P.o_lch0), meta + 1,
                      meta + 4, P.chunk_cap, kl_nc, seg);
   int seg_grid = 0;
-  if ((rc = seg_sort<K>(kl0k, kl0c, kl1k, kl1c, kl0k, kl0c, ~0ull, seg, meta + 1, 2 * P.k, true, nullptr, 0, n_cu,
-                        st, &seg_grid)))
+  if ((rc = seg_sort<K>(kl0k, kl0c, kl1k, kl1c, kl0k, kl0c, ~0ull, seg, meta + 1, std::min<u64>(P.B, P.chunk_cap),
+                        2 * P.k, true, nullptr, 0, n_cu, st, &seg_grid)))
     return rc;
   K* lks = kl0k;
   u32* lvs = kl0c;
@@ -630,9 +635,10 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     hipLaunchKernelGGL((k_msd_scatter<K>), dim3(ma.nb), dim3(512), 0, st, ma);
     hipLaunchKernelGGL((k_msd_fine<K>), dim3(256), dim3(1024), 0, st, ma);
   }
+  // the key ranges number 256 << g2, g2 growing with the survivor count (at most surv_cap)
+  const u64 max_ranges = 256ull << msd_g2(P.surv_cap, 2 * P.k, seg_range_target<K>());
   if ((rc = seg_sort<K>(s1k, s1c, s0k, s0c, reinterpret_cast<K*>(d_kmers), d_counts, pair_cap, seg, ctrl + C_NSEG,
-                        2 * P.k, false, surv_nc, seg_range_target<K>(), n_cu, st,
-                        &seg_grid)))
+                        max_ranges, 2 * P.k, false, surv_nc, seg_range_target<K>(), n_cu, st, &seg_grid)))
     return rc;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags,
                      meta, kl_n, P.B);

@@ -900,7 +900,7 @@ __global__ __launch_bounds__(256) void k_copy_pairs(const K* __restrict__ sk, co
 __global__ void k_finalize(DevTotals* tot, const u64* counters, const u64* surv_n, u64 rec_cap, u64 surv_cap,
                            const u32* flags, const u64* meta, const u64* kl_n, u32 B) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  tot->n_windows = counters[1];
+  tot->n_windows = meta[2] + meta[6] + meta[7];   // every valid window is in one record
   tot->n_records = counters[0];
   tot->n_pairs = *surv_n;
   u64 f = *flags & 1u;

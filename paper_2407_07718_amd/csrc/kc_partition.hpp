@@ -81,7 +81,6 @@ struct ExtractArgs {
   u32* hist;           // [C][nblk] records per coarse bucket group and block
   int log_f;           // coarse group = bucket >> log_f
   u32 C;               // coarse groups
-  u64* counters;       // [0] records written, [1] valid windows
   u64 n_span_cap;      // spans the record region holds
   u64 n_packed, n_mask;   // words in `packed` and in `nmask` / `starts`
 };
@@ -183,7 +182,9 @@ __device__ __forceinline__ u32 window_min_carry(u32 v, int nst, u32 rest, const 
 // works on span-relative 32-bit positions.
 // Block b covers spans [b*spb, (b+1)*spb), its four waves taking them in turn; its records
 // go densely to the block's slot range through an LDS counter, and an LDS histogram of
-// their coarse bucket groups feeds the partition.  RW = record words (4 or 8).
+// their coarse bucket groups feeds the partition (its scan also gives the record total;
+// the kernel touches no global counter, whose same-address atomics would serialize at
+// the end of short launches).  RW = record words (4 or 8).
 template <int RW>
 __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
   __shared__ u32 h[512];
@@ -214,7 +215,6 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
   const u64 kmask1 = (1ull << k) - 1;            // bases [p, p + k) of a k-mer at p
   const u64 kmask_cut = kmask1 & ~1ull;          // no read may start inside (p, p + k)
   const u32 bmask = (1u << A.log_b) - 1u;
-  u64 my_windows = 0;
 
   const u64 n_sp = min(n_spans, A.n_span_cap);
   const u64 s_end = min(n_sp, (u64)(blockIdx.x + 1) * A.spb);
@@ -285,7 +285,6 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
           atomicAdd(&h[b >> A.log_f], 1u);
         }
       }
-      my_windows += (u64)__popcll(VM);
       // carry the run of the last lane
       c_open = (VM >> 63) != 0;
       if (c_open) {
@@ -300,13 +299,9 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
       atomicAdd(&h[c_b >> A.log_f], 1u);
     }
   }
-  if (lane == 0 && my_windows) atomicAdd((unsigned long long*)&A.counters[1], (unsigned long long)my_windows);
   __syncthreads();
   for (u32 i = threadIdx.x; i < A.C; i += blockDim.x) A.hist[(u64)i * gridDim.x + blockIdx.x] = h[i];
-  if (threadIdx.x == 0) {
-    A.blk_cnt[blockIdx.x] = blk_n;
-    if (blk_n) atomicAdd((unsigned long long*)&A.counters[0], (unsigned long long)blk_n);
-  }
+  if (threadIdx.x == 0) A.blk_cnt[blockIdx.x] = blk_n;
 }
 
 // ---------------------------------------------------------------------------- bucket plan

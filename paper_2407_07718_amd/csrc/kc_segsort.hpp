@@ -46,13 +46,15 @@ __host__ __device__ __forceinline__ int msd_shift1(int nbits) { return nbits > 8
 __device__ __forceinline__ int msd_bits1(int nbits) { return nbits < 8 ? nbits : 8; }
 // Fine field width: the fewest bits that bring a range to about `target` keys, then
 // rounded up (within 8 and the key) until the bits left below the fields are a whole
-// number of 8-bit passes -- the extra bits cost no pass and make the ranges smaller.
+// number of 8-bit passes -- the extra bits save a pass -- unless that would leave ranges
+// of under target / 8 keys on average (then the per-range costs outweigh the pass).
 __host__ __device__ __forceinline__ int msd_g2(u64 n, int nbits, u32 target) {
   const int room = msd_shift1(nbits);
   int g2 = 0;
   while (g2 < 8 && g2 < room && (n >> (8 + g2)) > (u64)target) ++g2;
-  while (g2 < 8 && g2 < room && (room - g2) % 8 != 0) ++g2;
-  return g2;
+  int up = g2;
+  while (up < 8 && up < room && (room - up) % 8 != 0) ++up;
+  return (n >> (8 + up)) >= (u64)(target / 8) ? up : g2;
 }
 
 struct SegArgs {

@@ -63,6 +63,17 @@ def test_paths_and_bucket_counts(cfg, k):
     check(reads, offsets, k, 17, 2, 100, 1024, cfg=kc.make_config(**cfg), label=f"{cfg}")
 
 
+@pytest.mark.parametrize("k", [2, 5, 9, 14, 20, 26, 30, 32, 37, 45, 58, 63])
+def test_large_bucket_expansion_all_k(k):
+    """Every bucket expanded into HBM as a large one: small k gives records of up to
+    51 (k <= 31) or 64 (k >= 32) k-mers, whose last k-mers sit at the end of the record."""
+    rng = np.random.Generator(np.random.PCG64(1300 + k))
+    reads, offsets = _genome_reads(1300 + k, 300, 0, 500, genome=6000, p_n=0.001)
+    m = int(rng.integers(1, min(k - 1, 32) + 1)) if k > 2 else 1
+    cfg = _kc().make_config(force_hbm=True)
+    check(reads, offsets, k, m, 1, 1000, 300, cfg=cfg, label=f"all large k{k} m{m}")
+
+
 def _shared_low_bits_reads(seed, k, n_distinct, copies):
     """Reads of exactly k bases 'A' + random + a fixed 12-base tail ending in 'A': the
     forward value is canonical (first base A < T, the complement of the last), so every
