@@ -893,13 +893,12 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   wa.range = rb;
   wa.cap = P.cap;
   const dim3 gw((u32)P.n_tiles), gc((u32)P.n_tiles_cap);
+  int n_cu = 0;
+  if (int rc0 = device_info(&n_cu)) return rc0;
   stage_mark(1, st);
   if (rounds) {
     // key ranges of the rounds from the windows per key prefix
     fill(bins, EXT_NBINS, 0u);
-    int n_cu = 0;
-    int rc0 = device_info(&n_cu);
-    if (rc0) return rc0;
     hipLaunchKernelGGL((k_ext_prefix_hist<K>), dim3((u32)std::min<u64>(P.n_tiles, 4ull * n_cu)), dim3(EXT_T), 0, st, wa,
                        bins);
     hipLaunchKernelGGL(k_ext_plan_rounds, dim3(1), dim3(1024), 0, st, bins, P.cap, P.rounds, rb, flags);
@@ -933,6 +932,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   ra.occ_cap = occ_cap;
   ra.blk_heads = blk;
   ra.rbits = wa.rbits;
+  ra.n_tiles = P.n_tiles_cap;
   ra.max_len = ctrl + X_MAXLEN;
   ra.pair_base = ctrl + X_PBASE;
   ra.occ_base = ctrl + X_OBASE;
@@ -959,14 +959,15 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
     ra.vals = sv;
     ra.odst = odst;
     ra.hbits = hbits;
-    hipLaunchKernelGGL((k_ext_runs<K, false>), gc, dim3(EXT_T), 0, st, ra);
+    hipLaunchKernelGGL((k_ext_runs<K, false>), dim3((u32)std::min<u64>(P.n_tiles_cap, 4ull * n_cu)), dim3(EXT_T), 0,
+                       st, ra);
     scan_u32(bp, bp, (const u64*)nullptr, P.n_tiles_cap, ctrl + X_NPAIRS, scanbuf, st);
     scan_u32(bo, bo, (const u64*)nullptr, P.n_tiles_cap, ctrl + X_NOCC, scanbuf, st);
     if (!rounds) stage_mark(4, st);
     hipLaunchKernelGGL((k_ext_runs<K, true>), gc, dim3(EXT_T), 0, st, ra);
     hipLaunchKernelGGL((k_ext_occ<K>), gc, dim3(EXT_T), 0, st, ra);
     hipLaunchKernelGGL(k_ext_round_end, dim3(1), dim3(64), 0, st, ctrl + X_NPAIRS, ctrl + X_NOCC, ctrl + X_PBASE,
-                       ctrl + X_OBASE, ctrl + X_NWIN, ctrl + X_WTOT, P.cap, flags);
+                       ctrl + X_OBASE, ctrl + X_NWIN, ctrl + X_WTOT, P.cap, flags, ctrl + X_NRUNS, d_tot);
   }
   if (rounds) {
     stage_mark(3, st);

@@ -187,7 +187,9 @@ __device__ __forceinline__ void flush_stats(const RunSink& S, u64 ndist) {
     if (v) atomicAdd((unsigned long long*)&S.hist[i], (unsigned long long)v);
   }
   if (threadIdx.x == 0) {
-    atomicMax((unsigned long long*)&S.tot->max_count, (unsigned long long)*S.lmax);
+    // (each guard keeps empty blocks off these shared addresses: same-address atomics
+    // serialize, and many blocks of a persistent grid finish together)
+    if (*S.lmax) atomicMax((unsigned long long*)&S.tot->max_count, (unsigned long long)*S.lmax);
     if (*S.lover) atomicAdd((unsigned long long*)&S.tot->overflow_sum, *S.lover);
     if (ndist) atomicAdd((unsigned long long*)&S.tot->n_distinct, (unsigned long long)ndist);
   }

@@ -275,6 +275,7 @@ struct ExtRunArgs {
   const u64* max_len;
   const u64* pair_base;    // pairs and occurrences of earlier rounds
   const u64* occ_base;
+  u64 n_tiles;             // tiles of EXT_TILE sorted positions (blk_pairs / blk_occ entries)
 };
 
 // Run r of the sorted array: [hp[r], hp[r+1]) (the last run ends at n).
@@ -285,10 +286,12 @@ __device__ __forceinline__ void ext_run(const ExtRunArgs& A, u64 r, u64 nruns, u
   *c = (u32)(b - a);
 }
 
-// Pass 1 (WRITE = false): histogram, extremes and distinct count of every run, and per
-// block the reported runs and their summed counts.  Pass 2: reported runs written as
-// (k-mer, count, first occurrence) from the block's scanned offsets, with their
-// occurrences decoded into (read, position).
+// Pass 1 (WRITE = false): histogram and extremes of every run, and per tile of EXT_TILE
+// runs the reported runs and their summed counts; its blocks take tiles in turn and
+// flush their statistics once.  Pass 2 (one block per tile): reported runs written as
+// (k-mer, count, first occurrence) from the tile's scanned offsets, with their
+// occurrences decoded into (read, position).  (The distinct count is the run total,
+// added once per round.)
 template <typename K, bool WRITE>
 __global__ __launch_bounds__(EXT_T) void k_ext_runs(ExtRunArgs A) {
   __shared__ u32 hist_s[256];
@@ -297,7 +300,6 @@ __global__ __launch_bounds__(EXT_T) void k_ext_runs(ExtRunArgs A) {
   __shared__ u32 wp[EXT_T / 64], wo[EXT_T / 64];
   const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const u64 nruns = *A.nruns_ptr, n = *A.n_ptr;
-  const u64 e0 = (u64)blockIdx.x * EXT_TILE + (u64)wave * EXT_WAVE;
   if (!WRITE) {
     for (u32 i = tid; i < 256; i += EXT_T) hist_s[i] = 0;
     if (tid == 0) {
@@ -305,44 +307,57 @@ __global__ __launch_bounds__(EXT_T) void k_ext_runs(ExtRunArgs A) {
       lover = 0;
     }
     __syncthreads();
+    RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax, &lover};
+    for (u64 t = blockIdx.x; t < A.n_tiles; t += gridDim.x) {
+      const u64 e0 = t * EXT_TILE + (u64)wave * EXT_WAVE;
+      u32 np = 0, osum = 0;
+      for (int j = 0; j < (int)EXT_PER; ++j) {
+        const u64 r = e0 + (u64)j * 64 + lane;
+        const bool act = r < nruns;
+        u32 s = 0, c = 0;
+        if (act) ext_run(A, r, nruns, n, &s, &c);
+        const bool emit = act && c >= A.min_freq && c <= A.max_freq;
+        run_stats_lanes(sink, c, act);
+        np += (u32)__popcll(__ballot(emit));
+        osum += emit ? c : 0u;
+      }
+      // wave totals: lanes' sums reduced through the DPP scan, read from lane 63
+      const u32 otot = lane_read(wave_scan_u32(osum), 63);
+      if (lane == 0) {
+        wp[wave] = np;
+        wo[wave] = otot;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        u32 a = 0, b = 0;
+        for (u32 w = 0; w < EXT_T / 64; ++w) {
+          a += wp[w];
+          b += wo[w];
+        }
+        A.blk_pairs[t] = a;
+        A.blk_occ[t] = b;
+      }
+      __syncthreads();   // wp / wo are reused by the next tile
+    }
+    flush_stats(sink, 0);
+    return;
   }
-  RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax, &lover};
+  const u64 e0 = (u64)blockIdx.x * EXT_TILE + (u64)wave * EXT_WAVE;
   u32 np = 0, osum = 0;
   for (int j = 0; j < (int)EXT_PER; ++j) {
     const u64 r = e0 + (u64)j * 64 + lane;
-    const bool act = r < nruns;
     u32 s = 0, c = 0;
-    if (act) ext_run(A, r, nruns, n, &s, &c);
-    const bool emit = act && c >= A.min_freq && c <= A.max_freq;
-    if (!WRITE) run_stats_lanes(sink, c, act);
+    if (r < nruns) ext_run(A, r, nruns, n, &s, &c);
+    const bool emit = r < nruns && c >= A.min_freq && c <= A.max_freq;
     np += (u32)__popcll(__ballot(emit));
     osum += emit ? c : 0u;
   }
-  // wave totals: lanes' sums reduced through the DPP scan, read from lane 63
   const u32 otot = lane_read(wave_scan_u32(osum), 63);
   if (lane == 0) {
     wp[wave] = np;
     wo[wave] = otot;
   }
   __syncthreads();
-  if (!WRITE) {
-    if (tid == 0) {
-      u32 a = 0, b = 0;
-      for (u32 w = 0; w < EXT_T / 64; ++w) {
-        a += wp[w];
-        b += wo[w];
-      }
-      A.blk_pairs[blockIdx.x] = a;
-      A.blk_occ[blockIdx.x] = b;
-    }
-    flush_stats(sink, 0);
-    if (tid == 0) {
-      const u64 b0 = (u64)blockIdx.x * EXT_TILE;
-      const u64 d = nruns > b0 ? min((u64)EXT_TILE, nruns - b0) : 0ull;
-      if (d) atomicAdd((unsigned long long*)&A.tot->n_distinct, (unsigned long long)d);
-    }
-    return;
-  }
   u64 pbase = *A.pair_base + A.blk_pairs[blockIdx.x], obase = *A.occ_base + A.blk_occ[blockIdx.x];
   for (u32 w = 0; w < wave; ++w) {
     pbase += wp[w];
@@ -496,8 +511,9 @@ __global__ __launch_bounds__(1024) void k_ext_plan_rounds(const u32* __restrict_
 // After a round: its pairs, occurrences and windows are added to the running totals;
 // flag bit 3 when the round held more windows than fit.
 __global__ void k_ext_round_end(u64* ctrl_pairs, u64* ctrl_occ, u64* pair_base, u64* occ_base, const u64* n_win,
-                                u64* win_total, u64 cap, u32* flags) {
+                                u64* win_total, u64 cap, u32* flags, const u64* nruns, DevTotals* tot) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  tot->n_distinct += *nruns;
   *pair_base += *ctrl_pairs;
   *occ_base += *ctrl_occ;
   *win_total += *n_win;
