@@ -892,6 +892,8 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   wa.max_len = ctrl + X_MAXLEN;
   wa.range = rb;
   wa.cap = P.cap;
+  wa.n_packed = P.n_packed;
+  wa.n_mask = P.n_mask;
   const dim3 gw((u32)P.n_tiles), gc((u32)P.n_tiles_cap);
   int n_cu = 0;
   if (int rc0 = device_info(&n_cu)) return rc0;

@@ -137,28 +137,85 @@ struct ExtWinArgs {
   const u64* max_len;   // longest read
   const u32* range;  // this round's key prefixes [range[0], range[1])
   u64 cap;           // windows a round can hold; writes beyond it are dropped (and flagged)
+  u64 n_packed, n_mask;   // words in packed and in nmask / starts
 };
+
+// A wave's positions [e0, e0 + EXT_WAVE) read bases [e0, e0 + 1023 + 95] (the second
+// 64-bit view of a 128-bit key starts 32 bases on) and mask bits [e0, e0 + 1023 + 63]:
+// at most 69 words from word e0 / 16 and 36 from word e0 / 32, staged per wave in LDS.
+constexpr u32 EXT_PK = 128, EXT_MK = 64;
+static_assert(EXT_WAVE == 1024, "staging sized for 1024 positions per wave");
+
+// Canonical value of the k bases at q of the staged packed words (see ext_canon).
+__device__ __forceinline__ void ext_canon_lds(const u32* pk, u32 q, int k, u64* out) {
+  const u64 mask = (1ull << (2 * k)) - 1;
+  const u64 V = lds_bases64(pk, q) & mask;
+  const u64 F = rev2_64(V) >> (64 - 2 * k);
+  const u64 RC = ~V & mask;
+  *out = F < RC ? F : RC;
+}
+__device__ __forceinline__ void ext_canon_lds(const u32* pk, u32 q, int k, k128* out) {
+  const int hb = 2 * k - 64;
+  const u64 mhi = hb ? ((1ull << hb) - 1) : 0ull;
+  const u64 vlo = lds_bases64(pk, q), vhi = lds_bases64(pk, q + 32) & mhi;
+  const u64 rlo = rev2_64(vhi), rhi = rev2_64(vlo);
+  const int s = 128 - 2 * k;
+  k128 F, RC;
+  if (s == 64) {
+    F.lo = rhi;
+    F.hi = 0;
+  } else {
+    F.lo = (rlo >> s) | (rhi << (64 - s));
+    F.hi = rhi >> s;
+  }
+  RC.lo = ~vlo;
+  RC.hi = ~vhi & mhi;
+  *out = key_lt(F, RC) ? F : RC;
+}
 
 // Pass 1 (WRITE = false): valid windows per block.  Pass 2: the same windows written
 // densely in position order to keys/vals from the block's scanned offset.
 template <typename K, bool WRITE>
 __global__ __launch_bounds__(EXT_T) void k_ext_windows(ExtWinArgs A) {
   __shared__ u32 wtot[EXT_T / 64];
+  __shared__ u32 s_pk[EXT_T / 64][EXT_PK], s_nm[EXT_T / 64][EXT_MK], s_ct[EXT_T / 64][EXT_MK];
   const u32 lane = lane_id(), wave = threadIdx.x >> 6;
   const u64 e0 = (u64)blockIdx.x * EXT_TILE + (u64)wave * EXT_WAVE;
   const u64 lo = A.n_reads ? min(A.offsets[0], A.R) : 0;
   const u64 hi = A.n_reads ? min(A.offsets[A.n_reads], A.R) : 0;
   const u32 r0 = A.range[0], r1 = A.range[1];
   const bool all = r0 == 0 && r1 >= EXT_NBINS;
+  // the wave's words of packed bases, non-base mask and cut mask (non-base or read start)
+  u32* const pk = s_pk[wave];
+  u32* const nm = s_nm[wave];
+  u32* const ct = s_ct[wave];
+  const u32 offp = (u32)(e0 & 15), offm = (u32)(e0 & 31);
+  {
+    const u64 pw0 = e0 >> 4, mw0 = e0 >> 5;
+    const u64 i0 = pw0 + lane, i1 = pw0 + 64 + lane, jm = mw0 + lane;
+    const u32 a0 = i0 < A.n_packed ? A.packed[i0] : 0u;
+    const u32 a1 = i1 < A.n_packed ? A.packed[i1] : 0u;
+    const u32 b0 = jm < A.n_mask ? A.nmask[jm] : 0u;
+    const u32 c0 = b0 | (jm < A.n_mask ? A.starts[jm] : 0u);
+    pk[lane] = a0;
+    pk[64 + lane] = a1;
+    nm[lane] = b0;
+    ct[lane] = c0;
+    __builtin_amdgcn_wave_barrier();
+  }
+  const u64 kmask_cut = (A.k >= 64 ? ~0ull : ((1ull << A.k) - 1)) & ~1ull;   // no read may start inside
   u64 bal[EXT_PER];
   u32 cnt = 0;
 #pragma unroll
   for (int j = 0; j < (int)EXT_PER; ++j) {
-    const u64 i = e0 + (u64)j * 64 + lane;
-    bool v = i < A.n_pos && i >= lo && i + (u64)A.k <= hi && ext_window_valid(A.nmask, A.starts, i, A.k);
+    const u32 q = (u32)j * 64 + lane;            // position e0 + q
+    const u64 i = e0 + q;
+    bool v = i < A.n_pos && i >= lo && i + (u64)A.k <= hi;
+    const u32 x = v ? q + offm : 0u;
+    v = v && (lds_bits64(ct, x) & kmask_cut) == 0 && ((nm[x >> 5] >> (x & 31)) & 1u) == 0;
     if (v && !all) {
       K key;
-      ext_canon(A.packed, i, A.k, &key);
+      ext_canon_lds(pk, q + offp, A.k, &key);
       const u32 pf = ext_prefix(key, A.k);
       v = pf >= r0 && pf < r1;
     }
@@ -179,18 +236,18 @@ __global__ __launch_bounds__(EXT_T) void k_ext_windows(ExtWinArgs A) {
   for (u32 w = 0; w < wave; ++w) base += wtot[w];
   K* keys = reinterpret_cast<K*>(A.keys);
   const u64 ml = *A.max_len;
-  const bool pk = ext_packed(A.rbits, ml);
+  const bool packed_v = ext_packed(A.rbits, ml);
   const u32 pb = ext_pos_bits(ml);
 #pragma unroll
   for (int j = 0; j < (int)EXT_PER; ++j) {
-    const u64 i = e0 + (u64)j * 64 + lane;
+    const u32 q = (u32)j * 64 + lane;
     if ((bal[j] >> lane) & 1ull) {
-      const u64 p = i;
+      const u64 p = e0 + q;
       K key;
-      ext_canon(A.packed, p, A.k, &key);
+      ext_canon_lds(pk, q + offp, A.k, &key);
       const u64 at = base + mbcnt64(bal[j]);
       u32 v = (u32)p;
-      if (pk) {   // neighbouring lanes share the table entries and offsets they search
+      if (packed_v) {   // neighbouring lanes share the table entries and offsets they search
         const u32 rd = ext_find_read(A.offsets, A.n_reads, A.rid, A.n_blk, A.blk_sh, p);
         v = (pb < 32 ? (rd << pb) : 0u) | (u32)(p - A.offsets[rd]);
       }
