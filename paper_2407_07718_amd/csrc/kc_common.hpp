@@ -49,26 +49,10 @@ __device__ __forceinline__ u32 mmer_score(u64 x) {
   return (u32)(x >> 32);
 }
 
-// 32 bases (64 bits) of the 2-bit stream starting at base q; base q in bits 0-1.
-// The array must hold three readable words past word q/16.
-__device__ __forceinline__ u64 bases64(const u32* __restrict__ p, u64 q) {
-  u64 w = q >> 4;
-  u32 sh = (u32)(q & 15) * 2;
-  u64 a = (u64)p[w] | ((u64)p[w + 1] << 32);
-  u64 b = p[w + 2];
-  return sh ? (a >> sh) | (b << (64 - sh)) : a;
-}
-// 64 bits of a one-bit-per-base mask starting at base q.
-__device__ __forceinline__ u64 bits64(const u32* __restrict__ p, u64 q) {
-  u64 w = q >> 5;
-  u32 sh = (u32)(q & 31);
-  u64 a = (u64)p[w] | ((u64)p[w + 1] << 32);
-  u64 b = p[w + 2];
-  return sh ? (a >> sh) | (b << (64 - sh)) : a;
-}
-
-// bases64 / bits64 on a copy in LDS, q relative to the copy's first base: each 32-bit
-// half is one funnel shift (v_alignbit) of two neighbouring words.
+// 32 bases (64 bits) of a 2-bit stream, base q in bits 0-1 (lds_bases64), and 64 bits of a
+// one-bit-per-base mask from base q (lds_bits64), read from a copy in LDS, q relative to
+// the copy's first base (three readable words from word q/16, q/32): each 32-bit half is
+// one funnel shift (v_alignbit) of two neighbouring words.
 __device__ __forceinline__ u64 lds_bases64(const u32* p, u32 q) {
   const u32 w = q >> 4, sh = (q & 15) * 2;
   const u32 a = p[w], b = p[w + 1], c = p[w + 2];

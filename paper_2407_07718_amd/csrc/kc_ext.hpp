@@ -23,44 +23,11 @@ constexpr u32 EXT_WAVE = EXT_PER * 64;
 
 // ---------------------------------------------------------------------------- windows
 // Window at base p holds k valid bases of one read: no invalid byte in [p, p+k) and no
-// read start in (p, p+k).
-__device__ __forceinline__ bool ext_window_valid(const u32* __restrict__ nmask, const u32* __restrict__ starts, u64 p,
-                                                 int k) {
-  const u64 m1 = (k >= 64) ? ~0ull : ((1ull << k) - 1);
-  const u64 m2 = (1ull << (k - 1)) - 1;
-  return ((bits64(nmask, p) & m1) == 0) && ((bits64(starts, p + 1) & m2) == 0);
-}
-
-// Canonical value of the k bases at p (k <= 31): forward value with the first base most
-// significant, against the complement read backwards.
-__device__ __forceinline__ void ext_canon(const u32* __restrict__ packed, u64 p, int k, u64* out) {
-  const u64 mask = (1ull << (2 * k)) - 1;
-  const u64 V = bases64(packed, p) & mask;   // base j at bits 2j
-  const u64 F = rev2_64(V) >> (64 - 2 * k);
-  const u64 RC = ~V & mask;
-  *out = F < RC ? F : RC;
-}
-
-// 32 <= k <= 63: the window spans two 64-bit views; the forward value is the 2-bit
-// reversal of the 128-bit window shifted down by 128 - 2k.
-__device__ __forceinline__ void ext_canon(const u32* __restrict__ packed, u64 p, int k, k128* out) {
-  const int hb = 2 * k - 64;
-  const u64 mhi = hb ? ((1ull << hb) - 1) : 0ull;
-  const u64 vlo = bases64(packed, p), vhi = bases64(packed, p + 32) & mhi;
-  const u64 rlo = rev2_64(vhi), rhi = rev2_64(vlo);
-  const int s = 128 - 2 * k;
-  k128 F, RC;
-  if (s == 64) {
-    F.lo = rhi;
-    F.hi = 0;
-  } else {
-    F.lo = (rlo >> s) | (rhi << (64 - s));
-    F.hi = rhi >> s;
-  }
-  RC.lo = ~vlo;
-  RC.hi = ~vhi & mhi;
-  *out = key_lt(F, RC) ? F : RC;
-}
+// read start in (p, p+k).  Its key is the canonical value: the forward value with the
+// first base most significant, against the complement read backwards (for k >= 32 the
+// window spans two 64-bit views and the forward value is the 2-bit reversal of the
+// 128-bit window shifted down by 128 - 2k).  The kernels read both from per-wave LDS
+// copies of the packed bases and masks (ext_canon_lds, below).
 
 // rid[q] = the read holding base q << sh, for every block of 2^sh bases that starts
 // inside a read; other entries keep the fill value ~0.  The block size follows the mean
@@ -146,7 +113,7 @@ struct ExtWinArgs {
 constexpr u32 EXT_PK = 128, EXT_MK = 64;
 static_assert(EXT_WAVE == 1024, "staging sized for 1024 positions per wave");
 
-// Canonical value of the k bases at q of the staged packed words (see ext_canon).
+// Canonical value of the k bases at q of the staged packed words.
 __device__ __forceinline__ void ext_canon_lds(const u32* pk, u32 q, int k, u64* out) {
   const u64 mask = (1ull << (2 * k)) - 1;
   const u64 V = lds_bases64(pk, q) & mask;
@@ -512,20 +479,51 @@ __global__ __launch_bounds__(EXT_T) void k_ext_occ(ExtRunArgs A) {
   }
 }
 
-// Windows per key prefix, over all valid windows: persistent blocks stride over the
-// positions with LDS bins and add them to the global bins once at the end.
+// Windows per key prefix, over all valid windows: the waves of persistent blocks take
+// spans of EXT_WAVE positions in turn (staged in LDS as in k_ext_windows), count into the
+// block's LDS bins and add them to the global bins once at the end.
 template <typename K>
 __global__ __launch_bounds__(EXT_T) void k_ext_prefix_hist(ExtWinArgs A, u32* __restrict__ bins) {
   __shared__ u32 h[EXT_NBINS];
+  __shared__ u32 s_pk[EXT_T / 64][EXT_PK], s_nm[EXT_T / 64][EXT_MK], s_ct[EXT_T / 64][EXT_MK];
   for (u32 i = threadIdx.x; i < EXT_NBINS; i += EXT_T) h[i] = 0;
   __syncthreads();
+  const u32 lane = lane_id(), wave = threadIdx.x >> 6;
+  u32* const pk = s_pk[wave];
+  u32* const nm = s_nm[wave];
+  u32* const ct = s_ct[wave];
   const u64 lo = A.n_reads ? min(A.offsets[0], A.R) : 0;
   const u64 hi = A.n_reads ? min(A.offsets[A.n_reads], A.R) : 0;
-  for (u64 i = blockIdx.x * (u64)EXT_T + threadIdx.x; i < A.n_pos; i += (u64)gridDim.x * EXT_T) {
-    if (i >= lo && i + (u64)A.k <= hi && ext_window_valid(A.nmask, A.starts, i, A.k)) {
-      K key;
-      ext_canon(A.packed, i, A.k, &key);
-      atomicAdd(&h[ext_prefix(key, A.k)], 1u);
+  const u64 kmask_cut = (A.k >= 64 ? ~0ull : ((1ull << A.k) - 1)) & ~1ull;
+  const u64 n_spans = (A.n_pos + EXT_WAVE - 1) / EXT_WAVE;
+  for (u64 sp = (u64)blockIdx.x * (EXT_T / 64) + wave; sp < n_spans; sp += (u64)gridDim.x * (EXT_T / 64)) {
+    const u64 e0 = sp * EXT_WAVE;
+    const u32 offp = (u32)(e0 & 15), offm = (u32)(e0 & 31);
+    {
+      const u64 pw0 = e0 >> 4, mw0 = e0 >> 5;
+      const u64 i0 = pw0 + lane, i1 = pw0 + 64 + lane, jm = mw0 + lane;
+      const u32 a0 = i0 < A.n_packed ? A.packed[i0] : 0u;
+      const u32 a1 = i1 < A.n_packed ? A.packed[i1] : 0u;
+      const u32 b0 = jm < A.n_mask ? A.nmask[jm] : 0u;
+      const u32 c0 = b0 | (jm < A.n_mask ? A.starts[jm] : 0u);
+      __builtin_amdgcn_wave_barrier();   // the previous span's reads of the slice come first
+      pk[lane] = a0;
+      pk[64 + lane] = a1;
+      nm[lane] = b0;
+      ct[lane] = c0;
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int j = 0; j < (int)EXT_PER; ++j) {
+      const u32 q = (u32)j * 64 + lane;
+      const u64 i = e0 + q;
+      bool v = i < A.n_pos && i >= lo && i + (u64)A.k <= hi;
+      const u32 x = v ? q + offm : 0u;
+      v = v && (lds_bits64(ct, x) & kmask_cut) == 0 && ((nm[x >> 5] >> (x & 31)) & 1u) == 0;
+      if (v) {
+        K key;
+        ext_canon_lds(pk, q + offp, A.k, &key);
+        atomicAdd(&h[ext_prefix(key, A.k)], 1u);
+      }
     }
   }
   __syncthreads();
