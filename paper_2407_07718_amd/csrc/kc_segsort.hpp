@@ -345,26 +345,17 @@ __global__ __launch_bounds__(256) void k_msd_hist(MsdArgs A) {
   A.hist[(u64)threadIdx.x * A.nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Coarse scatter: the block's range in rounds staged through LDS, written group by group.
-template <typename K>
-__global__ __launch_bounds__(512) void k_msd_scatter(MsdArgs A) {
-  constexpr u32 T = 512, R = sizeof(K) == 8 ? 4096u : 2048u, IT = R / T;
-  __shared__ K sk[R];
-  __shared__ u32 sv[R];
-  __shared__ u32 cnt[256], lbase[256], gpos[256];
-  __shared__ u64 scr[17];
+// Elements [a, b) of in moved to out in rounds of R staged through LDS: each round is
+// ranked by its field (bits [sh, sh + nbits) of the key, nbits <= 8) with LDS counters,
+// staged in field order and written so that consecutive threads write consecutive slots
+// of a field's range; gpos[f] is the next output slot of field f (advanced per round).
+// cnt, lbase and gpos have 256 entries.  Block-wide (barriers inside).
+template <typename K, u32 T>
+__device__ __forceinline__ void msd_rounds(const K* __restrict__ in, const u32* __restrict__ in_v, u64 a, u64 b,
+                                           int sh, int nbits, K* __restrict__ out, u32* __restrict__ out_v, K* sk,
+                                           u32* sv, u32* cnt, u32* lbase, u32* gpos, u64* scr) {
+  constexpr u32 R = sizeof(K) == 8 ? 4096u : 2048u, IT = R / T;
   const u32 tid = threadIdx.x;
-  const u64 n = *A.n_ptr;
-  const u64 per = (n + A.nb - 1) / A.nb;
-  const u64 a = min(n, blockIdx.x * per), b = min(n, a + per);
-  const int sh = msd_shift1(A.nbits), nb = msd_bits1(A.nbits);
-  const K* in = reinterpret_cast<const K*>(A.in_k);
-  K* mid = reinterpret_cast<K*>(A.mid_k);
-  if (tid < 256) {
-    cnt[tid] = 0;
-    gpos[tid] = A.hist[(u64)tid * A.nb + blockIdx.x];
-  }
-  __syncthreads();
   for (u64 r0 = a; r0 < b; r0 += R) {
     const u32 nr = (u32)min((u64)R, b - r0);
     K kr[IT];
@@ -374,13 +365,13 @@ __global__ __launch_bounds__(512) void k_msd_scatter(MsdArgs A) {
       const u32 i = tid + j * T;
       if (i < nr) {
         kr[j] = in[r0 + i];
-        vr[j] = A.in_v[r0 + i];
+        vr[j] = in_v[r0 + i];
       }
     }
 #pragma unroll
     for (u32 j = 0; j < IT; ++j) {
       if (tid + j * T < nr) {
-        cc[j] = key_field(kr[j], sh, nb);
+        cc[j] = key_field(kr[j], sh, nbits);
         rk[j] = atomicAdd(&cnt[cc[j]], 1u);
       }
     }
@@ -399,10 +390,10 @@ __global__ __launch_bounds__(512) void k_msd_scatter(MsdArgs A) {
     }
     __syncthreads();
     for (u32 i = tid; i < nr; i += T) {
-      const u32 c = key_field(sk[i], sh, nb);
+      const u32 c = key_field(sk[i], sh, nbits);
       const u64 d = (u64)gpos[c] + (i - lbase[c]);
-      mid[d] = sk[i];
-      A.mid_v[d] = sv[i];
+      out[d] = sk[i];
+      out_v[d] = sv[i];
     }
     __syncthreads();
     if (tid < 256) {
@@ -413,10 +404,36 @@ __global__ __launch_bounds__(512) void k_msd_scatter(MsdArgs A) {
   }
 }
 
-// Fine pass: one block per coarse group; writes the range table.
+// Coarse scatter: the block's range in rounds staged through LDS, written group by group.
+template <typename K>
+__global__ __launch_bounds__(512) void k_msd_scatter(MsdArgs A) {
+  constexpr u32 T = 512, R = sizeof(K) == 8 ? 4096u : 2048u;
+  __shared__ K sk[R];
+  __shared__ u32 sv[R];
+  __shared__ u32 cnt[256], lbase[256], gpos[256];
+  __shared__ u64 scr[17];
+  const u32 tid = threadIdx.x;
+  const u64 n = *A.n_ptr;
+  const u64 per = (n + A.nb - 1) / A.nb;
+  const u64 a = min(n, blockIdx.x * per), b = min(n, a + per);
+  if (tid < 256) {
+    cnt[tid] = 0;
+    gpos[tid] = A.hist[(u64)tid * A.nb + blockIdx.x];
+  }
+  __syncthreads();
+  msd_rounds<K, T>(reinterpret_cast<const K*>(A.in_k), A.in_v, a, b, msd_shift1(A.nbits), msd_bits1(A.nbits),
+                   reinterpret_cast<K*>(A.mid_k), A.mid_v, sk, sv, cnt, lbase, gpos, scr);
+}
+
+// Fine pass: one block per coarse group; counts its sub-ranges, writes the range table,
+// then moves the group's elements into their sub-ranges in staged rounds.
 template <typename K>
 __global__ __launch_bounds__(1024) void k_msd_fine(MsdArgs A) {
-  __shared__ u32 cr[256], cur[256];
+  constexpr u32 T = 1024, R = sizeof(K) == 8 ? 4096u : 2048u;
+  __shared__ K sk[R];
+  __shared__ u32 sv[R];
+  __shared__ u32 cnt[256], lbase[256], cur[256];
+  __shared__ u64 scr[17];
   const u32 g = blockIdx.x, tid = threadIdx.x;
   const u64 n = *A.n_ptr;
   const int sh1 = msd_shift1(A.nbits), g2 = msd_g2(n, A.nbits, A.target), sh2 = sh1 - g2;
@@ -424,17 +441,16 @@ __global__ __launch_bounds__(1024) void k_msd_fine(MsdArgs A) {
   const u64 a = A.hist[(u64)g * A.nb];
   const u64 b = g + 1 < 256 ? (u64)A.hist[(u64)(g + 1) * A.nb] : n;
   const K* mid = reinterpret_cast<const K*>(A.mid_k);
-  K* out = reinterpret_cast<K*>(A.out_k);
-  if (tid < 256) cr[tid] = 0;
+  if (tid < 256) cnt[tid] = 0;
   __syncthreads();
-  for (u64 i = a + tid; i < b; i += 1024) atomicAdd(&cr[key_field(mid[i], sh2, g2)], 1u);
+  for (u64 i = a + tid; i < b; i += T) atomicAdd(&cnt[key_field(mid[i], sh2, g2)], 1u);
   __syncthreads();
   if (tid < 64) {
     // exclusive prefix over the F <= 256 sub-ranges: lane l owns sub-ranges 4l..4l+3
     u32 c[4], s = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      c[q] = 4 * tid + q < F ? cr[4 * tid + q] : 0u;
+      c[q] = 4 * tid + q < F ? cnt[4 * tid + q] : 0u;
       s += c[q];
     }
     u32 run = wave_scan_u32(s) - s;
@@ -453,10 +469,7 @@ __global__ __launch_bounds__(1024) void k_msd_fine(MsdArgs A) {
     *A.n_seg = (u64)256 << g2;
   }
   __syncthreads();
-  for (u64 i = a + tid; i < b; i += 1024) {
-    const K k = mid[i];
-    const u32 pos = atomicAdd(&cur[key_field(k, sh2, g2)], 1u);
-    out[pos] = k;
-    A.out_v[pos] = A.mid_v[i];
-  }
+  if (tid < 256) cnt[tid] = 0;
+  __syncthreads();
+  msd_rounds<K, T>(mid, A.mid_v, a, b, sh2, g2, reinterpret_cast<K*>(A.out_k), A.out_v, sk, sv, cnt, lbase, cur, scr);
 }
