@@ -139,15 +139,20 @@ __global__ __launch_bounds__(T) void k_seg_sort(SegArgs A) {
       }
       continue;
     }
-    // Long segment: stable LSD passes through HBM, ping-pong between in and tmp.
+    // Long segment: stable LSD passes through HBM, ping-pong between in and tmp.  When only
+    // grouping is needed the keys are mixed as they are first read, the low 8 * p0 bits
+    // are sorted first (p0 from the length, so that two distinct keys share those bits
+    // with a chance of about 1%), and the remaining passes run only if some group of
+    // equal low bits holds two keys; the keys are unmixed as they are written out.
     K* src_k = in_k;
     u32* src_v = A.vals;
     K* dst_k = tmp_k;
     u32* dst_v = A.tmp_v;
-    for (int p = 0; p < np; ++p) {
+    auto ld = [&](const K* src, u64 i, int p) { return (mixed && p == 0) ? mix_key(src[i]) : src[i]; };
+    auto pass = [&](int p) {
       for (u32 d = tid; d < 256; d += T) S.dcnt[d] = 0;
       __syncthreads();
-      for (u64 i = tid; i < n; i += T) atomicAdd(&S.dcnt[key_digit(src_k[s0 + i], 8 * p)], 1u);
+      for (u64 i = tid; i < n; i += T) atomicAdd(&S.dcnt[key_digit(ld(src_k, s0 + i, p), 8 * p)], 1u);
       __syncthreads();
       {
         u64 tot;
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(T) void k_seg_sort(SegArgs A) {
       for (u64 t0 = 0; t0 < n; t0 += CAP) {
         const u32 m = (u32)min((u64)CAP, n - t0), m_pad = (m + WB - 1) / WB * WB;
         for (u32 i = tid; i < m_pad; i += T) {
-          S.keys[i] = i < m ? src_k[s0 + t0 + i] : key_pad<K>();
+          S.keys[i] = i < m ? ld(src_k, s0 + t0 + i, p) : key_pad<K>();
           S.vals[i] = i < m ? src_v[s0 + t0 + i] : 0u;
         }
         for (u32 d = tid; d < 256; d += T) S.dcnt[d] = 0;
@@ -188,14 +193,31 @@ __global__ __launch_bounds__(T) void k_seg_sort(SegArgs A) {
       u32* tv = src_v;
       src_v = dst_v;
       dst_v = tv;
+    };
+    // 8 * p0 >= 2 log2(n) + 7 bits (one pass loop, so that the pass is inlined once)
+    const int p0 = mixed ? min((2 * (64 - __builtin_clzll(n)) + 14) / 8, np_mixed) : np;
+    int p_end = p0;
+    bool checked = !mixed;
+    for (int p = 0;;) {
+      for (; p < p_end; ++p) pass(p);
+      if (checked) break;
+      checked = true;
+      bool bad = false;
+      for (u64 i = tid; i < n; i += T) bad |= mixed_pair(src_k + s0, (u32)i, (u32)n, 8 * p0);
+      if (!__syncthreads_or(bad)) break;
+      p_end = np_mixed;
     }
-    if (src_k != out_k) {
+    if (src_k != out_k || mixed) {
       for (u64 i = tid; i < n; i += T) {
         if (s0 + i < A.out_cap) {
-          out_k[s0 + i] = src_k[s0 + i];
-          A.out_v[s0 + i] = src_v[s0 + i];
+          const K key = src_k[s0 + i];
+          out_k[s0 + i] = mixed ? unmix_key(key) : key;
         }
       }
+    }
+    if (src_v != A.out_v) {
+      for (u64 i = tid; i < n; i += T)
+        if (s0 + i < A.out_cap) A.out_v[s0 + i] = src_v[s0 + i];
     }
   }
 }
