@@ -151,6 +151,35 @@ __device__ __forceinline__ void expand_record(const u32* __restrict__ rec, u64 r
   }
 }
 
+// The canonical k-mer whose first base is bit q of a record's base field (k <= 31: a
+// u64; k >= 32: a 128-bit key), read with funnel shifts from the record words at rec.
+__device__ __forceinline__ u64 rec_bits64(const u32* p, u32 q) {   // 64 bits from bit q of p
+  const u32 w = q >> 5, sh = q & 31;
+  return ((u64)__builtin_amdgcn_alignbit(p[w + 2], p[w + 1], sh) << 32) | __builtin_amdgcn_alignbit(p[w + 1], p[w], sh);
+}
+template <typename K> __device__ __forceinline__ K canon_at(const u32* rec, u32 q, int k);
+template <> __device__ __forceinline__ u64 canon_at<u64>(const u32* rec, u32 q, int k) {
+  const u64 kmask = (1ull << (2 * k)) - 1;
+  const u64 V = rec_bits64(rec, q) & kmask;
+  const u64 F = rev2_64(V) >> (64 - 2 * k);
+  const u64 RC = ~V & kmask;
+  return F < RC ? F : RC;
+}
+template <> __device__ __forceinline__ k128 canon_at<k128>(const u32* rec, u32 q, int k) {
+  const int hb = 2 * k - 64;                      // bits in the high word, 0..62
+  const u64 mhi = hb ? ((1ull << hb) - 1) : 0ull;
+  const u64 vlo = rec_bits64(rec, q), vhi = rec_bits64(rec, q + 64) & mhi;
+  const u64 rlo = rev2_64(vhi), rhi = rev2_64(vlo);
+  const int s = 128 - 2 * k;                      // 2..64
+  k128 F, RC;
+  if (s == 64) { F.lo = rhi; F.hi = 0; }
+  else { F.lo = (rlo >> s) | (rhi << (64 - s)); F.hi = rhi >> s; }
+  RC.lo = ~vlo;
+  RC.hi = ~vhi & mhi;
+  return key_lt(F, RC) ? F : RC;
+}
+
+
 // ---------------------------------------------------------------------------- run output
 // One run (distinct key with count c): histogram, extremes and the filtered output.
 struct RunSink {
@@ -473,6 +502,7 @@ template <typename K, int T, int ITEMS>
 __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
   using SM = BucketSmem<K, T, ITEMS>;
   constexpr int CAP = SM::CAP;
+  static_assert(sizeof(decltype(SM::u)) >= 4 * CAP, "expansion maps fit the rank tables");
   __shared__ SM S;
   __shared__ unsigned long long lover;
   const u32 tid = threadIdx.x;
@@ -502,17 +532,39 @@ __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
       b = A.small_list[item - n_chunks];
       const u32 r0 = A.rec_off[b], nr = A.rec_off[b + 1] - r0;
       n = min((u32)A.bcnt[b], (u32)CAP);
-      // expand: thread t takes a contiguous range of records
+      // expand: thread t takes a contiguous range of records.  For u64 keys each thread
+      // rolls through its records' k-mers.  For 128-bit keys, whose rolling update is
+      // costly, the expansion is key-parallel: each record's first key index and, for each
+      // of its keys, the record index go to the (still unused) rank tables, then each
+      // thread computes keys o = tid, tid + T, ... straight from their records' bits.  (A
+      // small bucket has at most CAP k-mers, so at most CAP records.)
       const u32 pr = (nr + T - 1) / T;
       const u32 ra = min(nr, tid * pr), rb = min(nr, ra + pr);
       u64 gsum = 0;
       for (u32 r = ra; r < rb; ++r) gsum += record_g(A.rec, (u64)r0 + r, A.rec_words);
       u64 gall;
       u64 off = block_exclusive_scan<u64>(gsum, S.scr, &gall);
-      for (u32 r = ra; r < rb; ++r) {
-        const u32 g = record_g(A.rec, (u64)r0 + r, A.rec_words);
-        if (off + g <= (u64)CAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + off, g, mixed);
-        off += g;
+      if constexpr (sizeof(K) == 8) {
+        for (u32 r = ra; r < rb; ++r) {
+          const u32 g = record_g(A.rec, (u64)r0 + r, A.rec_words);
+          if (off + g <= (u64)CAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + off, g, mixed);
+          off += g;
+        }
+      } else {
+        u16* s_off = reinterpret_cast<u16*>(&S.u);   // [CAP] record -> its first key
+        u16* s_rid = s_off + CAP;                    // [CAP] key -> its record
+        for (u32 r = ra; r < rb; ++r) {
+          const u32 g = record_g(A.rec, (u64)r0 + r, A.rec_words);
+          s_off[r] = (u16)off;
+          for (u32 t = 0; t < g && off + t < (u64)CAP; ++t) s_rid[off + t] = (u16)r;
+          off += g;
+        }
+        __syncthreads();
+        for (u32 o = tid; o < n; o += T) {
+          const u32 r = s_rid[o];
+          const K key = canon_at<K>(A.rec + ((u64)r0 + r) * 8, 2u * (o - s_off[r]), A.k);
+          S.keys[o] = mixed ? mix_key(key) : key;
+        }
       }
     }
     // pad to whole waves of every wave of the block
@@ -621,23 +673,44 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
   K* skeys = reinterpret_cast<K*>(A.surv_k);
   u64 ndist = 0;
   const u64 gw = (u64)blockIdx.x * WPB + wave, nw = (u64)gridDim.x * WPB;
+  // key -> record map of a 64-record chunk, and each record's first key, in the rank
+  // tables' region (cleared for the sort only after the expansion)
+  constexpr u32 MAPB = sizeof(S.u) - 128;
+  u8* const rid = reinterpret_cast<u8*>(&S.u);
+  u16* const roff = reinterpret_cast<u16*>(rid + MAPB);
+  constexpr int RW = sizeof(K) == 8 ? 4 : 8;
   for (u64 item = gw; item < n_tiny; item += nw) {
-    for (u32 i = lane; i < 256; i += 64) {
-      S.u.r.tbl[i] = 0;
-      S.u.r.cnt[i] = 0;
-    }
     const u32 b = tiny_list[item];
     const u32 r0 = A.rec_off[b], nr = A.rec_off[b + 1] - r0;
     const u32 n = min((u32)A.bcnt[b], (u32)WCAP);
-    // expand 64 records at a time; each lane writes its record's k-mers
+    // expand 64 records at a time.  For 128-bit keys key-parallel: lanes take the chunk's
+    // keys in turn and compute each from its record's bits (a chunk too large for the
+    // map, possible only for very small k, is expanded by its records' lanes instead).
+    // For u64 keys each lane rolls through its record's k-mers (measured faster there).
     u32 off = 0;
     for (u32 c0 = 0; c0 < nr; c0 += 64) {
       const u32 r = c0 + lane;
       const u32 g = r < nr ? record_g(A.rec, (u64)r0 + r, A.rec_words) : 0u;
       const u32 inc = wave_scan_u32(g);
-      const u32 o = off + inc - g;
-      if (g && o + g <= (u32)WCAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + o, g, mixed);
-      off += (u32)__shfl((int)inc, 63, 64);
+      const u32 rel = inc - g;
+      const u32 G = lane_read(inc, 63);
+      if (sizeof(K) == 16 && G <= MAPB) {
+        roff[lane] = (u16)rel;
+        for (u32 t = 0; t < g; ++t) rid[rel + t] = (u8)lane;
+        for (u32 q = lane; q < G && off + q < (u32)WCAP; q += 64) {
+          const u32 l = rid[q];
+          const K key = canon_at<K>(A.rec + ((u64)r0 + c0 + l) * RW, 2u * (q - roff[l]), A.k);
+          S.keys[off + q] = mixed ? mix_key(key) : key;
+        }
+      } else {
+        const u32 o = off + rel;
+        if (g && o + g <= (u32)WCAP) expand_record(A.rec, (u64)r0 + r, A.k, S.keys + o, g, mixed);
+      }
+      off += G;
+    }
+    for (u32 i = lane; i < 256; i += 64) {
+      S.u.r.tbl[i] = 0;
+      S.u.r.cnt[i] = 0;
     }
     const u32 n_pad = (n + 63u) & ~63u;
     for (u32 i = n + lane; i < n_pad; i += 64) S.keys[i] = key_pad<K>();
@@ -697,32 +770,6 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
 // shifts, a 2-bit reversal, the smaller of the two strands), so the stores are coalesced
 // and no lane waits for a longer record of its wave.  RW = record words (4: k <= 31,
 // u64 keys; 8: k >= 32, 128-bit keys).
-__device__ __forceinline__ u64 rec_bits64(const u32* p, u32 q) {   // 64 bits from bit q of p
-  const u32 w = q >> 5, sh = q & 31;
-  return ((u64)__builtin_amdgcn_alignbit(p[w + 2], p[w + 1], sh) << 32) | __builtin_amdgcn_alignbit(p[w + 1], p[w], sh);
-}
-template <typename K> __device__ __forceinline__ K canon_at(const u32* rec, u32 q, int k);
-template <> __device__ __forceinline__ u64 canon_at<u64>(const u32* rec, u32 q, int k) {
-  const u64 kmask = (1ull << (2 * k)) - 1;
-  const u64 V = rec_bits64(rec, q) & kmask;
-  const u64 F = rev2_64(V) >> (64 - 2 * k);
-  const u64 RC = ~V & kmask;
-  return F < RC ? F : RC;
-}
-template <> __device__ __forceinline__ k128 canon_at<k128>(const u32* rec, u32 q, int k) {
-  const int hb = 2 * k - 64;                      // bits in the high word, 0..62
-  const u64 mhi = hb ? ((1ull << hb) - 1) : 0ull;
-  const u64 vlo = rec_bits64(rec, q), vhi = rec_bits64(rec, q + 64) & mhi;
-  const u64 rlo = rev2_64(vhi), rhi = rev2_64(vlo);
-  const int s = 128 - 2 * k;                      // 2..64
-  k128 F, RC;
-  if (s == 64) { F.lo = rhi; F.hi = 0; }
-  else { F.lo = (rlo >> s) | (rhi << (64 - s)); F.hi = rhi >> s; }
-  RC.lo = ~vlo;
-  RC.hi = ~vhi & mhi;
-  return key_lt(F, RC) ? F : RC;
-}
-
 template <typename K, int T>
 __global__ __launch_bounds__(T) void k_expand_large(CountArgs A, K* __restrict__ lkeys) {
   constexpr int W = T / 64, RW = sizeof(K) == 8 ? 4 : 8;
