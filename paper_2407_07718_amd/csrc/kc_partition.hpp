@@ -540,7 +540,10 @@ __global__ __launch_bounds__(512) void k_part_scatter(PartArgs P) {
 template <int RW>
 __global__ __launch_bounds__(1024) void k_part_fine(PartArgs P) {
   constexpr u32 T = 1024, Q = RW / 4;             // uint4 per record
-  constexpr u32 R = RW == 4 ? 2048u : 1024u;      // records staged per round (32 KB)
+  // records staged per round (64 KB): with many fine buckets per group (2^11 on the
+  // long-read workload) a round must hold several records per bucket for its writes to
+  // form runs; 4096 16-byte records measured faster than 2048 (at half the blocks per CU)
+  constexpr u32 R = RW == 4 ? 4096u : 2048u;
   constexpr u32 IT = R / T;
   __shared__ uint4 stage[R * Q];
   __shared__ u32 cr[2048], ck[2048], cur[2048], lbase[2048];
