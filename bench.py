@@ -354,7 +354,7 @@ def serving_leg(args, kc, sets, ref) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the counting path runs on one GPU; --gpus must be 1",
                           "requested_gpus": args.gpus}))
         sys.exit(2)
     import torch
