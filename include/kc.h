@@ -206,7 +206,7 @@ int kc_count_ext_device_async(const uint8_t *d_reads, uint64_t total_bases, cons
 /* ---------------------------------------------------------------- batched counting
  * One read set of a batch (or a server request).  reads/offsets are host pointers for
  * kc_count_batch and kc_server_submit (borrowed until the call returns / the job is
- * admitted), device pointers for kc_count_batch_device. */
+ * admitted), device pointers for kc_batch_create and kc_autotune. */
 typedef struct kc_job {
   const uint8_t *reads;
   const uint64_t *offsets;
@@ -224,7 +224,7 @@ typedef struct kc_job {
  * outs[i] is filled for every job on KC_OK (free each with kc_result_free).  Jobs may
  * mix k; a job with bad arguments fails the whole call with KC_EINVAL before any
  * device work. */
-int kc_count_batch(uint32_t n_jobs, const kc_job *jobs, const kc_config *cfg, kc_result *outs);
+int kc_count_batch(uint32_t n_jobs, const kc_job *jobs, kc_result *outs, const kc_config *cfg);
 
 /* A prepared batch over device-resident inputs, for repeated launches (benchmarks,
  * pipelines): kc_batch_create captures the schedule into a hipGraph over the given

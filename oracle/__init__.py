@@ -66,9 +66,6 @@ def _load():
                                   ctypes.POINTER(_Result)]
         lib.kco_count.restype = ctypes.c_int
         lib.kco_free.argtypes = [ctypes.POINTER(_Result)]
-        lib.kco_query.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
-                                  ctypes.c_uint64, ctypes.c_uint64]
-        lib.kco_query.restype = ctypes.c_uint64
         lib.kco_count_ext.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                       ctypes.POINTER(_Result), ctypes.POINTER(_Occ)]

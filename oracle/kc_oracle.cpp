@@ -289,26 +289,9 @@ void kco_free(kco_result *r) {
   memset(r, 0, sizeof(*r));
 }
 
-// Number of windows whose canonical value equals {lo_word, hi_word}: a direct count of
-// one k-mer, for spot checks of large outputs without sorting everything.
-uint64_t kco_query(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k,
-                   uint64_t lo_word, uint64_t hi_word) {
-  u128 want = ((u128)hi_word << 64) | lo_word;
-  uint64_t n = 0;
-  for (uint64_t r = 0; r < n_reads; ++r) {
-    uint64_t len = offsets[r + 1] - offsets[r];
-    if (len < (uint64_t)k) continue;
-    const uint8_t *read = reads + offsets[r];
-    for (uint64_t i = 0; i + (uint64_t)k <= len; ++i) {
-      u128 v;
-      if (window_value<u128>(read, i, k, &v) && v == want) ++n;
-    }
-  }
-  return n;
-}
-
-// Batch form of kco_query: counts for n_q query k-mers in one pass over the reads
-// (queries are looked up by binary search in a sorted copy).  Reads are split over
+// Direct counts of n_q chosen canonical k-mers ({low, high} words each) in one pass over
+// the reads, for spot checks of large outputs without sorting everything (queries are
+// looked up by binary search in a sorted copy).  Reads are split over
 // threads; each thread counts into its own array and the arrays are summed.
 void kco_query_many(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k,
                     const uint64_t *q_words, uint64_t n_q, uint64_t *counts_out) {

@@ -3,10 +3,10 @@
 // [min_freq, max_freq] survive, every run feeds the frequency histogram.
 //
 // Paper mapping: k-mers are extracted from the supermers of a task and sorted (Section
-// 3.4, heavy-hitter transform; Section 3.1), and one linear scan over the sorted array
+// 3.5, heavy-hitter transform; Section 3.1), and one linear scan over the sorted array
 // counts each value and records the histogram or copies the k-mers that meet the
 // frequency requirement to another array (Section 3.1).  A bucket is a task (Section
-// 3.3): independent of all others because equal k-mers never span two buckets.
+// 3.4): independent of all others because equal k-mers never span two buckets.
 #pragma once
 #include "kc_common.hpp"
 #include "kc_sort.hpp"
@@ -495,7 +495,7 @@ __device__ __forceinline__ u32 emit_runs_block(const K* keys, const u16* hp, u32
 // Persistent blocks take work items round-robin (item = block, block + grid, ...).
 // Items [0, n_chunks) are chunks of large buckets: their keys (already expanded in HBM)
 // are sorted and run-counted on chip into (k-mer, count) lists -- the paper's kmerlist
-// form of a heavy-hitter task (Section 3.4) -- merged later through HBM.  Items after
+// form of a heavy-hitter task (Section 3.5) -- merged later through HBM.  Items after
 // that are small buckets: their supermers are expanded into LDS, sorted, and their runs
 // are final counts.  Every item writes its output to its own slot range.
 template <typename K, int T, int ITEMS>

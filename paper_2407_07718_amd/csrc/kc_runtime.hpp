@@ -5,7 +5,7 @@
 //
 // Paper mapping: the paper spreads tasks over workers and assigns them to processes
 // with a greedy threshold rule so that the largest per-process sum stays close to the
-// average (Section 3.3, load balance).  Here jobs are spread over stream lanes with the
+// average (Section 3.5, load balance).  Here jobs are spread over stream lanes with the
 // greedy largest-first rule for the same purpose.
 #include <algorithm>
 #include <chrono>
@@ -414,7 +414,7 @@ int kc_batch_destroy(kc_batch* b) {
   return KC_OK;
 }
 
-int kc_count_batch(uint32_t n_jobs, const kc_job* jobs, const kc_config* cfg, kc_result* outs) {
+int kc_count_batch(uint32_t n_jobs, const kc_job* jobs, kc_result* outs, const kc_config* cfg) {
   g_err.clear();
   if ((n_jobs && (!jobs || !outs))) return fail(KC_EINVAL, "NULL argument");
   for (u32 i = 0; i < n_jobs; ++i) memset(&outs[i], 0, sizeof(kc_result));
@@ -675,10 +675,18 @@ struct kc_server {
       std::vector<int> done;
       for (size_t i = 0; i < slots.size(); ++i) {
         SrvJob* J = slots[i].job;
-        if (J && (J->rc != KC_OK || hipEventQuery(slots[i].done) == hipSuccess)) {
-          collect(J);
-          done.push_back((int)i);
+        if (!J) continue;
+        if (J->rc == KC_OK) {
+          const hipError_t q = hipEventQuery(slots[i].done);
+          if (q == hipErrorNotReady) continue;
+          if (q != hipSuccess) {
+            // a failed device (e.g. a kernel fault) retires the job as failed
+            J->rc = fail(KC_EDEVICE, "request failed on the device: %s", hipGetErrorString(q));
+            J->err = g_err;
+          }
         }
+        collect(J);
+        done.push_back((int)i);
       }
       std::vector<SrvJob*> admitted;
       {
@@ -815,6 +823,10 @@ int kc_server_cancel(kc_server* s, uint64_t ticket) {
   std::lock_guard<std::mutex> g(s->mu);
   auto it = s->jobs.find(ticket);
   if (it == s->jobs.end() || it->second->state != J_QUEUED) return fail(KC_EINVAL, "ticket not queued");
+  // Out of the queue at once: a later poll frees the job, so the scheduler must never
+  // see it again.
+  auto q = std::find(s->queue.begin(), s->queue.end(), it->second);
+  if (q != s->queue.end()) s->queue.erase(q);
   it->second->state = J_CANCELED;
   it->second->tm.done_s = s->now();
   return KC_OK;

@@ -1,6 +1,6 @@
 // Segmented sorts of (key, value) pairs, used where a stage needs keys in order but the
 // keys already fall into independent segments:
-//   * the (k-mer, count) lists of one heavy bucket (Section 3.4: lists are sorted and
+//   * the (k-mer, count) lists of one heavy bucket (Section 3.5: lists are sorted and
 //     merged again) -- equal k-mers never span two buckets, so each bucket's lists are
 //     sorted on their own and summed per run;
 //   * the survivors, split by their top key bits into key ranges (two scatter passes),

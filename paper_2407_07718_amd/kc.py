@@ -105,7 +105,7 @@ def _load() -> ctypes.CDLL:
     lib.kc_count_device_async.argtypes = dev_args
     lib.kc_count_device_async.restype = i32
     P = ctypes.POINTER
-    lib.kc_count_batch.argtypes = [u32, P(kc_job), P(kc_config), P(kc_result)]
+    lib.kc_count_batch.argtypes = [u32, P(kc_job), P(kc_result), P(kc_config)]
     lib.kc_count_batch.restype = i32
     lib.kc_batch_create.argtypes = [u32, P(kc_job), P(kc_config), P(vp)]
     lib.kc_batch_create.restype = i32
@@ -245,7 +245,7 @@ def kc_count_batch(jobs, cfg: Optional[kc_config] = None):
     """Count a list of Job read sets in one batched call; returns one Result per job."""
     arr = (kc_job * max(1, len(jobs)))(*[j.c() for j in jobs])
     outs = (kc_result * max(1, len(jobs)))()
-    _check(_lib.kc_count_batch(len(jobs), arr, ctypes.byref(cfg) if cfg is not None else None, outs))
+    _check(_lib.kc_count_batch(len(jobs), arr, outs, ctypes.byref(cfg) if cfg is not None else None))
     return [_take_result(outs[i], jobs[i].hist_len) for i in range(len(jobs))]
 
 

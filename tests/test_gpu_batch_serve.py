@@ -213,3 +213,34 @@ def test_server_cancel_and_failures():
         srv.close()
     assert isinstance(out[t1], kc.KCError) and out[t1].code == kc.KC_ENOMEM
     assert_same(out[t2][0], _oracle(small), "request after an oversized one")
+
+
+def test_server_cancel_then_poll_of_queued_ticket():
+    """A cancelled request that sits behind others in the queue is polled (and freed) at
+    once; the scheduler must not touch it afterwards, and later requests still run."""
+    kc = _kc()
+    big_r, big_o = _reads(61, 200000, 150, 150, genome=2_000_000, p_sub=0.005, p_n=0.0)
+    big = kc.Job(big_r, big_o, 31, 17, 2, 1000, 4096)
+    smalls = []
+    for s in range(4):
+        r, o = _reads(62 + s, 120, 100, 200)
+        smalls.append(kc.Job(r, o, 31, 17, 1, 100, 128))
+    print("case server cancel+poll of a queued non-head ticket", flush=True)
+    srv = kc.Server(hbm_budget=4 << 30, slots=1)
+    try:
+        t_big = srv.submit(big)
+        t_a = srv.submit(smalls[0])
+        t_b = srv.submit(smalls[1])
+        srv.cancel(t_b)                       # behind t_a, which waits for the slot
+        with pytest.raises(kc.KCError) as e:
+            srv.poll(t_b)                     # retires and frees the cancelled job
+        assert e.value.code == kc.KC_ECANCELED
+        t_c = srv.submit(smalls[2])
+        t_d = srv.submit(smalls[3])
+        out = _wait(srv, [t_big, t_a, t_c, t_d])
+    finally:
+        srv.close()
+    assert_same(out[t_big][0], _oracle(big), "big request")
+    for t, j, name in ((t_a, smalls[0], "a"), (t_c, smalls[2], "c"), (t_d, smalls[3], "d")):
+        assert not isinstance(out[t], Exception), f"request {name}: {out[t]}"
+        assert_same(out[t][0], _oracle(j), f"request {name} after a cancelled neighbour")
