@@ -17,13 +17,14 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "kc_oracle.cpp")
+_SRC_PAR = os.path.join(_HERE, "kc_cpu_parallel.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
 def build() -> str:
     """Compile liboracle.so with g++ (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC])
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, _SRC_PAR])
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -66,6 +67,10 @@ def _load():
                                   ctypes.POINTER(_Result)]
         lib.kco_count.restype = ctypes.c_int
         lib.kco_free.argtypes = [ctypes.POINTER(_Result)]
+        lib.kcp_count.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                  ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                                  ctypes.POINTER(_Result)]
+        lib.kcp_count.restype = ctypes.c_int
         lib.kco_count_ext.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                       ctypes.POINTER(_Result), ctypes.POINTER(_Occ)]
@@ -111,6 +116,32 @@ def count(reads, offsets, k: int, min_freq: int = 1, max_freq: int = 0xFFFFFFFF,
                        min_freq, max_freq, hist_len, ctypes.byref(res))
     if rc != 0:
         raise ValueError(f"oracle rejected arguments (k={k}, lo={min_freq}, hi={max_freq}, H={hist_len})")
+    try:
+        n, kw = int(res.n_pairs), int(res.key_words)
+        kmers = np.ctypeslib.as_array(res.kmers, shape=(max(1, n * kw),))[: n * kw].copy().reshape(n, kw)
+        counts = np.ctypeslib.as_array(res.counts, shape=(max(1, n),))[:n].copy()
+        hist = np.ctypeslib.as_array(res.hist, shape=(hist_len,)).copy()
+        return OracleResult(kmers, counts, hist, int(res.n_windows), int(res.n_distinct),
+                            int(res.overflow_sum), int(res.max_count))
+    finally:
+        lib.kco_free(ctypes.byref(res))
+
+
+def count_parallel(reads, offsets, k: int, min_freq: int = 1, max_freq: int = 0xFFFFFFFF,
+                   hist_len: int = 65536, threads: int = 0) -> OracleResult:
+    """The same count on ``threads`` host threads (0: all cores), the CPU-parallel
+    baseline of kc_cpu_parallel.cpp: value-range shards from sampled splitters, one
+    ``std::sort`` per shard.  Its result is identical to ``count``."""
+    lib = _load()
+    reads, offsets = _arrays(reads, offsets)
+    n_reads = offsets.shape[0] - 1
+    threads = threads or (len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count())
+    res = _Result()
+    rc = lib.kcp_count(reads.ctypes.data, offsets.ctypes.data, n_reads, k, min_freq, max_freq, hist_len,
+                       int(threads), ctypes.byref(res))
+    if rc != 0:
+        lib.kco_free(ctypes.byref(res))
+        raise ValueError(f"parallel baseline failed (rc={rc}, k={k}, lo={min_freq}, hi={max_freq}, H={hist_len})")
     try:
         n, kw = int(res.n_pairs), int(res.key_words)
         kmers = np.ctypeslib.as_array(res.kmers, shape=(max(1, n * kw),))[: n * kw].copy().reshape(n, kw)

@@ -306,15 +306,70 @@ def cached(name: str, make) -> ReadSet:
         meta = np.load(mp)
         reads = np.load(rp, mmap_mode="r")
         offsets = np.load(op)
-        rs = make(meta_only=True)
+        if make is None:
+            rs = ReadSet(np.zeros(0, np.uint8), np.zeros(1, np.uint64), *(int(x) for x in meta[:4]), name)
+        else:
+            rs = make(meta_only=True)
         rs.reads, rs.offsets = np.asarray(reads), offsets
         return rs
     rs = make(meta_only=False)
     os.makedirs(d, exist_ok=True)
-    np.save(rp, rs.reads)
-    np.save(op, rs.offsets)
-    np.save(mp, np.array([rs.k, rs.m, rs.min_freq, rs.max_freq], dtype=np.int64))
+    # written under temporary names and renamed, meta last: a cache entry is complete
+    # exactly when its meta file exists, even if several processes fill the cache
+    tag = f".tmp{os.getpid()}.npy"
+    np.save(rp + tag, rs.reads)
+    np.save(op + tag, rs.offsets)
+    np.save(mp + tag, np.array([rs.k, rs.m, rs.min_freq, rs.max_freq], dtype=np.int64))
+    os.replace(rp + tag, rp)
+    os.replace(op + tag, op)
+    os.replace(mp + tag, mp)
     return rs
+
+
+def _batch_cache_name(i: int, scale: float) -> str:
+    return f"batch{i:03d}_s{scale:g}"
+
+
+def _make_batch_cached(args) -> int:
+    i, scale = args
+
+    def make(meta_only=False):
+        if meta_only:
+            p = batch_set_params(i)
+            return ReadSet(np.zeros(0, np.uint8), np.zeros(1, np.uint64), p["k"], p["m"], 2, 50, f"batch{i:03d}")
+        return batch_set(i, scale)
+    cached(_batch_cache_name(i, scale), make)
+    return i
+
+
+def batch_sets(n_sets: int = 256, scale: float = 1.0, workers: int = 0) -> List[ReadSet]:
+    """Read sets 0 .. n_sets-1 of the batched workload, generated by ``workers`` processes
+    (0: one per host core, at most 16) into the on-disk cache and memory-mapped from it.
+    Each set depends only on its own seed, so the result is the same for any worker count."""
+    todo = [i for i in range(n_sets)
+            if not os.path.exists(os.path.join(_cache_dir(), _batch_cache_name(i, scale), "meta.npy"))]
+    if todo:
+        n_cpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        workers = workers or min(16, n_cpu)
+        # largest sets first, so that the pool's tail is short
+        todo.sort(key=lambda i: -batch_set_params(i)["total"])
+        if workers > 1 and len(todo) > 1:
+            import multiprocessing as mp
+            with mp.get_context("spawn").Pool(workers) as pool:
+                for _ in pool.imap_unordered(_make_batch_cached, [(i, scale) for i in todo]):
+                    pass
+        else:
+            for i in todo:
+                _make_batch_cached((i, scale))
+    out = []
+    for i in range(n_sets):
+        rs = cached(_batch_cache_name(i, scale), None)
+        rs.name = f"batch{i:03d}"
+        p = batch_set_params(i)
+        rs.info = {"genome": max(20_000, int(p["genome"] * scale)), "total": max(10_000, int(p["total"] * scale)),
+                   "long": p["long"], "seed": 4000 + i}
+        out.append(rs)
+    return out
 
 
 def config(i: int, k: Optional[int] = None) -> ReadSet:

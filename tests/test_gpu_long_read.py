@@ -1,7 +1,12 @@
 """Parity at the long-read configuration's full size (1 Gbp of lognormal reads, k=31 with
 u64 keys and k=51 with 128-bit keys), in the launch configuration bench.py times.
 
-The oracle cannot sort a billion windows in a test, so the check is
+The oracle's full result on this workload is stored as digests
+(tests/golden/long_read_digests.json, written by tests/golden/make_digests.py, which
+calls only the generator and the oracle): every pair, count and histogram bin is
+compared through SHA-256 of the arrays, with per-top-8-bit-range digests that name the
+key range of a mismatch, and the totals exactly.  The inputs' SHA-256 is checked first,
+so a drift of the generator cannot pass as a match.  On top of that:
 * exact properties at full size: total count = number of valid windows (closed form from
   the reads' ACGT runs), histogram sums, filtered pairs = histogram mass in the window,
   strict ascending order;
@@ -9,12 +14,18 @@ The oracle cannot sort a billion windows in a test, so the check is
   oracle's count, and 150 random windows must appear with the oracle's count exactly when
   that count is inside the frequency window.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 from paper_2407_07718_amd import synth
+from tests.golden import digests
 from tests.gpu_util import device_count
+
+_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "long_read_digests.json")
 
 pytestmark = pytest.mark.gpu
 
@@ -54,8 +65,17 @@ def _as_int(row) -> int:
 def test_long_read_full_size(k):
     rs = synth.config(3, k=k)
     print(f"case long-read full size: k={k} m={rs.m} bases={rs.n_bases} reads={rs.n_reads}", flush=True)
-    got = device_count(rs.reads, rs.offsets, k, rs.m, rs.min_freq, rs.max_freq, 65536)
+    with open(_GOLDEN) as f:
+        gold = json.load(f)
+    assert digests.input_digest(rs.reads, rs.offsets) == gold["inputs"], "generator drift: inputs differ"
+    got = device_count(rs.reads, rs.offsets, k, rs.m, rs.min_freq, rs.max_freq, gold["hist_len"])
     t = got.totals
+    # every pair, count and histogram bin against the oracle's stored result
+    d = digests.result_digest(got.kmers, got.counts, got.hist, k, t["n_windows"], t["n_distinct"],
+                              t["overflow_sum"], t["max_count"])
+    bad = digests.diff(d, gold[f"k{k}"])
+    assert not bad, "differs from the oracle: " + "; ".join(bad)
+    assert t["n_pairs"] == gold[f"k{k}"]["n_pairs"]
     H = got.hist.shape[0]
     cs = np.arange(H, dtype=np.uint64)
     # exact properties

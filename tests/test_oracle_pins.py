@@ -346,3 +346,51 @@ def test_ext_properties(k):
             assert occ == sorted(set(occ))
             for r, p in occ:
                 assert canonical_str(seqs[r][p:p + k]) == want
+
+
+# ---------------------------------------------------------------- CPU-parallel baseline
+def _same_result(a, b, label):
+    assert np.array_equal(a.kmers, b.kmers), f"{label}: k-mers"
+    assert np.array_equal(a.counts, b.counts), f"{label}: counts"
+    assert np.array_equal(a.hist, b.hist), f"{label}: histogram"
+    assert (a.n_windows, a.n_distinct, a.overflow_sum, a.max_count) == \
+        (b.n_windows, b.n_distinct, b.overflow_sum, b.max_count), f"{label}: totals"
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_parallel_baseline_equals_oracle_random(threads):
+    """The multi-threaded baseline (sampled value-range shards, one std::sort per shard,
+    rolling windows) returns exactly the oracle's result."""
+    rng = np.random.Generator(np.random.PCG64(9000 + threads))
+    for case in range(60):
+        k = int(rng.integers(1, 64))
+        reads, offsets = synth.random_small(rng, int(rng.integers(0, 60)), int(rng.integers(0, 200)), p_bad=0.03)
+        lo = int(rng.integers(1, 4))
+        hi = int(rng.integers(lo, 10))
+        H = int(rng.integers(2, 40))
+        _same_result(oracle.count_parallel(reads, offsets, k, lo, hi, H, threads=threads),
+                     oracle.count(reads, offsets, k, lo, hi, H), f"case {case} k={k} T={threads}")
+
+
+@pytest.mark.parametrize("k", [21, 31, 51])
+def test_parallel_baseline_equals_oracle_repeats(k):
+    """Repeated genome (many shards share heavy values): 40 kb genome with repeat
+    families, 3,000 reads of 100-400 bp."""
+    rng = np.random.Generator(np.random.PCG64(k))
+    g = synth.uniform_genome(rng, 40_000)
+    synth.add_repeat_families(rng, g, families=10, len_lo=200, len_hi=600, copies_lo=5, copies_hi=20)
+    reads, offsets = synth.sample_reads(rng, g, rng.integers(100, 401, 3000), p_sub=0.01, p_n=0.002)
+    ref = oracle.count(reads, offsets, k, 2, 50, 1000)
+    for threads in (2, 5, 16):
+        _same_result(oracle.count_parallel(reads, offsets, k, 2, 50, 1000, threads=threads), ref,
+                     f"k={k} T={threads}")
+
+
+def test_parallel_baseline_edge_cases():
+    empty_r, empty_o = np.zeros(0, np.uint8), np.zeros(1, np.uint64)
+    for threads in (1, 4):
+        r = oracle.count_parallel(empty_r, empty_o, 31, 1, 10, 16, threads=threads)
+        assert r.n_pairs == 0 and r.n_windows == 0 and int(r.hist.sum()) == 0
+        reads, offsets = synth.from_strings(["NNNN", "ACGTACGTAC", "", "acgtnACGT"])
+        _same_result(oracle.count_parallel(reads, offsets, 3, 1, 10, 16, threads=threads),
+                     oracle.count(reads, offsets, 3, 1, 10, 16), f"strings T={threads}")
