@@ -135,6 +135,28 @@ int kc_count_device_async(const uint8_t *d_reads, uint64_t total_bases, const ui
                           size_t workspace_bytes, uint64_t *d_kmers, uint32_t *d_counts,
                           uint64_t pair_capacity, uint64_t *d_hist, kc_totals *d_totals, void *stream);
 
+/* Bytes of the static device buffer that kc_count_device_noalloc uses as its workspace. */
+#define KC_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The same count as
+ * kc_count_device_async (same arguments, outputs and totals), without the workspace
+ * arguments: the workspace is a static device buffer of KC_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends.  The call allocates and
+ * frees no device memory and does not wait: read *d_totals after synchronizing the stream
+ * (totals.flags != 0 marks a failed count, n_pairs > pair_capacity a truncation).  The
+ * first call on a device looks up the buffer's address on that device.
+ *   Errors: KC_EINVAL as kc_count_device; KC_ENOMEM when kc_workspace_size(total_bases,
+ *   n_reads, k, cfg) exceeds KC_NOALLOC_SCRATCH_BYTES (about 5.3 M bases at k <= 31,
+ *   2.9 M bases at k >= 32); KC_EDEVICE if the buffer cannot be located.
+ *   Every call on one GPU shares that GPU's buffer (it keeps the last call's contents;
+ *   each count clears what it needs): calls that overlap on one GPU, from two streams or
+ *   two threads, race and must be serialized by the caller. */
+int kc_count_device_noalloc(const uint8_t *d_reads, uint64_t total_bases, const uint64_t *d_offsets,
+                            uint64_t n_reads, int k, int m, uint32_t min_freq, uint32_t max_freq,
+                            uint64_t hist_len, const kc_config *cfg, uint64_t *d_kmers, uint32_t *d_counts,
+                            uint64_t pair_capacity, uint64_t *d_hist, kc_totals *d_totals, void *stream);
+
 /* ---------------------------------------------------------------- extension version
  * The count with extension information (Section 2.2: a k-mer may carry the ID of the read
  * it came from and its position in that read; Section 3.3 compresses that information

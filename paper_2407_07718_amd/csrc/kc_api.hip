@@ -1065,6 +1065,63 @@ int kc_count_device(const uint8_t* d_reads, uint64_t total_bases, const uint64_t
   return KC_OK;
 }
 
+// ---------------------------------------------------------------- no-allocation entry point
+// The workspace of kc_count_device_noalloc: one static device buffer per GPU, held for
+// the life of the process.  Host code never uses the array's name as an address (on the
+// host it is only a stand-in for the symbol); it uses the per-device address that
+// hipGetSymbolAddress returns.
+}  // extern "C"
+
+static __device__ __align__(256) unsigned char scratch[KC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Set-up on the first call on a device (with that device current): the device address of
+// `scratch`, and the launch facts of the count, so that later calls make no queries.
+int scratch_for_device(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(KC_EDEVICE, "device %d beyond the supported range", dev);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(KC_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    if ((reinterpret_cast<uintptr_t>(p) & 255) != 0) return fail(KC_EDEVICE, "scratch buffer not 256-byte aligned");
+    int rc = warm_launch_facts();
+    if (rc) return rc;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int kc_count_device_noalloc(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* d_offsets,
+                            uint64_t n_reads, int k, int m, uint32_t min_freq, uint32_t max_freq, uint64_t hist_len,
+                            const kc_config* cfg, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_capacity,
+                            uint64_t* d_hist, kc_totals* d_totals, void* stream) {
+  g_err.clear();
+  int rc = check_args(k, m, min_freq, max_freq, hist_len);
+  if (rc) return rc;
+  if (total_bases >= (1ull << 32)) return fail(KC_EINVAL, "total_bases=%llu >= 2^32", (unsigned long long)total_bases);
+  Plan P;
+  if (!make_plan(total_bases, n_reads, total_bases, k, m, 1, cfg, &P)) return fail(KC_EINVAL, "bad kc_config");
+  if (P.bytes > KC_NOALLOC_SCRATCH_BYTES)
+    return fail(KC_ENOMEM, "needs %llu workspace bytes; the static scratch buffer holds %llu",
+                (unsigned long long)P.bytes, (unsigned long long)KC_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((rc = scratch_for_device(&ws))) return rc;
+  return device_common(d_reads, total_bases, d_offsets, n_reads, k, m, min_freq, max_freq, hist_len, cfg, ws,
+                       (size_t)KC_NOALLOC_SCRATCH_BYTES, d_kmers, d_counts, pair_capacity, d_hist, d_totals, stream);
+}
+
 int kc_profile(int enable) {
   g_profile = enable != 0;
   return KC_OK;

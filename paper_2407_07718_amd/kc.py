@@ -104,6 +104,9 @@ def _load() -> ctypes.CDLL:
     lib.kc_count_device.restype = i32
     lib.kc_count_device_async.argtypes = dev_args
     lib.kc_count_device_async.restype = i32
+    lib.kc_count_device_noalloc.argtypes = [vp, u64, vp, u64, i32, i32, u32, u32, u64, ctypes.POINTER(kc_config),
+                                            vp, vp, u64, vp, vp, vp]
+    lib.kc_count_device_noalloc.restype = i32
     P = ctypes.POINTER
     lib.kc_count_batch.argtypes = [u32, P(kc_job), P(kc_result), P(kc_config)]
     lib.kc_count_batch.restype = i32
@@ -369,6 +372,22 @@ def kc_count_device(d_reads, d_offsets, k: int, m: int, min_freq: int, max_freq:
         return tot.as_dict()
     _check(_lib.kc_count_device_async(*args))
     return None
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20   # KC_NOALLOC_SCRATCH_BYTES of include/kc.h
+
+
+def kc_count_device_noalloc(d_reads, d_offsets, k: int, m: int, min_freq: int, max_freq: int, hist_len: int,
+                            cfg: Optional[kc_config], d_kmers, d_counts, d_hist, d_totals, stream=None) -> None:
+    """kc_count_device_noalloc on torch tensors (as kc_count_device, without a workspace):
+    only queues the work on ``stream``; read ``d_totals`` after synchronizing it."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    cap = int(d_counts.shape[0]) if d_counts is not None else 0
+    _check(_lib.kc_count_device_noalloc(
+        _ptr(d_reads), int(d_reads.numel()), _ptr(d_offsets), int(d_offsets.numel()) - 1, k, m, min_freq, max_freq,
+        hist_len, ctypes.byref(cfg) if cfg is not None else None, _ptr(d_kmers), _ptr(d_counts), cap, _ptr(d_hist),
+        _ptr(d_totals), ctypes.c_void_p(st.cuda_stream)))
 
 
 class DeviceCounter:
