@@ -580,8 +580,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str) -> None:
     short = lambda n: n.split("(")[0].split("<")[0].strip().replace("void ", "")
     kernels, total = {}, 0.0
     for name in sorted(set(fe) | set(wr)):
-        if "copy" in name.lower():
-            continue
+        if not short(name).startswith("k_"):
+            continue            # calibration copy and fill, torch's own kernels
         f_avg = float(np.mean(list(fe.get(name, {0: 0.0}).values())))
         w_avg = float(np.mean(list(wr.get(name, {0: 0.0}).values())))
         key = short(name)

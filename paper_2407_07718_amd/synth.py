@@ -344,13 +344,13 @@ def _make_batch_cached(args) -> int:
 
 def batch_sets(n_sets: int = 256, scale: float = 1.0, workers: int = 0) -> List[ReadSet]:
     """Read sets 0 .. n_sets-1 of the batched workload, generated by ``workers`` processes
-    (0: one per host core, at most 16) into the on-disk cache and memory-mapped from it.
+    (0: one per host core, at most 12) into the on-disk cache and memory-mapped from it.
     Each set depends only on its own seed, so the result is the same for any worker count."""
     todo = [i for i in range(n_sets)
             if not os.path.exists(os.path.join(_cache_dir(), _batch_cache_name(i, scale), "meta.npy"))]
     if todo:
         n_cpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-        workers = workers or min(16, n_cpu)
+        workers = workers or min(12, n_cpu)
         # largest sets first, so that the pool's tail is short
         todo.sort(key=lambda i: -batch_set_params(i)["total"])
         if workers > 1 and len(todo) > 1:
