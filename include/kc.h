@@ -50,7 +50,8 @@ typedef struct kc_config {
   uint32_t force_hbm;      /* 1 = route every bucket through the chunk-list merge (testing) */
   uint32_t small_variant;  /* on-chip sort block shape: 0 auto, 1 = 256x16, 2 = 512x16 */
   uint32_t lanes;          /* batch / server: concurrent stream lanes (0 = 8) */
-  uint64_t hbm_budget;     /* max device bytes; 0 = no limit other than free HBM */
+  uint64_t hbm_budget;     /* max bytes of a count's device workspace (see kc_workspace_size:
+                              above it a count runs in rounds); 0 = no limit other than free HBM */
   uint32_t no_graph;       /* batch: 1 = plain stream launches instead of one hipGraph */
   uint32_t autotune;       /* batch: 1 = tune bucket count and block shape per job class */
 } kc_config;
@@ -96,9 +97,11 @@ const char *kc_last_error(void);
 /* Host API.  Count the canonical k-mers of a read set held in host memory.
  *   reads, offsets: host pointers (borrowed, not modified); total bases = offsets[n_reads].
  *   k in [1, 63]; m in [1, min(k-1, 32)]; 1 <= min_freq <= max_freq; hist_len >= 2.
- *   cfg may be NULL.  On KC_OK, *out owns host arrays that kc_result_free releases.
+ *   cfg may be NULL; cfg->hbm_budget bounds the device workspace (rounds, see
+ *   kc_workspace_size).  On KC_OK, *out owns host arrays that kc_result_free releases.
  *   Errors: KC_EINVAL (arguments, non-monotone offsets, more than 2^32-1 windows),
- *   KC_ENOMEM, KC_EDEVICE. */
+ *   KC_ENOMEM (no plan fits the budget or free HBM; a count in rounds that could not
+ *   finish), KC_EDEVICE. */
 int kc_count(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k, int m,
              uint32_t min_freq, uint32_t max_freq, uint64_t hist_len, const kc_config *cfg,
              kc_result *out);
@@ -107,7 +110,22 @@ int kc_count(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, in
 void kc_result_free(kc_result *res);
 
 /* Bytes of device workspace kc_count_device needs for a read buffer of total_bases
- * bytes split into n_reads reads, at this k (0 on bad arguments). */
+ * bytes split into n_reads reads, at this k (0 on bad arguments, or when cfg->hbm_budget
+ * is set and no plan fits it).
+ *
+ * Memory-bounded counting (Section 3.1: with too little memory the paper sorts in place;
+ * Section 3.3: the exchange runs in rounds of bounded size).  When cfg->hbm_budget is
+ * smaller than the one-pass workspace, the plan counts in rounds and its workspace fits
+ * the budget: a count pass of the minimizer stage finds the records and k-mers of every
+ * coarse group of buckets; the groups are split into consecutive ranges that fit a
+ * round; each round regenerates the supermers of its groups from the 2-bit reads and
+ * partitions, sorts and counts them exactly as the one-pass count does; the survivors
+ * of all rounds are sorted by k-mer at the end.  A distinct k-mer lies in one bucket,
+ * hence in one round, so results are identical to a one-pass count.  What the fixed part
+ * (2-bit reads, masks, bucket tables) leaves of the budget goes half to the rounds and
+ * half to a pool for the survivors.  A count in rounds fails with KC_ENOMEM when one
+ * coarse group holds more k-mers than a round (extreme skew) or when the survivors
+ * outgrow the pool (e.g. min_freq = 1 on mostly distinct k-mers under a small budget). */
 size_t kc_workspace_size(uint64_t total_bases, uint64_t n_reads, int k, const kc_config *cfg);
 
 /* Device API.  Same count with every buffer in device memory owned by the caller.
@@ -119,7 +137,9 @@ size_t kc_workspace_size(uint64_t total_bases, uint64_t n_reads, int k, const kc
  *   The call waits for the stream, copies the totals to *totals_out (may be NULL) and
  *   returns KC_ETRUNC when n_pairs > pair_capacity (the first pair_capacity pairs are
  *   written, totals give the size needed); KC_EINVAL if the offsets are not monotone
- *   or exceed total_bases.  Calls on one workspace must not overlap. */
+ *   or exceed total_bases; KC_ENOMEM when cfg->hbm_budget admits no plan, or a count in
+ *   rounds could not finish (totals.flags bit 3: a bucket group larger than a round,
+ *   bit 4: survivors beyond the pool).  Calls on one workspace must not overlap. */
 int kc_count_device(const uint8_t *d_reads, uint64_t total_bases, const uint64_t *d_offsets,
                     uint64_t n_reads, int k, int m, uint32_t min_freq, uint32_t max_freq,
                     uint64_t hist_len, const kc_config *cfg, void *d_workspace, size_t workspace_bytes,
@@ -314,6 +334,8 @@ int kc_server_destroy(kc_server *s);
  *   5 wave_sort   (tiny buckets: one wave each)                     -- one kernel
  *   6 merge       (chunk lists: compact, HBM radix sort, summed runs)
  *   7 output      (survivor compaction, sort by key, copy, totals)
+ * A plain count in rounds (memory-bounded) uses 1 for the count pass and the round
+ * plan, 2 for all rounds (3-6 empty) and 7 for the final sort of the survivors.
  * An extension count (kc_count_ext*) uses the slots as 0 encode, 1 windows, 2 sort,
  * 3 runs, 4 emit (5-7 empty); under a memory budget its rounds are timed as one: slot 1
  * holds the key-range planning and slot 2 all rounds.

@@ -101,6 +101,12 @@ struct Plan {
   int log_c = 0, log_f = 0;
   u32 part_nblk = 1, part_spb = 1, nblk_cap = 1;   // extract blocks: this count's, and the bound over m
   u64 n_packed, n_mask, bytes = 0;
+  // Memory-bounded counting (rounds > 1): the coarse bucket groups are counted in rounds
+  // of at most cap_r records and cap_k k-mers; the survivors of all rounds collect in a
+  // pool of pool_cap pairs, sorted by key at the end.  max_rounds rounds are enqueued.
+  u32 rounds = 1, max_rounds = 1;
+  u64 cap_k = 0, cap_r = 0, pool_cap = 0;
+  u64 o_hrec = 0, o_hkm = 0, o_gsum = 0, o_rng = 0, o_bbase = 0, o_bcnt_r = 0, o_pool = 0, o_pmid = 0;
 };
 
 // Control words (all zeroed at the start of a count).
@@ -114,7 +120,11 @@ enum Ctrl : int {
   C_KL_N = 14,      // (k-mer, count) list entries
   C_KL_NC = 15,     // ... clamped to capacity
   C_NSEG = 16,      // key ranges of the survivors
-  C_WORDS = 17
+  C_ROUND_END = 17, // words [0, C_ROUND_END) but C_FLAGS start over in every round
+  C_ACC = 17,       // rounds: 10 running totals (see k_round_end)
+  C_POOL_N = 27,    // rounds: survivors in the pool so far
+  C_POOL_NC = 28,   // ... clamped to the pool's capacity
+  C_WORDS = 29
 };
 static_assert(C_META + 8 <= C_FLAGS, "meta overlaps the flags");
 
@@ -123,6 +133,8 @@ u32 small_cap(int key_words, u32 variant) {
   if (key_words == 1) return variant == 2 ? 512u * 16u : 256u * 16u;
   return variant == 2 ? 512u * 8u : 256u * 8u;
 }
+
+void plan_layout(Plan* p);
 
 bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, const kc_config* cfg,
                Plan* p) {
@@ -176,13 +188,25 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
     p->slots = std::max<u64>(R, 1) + (u64)EX_SPAN_MAX * (1 + spb_max);
   }
   (void)min_freq;
-  p->surv_cap = std::max<u64>(1, n_max);   // survivors sit at their bucket's k-mer slots first
-  const u64 w = 8ull * p->key_words;
-  const u64 tile = (u64)RADIX_T * (p->key_words == 1 ? RADIX_ITEMS_64 : RADIX_ITEMS_128);
-  p->nb_large = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(n_max, tile * 2)));
-  p->nb_surv = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(p->surv_cap, tile * 2)));
   p->n_packed = R / 16 + 16;
   p->n_mask = R / 32 + 16;
+  p->rounds = 1;
+  plan_layout(p);
+  return true;
+}
+
+// Byte offsets of every region.  One pass: regions sized for all k-mers.  Rounds: regions
+// sized for one round (cap_r records, cap_k k-mers) plus the count pass's histograms, the
+// round ranges and the survivor pool.
+void plan_layout(Plan* p) {
+  const bool rounds = p->rounds > 1;
+  const u64 n_k = rounds ? std::max<u64>(1, p->cap_k) : std::max<u64>(1, p->n_max);
+  p->rec_cap = rounds ? std::max<u64>(1, p->cap_r) : n_k;
+  p->surv_cap = n_k;   // a count's (or round's) survivors sit at their bucket's k-mer slots first
+  const u64 w = 8ull * p->key_words;
+  const u64 tile = (u64)RADIX_T * (p->key_words == 1 ? RADIX_ITEMS_64 : RADIX_ITEMS_128);
+  p->nb_large = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(n_k, tile * 2)));
+  p->nb_surv = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(p->surv_cap, tile * 2)));
   u64 o = 0;
   auto take = [&](u64 bytes) {
     u64 r = o;
@@ -190,7 +214,7 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
     return r;
   };
   const u64 rb = 4ull * p->rec_words;
-  const u64 N = p->rec_cap;
+  const u64 N = n_k;
   p->chunk_cap = N / p->cap_chunk + p->B + 1;
   p->kl_cap = N;
   p->o_packed = take(4 * p->n_packed);
@@ -203,8 +227,9 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   //      overwritten in place by the chunk lists, + list counts -> second sort buffer
   //   Z: survivors at their bucket's k-mer slots -> second buffer of the survivor sort
   // The final dense survivors use whichever of X / Y the chunk-list sort left free.
-  p->o_X = take(std::max(std::max(rb * p->slots, rb * N), (w + 4) * N));
-  p->o_Y = take(std::max(rb * N, (w + 4) * N));
+  // (rounds: records packed densely, cap_r of them; one pass: one slot per k-mer position)
+  p->o_X = take(std::max(rounds ? rb * p->rec_cap : std::max(rb * p->slots, rb * N), (w + 4) * N));
+  p->o_Y = take(std::max(rb * p->rec_cap, (w + 4) * N));
   p->o_Z = take((w + 4) * N);
   p->o_blkcnt = take(4ull * p->nblk_cap);
   p->o_bcnt = take(8ull * p->B);
@@ -234,8 +259,73 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   p->o_lch0 = take(4ull * p->B);
   p->o_seg = take(8ull * (std::max<u64>(p->B, (u64)256 << 8) + 2));
   p->o_mhist = take(4ull * 256 * MSD_NB);
+  if (rounds) {
+    const u64 C = 1ull << p->log_c;
+    p->o_hrec = take(4ull * C * p->nblk_cap);
+    p->o_hkm = take(4ull * C * p->nblk_cap);
+    p->o_gsum = take(16ull * C);
+    p->o_rng = take(4ull * (p->max_rounds + 1));
+    p->o_bcnt_r = take(4ull * p->nblk_cap);
+    p->o_bbase = take(4ull * p->nblk_cap);
+    p->o_pool = take((w + 4) * std::max<u64>(1, p->pool_cap));
+    p->o_pmid = take((w + 4) * std::max<u64>(1, p->pool_cap));
+  }
   p->bytes = o;
-  return true;
+}
+
+// Under an HBM budget smaller than the one-pass workspace: rounds.  What the fixed part
+// (packed reads and masks, bucket tables, histograms) leaves of the budget goes half to
+// the survivor pool (two buffers of pool_cap pairs: the survivors and the key-range
+// split's second buffer) and half to the rounds (per k-mer of a round: three regions of
+// a (k-mer, count) pair plus a run head).  False when the budget cannot hold a round of
+// at least 16 on-chip chunks.
+bool plan_rounds(Plan* p, u64 budget) {
+  const u64 w = 8ull * p->key_words, rb = 4ull * p->rec_words;
+  const u64 per_k = 3 * (w + 4) + 4, per_pool = 2 * (w + 4);
+  Plan q = *p;
+  q.rounds = 2;
+  q.cap_k = q.cap_r = 1;
+  q.pool_cap = 1;
+  q.max_rounds = 1;
+  plan_layout(&q);
+  const u64 min_cap = 16ull * p->cap_chunk;
+  if (budget <= q.bytes + 1024 * 1024) return false;
+  const u64 free_b = budget - q.bytes - 1024 * 1024;   // (slack for alignment and the round table)
+  const u64 pool = std::max<u64>(1, std::min<u64>(p->n_max + 1, free_b / 2 / per_pool));
+  u64 cap = (free_b - std::min(free_b, pool * per_pool)) / per_k;
+  for (; cap >= min_cap; cap -= std::max<u64>(1, cap / 64)) {
+    q = *p;
+    q.rounds = 2;
+    q.cap_k = cap;
+    q.cap_r = cap * (w + 4) / rb;   // records of a round fit the regions sized for its k-mers
+    q.pool_cap = pool;
+    q.max_rounds = (u32)std::min<u64>(1u << 20, 2 * ceil_div(std::max<u64>(1, p->n_max), std::min(q.cap_k, q.cap_r)) + 1);
+    plan_layout(&q);
+    if (q.bytes <= budget) {
+      *p = q;
+      return true;
+    }
+  }
+  return false;
+}
+
+// The plan of a count under cfg->hbm_budget: one pass when it fits, else rounds.
+// KC_ENOMEM when not even rounds fit.
+// Pairs a count can report at most (the bound the outputs of the host API are sized for).
+u64 pair_bound(const Plan& p) { return p.rounds > 1 ? p.pool_cap : p.surv_cap; }
+
+// Message of a memory-bounded count that could not finish (totals.flags bits 3 and 4).
+const char* rounds_failure(u64 flags) {
+  return (flags & 8) ? "a bucket group holds more k-mers or records than a round of the budget"
+                     : "the survivors outgrow the memory-bounded pool of the budget";
+}
+
+int fit_budget(Plan* p, const kc_config* cfg) {
+  const u64 budget = cfg ? cfg->hbm_budget : 0;
+  if (!budget || p->bytes <= budget) return KC_OK;
+  if (plan_rounds(p, budget)) return KC_OK;
+  return fail(KC_ENOMEM, "no plan fits a workspace budget of %llu bytes (one pass needs %llu)",
+              (unsigned long long)budget, (unsigned long long)p->bytes);
 }
 
 int check_args(int k, int m, uint32_t lo, uint32_t hi, uint64_t hist_len) {
@@ -376,6 +466,243 @@ int seg_sort(K* keys, u32* vals, K* tmp_k, u32* tmp_v, K* out_k, u32* out_v, u64
   return KC_OK;
 }
 
+// Pointers of one count's workspace regions.
+template <typename K>
+struct Ws {
+  u32 *packed, *nmask, *starts, *recA, *ptmp_rec, *recB, *klsc, *s0c, *kl0c, *kl1c;
+  K *lk0, *s0k, *kl0k, *kl1k;
+  u64* bcnt;
+  u32 *recoff, *cursor, *small, *tiny, *klcnt, *kloff, *scnt, *soff, *large, *blkcnt, *chlen, *bc, *hp, *lch0, *phist,
+      *mhist;
+  u64 *kall, *bsum, *scanbuf, *lkoff, *ctrl, *chstart, *seg;
+  u64 *counters, *meta, *surv_n, *nruns, *surv_nc, *kl_n, *kl_nc;
+  u32* flags;
+};
+
+template <typename K>
+Ws<K> ws_ptrs(const Plan& P, void* ws) {
+  Ws<K> W;
+  const u64 N = P.kl_cap, WK = sizeof(K);
+  char* X = at<char>(ws, P.o_X);
+  char* Y = at<char>(ws, P.o_Y);
+  char* Z = at<char>(ws, P.o_Z);
+  W.packed = at<u32>(ws, P.o_packed);
+  W.nmask = at<u32>(ws, P.o_nmask);
+  W.starts = at<u32>(ws, P.o_starts);
+  W.recA = reinterpret_cast<u32*>(X);                       // extract block slots
+  W.ptmp_rec = reinterpret_cast<u32*>(Y);                   // coarse partition
+  W.recB = reinterpret_cast<u32*>(X);                       // bucket order
+  W.lk0 = reinterpret_cast<K*>(Y);                          // large keys -> chunk lists
+  W.klsc = reinterpret_cast<u32*>(Y + WK * N);
+  W.s0k = reinterpret_cast<K*>(Z);                          // survivors at bucket slots
+  W.s0c = reinterpret_cast<u32*>(Z + WK * N);
+  W.kl0k = reinterpret_cast<K*>(X);                         // chunk-list sort buffers
+  W.kl0c = reinterpret_cast<u32*>(X + WK * N);
+  W.kl1k = reinterpret_cast<K*>(Y);
+  W.kl1c = reinterpret_cast<u32*>(Y + WK * N);
+  W.bcnt = at<u64>(ws, P.o_bcnt);
+  W.recoff = at<u32>(ws, P.o_recoff);
+  W.cursor = at<u32>(ws, P.o_cursor);
+  W.small = at<u32>(ws, P.o_small);
+  W.tiny = at<u32>(ws, P.o_tiny);
+  W.kall = at<u64>(ws, P.o_kall);
+  W.klcnt = at<u32>(ws, P.o_klcnt);
+  W.kloff = at<u32>(ws, P.o_kloff);
+  W.scnt = at<u32>(ws, P.o_scnt);
+  W.soff = at<u32>(ws, P.o_soff);
+  W.bsum = at<u64>(ws, P.o_bsum);
+  W.scanbuf = at<u64>(ws, P.o_scanbuf);
+  W.large = at<u32>(ws, P.o_large);
+  W.lkoff = at<u64>(ws, P.o_lkoff);
+  W.ctrl = at<u64>(ws, P.o_ctrl);
+  W.blkcnt = at<u32>(ws, P.o_blkcnt);
+  W.chstart = at<u64>(ws, P.o_chstart);
+  W.chlen = at<u32>(ws, P.o_chlen);
+  W.bc = at<u32>(ws, P.o_bc);
+  W.hp = at<u32>(ws, P.o_hp);
+  W.lch0 = at<u32>(ws, P.o_lch0);
+  W.phist = at<u32>(ws, P.o_phist);
+  W.seg = at<u64>(ws, P.o_seg);
+  W.mhist = at<u32>(ws, P.o_mhist);
+  W.counters = W.ctrl + C_COUNTERS;
+  W.meta = W.ctrl + C_META;
+  W.flags = reinterpret_cast<u32*>(W.ctrl + C_FLAGS);
+  W.surv_n = W.ctrl + C_SURV_N;
+  W.nruns = W.ctrl + C_NRUNS;
+  W.surv_nc = W.ctrl + C_SURV_NC;
+  W.kl_n = W.ctrl + C_KL_N;
+  W.kl_nc = W.ctrl + C_KL_NC;
+  return W;
+}
+
+// From the extract stage's records to the survivors of every bucket, compacted into
+// out_k / out_c from the slot *out_base on (a null out_base: from slot 0) and at most out_cap
+// slots: partition, bucket plan, the per-bucket sorts and counts, the merge of the heavy
+// buckets' chunk lists.  One pass runs it once; a memory-bounded count once per round
+// (blk_base: the round's dense record slots of every extract block; no stage marks).
+template <typename K>
+int count_buckets(const Plan& P, const Ws<K>& W, const u32* blk_base, uint32_t lo, uint32_t hi, uint64_t hist_len,
+                  uint64_t* d_hist, DevTotals* d_tot, K* out_k, u32* out_c, const u64* out_base, u64 out_cap,
+                  bool marks, int n_cu, hipStream_t st) {
+  int rc = KC_OK;
+  if (marks) stage_mark(2, st);
+  {
+    PartArgs pp;
+    pp.rec = W.recA;
+    pp.blk_cnt = W.blkcnt;
+    pp.blk_slots = (u64)P.part_spb * P.span;
+    pp.nblk = P.part_nblk;
+    pp.log_c = P.log_c;
+    pp.log_f = P.log_f;
+    pp.rec_words = P.rec_words;
+    pp.hist = W.phist;
+    pp.tmp_rec = W.ptmp_rec;
+    pp.rec_out = W.recB;
+    pp.bcnt = W.bcnt;
+    pp.n_rec_ptr = W.counters;
+    pp.blk_base = blk_base;
+    const u64 nh = ((u64)1 << P.log_c) * P.part_nblk;
+    scan_u32(W.phist, W.phist, (const u64*)nullptr, nh, W.counters, W.scanbuf, st);   // counters[0] = records
+    if (P.rec_words == 4)
+      hipLaunchKernelGGL(k_part_scatter<4>, dim3(P.part_nblk), dim3(512), 0, st, pp);
+    else
+      hipLaunchKernelGGL(k_part_scatter<8>, dim3(P.part_nblk), dim3(512), 0, st, pp);
+    if (P.rec_words == 4)
+      hipLaunchKernelGGL(k_part_fine<4>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
+    else
+      hipLaunchKernelGGL(k_part_fine<8>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
+  }
+  {
+    PlanArgs pa{W.bcnt, P.B, P.cap_tiny, P.cap, P.cap_chunk, W.bsum, W.tiny, W.recoff, W.cursor, W.small, W.large,
+                W.lkoff, W.chstart, W.chlen, P.chunk_cap, W.kall, W.meta, W.lch0};
+    const u32 nbp = (P.B + PLAN_BLOCK - 1) / PLAN_BLOCK;
+    if (nbp == 1) {
+      hipLaunchKernelGGL(k_plan_write<true>, dim3(1), dim3(PLAN_T), 0, st, pa);
+    } else {
+      hipLaunchKernelGGL(k_plan_reduce, dim3(nbp), dim3(PLAN_T), 0, st, pa);
+      hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, st, pa, nbp);
+      hipLaunchKernelGGL(k_plan_write<false>, dim3(nbp), dim3(PLAN_T), 0, st, pa);
+    }
+  }
+
+  if (marks) stage_mark(3, st);
+  // ---- per bucket sort + count
+  CountArgs ca;
+  ca.rec = W.recB;
+  ca.rec_off = W.recoff;
+  ca.bcnt = W.bcnt;
+  ca.small_list = W.small;
+  ca.large_list = W.large;
+  ca.large_koff = W.lkoff;
+  ca.chunk_start = W.chstart;
+  ca.chunk_len = W.chlen;
+  ca.meta = W.meta;
+  ca.kall_off = W.kall;
+  ca.k = P.k;
+  ca.rec_words = P.rec_words;
+  ca.min_freq = lo;
+  ca.max_freq = hi;
+  ca.hist_len = hist_len;
+  ca.hist = d_hist;
+  ca.tot = d_tot;
+  ca.surv_k = W.s0k;           // sparse: bucket b's survivors at kall[b] + i
+  ca.surv_c = W.s0c;
+  ca.surv_cnt = W.scnt;
+  ca.lkeys = W.lk0;
+  ca.kl_k = W.lk0;             // a chunk's list overwrites its own keys (read into LDS first)
+  ca.kl_c = W.klsc;
+  ca.kl_cnt = W.klcnt;
+  // large buckets: expand their k-mers into HBM, cut later into chunks
+  hipLaunchKernelGGL((k_expand_large<K, 256>), dim3(1024), dim3(256), 0, st, ca, W.lk0);
+  if (marks) stage_mark(4, st);
+  constexpr bool WIDE = sizeof(K) == 16;
+  if (P.variant == 2) {
+    constexpr int T = 512, IT = WIDE ? 8 : 16;
+    int per_cu = 0;
+    if ((rc = blocks_per_cu(k_bucket_sort_count<K, T, IT>, T, &per_cu))) return rc;
+    hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+  } else {
+    constexpr int T = 256, IT = WIDE ? 8 : 16;
+    int per_cu = 0;
+    if ((rc = blocks_per_cu(k_bucket_sort_count<K, T, IT>, T, &per_cu))) return rc;
+    hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+  }
+  if (marks) stage_mark(5, st);
+  {
+    constexpr u32 WC = WIDE ? WAVE_CAP_128 : WAVE_CAP_64;
+    int per_cu = 0;
+    if ((rc = blocks_per_cu(k_wave_sort_count<K, WC, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &per_cu))) return rc;
+    hipLaunchKernelGGL((k_wave_sort_count<K, WC, WAVES_PER_BLOCK>), dim3(std::max(1, per_cu) * n_cu),
+                       dim3(WAVES_PER_BLOCK * 64), 0, st, ca, W.tiny, W.meta + 5);
+  }
+  if (marks) stage_mark(6, st);
+  // merge the chunks' (k-mer, count) lists: compact, sort by k-mer, sum each run's counts
+  scan_u32(W.klcnt, W.kloff, W.meta + 4, P.chunk_cap, W.kl_n, W.scanbuf, st, W.kl_nc, P.kl_cap);
+  hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.chunk_cap, 4, 4096), dim3(256), 0, st, W.lk0, W.klsc,
+                     W.chstart, (const u64*)nullptr, 0u, W.klcnt, W.kloff, W.meta + 4, P.chunk_cap, W.kl0k, W.kl0c,
+                     (const u64*)nullptr, ~0ull);
+  // each heavy bucket's lists are one segment, sorted on its own (in place)
+  hipLaunchKernelGGL(k_merge_segs, grid_for(P.B + 1, 256, 1024), dim3(256), 0, st, W.kloff, W.lch0, W.meta + 1,
+                     W.meta + 4, P.chunk_cap, W.kl_nc, W.seg);
+  int seg_grid = 0;
+  if ((rc = seg_sort<K>(W.kl0k, W.kl0c, W.kl1k, W.kl1c, W.kl0k, W.kl0c, ~0ull, W.seg, W.meta + 1,
+                        std::min<u64>(P.B, P.chunk_cap), 2 * P.k, true, nullptr, 0, n_cu, st, &seg_grid)))
+    return rc;
+  K* lks = W.kl0k;
+  u32* lvs = W.kl0c;
+  K* fk = W.kl1k;                    // the free buffer holds the merged runs' survivors
+  u32* fc = W.kl1c;
+  hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, W.kl_nc, W.bc);
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, W.bc, W.bc, (const u64*)nullptr, (u64)P.nb_large,
+                     W.nruns, (u64*)nullptr, 0ull);
+  hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, W.kl_nc, W.bc, W.hp);
+  hipLaunchKernelGGL((k_rle_runs<K>), dim3(RUN_BLOCKS), dim3(256), 0, st, ca, lks, lvs, W.kl_nc, W.hp, W.nruns, fk,
+                     fc, W.scnt + P.B);
+
+  if (marks) stage_mark(7, st);
+  // ---- compact the survivors (buckets, then merged runs)
+  scan_u32(W.scnt, W.soff, (const u64*)nullptr, (u64)P.B + RUN_BLOCKS, W.surv_n, W.scanbuf, st, W.surv_nc,
+           P.surv_cap);
+  hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.B, 4, 4096), dim3(256), 0, st, W.s0k, W.s0c, W.kall,
+                     (const u64*)nullptr, 0u, W.scnt, W.soff, (const u64*)nullptr, (u64)P.B, out_k, out_c, out_base,
+                     out_cap);
+  hipLaunchKernelGGL((k_gather_segments<K>), grid_for(RUN_BLOCKS, 4, 4096), dim3(256), 0, st, fk, fc,
+                     (const u64*)nullptr, W.nruns, RUN_BLOCKS, W.scnt + P.B, W.soff + P.B, (const u64*)nullptr,
+                     (u64)RUN_BLOCKS, out_k, out_c, out_base, out_cap);
+  return KC_OK;
+}
+
+// Survivors in[0, *n_ptr) (their count at most n_cap) -> split into key ranges by their
+// top bits (in -> mid -> in), then each range sorted on chip into the caller's buffers.
+template <typename K>
+int sort_survivors(const Plan& P, const Ws<K>& W, K* in_k, u32* in_c, K* mid_k, u32* mid_c, const u64* n_ptr,
+                   u64 n_cap, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap, int n_cu, hipStream_t st) {
+  MsdArgs ma;
+  ma.in_k = in_k;
+  ma.in_v = in_c;
+  ma.n_ptr = n_ptr;
+  ma.mid_k = mid_k;
+  ma.mid_v = mid_c;
+  ma.out_k = in_k;
+  ma.out_v = in_c;
+  ma.hist = W.mhist;
+  ma.seg = W.seg;
+  ma.n_seg = W.ctrl + C_NSEG;
+  ma.nbits = 2 * P.k;
+  ma.target = seg_range_target<K>();
+  // blocks of the coarse pass: about 16K survivors each at most, up to MSD_NB
+  ma.nb = (u32)std::min<u64>(MSD_NB, std::max<u64>(1, ceil_div(n_cap, 16384)));
+  hipLaunchKernelGGL((k_msd_hist<K>), dim3(ma.nb), dim3(256), 0, st, ma);
+  scan_u32(ma.hist, ma.hist, (const u64*)nullptr, 256ull * ma.nb, (u64*)nullptr, W.scanbuf, st);
+  hipLaunchKernelGGL((k_msd_scatter<K>), dim3(ma.nb), dim3(512), 0, st, ma);
+  hipLaunchKernelGGL((k_msd_fine<K>), dim3(256), dim3(1024), 0, st, ma);
+  // the key ranges number 256 << g2, g2 growing with the survivor count (at most n_cap)
+  const u64 max_ranges = 256ull << msd_g2(n_cap, 2 * P.k, seg_range_target<K>());
+  int seg_grid = 0;
+  return seg_sort<K>(in_k, in_c, mid_k, mid_c, reinterpret_cast<K*>(d_kmers), d_counts, pair_cap, W.seg,
+                     W.ctrl + C_NSEG, max_ranges, 2 * P.k, false, n_ptr, seg_range_target<K>(), n_cu, st, &seg_grid);
+}
+
 template <typename K>
 int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_offsets, uint32_t lo, uint32_t hi,
             uint64_t hist_len, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap, uint64_t* d_hist,
@@ -383,56 +710,8 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   int n_cu = 0;
   int rc = device_info(&n_cu);
   if (rc) return rc;
-  const u64 N = P.rec_cap, RB = 4ull * P.rec_words, WK = sizeof(K);
-  char* X = at<char>(ws, P.o_X);
-  char* Y = at<char>(ws, P.o_Y);
-  char* Z = at<char>(ws, P.o_Z);
-  u32* packed = at<u32>(ws, P.o_packed);
-  u32* nmask = at<u32>(ws, P.o_nmask);
-  u32* starts = at<u32>(ws, P.o_starts);
-  u32* recA = reinterpret_cast<u32*>(X);                       // extract block slots
-  u32* ptmp_rec = reinterpret_cast<u32*>(Y);                   // coarse partition
-  u32* recB = reinterpret_cast<u32*>(X);                       // bucket order
-  K* lk0 = reinterpret_cast<K*>(Y);                            // large keys -> chunk lists
-  u32* klsc = reinterpret_cast<u32*>(Y + WK * N);
-  K* s0k = reinterpret_cast<K*>(Z);                            // survivors at bucket slots
-  u32* s0c = reinterpret_cast<u32*>(Z + WK * N);
-  K* kl0k = reinterpret_cast<K*>(X);                           // chunk-list sort buffers
-  u32* kl0c = reinterpret_cast<u32*>(X + WK * N);
-  K* kl1k = reinterpret_cast<K*>(Y);
-  u32* kl1c = reinterpret_cast<u32*>(Y + WK * N);
-  u64* bcnt = at<u64>(ws, P.o_bcnt);
-  u32* recoff = at<u32>(ws, P.o_recoff);
-  u32* cursor = at<u32>(ws, P.o_cursor);
-  u32* small = at<u32>(ws, P.o_small);
-  u32* tiny = at<u32>(ws, P.o_tiny);
-  u64* kall = at<u64>(ws, P.o_kall);
-  u32* klcnt = at<u32>(ws, P.o_klcnt);
-  u32* kloff = at<u32>(ws, P.o_kloff);
-  u32* scnt = at<u32>(ws, P.o_scnt);
-  u32* soff = at<u32>(ws, P.o_soff);
-  u64* bsum = at<u64>(ws, P.o_bsum);
-  u64* scanbuf = at<u64>(ws, P.o_scanbuf);
-  u32* large = at<u32>(ws, P.o_large);
-  u64* lkoff = at<u64>(ws, P.o_lkoff);
-  u64* ctrl = at<u64>(ws, P.o_ctrl);
-  u32* cnt_large = at<u32>(ws, P.o_cnt_large);
-  u32* cnt_surv = at<u32>(ws, P.o_cnt_surv);
-  u32* tot_large = at<u32>(ws, P.o_tot_large);
-  u32* tot_surv = at<u32>(ws, P.o_tot_surv);
-  u32* blkcnt = at<u32>(ws, P.o_blkcnt);
-  u64* chstart = at<u64>(ws, P.o_chstart);
-  u32* chlen = at<u32>(ws, P.o_chlen);
-  u32* bc = at<u32>(ws, P.o_bc);
-  u32* hp = at<u32>(ws, P.o_hp);
-  u64* counters = ctrl + C_COUNTERS;
-  u64* meta = ctrl + C_META;
-  u32* flags = reinterpret_cast<u32*>(ctrl + C_FLAGS);
-  u64* surv_n = ctrl + C_SURV_N;
-  u64* nruns = ctrl + C_NRUNS;
-  u64* surv_nc = ctrl + C_SURV_NC;
-  u64* kl_n = ctrl + C_KL_N;
-  u64* kl_nc = ctrl + C_KL_NC;
+  Ws<K> W = ws_ptrs<K>(P, ws);
+  const bool rounds = P.rounds > 1;
 
   // zero everything that accumulates (one launch)
   stage_mark(0, st);
@@ -447,25 +726,25 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
       ++fl.cnt;
       most = std::max(most, n_words);
     };
-    add(ctrl, 2ull * C_WORDS);
+    add(W.ctrl, 2ull * C_WORDS);
     add(d_hist, 2ull * hist_len);
     add(d_tot, sizeof(DevTotals) / 4);
-    add(starts, P.n_mask);
-    add(scnt, P.B);
-    add(packed + 2 * n32, P.n_packed - 2 * n32);
-    add(nmask + n32, P.n_mask - n32);
+    add(W.starts, P.n_mask);
+    add(W.scnt, P.B);
+    add(W.packed + 2 * n32, P.n_packed - 2 * n32);
+    add(W.nmask + n32, P.n_mask - n32);
     hipLaunchKernelGGL(k_fill_multi, grid_for(most, 256, 4096), dim3(256), 0, st, fl);
   }
 
   // ---- stage 1: encode, read starts, minimizers and supermers, bucket partition
-  if (P.R) hipLaunchKernelGGL(k_pack, grid_for(n32, 256), dim3(256), 0, st, d_reads, P.R, packed, nmask);
+  if (P.R) hipLaunchKernelGGL(k_pack, grid_for(n32, 256), dim3(256), 0, st, d_reads, P.R, W.packed, W.nmask);
   if (P.n_reads)
-    hipLaunchKernelGGL(k_read_starts, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R, starts,
-                       flags);
+    hipLaunchKernelGGL(k_read_starts, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R,
+                       W.starts, W.flags);
   ExtractArgs ea;
-  ea.packed = packed;
-  ea.nmask = nmask;
-  ea.starts = starts;
+  ea.packed = W.packed;
+  ea.nmask = W.nmask;
+  ea.starts = W.starts;
   ea.offsets = d_offsets;
   ea.n_reads = P.n_reads;
   ea.R = P.R;
@@ -478,170 +757,96 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
   ea.span = P.span;
   ea.spb = P.part_spb;
   ea.blk_slots = (u64)P.part_spb * P.span;
-  ea.rec = recA;
-  ea.blk_cnt = blkcnt;
-  ea.hist = at<u32>(ws, P.o_phist);
+  ea.rec = W.recA;
+  ea.blk_cnt = W.blkcnt;
+  ea.hist = W.phist;
   ea.log_f = P.log_f;
   ea.C = 1u << P.log_c;
   ea.n_span_cap = P.n_span_cap;
   ea.n_packed = P.n_packed;
   ea.n_mask = P.n_mask;
+  ea.blk_base = nullptr;
+  ea.rng = nullptr;
+  ea.hist_km = nullptr;
+  K* s1k = W.kl0k;   // dense survivors of a one-pass count: where the sorted lists were
+  u32* s1c = W.kl0c;
   stage_mark(1, st);
-  if (P.rec_words == 4)
-    hipLaunchKernelGGL(k_extract<4>, dim3(P.part_nblk), dim3(256), 0, st, ea);
-  else
-    hipLaunchKernelGGL(k_extract<8>, dim3(P.part_nblk), dim3(256), 0, st, ea);
-  stage_mark(2, st);
-  {
-    PartArgs pp;
-    pp.rec = recA;
-    pp.blk_cnt = blkcnt;
-    pp.blk_slots = ea.blk_slots;
-    pp.nblk = P.part_nblk;
-    pp.log_c = P.log_c;
-    pp.log_f = P.log_f;
-    pp.rec_words = P.rec_words;
-    pp.hist = ea.hist;
-    pp.tmp_rec = ptmp_rec;
-    pp.rec_out = recB;
-    pp.bcnt = bcnt;
-    pp.n_rec_ptr = counters;
-    const u64 nh = ((u64)1 << P.log_c) * P.part_nblk;
-    scan_u32(ea.hist, ea.hist, (const u64*)nullptr, nh, counters, scanbuf, st);   // counters[0] = records
+  if (!rounds) {
     if (P.rec_words == 4)
-      hipLaunchKernelGGL(k_part_scatter<4>, dim3(P.part_nblk), dim3(512), 0, st, pp);
+      hipLaunchKernelGGL((k_extract<4, EX_ONE>), dim3(P.part_nblk), dim3(256), 0, st, ea);
     else
-      hipLaunchKernelGGL(k_part_scatter<8>, dim3(P.part_nblk), dim3(512), 0, st, pp);
-    if (P.rec_words == 4)
-      hipLaunchKernelGGL(k_part_fine<4>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
-    else
-      hipLaunchKernelGGL(k_part_fine<8>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
-  }
-  {
-    PlanArgs pa{bcnt, P.B, P.cap_tiny, P.cap, P.cap_chunk, bsum, tiny, recoff, cursor, small, large, lkoff, chstart,
-                chlen, P.chunk_cap, kall, meta, at<u32>(ws, P.o_lch0)};
-    const u32 nbp = (P.B + PLAN_BLOCK - 1) / PLAN_BLOCK;
-    if (nbp == 1) {
-      hipLaunchKernelGGL(k_plan_write<true>, dim3(1), dim3(PLAN_T), 0, st, pa);
-    } else {
-      hipLaunchKernelGGL(k_plan_reduce, dim3(nbp), dim3(PLAN_T), 0, st, pa);
-      hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, st, pa, nbp);
-      hipLaunchKernelGGL(k_plan_write<false>, dim3(nbp), dim3(PLAN_T), 0, st, pa);
-    }
-  }
-
-  stage_mark(3, st);
-  // ---- per bucket sort + count
-  CountArgs ca;
-  ca.rec = recB;
-  ca.rec_off = recoff;
-  ca.bcnt = bcnt;
-  ca.small_list = small;
-  ca.large_list = large;
-  ca.large_koff = lkoff;
-  ca.chunk_start = chstart;
-  ca.chunk_len = chlen;
-  ca.meta = meta;
-  ca.kall_off = kall;
-  ca.k = P.k;
-  ca.rec_words = P.rec_words;
-  ca.min_freq = lo;
-  ca.max_freq = hi;
-  ca.hist_len = hist_len;
-  ca.hist = d_hist;
-  ca.tot = d_tot;
-  ca.surv_k = s0k;           // sparse: bucket b's survivors at kall[b] + i
-  ca.surv_c = s0c;
-  ca.surv_cnt = scnt;
-  ca.lkeys = lk0;
-  ca.kl_k = lk0;             // a chunk's list overwrites its own keys (read into LDS first)
-  ca.kl_c = klsc;
-  ca.kl_cnt = klcnt;
-  // large buckets: expand their k-mers into HBM, cut later into chunks
-  hipLaunchKernelGGL((k_expand_large<K, 256>), dim3(1024), dim3(256), 0, st, ca, lk0);
-  stage_mark(4, st);
-  constexpr bool WIDE = sizeof(K) == 16;
-  if (P.variant == 2) {
-    constexpr int T = 512, IT = WIDE ? 8 : 16;
-    int per_cu = 0;
-    if ((rc = blocks_per_cu(k_bucket_sort_count<K, T, IT>, T, &per_cu))) return rc;
-    hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+      hipLaunchKernelGGL((k_extract<8, EX_ONE>), dim3(P.part_nblk), dim3(256), 0, st, ea);
+    if ((rc = count_buckets<K>(P, W, nullptr, lo, hi, hist_len, d_hist, d_tot, s1k, s1c, nullptr, ~0ull, true, n_cu,
+                               st)))
+      return rc;
+    // ---- output: the survivors sorted by key straight into the caller's buffers
+    if ((rc = sort_survivors<K>(P, W, s1k, s1c, W.s0k, W.s0c, W.surv_nc, P.surv_cap, d_kmers, d_counts, pair_cap, n_cu,
+                                st)))
+      return rc;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, W.counters, W.surv_n, P.rec_cap, P.surv_cap,
+                       W.flags, W.meta, W.kl_n, P.B);
   } else {
-    constexpr int T = 256, IT = WIDE ? 8 : 16;
-    int per_cu = 0;
-    if ((rc = blocks_per_cu(k_bucket_sort_count<K, T, IT>, T, &per_cu))) return rc;
-    hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+    // ---- memory-bounded: count pass, round plan, then one pass per round of coarse groups
+    const u32 C = 1u << P.log_c;
+    u32* hrec = at<u32>(ws, P.o_hrec);
+    u32* hkm = at<u32>(ws, P.o_hkm);
+    u64* gsum = at<u64>(ws, P.o_gsum);
+    u32* rng = at<u32>(ws, P.o_rng);
+    u32* bcnt_r = at<u32>(ws, P.o_bcnt_r);
+    u32* bbase = at<u32>(ws, P.o_bbase);
+    K* pool_k = at<K>(ws, P.o_pool);
+    u32* pool_c = reinterpret_cast<u32*>(reinterpret_cast<char*>(pool_k) + sizeof(K) * P.pool_cap);
+    K* pmid_k = at<K>(ws, P.o_pmid);
+    u32* pmid_c = reinterpret_cast<u32*>(reinterpret_cast<char*>(pmid_k) + sizeof(K) * P.pool_cap);
+    u64* acc = W.ctrl + C_ACC;
+    u64* pool_n = W.ctrl + C_POOL_N;
+    ExtractArgs ec = ea;
+    ec.hist = hrec;
+    ec.hist_km = hkm;
+    if (P.rec_words == 4)
+      hipLaunchKernelGGL((k_extract<4, EX_COUNT>), dim3(P.part_nblk), dim3(256), 0, st, ec);
+    else
+      hipLaunchKernelGGL((k_extract<8, EX_COUNT>), dim3(P.part_nblk), dim3(256), 0, st, ec);
+    hipLaunchKernelGGL(k_group_sums, dim3(C), dim3(256), 0, st, hrec, hkm, P.part_nblk, gsum);
+    hipLaunchKernelGGL(k_round_plan, dim3(1), dim3(64), 0, st, gsum, C, P.cap_r, P.cap_k, P.max_rounds, rng, W.flags);
+    stage_mark(2, st);
+    for (u32 q = 0; q < P.max_rounds; ++q) {
+      {
+        FillList fl{};
+        fl.p[0] = (u32*)W.ctrl;
+        fl.n[0] = 2ull * C_FLAGS;
+        fl.p[1] = (u32*)(W.ctrl + C_SURV_N);
+        fl.n[1] = 2ull * (C_ROUND_END - C_SURV_N);
+        fl.p[2] = W.scnt;
+        fl.n[2] = P.B;
+        fl.cnt = 3;
+        hipLaunchKernelGGL(k_fill_multi, grid_for(P.B, 256, 4096), dim3(256), 0, st, fl);
+      }
+      hipLaunchKernelGGL(k_round_blocks, grid_for(P.part_nblk, 256, 1024), dim3(256), 0, st, hrec, P.part_nblk,
+                         rng + q, bcnt_r);
+      scan_u32(bcnt_r, bbase, (const u64*)nullptr, P.part_nblk, (u64*)nullptr, W.scanbuf, st);
+      ExtractArgs er = ea;
+      er.blk_base = bbase;
+      er.rng = rng + q;
+      if (P.rec_words == 4)
+        hipLaunchKernelGGL((k_extract<4, EX_ROUND>), dim3(P.part_nblk), dim3(256), 0, st, er);
+      else
+        hipLaunchKernelGGL((k_extract<8, EX_ROUND>), dim3(P.part_nblk), dim3(256), 0, st, er);
+      if ((rc = count_buckets<K>(P, W, bbase, lo, hi, hist_len, d_hist, d_tot, pool_k, pool_c, pool_n, P.pool_cap,
+                                 false, n_cu, st)))
+        return rc;
+      hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, st, W.counters, W.meta, W.surv_n, W.kl_n, P.rec_cap, acc,
+                         pool_n, P.pool_cap, W.flags);
+    }
+    for (int i = 3; i <= 6; ++i) stage_mark(i, st);
+    stage_mark(7, st);
+    // ---- output: every round's survivors sorted by key into the caller's buffers
+    hipLaunchKernelGGL(k_clamp_u64, dim3(1), dim3(64), 0, st, pool_n, P.pool_cap, W.ctrl + C_POOL_NC);
+    if ((rc = sort_survivors<K>(P, W, pool_k, pool_c, pmid_k, pmid_c, W.ctrl + C_POOL_NC, P.pool_cap, d_kmers,
+                                d_counts, pair_cap, n_cu, st)))
+      return rc;
+    hipLaunchKernelGGL(k_finalize_rounds, dim3(1), dim3(64), 0, st, d_tot, acc, pool_n, W.flags, P.B);
   }
-  stage_mark(5, st);
-  {
-    constexpr u32 WC = WIDE ? WAVE_CAP_128 : WAVE_CAP_64;
-    int per_cu = 0;
-    if ((rc = blocks_per_cu(k_wave_sort_count<K, WC, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &per_cu))) return rc;
-    hipLaunchKernelGGL((k_wave_sort_count<K, WC, WAVES_PER_BLOCK>), dim3(std::max(1, per_cu) * n_cu),
-                       dim3(WAVES_PER_BLOCK * 64), 0, st, ca, tiny, meta + 5);
-  }
-  stage_mark(6, st);
-  // merge the chunks' (k-mer, count) lists: compact, sort by k-mer, sum each run's counts
-  scan_u32(klcnt, kloff, meta + 4, P.chunk_cap, kl_n, scanbuf, st, kl_nc, P.kl_cap);
-  hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.chunk_cap, 4, 4096), dim3(256), 0, st, lk0, klsc, chstart,
-                     (const u64*)nullptr, 0u, klcnt, kloff, meta + 4, P.chunk_cap, kl0k, kl0c);
-  // each heavy bucket's lists are one segment, sorted on its own (in place)
-  u64* seg = at<u64>(ws, P.o_seg);
-  hipLaunchKernelGGL(k_merge_segs, grid_for(P.B + 1, 256, 1024), dim3(256), 0, st, kloff, at<u32>(ws, P.o_lch0), meta + 1,
-                     meta + 4, P.chunk_cap, kl_nc, seg);
-  int seg_grid = 0;
-  if ((rc = seg_sort<K>(kl0k, kl0c, kl1k, kl1c, kl0k, kl0c, ~0ull, seg, meta + 1, std::min<u64>(P.B, P.chunk_cap),
-                        2 * P.k, true, nullptr, 0, n_cu, st, &seg_grid)))
-    return rc;
-  K* lks = kl0k;
-  u32* lvs = kl0c;
-  K* fk = kl1k;                      // the free buffer holds the merged runs' survivors
-  u32* fc = kl1c;
-  K* s1k = lks;                      // dense survivors go where the sorted lists were
-  u32* s1c = lvs;
-  hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc);
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, bc, bc, (const u64*)nullptr, (u64)P.nb_large, nruns,
-                     (u64*)nullptr, 0ull);
-  hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, kl_nc, bc, hp);
-  hipLaunchKernelGGL((k_rle_runs<K>), dim3(RUN_BLOCKS), dim3(256), 0, st, ca, lks, lvs, kl_nc, hp, nruns, fk, fc,
-                     scnt + P.B);
-
-  stage_mark(7, st);
-  // ---- output: compact the survivors (buckets, then merged runs), sort them by key
-  scan_u32(scnt, soff, (const u64*)nullptr, (u64)P.B + RUN_BLOCKS, surv_n, scanbuf, st, surv_nc, P.surv_cap);
-  hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.B, 4, 4096), dim3(256), 0, st, s0k, s0c, kall, (const u64*)nullptr,
-                     0u, scnt, soff, (const u64*)nullptr, (u64)P.B, s1k, s1c);
-  hipLaunchKernelGGL((k_gather_segments<K>), grid_for(RUN_BLOCKS, 4, 4096), dim3(256), 0, st, fk, fc, (const u64*)nullptr,
-                     nruns, RUN_BLOCKS, scnt + P.B, soff + P.B, (const u64*)nullptr, (u64)RUN_BLOCKS, s1k, s1c);
-  // key ranges by the top bits (s1 -> s0 -> s1), then each range sorted into the output
-  {
-    MsdArgs ma;
-    ma.in_k = s1k;
-    ma.in_v = s1c;
-    ma.n_ptr = surv_nc;
-    ma.mid_k = s0k;
-    ma.mid_v = s0c;
-    ma.out_k = s1k;
-    ma.out_v = s1c;
-    ma.hist = at<u32>(ws, P.o_mhist);
-    ma.seg = seg;
-    ma.n_seg = ctrl + C_NSEG;
-    ma.nbits = 2 * P.k;
-    ma.target = seg_range_target<K>();
-    // blocks of the coarse pass: about 16K survivors each at most, up to MSD_NB
-    ma.nb = (u32)std::min<u64>(MSD_NB, std::max<u64>(1, ceil_div(P.surv_cap, 16384)));
-    hipLaunchKernelGGL((k_msd_hist<K>), dim3(ma.nb), dim3(256), 0, st, ma);
-    scan_u32(ma.hist, ma.hist, (const u64*)nullptr, 256ull * ma.nb, (u64*)nullptr, scanbuf, st);
-    hipLaunchKernelGGL((k_msd_scatter<K>), dim3(ma.nb), dim3(512), 0, st, ma);
-    hipLaunchKernelGGL((k_msd_fine<K>), dim3(256), dim3(1024), 0, st, ma);
-  }
-  // the key ranges number 256 << g2, g2 growing with the survivor count (at most surv_cap)
-  const u64 max_ranges = 256ull << msd_g2(P.surv_cap, 2 * P.k, seg_range_target<K>());
-  if ((rc = seg_sort<K>(s1k, s1c, s0k, s0c, reinterpret_cast<K*>(d_kmers), d_counts, pair_cap, seg, ctrl + C_NSEG,
-                        max_ranges, 2 * P.k, false, surv_nc, seg_range_target<K>(), n_cu, st, &seg_grid)))
-    return rc;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, d_tot, counters, surv_n, P.rec_cap, P.surv_cap, flags,
-                     meta, kl_n, P.B);
   stage_mark(8, st);
   HIP_TRY(hipGetLastError());
   return KC_OK;
@@ -699,11 +904,9 @@ int device_common(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* 
   Plan P;
   if (!make_plan(total_bases, n_reads, total_bases, k, m, 1, cfg, &P))
     return fail(KC_EINVAL, "bad kc_config");
+  if ((rc = fit_budget(&P, cfg))) return rc;
   if (ws_bytes < P.bytes)
     return fail(KC_EINVAL, "workspace of %zu bytes < %llu needed", ws_bytes, (unsigned long long)P.bytes);
-  if (cfg && cfg->hbm_budget && P.bytes > cfg->hbm_budget)
-    return fail(KC_ENOMEM, "workspace %llu bytes > budget %llu", (unsigned long long)P.bytes,
-                (unsigned long long)cfg->hbm_budget);
   return enqueue_any(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_hist,
                      reinterpret_cast<DevTotals*>(d_tot), reinterpret_cast<hipStream_t>(stream));
 }
@@ -1031,6 +1234,10 @@ size_t kc_workspace_size(uint64_t total_bases, uint64_t n_reads, int k, const kc
   if (k < 1 || k > 63) return 0;
   Plan P;
   if (!make_plan(total_bases, n_reads, total_bases, k, 1, 1, cfg, &P)) return 0;
+  if (fit_budget(&P, cfg)) {
+    g_err.clear();
+    return 0;
+  }
   return (size_t)P.bytes;
 }
 
@@ -1058,6 +1265,7 @@ int kc_count_device(const uint8_t* d_reads, uint64_t total_bases, const uint64_t
   HIP_TRY(hipStreamSynchronize(st));
   if (totals_out) *totals_out = t;
   if (t.flags & 1) return fail(KC_EINVAL, "offsets are not non-decreasing or exceed total_bases");
+  if (t.flags & 24) return fail(KC_ENOMEM, "%s", rounds_failure(t.flags));
   if (t.flags) return fail(KC_EDEVICE, "internal capacity exceeded (flags=%llu)", (unsigned long long)t.flags);
   if (t.n_pairs > pair_capacity)
     return fail(KC_ETRUNC, "%llu pairs > capacity %llu", (unsigned long long)t.n_pairs,
@@ -1113,6 +1321,7 @@ int kc_count_device_noalloc(const uint8_t* d_reads, uint64_t total_bases, const 
   if (total_bases >= (1ull << 32)) return fail(KC_EINVAL, "total_bases=%llu >= 2^32", (unsigned long long)total_bases);
   Plan P;
   if (!make_plan(total_bases, n_reads, total_bases, k, m, 1, cfg, &P)) return fail(KC_EINVAL, "bad kc_config");
+  if ((rc = fit_budget(&P, cfg))) return rc;
   if (P.bytes > KC_NOALLOC_SCRATCH_BYTES)
     return fail(KC_ENOMEM, "needs %llu workspace bytes; the static scratch buffer holds %llu",
                 (unsigned long long)P.bytes, (unsigned long long)KC_NOALLOC_SCRATCH_BYTES);
@@ -1174,12 +1383,11 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
                 (unsigned long long)R);
   Plan P;
   if (!make_plan(R, n_reads, n_max, k, m, min_freq, cfg, &P)) return fail(KC_EINVAL, "bad kc_config");
-  if (cfg && cfg->hbm_budget && P.bytes > cfg->hbm_budget)
-    return fail(KC_ENOMEM, "workspace %llu bytes > budget %llu", (unsigned long long)P.bytes,
-                (unsigned long long)cfg->hbm_budget);
+  if ((rc = fit_budget(&P, cfg))) return rc;
   const u64 w = 8ull * P.key_words;
+  const u64 pcap = pair_bound(P);
   const u64 in_bytes = align_up(R + 16, 256) + align_up(8 * (n_reads + 1), 256);
-  const u64 out_bytes = align_up(w * P.surv_cap, 256) + align_up(4 * P.surv_cap, 256) + align_up(sizeof(kc_totals), 256) +
+  const u64 out_bytes = align_up(w * pcap, 256) + align_up(4 * pcap, 256) + align_up(sizeof(kc_totals), 256) +
                         align_up(8 * hist_len, 256);
   size_t free_b = 0, total_b = 0;
   HIP_TRY(hipMemGetInfo(&free_b, &total_b));
@@ -1193,8 +1401,8 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
   uint64_t* d_offsets = reinterpret_cast<uint64_t*>(dmem + P.bytes + align_up(R + 16, 256));
   char* ob = dmem + P.bytes + in_bytes;
   uint64_t* d_kmers = reinterpret_cast<uint64_t*>(ob);
-  uint32_t* d_counts = reinterpret_cast<uint32_t*>(ob + align_up(w * P.surv_cap, 256));
-  kc_totals* d_tot = reinterpret_cast<kc_totals*>(ob + align_up(w * P.surv_cap, 256) + align_up(4 * P.surv_cap, 256));
+  uint32_t* d_counts = reinterpret_cast<uint32_t*>(ob + align_up(w * pcap, 256));
+  kc_totals* d_tot = reinterpret_cast<kc_totals*>(ob + align_up(w * pcap, 256) + align_up(4 * pcap, 256));
   uint64_t* d_hist = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(d_tot) + align_up(sizeof(kc_totals), 256));
   hipStream_t st = nullptr;
   auto cleanup = [&](int code) {
@@ -1206,13 +1414,14 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
     return cleanup(fail(KC_EDEVICE, "H2D reads failed"));
   if (hipMemcpyAsync(d_offsets, offsets, 8 * (n_reads + 1), hipMemcpyHostToDevice, st) != hipSuccess)
     return cleanup(fail(KC_EDEVICE, "H2D offsets failed"));
-  rc = enqueue_any(P, ws, d_reads, d_offsets, min_freq, max_freq, hist_len, d_kmers, d_counts, P.surv_cap, d_hist,
+  rc = enqueue_any(P, ws, d_reads, d_offsets, min_freq, max_freq, hist_len, d_kmers, d_counts, pcap, d_hist,
                    reinterpret_cast<DevTotals*>(d_tot), st);
   if (rc) return cleanup(rc);
   kc_totals t;
   if (hipMemcpyAsync(&t, d_tot, sizeof(t), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return cleanup(fail(KC_EDEVICE, "count failed: %s", hipGetErrorString(hipGetLastError())));
+  if (t.flags & 24) return cleanup(fail(KC_ENOMEM, "%s", rounds_failure(t.flags)));
   if (t.flags) return cleanup(fail(KC_EDEVICE, "internal capacity exceeded (flags=%llu)", (unsigned long long)t.flags));
   out->n_pairs = t.n_pairs;
   out->key_words = (uint32_t)P.key_words;

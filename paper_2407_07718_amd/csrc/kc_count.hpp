@@ -18,7 +18,8 @@ struct DevTotals {
   u64 overflow_sum;   // sum of counts that fall into the last histogram bin
   u64 max_count;
   u64 n_records;      // supermer records written
-  u64 flags;          // bit 0: bad offsets, bit 1: record buffer overflow, bit 2: survivor overflow
+  u64 flags;          // bit 0: bad offsets, bit 1: record buffer overflow, bit 2: survivor overflow;
+                      // rounds: bit 3: a bucket group exceeds a round, bit 4: survivors exceed the pool
   u64 large_keys;     // k-mers of large buckets
   u64 tiny_buckets, tiny_kmers, small_buckets, small_kmers, large_buckets, chunks, list_entries, buckets;
   u64 n_occ;          // extension version: occurrences of the reported k-mers
@@ -907,8 +908,11 @@ __global__ __launch_bounds__(256) void k_gather_segments(const K* __restrict__ s
                                                          const u64* __restrict__ base_range_n, u32 base_range_nb,
                                                          const u32* __restrict__ cnt, const u32* __restrict__ off,
                                                          const u64* __restrict__ n_seg_ptr, u64 n_seg_max,
-                                                         K* __restrict__ dst_k, u32* __restrict__ dst_c) {
+                                                         K* __restrict__ dst_k, u32* __restrict__ dst_c,
+                                                         const u64* __restrict__ dst_base = nullptr,
+                                                         u64 dst_cap = ~0ull) {
   const u64 n_seg = n_seg_ptr ? min(*n_seg_ptr, n_seg_max) : n_seg_max;
+  const u64 db = dst_base ? *dst_base : 0ull;   // rounds: the pool's fill so far
   const u64 wave = (blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6;
   const u64 n_waves = ((u64)gridDim.x * blockDim.x) >> 6;
   const u32 lane = lane_id();
@@ -924,10 +928,12 @@ __global__ __launch_bounds__(256) void k_gather_segments(const K* __restrict__ s
       const u64 per = (nr + base_range_nb - 1) / base_range_nb;
       base = min(nr, i * per);
     }
-    const u64 o = off[i];
+    const u64 o = db + off[i];
     for (u32 j = lane; j < c; j += 64) {
-      dst_k[o + j] = src_k[base + j];
-      dst_c[o + j] = src_c[base + j];
+      if (o + j < dst_cap) {
+        dst_k[o + j] = src_k[base + j];
+        dst_c[o + j] = src_c[base + j];
+      }
     }
   }
 }
@@ -942,6 +948,52 @@ __global__ __launch_bounds__(256) void k_copy_pairs(const K* __restrict__ sk, co
     ok[i] = sk[i];
     oc[i] = sc[i];
   }
+}
+
+// Memory-bounded counting: after each round its figures join the running totals
+// (acc: windows, records, large k-mers, tiny buckets, tiny k-mers, small buckets, small
+// k-mers, large buckets, chunks, list entries) and its survivors, gathered behind the
+// previous rounds' in the pool, advance the pool's fill.  Flag bit 1: a round's records
+// overflowed; bit 4: the survivors outgrew the pool.
+__global__ void k_round_end(const u64* counters, const u64* meta, const u64* surv_n, const u64* kl_n, u64 rec_cap,
+                            u64* acc, u64* pool_n, u64 pool_cap, u32* flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  acc[0] += meta[2] + meta[6] + meta[7];
+  acc[1] += counters[0];
+  acc[2] += meta[2];
+  acc[3] += meta[5];
+  acc[4] += meta[6];
+  acc[5] += meta[0];
+  acc[6] += meta[7];
+  acc[7] += meta[1];
+  acc[8] += meta[4];
+  acc[9] += *kl_n;
+  if (counters[0] > rec_cap) *flags |= 2u;
+  *pool_n += *surv_n;
+  if (*pool_n > pool_cap) *flags |= 16u;
+}
+
+// *out = min(*in, cap).
+__global__ void k_clamp_u64(const u64* in, u64 cap, u64* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = min(*in, cap);
+}
+
+// Totals of a count in rounds, from the running totals.
+__global__ void k_finalize_rounds(DevTotals* tot, const u64* acc, const u64* pool_n, const u32* flags, u32 B) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  tot->n_windows = acc[0];
+  tot->n_records = acc[1];
+  tot->n_pairs = *pool_n;
+  tot->flags = *flags;
+  tot->large_keys = acc[2];
+  tot->tiny_buckets = acc[3];
+  tot->tiny_kmers = acc[4];
+  tot->small_buckets = acc[5];
+  tot->small_kmers = acc[6];
+  tot->large_buckets = acc[7];
+  tot->chunks = acc[8];
+  tot->list_entries = acc[9];
+  tot->buckets = B;
 }
 
 // Totals of a count, with the bucket-plan figures (meta: small, large, large k-mers,

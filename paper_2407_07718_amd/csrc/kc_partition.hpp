@@ -83,7 +83,16 @@ struct ExtractArgs {
   u32 C;               // coarse groups
   u64 n_span_cap;      // spans the record region holds
   u64 n_packed, n_mask;   // words in `packed` and in `nmask` / `starts`
+  // memory-bounded counting in rounds of coarse bucket groups (see k_extract's MODE)
+  const u32* blk_base;    // round: first record slot of each block (records packed densely)
+  const u32* rng;         // round: coarse groups [rng[0], rng[1]) are written
+  u32* hist_km;           // count pass: [C][nblk] k-mers per coarse group and block
 };
+
+// k_extract modes: one pass over everything; a count pass that writes no records, only
+// the records and k-mers per coarse group and block; a round that writes only the records
+// of a range of coarse groups, densely from the block's base slot.
+constexpr int EX_ONE = 0, EX_COUNT = 1, EX_ROUND = 2;
 
 // A supermer record (16 bytes for k <= 31, 32 bytes for k >= 32) holds its bases, two
 // bits each from bit 0 (at most 51 / 115 bases), its bucket in 20 bits and (g - 1) in the
@@ -185,9 +194,10 @@ __device__ __forceinline__ u32 window_min_carry(u32 v, int nst, u32 rest, const 
 // their coarse bucket groups feeds the partition (its scan also gives the record total;
 // the kernel touches no global counter, whose same-address atomics would serialize at
 // the end of short launches).  RW = record words (4 or 8).
-template <int RW>
+template <int RW, int MODE>
 __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
   __shared__ u32 h[512];
+  __shared__ u32 hk[MODE == EX_COUNT ? 512 : 1];
   __shared__ u32 blk_n;
   __shared__ u32 s_pk[4][EX_PK], s_nm[4][EX_MK], s_ct[4][EX_MK];
   const u32 lane = lane_id();
@@ -195,9 +205,13 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
   u32* const nm = s_nm[threadIdx.x >> 6];
   u32* const ct = s_ct[threadIdx.x >> 6];
   for (u32 i = threadIdx.x; i < 512; i += blockDim.x) h[i] = 0;
+  if constexpr (MODE == EX_COUNT)
+    for (u32 i = threadIdx.x; i < 512; i += blockDim.x) hk[i] = 0;
   if (threadIdx.x == 0) blk_n = 0;
   __syncthreads();
   const int k = A.k, m = A.m, w = k - m + 1;
+  // rounds: records whose coarse group is in [g_lo, g_lo + g_n) are written
+  const u32 g_lo = MODE == EX_ROUND ? A.rng[0] : 0u, g_n = MODE == EX_ROUND ? A.rng[1] - g_lo : ~0u;
   const u32 back = (u32)(w - 1);                 // k-mer position = m-mer position - back
   const u32 gmax = (u32)A.gmax;
   const int nst = 31 - __builtin_clz((u32)w);    // doubling steps of the window minimum
@@ -218,7 +232,8 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
 
   const u64 n_sp = min(n_spans, A.n_span_cap);
   const u64 s_end = min(n_sp, (u64)(blockIdx.x + 1) * A.spb);
-  const u64 slot0 = (u64)blockIdx.x * A.blk_slots;   // records of this block: slot0 + [0, blk_n)
+  // records of this block: slot0 + [0, blk_n)
+  const u64 slot0 = MODE == EX_ROUND ? (u64)A.blk_base[blockIdx.x] : (u64)blockIdx.x * A.blk_slots;
   const u32 nwv = blockDim.x >> 6;
   const u64 s_first = (u64)blockIdx.x * A.spb + (threadIdx.x >> 6);
   for (u64 s = s_first; s < s_end; s += nwv) {
@@ -268,21 +283,37 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
       const u32 pm = pos - div_small(pos, A.gmax_magic) * gmax;   // pos % gmax
       const u64 HD = VM & __ballot(pm == 0);     // a record starts here (runs cut every gmax)
       // a record ends at a valid lane whose successor in this tile is invalid or starts one
-      const u64 CL = VM & (~(VM >> 1) | (HD >> 1)) & ~(1ull << 63);
-      const bool carry_close = c_open && !((CONT & 1) && !(HD & 1));
+      u64 CL = VM & (~(VM >> 1) | (HD >> 1)) & ~(1ull << 63);
+      bool carry_close = c_open && !((CONT & 1) && !(HD & 1));
+      if constexpr (MODE == EX_ROUND) {   // only the round's coarse groups
+        CL &= __ballot((b >> A.log_f) - g_lo < g_n);
+        carry_close = carry_close && (c_b >> A.log_f) - g_lo < g_n;
+      }
       const u32 n_close = (u32)__popcll(CL) + (carry_close ? 1u : 0u);
       if (n_close) {
-        u32 at = 0;
-        if (lane == 0) at = atomicAdd(&blk_n, n_close);
-        const u64 base = slot0 + lane_read(at, 0);
-        if (carry_close && lane == 0) {
-          const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
-          write_record<RW>(A.rec, k, pk, base, c_p - cm + offp, cm + 1, c_b);
-          atomicAdd(&h[c_b >> A.log_f], 1u);
-        }
-        if ((CL >> lane) & 1) {
-          write_record<RW>(A.rec, k, pk, base + (carry_close ? 1 : 0) + mbcnt64(CL), p - pm + offp, pm + 1, b);
-          atomicAdd(&h[b >> A.log_f], 1u);
+        if constexpr (MODE == EX_COUNT) {
+          if (carry_close && lane == 0) {
+            const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
+            atomicAdd(&h[c_b >> A.log_f], 1u);
+            atomicAdd(&hk[c_b >> A.log_f], cm + 1);
+          }
+          if ((CL >> lane) & 1) {
+            atomicAdd(&h[b >> A.log_f], 1u);
+            atomicAdd(&hk[b >> A.log_f], pm + 1);
+          }
+        } else {
+          u32 at = 0;
+          if (lane == 0) at = atomicAdd(&blk_n, n_close);
+          const u64 base = slot0 + lane_read(at, 0);
+          if (carry_close && lane == 0) {
+            const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
+            write_record<RW>(A.rec, k, pk, base, c_p - cm + offp, cm + 1, c_b);
+            atomicAdd(&h[c_b >> A.log_f], 1u);
+          }
+          if ((CL >> lane) & 1) {
+            write_record<RW>(A.rec, k, pk, base + (carry_close ? 1 : 0) + mbcnt64(CL), p - pm + offp, pm + 1, b);
+            atomicAdd(&h[b >> A.log_f], 1u);
+          }
         }
       }
       // carry the run of the last lane
@@ -293,14 +324,20 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
         c_p = t0 + 63 - back;
       }
     }
-    if (c_open && lane == 0) {
+    if (c_open && lane == 0 && (MODE != EX_ROUND || (c_b >> A.log_f) - g_lo < g_n)) {
       const u32 cm = c_pos - div_small(c_pos, A.gmax_magic) * gmax;
-      write_record<RW>(A.rec, k, pk, slot0 + atomicAdd(&blk_n, 1u), c_p - cm + offp, cm + 1, c_b);
+      if constexpr (MODE == EX_COUNT) {
+        atomicAdd(&hk[c_b >> A.log_f], cm + 1);
+      } else {
+        write_record<RW>(A.rec, k, pk, slot0 + atomicAdd(&blk_n, 1u), c_p - cm + offp, cm + 1, c_b);
+      }
       atomicAdd(&h[c_b >> A.log_f], 1u);
     }
   }
   __syncthreads();
   for (u32 i = threadIdx.x; i < A.C; i += blockDim.x) A.hist[(u64)i * gridDim.x + blockIdx.x] = h[i];
+  if constexpr (MODE == EX_COUNT)
+    for (u32 i = threadIdx.x; i < A.C; i += blockDim.x) A.hist_km[(u64)i * gridDim.x + blockIdx.x] = hk[i];
   if (threadIdx.x == 0) A.blk_cnt[blockIdx.x] = blk_n;
 }
 
@@ -446,6 +483,84 @@ __global__ __launch_bounds__(PLAN_T) void k_plan_write(PlanArgs P) {
   }
 }
 
+// ---------------------------------------------------------------------------- rounds
+// Memory-bounded counting (with too little memory for all k-mers at once the paper sorts
+// in place, Section 3.1, and exchanges in rounds of bounded size, Section 3.3): the
+// coarse bucket groups are counted in rounds.  A count pass of k_extract gives the
+// records and k-mers of every (group, extract block); the groups are split greedily into
+// consecutive ranges of at most cap_r records and cap_k k-mers.  A distinct k-mer lies in
+// one bucket, hence in one group and one round, so the rounds' counts are disjoint and
+// their results add up.  Before each round every extract block gets a dense slot range
+// for its records of the round.
+
+// Records and k-mers of each coarse group over all extract blocks (one block per group):
+// gsum[2c] records, gsum[2c + 1] k-mers.
+__global__ __launch_bounds__(256) void k_group_sums(const u32* __restrict__ hrec, const u32* __restrict__ hkm,
+                                                    u32 nblk, u64* __restrict__ gsum) {
+  __shared__ u64 scr[17];
+  const u32 c = blockIdx.x;
+  u64 r = 0, km = 0;
+  for (u32 b = threadIdx.x; b < nblk; b += blockDim.x) {
+    r += hrec[(u64)c * nblk + b];
+    km += hkm[(u64)c * nblk + b];
+  }
+  u64 tr, tk;
+  block_exclusive_scan<u64>(r, scr, &tr);
+  block_exclusive_scan<u64>(km, scr, &tk);
+  if (threadIdx.x == 0) {
+    gsum[2 * c] = tr;
+    gsum[2 * c + 1] = tk;
+  }
+}
+
+// One thread: greedy split of the C groups into at most max_rounds consecutive ranges;
+// round q covers groups [rng[q], rng[q + 1]) (empty once the groups run out).  A group
+// above a cap, or more rounds than max_rounds, sets flag bit 3 and empties every round, so
+// that no round can outgrow its buffers (the count then reports the budget as too small).
+__global__ void k_round_plan(const u64* __restrict__ gsum, u32 C, u64 cap_r, u64 cap_k, u32 max_rounds,
+                             u32* __restrict__ rng, u32* __restrict__ flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  u32 q = 0;
+  u64 sr = 0, sk = 0;
+  bool bad = false;
+  rng[0] = 0;
+  for (u32 c = 0; c < C && !bad; ++c) {
+    const u64 r = gsum[2 * c], km = gsum[2 * c + 1];
+    if (r > cap_r || km > cap_k) {
+      bad = true;
+      break;
+    }
+    if (sr + r > cap_r || sk + km > cap_k) {   // round q closes before group c
+      if (++q >= max_rounds) {
+        bad = true;
+        break;
+      }
+      rng[q] = c;
+      sr = sk = 0;
+    }
+    sr += r;
+    sk += km;
+  }
+  if (bad) {
+    *flags |= 8u;
+    for (u32 j = 0; j <= max_rounds; ++j) rng[j] = C;
+    return;
+  }
+  for (u32 j = q + 1; j <= max_rounds; ++j) rng[j] = C;
+}
+
+// Records of the round's groups [rng[0], rng[1]) per extract block (scanned afterwards
+// into the blocks' dense slot bases).
+__global__ __launch_bounds__(256) void k_round_blocks(const u32* __restrict__ hrec, u32 nblk,
+                                                      const u32* __restrict__ rng, u32* __restrict__ cnt) {
+  const u32 g0 = rng[0], g1 = rng[1];
+  for (u32 b = blockIdx.x * blockDim.x + threadIdx.x; b < nblk; b += gridDim.x * blockDim.x) {
+    u32 s = 0;
+    for (u32 c = g0; c < g1; ++c) s += hrec[(u64)c * nblk + b];
+    cnt[b] = s;
+  }
+}
+
 // ---------------------------------------------------------------------------- partition
 // Records move from the extract blocks' slots into bucket order in two passes with no
 // global atomics: a coarse pass on the top log_c bits of the bucket (the extract blocks'
@@ -465,6 +580,7 @@ struct PartArgs {
   u32* rec_out;            // records in bucket order
   u64* bcnt;               // per bucket: (records << 32) | k-mers
   const u64* n_rec_ptr;    // records in total
+  const u32* blk_base;     // rounds: first slot of each extract block's records (else b * blk_slots)
 };
 
 
@@ -484,7 +600,8 @@ __global__ __launch_bounds__(512) void k_part_scatter(PartArgs P) {
   __shared__ u64 scr[17];
   const u32 C = 1u << P.log_c, tid = threadIdx.x, blk = blockIdx.x;
   const u32 total = P.blk_cnt[blk];
-  const uint4* src = reinterpret_cast<const uint4*>(P.rec) + (u64)blk * P.blk_slots * Q;
+  const uint4* src =
+      reinterpret_cast<const uint4*>(P.rec) + (P.blk_base ? (u64)P.blk_base[blk] : (u64)blk * P.blk_slots) * Q;
   uint4* dst = reinterpret_cast<uint4*>(P.tmp_rec);
   for (u32 c = tid; c < 512; c += T) {
     cnt[c] = 0;

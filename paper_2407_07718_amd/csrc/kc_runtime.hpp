@@ -185,6 +185,7 @@ int fetch_result(const DevTotals* d_tot, const uint64_t* d_kmers, const uint32_t
   HIP_TRY(hipMemcpyAsync(&t, d_tot, sizeof(t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (t.flags & 1) return fail(KC_EINVAL, "offsets are not non-decreasing or exceed the reads");
+  if (t.flags & 24) return fail(KC_ENOMEM, "%s", rounds_failure(t.flags));
   if (t.flags) return fail(KC_EDEVICE, "internal capacity exceeded (flags=%llu)", (unsigned long long)t.flags);
   if (t.n_pairs > pair_cap) return fail(KC_EDEVICE, "pair capacity exceeded");
   out->n_pairs = t.n_pairs;
@@ -778,8 +779,20 @@ int kc_server_submit(kc_server* s, const kc_job* job, uint64_t* ticket) {
   if (!make_plan(J->ji.R, job->n_reads, J->ji.n_max, job->k, job->m, job->min_freq, &s->cfg.count, &J->P))
     return fail(KC_EINVAL, "bad kc_config");
   J->est = J->ji.R * (u64)job->k;
-  J->bytes = align_up(J->ji.R + 16, 256) + align_up(8 * (job->n_reads + 1), 256) + align_up(J->P.bytes, 256) +
-             outputs_bytes(J->ji, job->hist_len);
+  const u64 io = align_up(J->ji.R + 16, 256) + align_up(8 * (job->n_reads + 1), 256) + outputs_bytes(J->ji, job->hist_len);
+  J->bytes = io + align_up(J->P.bytes, 256);
+  if (J->bytes > s->cfg.arena_bytes && s->cfg.arena_bytes > io) {
+    // too large for the arena in one pass: count in rounds within half of what the arena
+    // leaves after the request's inputs and outputs
+    kc_config c = s->cfg.count;
+    c.hbm_budget = (s->cfg.arena_bytes - io) / 2;
+    Plan q = J->P;
+    if (fit_budget(&q, &c) == KC_OK) {
+      J->P = q;
+      J->bytes = io + align_up(J->P.bytes, 256);
+    }
+    g_err.clear();
+  }
   std::lock_guard<std::mutex> g(s->mu);
   J->ticket = s->next_ticket++;
   J->tm.submit_s = s->now();
