@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 SRC_DIR = os.path.join(ROOT, "paper_2407_07718_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 GOLDEN = os.path.join(ROOT, "tests", "golden")
-ALL_LEGS = "k51,short,ext,cpu,batch,serve"
+ALL_LEGS = "k51,bounded,short,ext,cpu,batch,serve"
 HIST_LEN = 65536
 
 
@@ -230,6 +230,48 @@ def count_leg(args, torch, kc, rs, steps: int, warmup: int, kind: str, traffic_n
     del ctr, d_reads, d_offsets
     torch.cuda.empty_cache()
     return out, sha, res
+
+
+def bounded_leg(torch, kc, rs, fracs=(0.2, 0.08), steps: int = 3) -> dict:
+    """The plain count under HBM budgets below its one-pass workspace (it then runs in
+    rounds of coarse bucket groups): time per count and identity with the one-pass
+    result (the oracle's stored digest)."""
+    from tests.golden import digests
+    dev = torch.device("cuda:0")
+    d_reads = torch.from_numpy(np.ascontiguousarray(rs.reads)).to(dev)
+    d_offsets = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
+    one = kc.kc_workspace_size(rs.n_bases, rs.n_reads, rs.k, None)
+    _, want = golden("long", rs.k)
+    out = {"one_pass_workspace_bytes": one, "budgets": {}}
+    st = torch.cuda.current_stream()
+    for f in fracs:
+        cfg = kc.make_config(hbm_budget=int(one * f))
+        ctr = kc.DeviceCounter(rs.n_bases, rs.n_reads, rs.k, rs.m, rs.min_freq, rs.max_freq, HIST_LEN, cfg)
+        tot = ctr.count(d_reads, d_offsets)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            ctr.count(d_reads, d_offsets, stream=st, sync=False)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        final = dict(zip([f_ for f_, _ in kc.kc_totals._fields_], ctr.totals.cpu().numpy().view(np.uint64).tolist()))
+        res = ctr.result(final)
+        exact = None
+        if want is not None:
+            d = digests.result_digest(res.kmers, res.counts, res.hist, rs.k, final["n_windows"], final["n_distinct"],
+                                      final["overflow_sum"], final["max_count"])
+            exact = not digests.diff(d, want)
+            assert exact, "memory-bounded count differs from the oracle's digest"
+        out["budgets"][str(f)] = {"budget_bytes": int(one * f), "workspace_bytes": int(ctr.workspace.numel()),
+                                  "ms_per_step": round(ms, 3), "value": final["n_windows"] / (ms * 1e-3),
+                                  "bit_exact_vs_oracle_digest": exact}
+        del ctr, res
+        torch.cuda.empty_cache()
+    del d_reads, d_offsets
+    torch.cuda.empty_cache()
+    return out
 
 
 # ---------------------------------------------------------------------------- CPU baselines
@@ -664,6 +706,9 @@ def main():
         rs51 = synth.config(3, k=51)
         legs["long_read_k51"], _, r = count_leg(args, torch, kc, rs51, args.leg_steps, 2, "long", "long_k51")
         del r, rs51
+    if "bounded" in args.legs and kind == "long":
+        log("leg: memory-bounded long-read counts (rounds)")
+        legs["long_read_bounded"] = bounded_leg(torch, kc, synth.config(3, k=args.k))
     if "short" in args.legs or "ext" in args.legs:
         rs2 = synth.config(2)
         if "short" in args.legs and kind != "short":
