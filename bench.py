@@ -428,43 +428,56 @@ def ext_leg(args, torch, kc, rs, plain_sha) -> dict:
     """The extension version on the short-read workload: every reported k-mer with the
     list of its occurrences (read, position).  Same timing discipline as the count legs;
     the radix sort of (key, 32-bit value) pairs is HBM-bound and reported against the
-    HBM peak."""
+    HBM peak.  The digit width of its radix passes is the one kc_autotune picks for the
+    workload; both widths are timed and must give the same result."""
     dev = torch.device("cuda:0")
     d_reads = torch.from_numpy(np.ascontiguousarray(rs.reads)).to(dev)
     d_offsets = torch.from_numpy(rs.offsets.view(np.int64)).to(dev)
-    ctr = kc.DeviceExtCounter(rs.n_bases, rs.n_reads, rs.k, rs.min_freq, rs.max_freq, HIST_LEN)
-    tot = None
-    for _ in range(max(1, args.warmup)):
-        tot = ctr.count(d_reads, d_offsets)
-    res = ctr.result(tot)
-    same = result_sha(res.pairs.kmers, res.pairs.counts, res.pairs.hist) == plain_sha
+    tuned_cfg, _ = kc.kc_autotune(d_reads, d_offsets, rs.k, rs.m, rs.min_freq, rs.max_freq, HIST_LEN)
+    tuned = int(tuned_cfg.radix_bits) or 8
     st = torch.cuda.current_stream()
-    kc.kc_profile(True)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(args.ext_steps):
-        ctr.count(d_reads, d_offsets, stream=st, sync=False)
-    e1.record(st)
-    torch.cuda.synchronize()
-    kc.kc_profile(False)
-    stages = kc.kc_profile_read()
-    ms = e0.elapsed_time(e1) / args.ext_steps
-    per = {name: stages[s] / max(1, stages["n_counts"]) for name, s in zip(EXT_STAGES, kc.STAGES)}
-    n_win, w = int(tot["n_windows"]), 8 * (1 if rs.k <= 31 else 2)
-    passes = (2 * rs.k + 7) // 8
-    # per 8-bit pass: the upsweep reads every key, the downsweep reads and writes every
-    # (key, 32-bit value) pair
-    sort_bytes = passes * n_win * (w + 2 * (w + 4))
-    gbs = sort_bytes / (per["sort"] * 1e-3) / 1e9
-    one = result_sha(res.pairs.kmers, res.pairs.counts, res.pairs.hist) + result_sha(res.occ_off, res.occ_read,
-                                                                                     res.occ_pos)
-    full = int(ctr.workspace.numel())
-    del ctr, res
-    torch.cuda.empty_cache()
+    n_win, w = 0, 8 * (1 if rs.k <= 31 else 2)
+    runs = {}
+    full = 0
+    for bits in (8, 9):
+        ctr = kc.DeviceExtCounter(rs.n_bases, rs.n_reads, rs.k, rs.min_freq, rs.max_freq, HIST_LEN,
+                                  cfg=kc.make_config(radix_bits=bits))
+        tot = None
+        for _ in range(max(1, args.warmup)):
+            tot = ctr.count(d_reads, d_offsets)
+        res = ctr.result(tot)
+        kc.kc_profile(True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(args.ext_steps):
+            ctr.count(d_reads, d_offsets, stream=st, sync=False)
+        e1.record(st)
+        torch.cuda.synchronize()
+        kc.kc_profile(False)
+        stages = kc.kc_profile_read()
+        ms = e0.elapsed_time(e1) / args.ext_steps
+        per = {name: stages[s] / max(1, stages["n_counts"]) for name, s in zip(EXT_STAGES, kc.STAGES)}
+        n_win = int(tot["n_windows"])
+        passes = (2 * rs.k + bits - 1) // bits
+        # per pass: the upsweep reads every key, the downsweep reads and writes every
+        # (key, 32-bit value) pair
+        sort_bytes = passes * n_win * (w + 2 * (w + 4))
+        runs[bits] = {"ms": ms, "per": per, "tot": tot, "passes": passes, "sort_bytes": sort_bytes,
+                      "pairs_sha": result_sha(res.pairs.kmers, res.pairs.counts, res.pairs.hist),
+                      "all_sha": result_sha(res.pairs.kmers, res.pairs.counts, res.pairs.hist)
+                      + result_sha(res.occ_off, res.occ_read, res.occ_pos)}
+        full = int(ctr.workspace.numel())
+        del ctr, res
+        torch.cuda.empty_cache()
+    r = runs[tuned]
+    same = r["pairs_sha"] == plain_sha
+    widths_agree = runs[8]["all_sha"] == runs[9]["all_sha"]
+    gbs = r["sort_bytes"] / (r["per"]["sort"] * 1e-3) / 1e9
+    one = r["all_sha"]
     # memory-bounded: the same count with a quarter of the one-pass workspace (rounds of
     # key ranges); checked identical to the one-pass result
-    cfg = kc.make_config(hbm_budget=full // 4)
+    cfg = kc.make_config(hbm_budget=full // 4, radix_bits=tuned)
     ctr2 = kc.DeviceExtCounter(rs.n_bases, rs.n_reads, rs.k, rs.min_freq, rs.max_freq, HIST_LEN, cfg=cfg)
     t2 = None
     for _ in range(max(1, args.warmup)):
@@ -485,14 +498,20 @@ def ext_leg(args, torch, kc, rs, plain_sha) -> dict:
     del ctr2, d_reads, d_offsets
     torch.cuda.empty_cache()
     return {
-        "value": n_win / (ms * 1e-3), "unit": "k-mers/s", "ms_per_step": round(ms, 4), "steps": args.ext_steps,
+        "value": n_win / (r["ms"] * 1e-3), "unit": "k-mers/s", "ms_per_step": round(r["ms"], 4),
+        "steps": args.ext_steps, "radix_bits": tuned,
+        "radix_bits_ms": {str(b): round(runs[b]["ms"], 4) for b in runs},
+        "radix_bits_sort_ms": {str(b): round(runs[b]["per"]["sort"], 4) for b in runs},
+        "widths_identical": widths_agree,
         "memory_bounded": bounded,
-        "n_pairs": int(tot["n_pairs"]), "n_occ": int(tot["n_occ"]),
-        "stage_ms": {k: round(v, 4) for k, v in per.items()},
+        "n_pairs": int(r["tot"]["n_pairs"]), "n_occ": int(r["tot"]["n_occ"]),
+        "stage_ms": {k: round(v, 4) for k, v in r["per"].items()},
         "pairs_equal_plain_count": same,
-        "sort_roofline": {"bound": "hbm", "kernels": "k_radix_upsweep/rowscan/downsweep x %d passes" % passes,
+        "sort_roofline": {"bound": "hbm",
+                          "kernels": "k_radix_upsweep/rowscan/downsweep x %d passes of %d-bit digits"
+                                     % (r["passes"], tuned),
                           "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(gbs / HBM_PEAK_GBS, 4), "algo_bytes": int(sort_bytes)},
+                          "frac": round(gbs / HBM_PEAK_GBS, 4), "algo_bytes": int(r["sort_bytes"])},
     }
 
 
@@ -725,6 +744,7 @@ def main():
             legs["extension"] = ext_leg(args, torch, kc, rs2, sha2)
             assert legs["extension"]["pairs_equal_plain_count"], "extension pairs differ from the plain count"
             assert legs["extension"]["memory_bounded"]["identical_to_one_pass"], "memory-bounded result differs"
+            assert legs["extension"]["widths_identical"], "8- and 9-bit radix passes disagree"
         del rs2
     out["legs"] = legs
     if "batch" in args.legs and args.batch_sets > 0:

@@ -54,6 +54,9 @@ typedef struct kc_config {
                               above it a count runs in rounds); 0 = no limit other than free HBM */
   uint32_t no_graph;       /* batch: 1 = plain stream launches instead of one hipGraph */
   uint32_t autotune;       /* batch: 1 = tune bucket count and block shape per job class */
+  uint32_t radix_bits;     /* extension version: digit width of its HBM radix passes, 8 or 9
+                              (9 bits: 7 passes instead of 8 at k = 31); 0 = 8.  kc_autotune
+                              returns the faster width for a job class. */
 } kc_config;
 
 /* Totals of one count, as also written to device memory by kc_count_device. */
@@ -281,7 +284,10 @@ int kc_batch_destroy(kc_batch *b);
 /* Autotuner: times the count of one representative job under candidate bucket counts
  * and block shapes and returns the fastest setting in *out (its other fields copied
  * from base).  Results are remembered per (key width, k, size class, read-length
- * class) for the life of the process and reused by kc_count_batch with autotune set. */
+ * class) for the life of the process and reused by kc_count_batch with autotune set.
+ * Unless base->radix_bits is set, it also times the job's extension count with 8- and
+ * 9-bit HBM radix passes and returns the faster width in out->radix_bits (for
+ * kc_count_ext* of jobs of that class). */
 int kc_autotune(const kc_job *device_job, const kc_config *base, kc_config *out, double *best_ms);
 
 /* ---------------------------------------------------------------- serving

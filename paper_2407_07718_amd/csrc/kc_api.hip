@@ -379,25 +379,40 @@ K* at(void* ws, u64 off) {
   return reinterpret_cast<K*>(reinterpret_cast<char*>(ws) + off);
 }
 
+// Digit widths of the HBM radix passes: 8 or 9 bits (a 9-bit tile ranking needs 116 KB
+// of LDS at 512 threads; 10 bits would not fit a block).  counts holds NB_MAX x nb words.
+constexpr u32 RADIX_BITS_MIN = 8, RADIX_BITS_MAX = 9, RADIX_NB_MAX = 1u << RADIX_BITS_MAX;
+
+template <typename K, bool HASV, int DB>
+void radix_passes(K*& src, K*& dst, u32*& vs, u32*& vd, const u64* n_ptr, u32* counts, u32* totals, u32 nb,
+                  int nbits, hipStream_t st, int* passes) {
+  constexpr int ITEMS = sizeof(K) == 8 ? RADIX_ITEMS_64 : RADIX_ITEMS_128;
+  for (int sh = 0; sh < nbits; sh += DB) {
+    hipLaunchKernelGGL((k_radix_upsweep<K, DB>), dim3(nb), dim3(256), 0, st, src, n_ptr, counts, sh);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << DB), dim3(256), 0, st, counts, nb, totals);
+    hipLaunchKernelGGL((k_radix_downsweep<K, HASV, RADIX_T, ITEMS, KC_RADIX_SHARED != 0, DB>), dim3(nb),
+                       dim3(RADIX_T), 0, st, src, dst, vs, vd, n_ptr, counts, totals, sh);
+    std::swap(src, dst);
+    std::swap(vs, vd);
+    ++*passes;
+  }
+}
+
+// Stable LSD radix sort of (key, value) pairs through HBM over bits [0, nbits), digits of
+// `bits` bits (8 or 9): ceil(nbits / bits) passes, each an upsweep (per-block digit
+// counts), a row scan and a downsweep.
 template <typename K, bool HASV>
 int radix_sort(K* k0, K* k1, u32* v0, u32* v1, const u64* n_ptr, u32* counts, u32* totals, u32 nb, int nbits,
-               hipStream_t st, bool* in_second) {
-  constexpr int ITEMS = sizeof(K) == 8 ? RADIX_ITEMS_64 : RADIX_ITEMS_128;
+               u32 bits, hipStream_t st, bool* in_second) {
   K* src = k0;
   K* dst = k1;
   u32* vs = v0;
   u32* vd = v1;
   int passes = 0;
-  for (int sh = 0; sh < nbits; sh += 8) {
-    hipLaunchKernelGGL((k_radix_upsweep<K>), dim3(nb), dim3(256), 0, st, src, n_ptr, counts, sh);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, st, counts, nb, totals);
-    hipLaunchKernelGGL((k_radix_downsweep<K, HASV, RADIX_T, ITEMS, KC_RADIX_SHARED != 0>), dim3(nb), dim3(RADIX_T), 0,
-                       st, src, dst, vs,
-                       vd, n_ptr, counts, totals, sh);
-    std::swap(src, dst);
-    std::swap(vs, vd);
-    ++passes;
-  }
+  if (bits == 9)
+    radix_passes<K, HASV, 9>(src, dst, vs, vd, n_ptr, counts, totals, nb, nbits, st, &passes);
+  else
+    radix_passes<K, HASV, 8>(src, dst, vs, vd, n_ptr, counts, totals, nb, nbits, st, &passes);
   *in_second = (passes & 1) != 0;
   HIP_TRY(hipGetLastError());
   return KC_OK;
@@ -921,6 +936,7 @@ struct ExtPlan {
   u64 R = 0, n_reads = 0, N = 0;   // bases, reads, window positions (upper bound)
   u64 cap = 0;                     // windows sorted per round
   u32 rounds = 1;                  // rounds enqueued (1: all windows at once)
+  u32 rbits = 8;                   // digit width of the HBM radix passes
   u64 n_tiles = 1, n_tiles_cap = 1, n_packed = 0, n_mask = 0, n_blk = 0;
   u32 blk_sh = 6;                  // read table: one entry per 2^blk_sh bases
   u32 nb = 1;                      // radix blocks
@@ -977,8 +993,8 @@ void ext_layout(ExtPlan* p, u64 cap) {
   p->o_bo = take(4 * p->n_tiles_cap);
   p->o_rid = take(4 * p->n_blk);
   p->o_ctrl = take(8ull * X_WORDS);
-  p->o_cnt = take(4ull * 256 * p->nb);
-  p->o_tot = take(4ull * 256);
+  p->o_cnt = take(4ull * RADIX_NB_MAX * p->nb);
+  p->o_tot = take(4ull * RADIX_NB_MAX);
   p->o_scan = take(8ull * 1024);
   p->o_bins = take(4ull * EXT_NBINS);
   p->o_rb = take(4ull * (p->rounds + 1));
@@ -1149,7 +1165,7 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
     if (!rounds) stage_mark(2, st);
     bool second = false;
     int rc = radix_sort<K, true>(k0, k1, v0, v1, ctrl + X_NWINC, at<u32>(ws, P.o_cnt), at<u32>(ws, P.o_tot), P.nb,
-                                 2 * P.k, st, &second);
+                                 2 * P.k, P.rbits, st, &second);
     if (rc) return rc;
     const K* sk = second ? k1 : k0;
     const u32* sv = second ? v1 : v0;
@@ -1183,6 +1199,16 @@ int enqueue_ext(const ExtPlan& P, void* ws, const uint8_t* d_reads, const uint64
   stage_mark(5, st);
   HIP_TRY(hipGetLastError());
   return KC_OK;
+}
+
+// Digit width of the extension version's HBM radix passes: cfg->radix_bits, else the
+// default.  False for a width outside [RADIX_BITS_MIN, RADIX_BITS_MAX].
+constexpr u32 RADIX_BITS_DEFAULT = 8;
+bool ext_radix_bits(const kc_config* cfg, u32* bits) {
+  const u32 b = (cfg && cfg->radix_bits) ? cfg->radix_bits : RADIX_BITS_DEFAULT;
+  if (b < RADIX_BITS_MIN || b > RADIX_BITS_MAX) return false;
+  *bits = b;
+  return true;
 }
 
 int ext_check(int k, uint32_t lo, uint32_t hi, uint64_t hist_len, uint64_t total_bases, uint64_t n_reads) {
@@ -1462,6 +1488,7 @@ static int ext_device_common(const uint8_t* d_reads, uint64_t total_bases, const
   if (!make_ext_plan(total_bases, n_reads, k, budget, &P))
     return budget ? fail(KC_ENOMEM, "no plan fits a workspace budget of %llu bytes", (unsigned long long)budget)
                   : fail(KC_EINVAL, "input too large");
+  if (!ext_radix_bits(cfg, &P.rbits)) return fail(KC_EINVAL, "radix_bits=%u outside [8, 9]", cfg->radix_bits);
   if (ws_bytes < P.bytes)
     return fail(KC_EINVAL, "workspace of %zu bytes < %llu needed", ws_bytes, (unsigned long long)P.bytes);
   return enqueue_ext_any(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_occ_off,
@@ -1535,6 +1562,7 @@ int kc_count_ext(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads
   if (!make_ext_plan(R, n_reads, k, budget, &P))
     return budget ? fail(KC_ENOMEM, "no plan fits a workspace budget of %llu bytes", (unsigned long long)budget)
                   : fail(KC_EINVAL, "input too large");
+  if (!ext_radix_bits(cfg, &P.rbits)) return fail(KC_EINVAL, "radix_bits=%u outside [8, 9]", cfg->radix_bits);
   const u64 w = 8ull * P.key_words, cap = std::max<u64>(1, n_max);
   const u64 in_bytes = align_up(R + 16, 256) + align_up(8 * (n_reads + 1), 256);
   const u64 o_k = 0, o_c = o_k + align_up(w * cap, 256), o_off = o_c + align_up(4 * cap, 256),

@@ -177,6 +177,69 @@ int autotune_device(const kc_job& j, const JobInfo& ji, const kc_config* base, k
   return KC_OK;
 }
 
+// The extension version's digit width for a job: its count timed with 8- and 9-bit HBM
+// radix passes (median of two after a warm-up); the faster is returned and remembered
+// per job class.
+std::map<TuneKey, u32> g_tune_bits;
+
+int tune_radix_bits(const kc_job& j, const JobInfo& ji, u32* best_bits) {
+  ExtPlan P;
+  if (!make_ext_plan(ji.R, j.n_reads, j.k, 0, &P)) return fail(KC_EINVAL, "job too large for the extension version");
+  const u64 w = 8ull * ji.key_words, cap = std::max<u64>(1, ji.n_max), pcap = ji.pair_cap;
+  const u64 o_k = align_up(P.bytes, 256), o_c = o_k + align_up(w * pcap, 256), o_off = o_c + align_up(4 * pcap, 256),
+            o_rd = o_off + align_up(8 * (pcap + 1), 256), o_ps = o_rd + align_up(4 * cap, 256),
+            o_h = o_ps + align_up(4 * cap, 256), o_t = o_h + align_up(8 * j.hist_len, 256),
+            total = o_t + align_up(sizeof(DevTotals), 256);
+  char* mem = nullptr;
+  HIP_TRY(hipMalloc(&mem, total));
+  hipStream_t st;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipFree(mem);
+    return fail(KC_EDEVICE, "stream creation failed");
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int rc = KC_OK;
+  double best = 1e30;
+  u32 bb = RADIX_BITS_DEFAULT;
+  for (u32 bits = RADIX_BITS_MIN; bits <= RADIX_BITS_MAX && rc == KC_OK; ++bits) {
+    P.rbits = bits;
+    std::vector<double> t;
+    for (int r = 0; r < 3 && rc == KC_OK; ++r) {
+      (void)hipEventRecord(e0, st);
+      rc = enqueue_ext_any(P, mem, j.reads, j.offsets, j.min_freq, j.max_freq, j.hist_len,
+                           reinterpret_cast<uint64_t*>(mem + o_k), reinterpret_cast<uint32_t*>(mem + o_c), pcap,
+                           reinterpret_cast<uint64_t*>(mem + o_off), reinterpret_cast<uint32_t*>(mem + o_rd),
+                           reinterpret_cast<uint32_t*>(mem + o_ps), cap, reinterpret_cast<uint64_t*>(mem + o_h),
+                           reinterpret_cast<DevTotals*>(mem + o_t), st);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) rc = fail(KC_EDEVICE, "tuning run failed");
+      float f = 0;
+      (void)hipEventElapsedTime(&f, e0, e1);
+      if (r > 0) t.push_back(f);
+    }
+    if (rc) break;
+    std::sort(t.begin(), t.end());
+    const double ms = t[t.size() / 2];
+    if (ms < best) {
+      best = ms;
+      bb = bits;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(st);
+  (void)hipFree(mem);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_bits[tune_key(ji, j.k, j.n_reads)] = bb;
+  }
+  *best_bits = bb;
+  return KC_OK;
+}
+
 // Copy one job's result (device outputs) to a host kc_result.
 int fetch_result(const DevTotals* d_tot, const uint64_t* d_kmers, const uint32_t* d_counts, const uint64_t* d_hist,
                  u64 pair_cap, u64 hist_len, int key_words, hipStream_t st, kc_result* out) {
@@ -473,8 +536,16 @@ int kc_autotune(const kc_job* device_job, const kc_config* base, kc_config* out,
   JobInfo ji;
   rc = host_job_info(off.data(), device_job->n_reads, device_job->k, device_job->min_freq, &ji);
   if (rc) return rc;
-  return autotune_device(*device_job, ji, base, out, best_ms);
+  rc = autotune_device(*device_job, ji, base, out, best_ms);
+  if (rc) return rc;
+  if (!base || !base->radix_bits) {
+    u32 bits = 0;
+    if ((rc = tune_radix_bits(*device_job, ji, &bits))) return rc;
+    out->radix_bits = bits;
+  }
+  return KC_OK;
 }
+
 
 }  // extern "C"
 

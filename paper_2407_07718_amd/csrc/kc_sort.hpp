@@ -1,5 +1,5 @@
-// LSD radix sort of canonical k-mer keys (u64 for k <= 31, k128 for k <= 63), 8-bit
-// digits over the low 2k bits.
+// LSD radix sort of canonical k-mer keys (u64 for k <= 31, k128 for k <= 63), digits of
+// DB bits (8 or 9) over the low 2k bits.
 //
 // Paper mapping: the k-mers are sorted so that equal values become adjacent (Section
 // 3.1); the paper uses the CPU radix sorts RADULS (out of place) and PARADIS (in place)
@@ -17,11 +17,22 @@
 #pragma once
 #include "kc_common.hpp"
 
-template <int W>
+// Radix digit of DB bits starting at bit sh; for 128-bit keys a digit may straddle the
+// two words.
+template <int DB> __device__ __forceinline__ u32 key_digit_w(u64 k, int sh) {
+  return (u32)(k >> sh) & ((1u << DB) - 1u);
+}
+template <int DB> __device__ __forceinline__ u32 key_digit_w(k128 k, int sh) {
+  const u64 v = sh >= 64 ? (k.hi >> (sh - 64)) : sh == 0 ? k.lo : ((k.lo >> sh) | (k.hi << (64 - sh)));
+  return (u32)v & ((1u << DB) - 1u);
+}
+
+template <int W, int DB = 8>
 struct RankSmem {
-  u64 tbl[W][256];   // lane masks per digit; all zero between uses
-  u32 cnt[W][256];   // per-wave digit counts, then the items' base offsets
-  u32 dstart[257];   // per-digit exclusive start within the tile; [256] = tile size
+  static constexpr int NB = 1 << DB;
+  u64 tbl[W][NB];    // lane masks per digit; all zero between uses
+  u32 cnt[W][NB];    // per-wave digit counts, then the items' base offsets
+  u32 dstart[NB + 1];   // per-digit exclusive start within the tile; [NB] = tile size
   u64 scr[17];       // block-scan scratch
 };
 
@@ -29,13 +40,14 @@ struct RankSmem {
 // (v*per + j)*64 + l; it is active iff that index is < n.  On return rk[j] holds the
 // item's stable position in digit order and S.dstart the per-digit starts.
 // Every thread of the block must call this (it contains barriers).
-template <int T, int ITEMS>
+template <int T, int ITEMS, int DB = 8>
 __device__ __forceinline__ void rank_by_digit(const u32 (&dg)[ITEMS], u32 (&rk)[ITEMS], int per, u32 n,
-                                              RankSmem<T / 64>& S) {
-  constexpr int W = T / 64;
+                                              RankSmem<T / 64, DB>& S) {
+  constexpr int W = T / 64, NB = 1 << DB;
+  static_assert(NB <= T, "one thread per digit in the offsets step");
   const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   u32* cntf = &S.cnt[0][0];
-  for (u32 i = tid; i < W * 256; i += T) cntf[i] = 0;
+  for (u32 i = tid; i < W * NB; i += T) cntf[i] = 0;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
@@ -62,7 +74,7 @@ __device__ __forceinline__ void rank_by_digit(const u32 (&dg)[ITEMS], u32 (&rk)[
   }
   __syncthreads();
   u32 tot = 0;
-  if (tid < 256) {
+  if (tid < NB) {
 #pragma unroll
     for (int v = 0; v < W; ++v) {
       u32 c = S.cnt[v][tid];
@@ -72,45 +84,16 @@ __device__ __forceinline__ void rank_by_digit(const u32 (&dg)[ITEMS], u32 (&rk)[
   }
   u64 all;
   const u64 start = block_exclusive_scan<u64>((u64)tot, S.scr, &all);
-  if (tid < 256) {
+  if (tid < NB) {
     S.dstart[tid] = (u32)start;
 #pragma unroll
     for (int v = 0; v < W; ++v) S.cnt[v][tid] += (u32)start;
   }
-  if (tid == 0) S.dstart[256] = (u32)all;
+  if (tid == 0) S.dstart[NB] = (u32)all;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     if (j < per) rk[j] += S.cnt[wave][dg[j]];
-  }
-}
-
-// Sort keys[0, n) in LDS by bits [0, nbits), n <= T * ITEMS.
-template <typename K, int T, int ITEMS>
-__device__ void lds_sort(K* keys, u32 n, int nbits, RankSmem<T / 64>& S) {
-  constexpr int W = T / 64;
-  const u32 lane = lane_id(), wave = threadIdx.x >> 6;
-  const int per = (int)((n + 64u * W - 1) / (64u * W));
-  for (int sh = 0; sh < nbits; sh += 8) {
-    K kr[ITEMS];
-    u32 dg[ITEMS], rk[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      if (j < per) {
-        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
-        kr[j] = idx < n ? keys[idx] : key_zero<K>();
-        dg[j] = key_digit(kr[j], sh);
-      }
-    }
-    rank_by_digit<T, ITEMS>(dg, rk, per, n, S);
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      if (j < per) {
-        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
-        if (idx < n) keys[rk[j]] = kr[j];
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -122,13 +105,14 @@ __device__ __forceinline__ void block_range(u64 n, u32 nb, u64* s, u64* e) {
   *e = min(n, *s + per);
 }
 
-// counts[d * nb + b] = number of keys of block b with digit d.
-template <typename K>
+// counts[d * nb + b] = number of keys of block b with digit d (DB-bit digits).
+template <typename K, int DB = 8>
 __global__ __launch_bounds__(256) void k_radix_upsweep(const K* __restrict__ keys, const u64* __restrict__ n_ptr,
                                                        u32* __restrict__ counts, int sh) {
-  __shared__ u32 h[4][256];
+  constexpr u32 NB = 1u << DB;
+  __shared__ u32 h[4][NB];
   const u32 nb = gridDim.x, tid = threadIdx.x, wave = tid >> 6;
-  for (u32 i = tid; i < 4 * 256; i += 256) (&h[0][0])[i] = 0;
+  for (u32 i = tid; i < 4 * NB; i += 256) (&h[0][0])[i] = 0;
   __syncthreads();
   u64 s, e;
   block_range(*n_ptr, nb, &s, &e);
@@ -148,12 +132,12 @@ __global__ __launch_bounds__(256) void k_radix_upsweep(const K* __restrict__ key
     if (i0 + 256 * U < e) load(kb, i0 + 256 * U);
 #pragma unroll
     for (u32 u = 0; u < U; ++u)
-      if (i0 + (u64)u * 256 < e) atomicAdd(&h[wave][key_digit(ka[u], sh)], 1u);
+      if (i0 + (u64)u * 256 < e) atomicAdd(&h[wave][key_digit_w<DB>(ka[u], sh)], 1u);
 #pragma unroll
     for (u32 u = 0; u < U; ++u) ka[u] = kb[u];
   }
   __syncthreads();
-  counts[(u64)tid * nb + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+  for (u32 d = tid; d < NB; d += 256) counts[(u64)d * nb + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
 // Exclusive scan out[i] = sum of in[0, i) for i < n by one block; n = min(*n_ptr, n_max)
@@ -254,24 +238,25 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(u32* __restrict__ counts,
 // Stable scatter of one pass.  Each tile of T*ITEMS keys is ranked by digit, staged in
 // LDS in digit order and written out as one run per digit.  With SHARED the values are
 // staged after the keys in the same LDS buffer (less LDS per block, one more barrier).
-template <typename K, bool HASV, int T, int ITEMS, bool SHARED = false>
+template <typename K, bool HASV, int T, int ITEMS, bool SHARED = false, int DB = 8>
 __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin, K* __restrict__ kout,
                                                        const u32* __restrict__ vin, u32* __restrict__ vout,
                                                        const u64* __restrict__ n_ptr, const u32* __restrict__ counts,
                                                        const u32* __restrict__ totals, int sh) {
-  constexpr int W = T / 64, TILE = T * ITEMS;
-  __shared__ RankSmem<W> S;
+  constexpr int W = T / 64, TILE = T * ITEMS, NB = 1 << DB;
+  static_assert(NB <= T, "one thread per digit");
+  __shared__ RankSmem<W, DB> S;
   __shared__ K stage_k[TILE];
   __shared__ u32 stage_v[(HASV && !SHARED) ? TILE : 1];
-  __shared__ u32 run_base[256];
+  __shared__ u32 run_base[NB];
   const u32 nb = gridDim.x, tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-  for (u32 i = tid; i < W * 256; i += T) (&S.tbl[0][0])[i] = 0;
+  for (u32 i = tid; i < W * NB; i += T) (&S.tbl[0][0])[i] = 0;
   {
     // digit d of this block starts at (sum of all smaller digits) + (digit d in earlier blocks)
-    const u64 t = tid < 256 ? totals[tid] : 0u;
+    const u64 t = tid < (u32)NB ? totals[tid] : 0u;
     u64 all;
     const u64 dbase = block_exclusive_scan<u64>(t, S.scr, &all);
-    if (tid < 256) run_base[tid] = (u32)dbase + counts[(u64)tid * nb + blockIdx.x];
+    if (tid < (u32)NB) run_base[tid] = (u32)dbase + counts[(u64)tid * nb + blockIdx.x];
   }
   __syncthreads();
   u64 s, e;
@@ -311,9 +296,9 @@ __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin
     if (t0 + TILE < e) load_tile(t0 + TILE);
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      if (j < per) dg[j] = key_digit(kr[j], sh);
+      if (j < per) dg[j] = key_digit_w<DB>(kr[j], sh);
     }
-    rank_by_digit<T, ITEMS>(dg, rk, per, nt, S);
+    rank_by_digit<T, ITEMS, DB>(dg, rk, per, nt, S);
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       if (j < per) {
@@ -333,7 +318,7 @@ __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin
         const u32 i = tid + (u32)j * T;
         if (i < nt) {
           const K key = stage_k[i];
-          const u32 d = key_digit(key, sh);
+          const u32 d = key_digit_w<DB>(key, sh);
           dsts[j] = run_base[d] + (i - S.dstart[d]);
           kout[dsts[j]] = key;
         }
@@ -356,14 +341,14 @@ __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin
     } else {
       for (u32 i = tid; i < nt; i += T) {
         const K key = stage_k[i];
-        const u32 d = key_digit(key, sh);
+        const u32 d = key_digit_w<DB>(key, sh);
         const u64 dst = (u64)run_base[d] + (i - S.dstart[d]);
         kout[dst] = key;
         if (HASV) vout[dst] = stage_v[i];
       }
     }
     __syncthreads();
-    if (tid < 256) run_base[tid] += S.dstart[tid + 1] - S.dstart[tid];
+    if (tid < (u32)NB) run_base[tid] += S.dstart[tid + 1] - S.dstart[tid];
     __syncthreads();
   }
 }

@@ -30,7 +30,8 @@ class KCError(RuntimeError):
 class kc_config(ctypes.Structure):
     _fields_ = [("log2_buckets", ctypes.c_uint32), ("force_hbm", ctypes.c_uint32),
                 ("small_variant", ctypes.c_uint32), ("lanes", ctypes.c_uint32),
-                ("hbm_budget", ctypes.c_uint64), ("no_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32)]
+                ("hbm_budget", ctypes.c_uint64), ("no_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
+                ("radix_bits", ctypes.c_uint32)]
 
 
 class kc_totals(ctypes.Structure):
@@ -180,8 +181,10 @@ def kc_profile_read() -> dict:
 
 
 def make_config(log2_buckets: int = 0, force_hbm: bool = False, small_variant: int = 0,
-                hbm_budget: int = 0, lanes: int = 0, no_graph: bool = False, autotune: bool = False) -> kc_config:
-    return kc_config(log2_buckets, int(force_hbm), small_variant, lanes, hbm_budget, int(no_graph), int(autotune))
+                hbm_budget: int = 0, lanes: int = 0, no_graph: bool = False, autotune: bool = False,
+                radix_bits: int = 0) -> kc_config:
+    return kc_config(log2_buckets, int(force_hbm), small_variant, lanes, hbm_budget, int(no_graph), int(autotune),
+                     radix_bits)
 
 
 @dataclass

@@ -79,10 +79,39 @@ def test_header_declares_batch_and_server_entry_points():
 def test_struct_sizes_match_header_layout():
     from paper_2407_07718_amd import kc
     assert ctypes.sizeof(kc.kc_totals) == 17 * 8
-    assert ctypes.sizeof(kc.kc_config) == 4 * 4 + 8 + 2 * 4
+    assert ctypes.sizeof(kc.kc_config) == 4 * 4 + 8 + 3 * 4 + 4          # (tail padding to 8)
     assert ctypes.sizeof(kc.kc_job) == 8 * 3 + 4 * 4 + 8
     assert ctypes.sizeof(kc.kc_server_cfg) == 8 + 2 * 4 + 8 + ctypes.sizeof(kc.kc_config)
     assert ctypes.sizeof(kc.kc_timing) == 3 * 8 + 2 * 8
+
+
+def test_binding_structs_match_the_c_compiler(tmp_path):
+    """Every field offset and struct size of the Python binding equals what a C compiler
+    makes of include/kc.h."""
+    import shutil
+    import subprocess
+    from paper_2407_07718_amd import kc
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = [kc.kc_config, kc.kc_totals, kc.kc_result, kc.kc_ext_result, kc.kc_job, kc.kc_server_cfg,
+               kc.kc_timing, kc.kc_stage_times]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-o", str(exe), str(src)])
+    got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[name]) == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, f"{name}.{f}"
 
 
 def test_batch_rejects_bad_job_before_device_work():
