@@ -356,6 +356,45 @@ typedef struct kc_stage_times {
 int kc_profile(int enable);
 int kc_profile_read(kc_stage_times *out);
 
+/* ---------------------------------------------------------------- partition inspection
+ * The state of a plain count after its first stage, for checking that stage on its own:
+ * the supermers (Section 2.4: runs of consecutive k-mers of one read that share a
+ * minimizer, stored once as bases) and their buckets (Section 3.2: the minimizer is the
+ * m-mer of lowest hash score, and the same score modulo the number of targets is the
+ * destination).  Here the score of an m-mer is the upper 32 bits of MurmurHash3's 64-bit
+ * finalizer of its canonical value (the smaller of forward and reverse complement, first
+ * base most significant), and a window's bucket is the least score of its k - m + 1
+ * m-mers modulo B.  Runs the count's encode, extract and partition kernels on the GPU, on
+ * host inputs (copied in), with the configuration's bucket count; hbm_budget is ignored
+ * (one pass).  Nothing is counted.
+ *
+ * Each record is record_words 32-bit words (4 for k <= 31, 8 for k >= 32), read as
+ * record_words / 2 little-endian 64-bit words: the supermer's bases, two bits each from
+ * bit 0 of word 0 (A0 C1 G2 T3, first base lowest), g + k - 1 bases for g k-mers; in
+ * the last 64-bit word, bits 38..57 hold the bucket and bits 58..63 hold g - 1.  Every
+ * valid window (k bases, no other byte, inside one read) is carried by exactly one
+ * record; a record's windows sit at consecutive positions and share one bucket.  A run
+ * is cut into records of gmax k-mers from its start, and runs are also
+ * cut where a window position (counted from offsets[0]) is a multiple of span.  Records
+ * are in bucket order (their order inside a bucket is unspecified).
+ *
+ * Returns KC_OK, KC_EINVAL (bad arguments or configuration, offsets decreasing or past
+ * the reads), KC_ENOMEM (device or host memory) or KC_EDEVICE.  On KC_OK, *out owns
+ * host arrays that kc_partition_free releases; on failure *out holds none. */
+typedef struct kc_partition {
+  uint32_t log2_buckets;    /* B = 2^log2_buckets buckets */
+  uint32_t record_words;    /* 32-bit words per record */
+  uint32_t gmax;            /* most k-mers one record carries */
+  uint32_t span;            /* window positions per extract span */
+  uint64_t n_records;
+  uint32_t *records;        /* n_records * record_words words, in bucket order */
+  uint64_t *bucket_counts;  /* B entries: (records of the bucket << 32) | its k-mers */
+} kc_partition;
+
+int kc_partition_inspect(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, int k, int m,
+                         const kc_config *cfg, kc_partition *out);
+void kc_partition_free(kc_partition *p);
+
 #ifdef __cplusplus
 }
 #endif

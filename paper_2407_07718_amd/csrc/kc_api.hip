@@ -555,38 +555,120 @@ Ws<K> ws_ptrs(const Plan& P, void* ws) {
 // slots: partition, bucket plan, the per-bucket sorts and counts, the merge of the heavy
 // buckets' chunk lists.  One pass runs it once; a memory-bounded count once per round
 // (blk_base: the round's dense record slots of every extract block; no stage marks).
+// Zero everything a count accumulates, and the packed words past the reads (one
+// launch).  d_hist / d_tot may be null (the partition inspection has none).
+template <typename K>
+void launch_clear(const Plan& P, const Ws<K>& W, uint64_t* d_hist, uint64_t hist_len, DevTotals* d_tot,
+                  hipStream_t st) {
+  const u64 n32 = ceil_div(P.R, 32);
+  FillList fl{};
+  u64 most = 0;
+  auto add = [&](void* p, u64 n_words) {
+    fl.p[fl.cnt] = (u32*)p;
+    fl.n[fl.cnt] = n_words;
+    fl.v[fl.cnt] = 0u;
+    ++fl.cnt;
+    most = std::max(most, n_words);
+  };
+  add(W.ctrl, 2ull * C_WORDS);
+  if (d_hist) add(d_hist, 2ull * hist_len);
+  if (d_tot) add(d_tot, sizeof(DevTotals) / 4);
+  add(W.starts, P.n_mask);
+  add(W.scnt, P.B);
+  add(W.packed + 2 * n32, P.n_packed - 2 * n32);
+  add(W.nmask + n32, P.n_mask - n32);
+  hipLaunchKernelGGL(k_fill_multi, grid_for(most, 256, 4096), dim3(256), 0, st, fl);
+}
+
+// Encode the reads (2-bit codes and non-base mask) and mark the read starts.
+template <typename K>
+void launch_encode(const Plan& P, const Ws<K>& W, const uint8_t* d_reads, const uint64_t* d_offsets, hipStream_t st) {
+  const u64 n32 = ceil_div(P.R, 32);
+  if (P.R) hipLaunchKernelGGL(k_pack, grid_for(n32, 256), dim3(256), 0, st, d_reads, P.R, W.packed, W.nmask);
+  if (P.n_reads)
+    hipLaunchKernelGGL(k_read_starts, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R,
+                       W.starts, W.flags);
+}
+
+// Arguments of the extract kernel for a one-pass count (rounds override blk_base / rng /
+// hist / hist_km).
+template <typename K>
+ExtractArgs extract_args(const Plan& P, const Ws<K>& W, const uint64_t* d_offsets) {
+  ExtractArgs ea;
+  ea.packed = W.packed;
+  ea.nmask = W.nmask;
+  ea.starts = W.starts;
+  ea.offsets = d_offsets;
+  ea.n_reads = P.n_reads;
+  ea.R = P.R;
+  ea.k = P.k;
+  ea.m = P.m;
+  ea.log_b = P.log_b;
+  ea.gmax = P.gmax;
+  ea.gmax_magic = (u32)(((1ull << 32) + (u64)P.gmax - 1) / (u64)P.gmax);
+  ea.rec_words = P.rec_words;
+  ea.span = P.span;
+  ea.spb = P.part_spb;
+  ea.blk_slots = (u64)P.part_spb * P.span;
+  ea.rec = W.recA;
+  ea.blk_cnt = W.blkcnt;
+  ea.hist = W.phist;
+  ea.log_f = P.log_f;
+  ea.C = 1u << P.log_c;
+  ea.n_span_cap = P.n_span_cap;
+  ea.n_packed = P.n_packed;
+  ea.n_mask = P.n_mask;
+  ea.blk_base = nullptr;
+  ea.rng = nullptr;
+  ea.hist_km = nullptr;
+  return ea;
+}
+
+template <int MODE>
+void launch_extract(const Plan& P, const ExtractArgs& ea, hipStream_t st) {
+  if (P.rec_words == 4)
+    hipLaunchKernelGGL((k_extract<4, MODE>), dim3(P.part_nblk), dim3(256), 0, st, ea);
+  else
+    hipLaunchKernelGGL((k_extract<8, MODE>), dim3(P.part_nblk), dim3(256), 0, st, ea);
+}
+
+// The extract blocks' records -> records in bucket order (recB) with per-bucket
+// (records << 32) | k-mers (bcnt); counters[0] = records.  blk_base: rounds (null: one pass).
+template <typename K>
+void launch_partition(const Plan& P, const Ws<K>& W, const u32* blk_base, hipStream_t st) {
+  PartArgs pp;
+  pp.rec = W.recA;
+  pp.blk_cnt = W.blkcnt;
+  pp.blk_slots = (u64)P.part_spb * P.span;
+  pp.nblk = P.part_nblk;
+  pp.log_c = P.log_c;
+  pp.log_f = P.log_f;
+  pp.rec_words = P.rec_words;
+  pp.hist = W.phist;
+  pp.tmp_rec = W.ptmp_rec;
+  pp.rec_out = W.recB;
+  pp.bcnt = W.bcnt;
+  pp.n_rec_ptr = W.counters;
+  pp.blk_base = blk_base;
+  const u64 nh = ((u64)1 << P.log_c) * P.part_nblk;
+  scan_u32(W.phist, W.phist, (const u64*)nullptr, nh, W.counters, W.scanbuf, st);   // counters[0] = records
+  if (P.rec_words == 4)
+    hipLaunchKernelGGL(k_part_scatter<4>, dim3(P.part_nblk), dim3(512), 0, st, pp);
+  else
+    hipLaunchKernelGGL(k_part_scatter<8>, dim3(P.part_nblk), dim3(512), 0, st, pp);
+  if (P.rec_words == 4)
+    hipLaunchKernelGGL(k_part_fine<4>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
+  else
+    hipLaunchKernelGGL(k_part_fine<8>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
+}
+
 template <typename K>
 int count_buckets(const Plan& P, const Ws<K>& W, const u32* blk_base, uint32_t lo, uint32_t hi, uint64_t hist_len,
                   uint64_t* d_hist, DevTotals* d_tot, K* out_k, u32* out_c, const u64* out_base, u64 out_cap,
                   bool marks, int n_cu, hipStream_t st) {
   int rc = KC_OK;
   if (marks) stage_mark(2, st);
-  {
-    PartArgs pp;
-    pp.rec = W.recA;
-    pp.blk_cnt = W.blkcnt;
-    pp.blk_slots = (u64)P.part_spb * P.span;
-    pp.nblk = P.part_nblk;
-    pp.log_c = P.log_c;
-    pp.log_f = P.log_f;
-    pp.rec_words = P.rec_words;
-    pp.hist = W.phist;
-    pp.tmp_rec = W.ptmp_rec;
-    pp.rec_out = W.recB;
-    pp.bcnt = W.bcnt;
-    pp.n_rec_ptr = W.counters;
-    pp.blk_base = blk_base;
-    const u64 nh = ((u64)1 << P.log_c) * P.part_nblk;
-    scan_u32(W.phist, W.phist, (const u64*)nullptr, nh, W.counters, W.scanbuf, st);   // counters[0] = records
-    if (P.rec_words == 4)
-      hipLaunchKernelGGL(k_part_scatter<4>, dim3(P.part_nblk), dim3(512), 0, st, pp);
-    else
-      hipLaunchKernelGGL(k_part_scatter<8>, dim3(P.part_nblk), dim3(512), 0, st, pp);
-    if (P.rec_words == 4)
-      hipLaunchKernelGGL(k_part_fine<4>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
-    else
-      hipLaunchKernelGGL(k_part_fine<8>, dim3(1u << P.log_c), dim3(1024), 0, st, pp);
-  }
+  launch_partition<K>(P, W, blk_base, st);
   {
     PlanArgs pa{W.bcnt, P.B, P.cap_tiny, P.cap, P.cap_chunk, W.bsum, W.tiny, W.recoff, W.cursor, W.small, W.large,
                 W.lkoff, W.chstart, W.chlen, P.chunk_cap, W.kall, W.meta, W.lch0};
@@ -730,67 +812,16 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
 
   // zero everything that accumulates (one launch)
   stage_mark(0, st);
-  const u64 n32 = ceil_div(P.R, 32);
-  {
-    FillList fl{};
-    u64 most = 0;
-    auto add = [&](void* p, u64 n_words) {
-      fl.p[fl.cnt] = (u32*)p;
-      fl.n[fl.cnt] = n_words;
-      fl.v[fl.cnt] = 0u;
-      ++fl.cnt;
-      most = std::max(most, n_words);
-    };
-    add(W.ctrl, 2ull * C_WORDS);
-    add(d_hist, 2ull * hist_len);
-    add(d_tot, sizeof(DevTotals) / 4);
-    add(W.starts, P.n_mask);
-    add(W.scnt, P.B);
-    add(W.packed + 2 * n32, P.n_packed - 2 * n32);
-    add(W.nmask + n32, P.n_mask - n32);
-    hipLaunchKernelGGL(k_fill_multi, grid_for(most, 256, 4096), dim3(256), 0, st, fl);
-  }
+  launch_clear<K>(P, W, d_hist, hist_len, d_tot, st);
 
   // ---- stage 1: encode, read starts, minimizers and supermers, bucket partition
-  if (P.R) hipLaunchKernelGGL(k_pack, grid_for(n32, 256), dim3(256), 0, st, d_reads, P.R, W.packed, W.nmask);
-  if (P.n_reads)
-    hipLaunchKernelGGL(k_read_starts, grid_for(P.n_reads, 256), dim3(256), 0, st, d_offsets, P.n_reads, P.R,
-                       W.starts, W.flags);
-  ExtractArgs ea;
-  ea.packed = W.packed;
-  ea.nmask = W.nmask;
-  ea.starts = W.starts;
-  ea.offsets = d_offsets;
-  ea.n_reads = P.n_reads;
-  ea.R = P.R;
-  ea.k = P.k;
-  ea.m = P.m;
-  ea.log_b = P.log_b;
-  ea.gmax = P.gmax;
-  ea.gmax_magic = (u32)(((1ull << 32) + (u64)P.gmax - 1) / (u64)P.gmax);
-  ea.rec_words = P.rec_words;
-  ea.span = P.span;
-  ea.spb = P.part_spb;
-  ea.blk_slots = (u64)P.part_spb * P.span;
-  ea.rec = W.recA;
-  ea.blk_cnt = W.blkcnt;
-  ea.hist = W.phist;
-  ea.log_f = P.log_f;
-  ea.C = 1u << P.log_c;
-  ea.n_span_cap = P.n_span_cap;
-  ea.n_packed = P.n_packed;
-  ea.n_mask = P.n_mask;
-  ea.blk_base = nullptr;
-  ea.rng = nullptr;
-  ea.hist_km = nullptr;
+  launch_encode<K>(P, W, d_reads, d_offsets, st);
+  const ExtractArgs ea = extract_args<K>(P, W, d_offsets);
   K* s1k = W.kl0k;   // dense survivors of a one-pass count: where the sorted lists were
   u32* s1c = W.kl0c;
   stage_mark(1, st);
   if (!rounds) {
-    if (P.rec_words == 4)
-      hipLaunchKernelGGL((k_extract<4, EX_ONE>), dim3(P.part_nblk), dim3(256), 0, st, ea);
-    else
-      hipLaunchKernelGGL((k_extract<8, EX_ONE>), dim3(P.part_nblk), dim3(256), 0, st, ea);
+    launch_extract<EX_ONE>(P, ea, st);
     if ((rc = count_buckets<K>(P, W, nullptr, lo, hi, hist_len, d_hist, d_tot, s1k, s1c, nullptr, ~0ull, true, n_cu,
                                st)))
       return rc;
@@ -818,10 +849,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
     ExtractArgs ec = ea;
     ec.hist = hrec;
     ec.hist_km = hkm;
-    if (P.rec_words == 4)
-      hipLaunchKernelGGL((k_extract<4, EX_COUNT>), dim3(P.part_nblk), dim3(256), 0, st, ec);
-    else
-      hipLaunchKernelGGL((k_extract<8, EX_COUNT>), dim3(P.part_nblk), dim3(256), 0, st, ec);
+    launch_extract<EX_COUNT>(P, ec, st);
     hipLaunchKernelGGL(k_group_sums, dim3(C), dim3(256), 0, st, hrec, hkm, P.part_nblk, gsum);
     hipLaunchKernelGGL(k_round_plan, dim3(1), dim3(64), 0, st, gsum, C, P.cap_r, P.cap_k, P.max_rounds, rng, W.flags);
     stage_mark(2, st);
@@ -843,10 +871,7 @@ int enqueue(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t* d_o
       ExtractArgs er = ea;
       er.blk_base = bbase;
       er.rng = rng + q;
-      if (P.rec_words == 4)
-        hipLaunchKernelGGL((k_extract<4, EX_ROUND>), dim3(P.part_nblk), dim3(256), 0, st, er);
-      else
-        hipLaunchKernelGGL((k_extract<8, EX_ROUND>), dim3(P.part_nblk), dim3(256), 0, st, er);
+      launch_extract<EX_ROUND>(P, er, st);
       if ((rc = count_buckets<K>(P, W, bbase, lo, hi, hist_len, d_hist, d_tot, pool_k, pool_c, pool_n, P.pool_cap,
                                  false, n_cu, st)))
         return rc;
@@ -1460,6 +1485,85 @@ int kc_count(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, in
   if ((t.n_pairs && (hipMemcpy(out->kmers, d_kmers, t.n_pairs * w, hipMemcpyDeviceToHost) != hipSuccess ||
                      hipMemcpy(out->counts, d_counts, t.n_pairs * 4, hipMemcpyDeviceToHost) != hipSuccess)) ||
       hipMemcpy(out->hist, d_hist, hist_len * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "D2H failed"));
+  return cleanup(KC_OK);
+}
+
+// ---------------------------------------------------------------- partition inspection
+void kc_partition_free(kc_partition* p) {
+  if (!p) return;
+  free(p->records);
+  free(p->bucket_counts);
+  memset(p, 0, sizeof(*p));
+}
+
+int kc_partition_inspect(const uint8_t* reads, const uint64_t* offsets, uint64_t n_reads, int k, int m,
+                         const kc_config* cfg, kc_partition* out) {
+  g_err.clear();
+  if (!out) return fail(KC_EINVAL, "out is NULL");
+  memset(out, 0, sizeof(*out));
+  int rc = check_args(k, m, 1, 1, 2);
+  if (rc) return rc;
+  if (!offsets || (n_reads && !reads)) return fail(KC_EINVAL, "NULL host pointer");
+  u64 n_max = 0;
+  for (u64 r = 0; r < n_reads; ++r) {
+    if (offsets[r + 1] < offsets[r]) return fail(KC_EINVAL, "offsets decrease at read %llu", (unsigned long long)r);
+    const u64 L = offsets[r + 1] - offsets[r];
+    if (L >= (u64)k) n_max += L - (u64)k + 1;
+  }
+  const u64 R = n_reads ? offsets[n_reads] : 0;
+  if (n_max >= (1ull << 32) || R >= (1ull << 32))
+    return fail(KC_EINVAL, "%llu windows / %llu bases exceed 2^32 - 1", (unsigned long long)n_max,
+                (unsigned long long)R);
+  kc_config one{};
+  if (cfg) one = *cfg;
+  one.hbm_budget = 0;
+  Plan P;
+  if (!make_plan(R, n_reads, n_max, k, m, 1, &one, &P)) return fail(KC_EINVAL, "bad kc_config");
+  const u64 in_bytes = align_up(R + 16, 256) + align_up(8 * (n_reads + 1), 256);
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  if (P.bytes + in_bytes > free_b)
+    return fail(KC_ENOMEM, "needs %llu bytes of HBM, %zu free", (unsigned long long)(P.bytes + in_bytes), free_b);
+  char* dmem = nullptr;
+  HIP_TRY(hipMalloc(&dmem, P.bytes + in_bytes));
+  uint8_t* d_reads = reinterpret_cast<uint8_t*>(dmem + P.bytes);
+  uint64_t* d_offsets = reinterpret_cast<uint64_t*>(dmem + P.bytes + align_up(R + 16, 256));
+  hipStream_t st = nullptr;
+  auto cleanup = [&](int code) {
+    (void)hipFree(dmem);
+    if (code) kc_partition_free(out);
+    return code;
+  };
+  if (R && hipMemcpyAsync(d_reads, reads, R, hipMemcpyHostToDevice, st) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "H2D reads failed"));
+  if (hipMemcpyAsync(d_offsets, offsets, 8 * (n_reads + 1), hipMemcpyHostToDevice, st) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "H2D offsets failed"));
+  // the key type only places the count's later regions; stage 1 is the same for both
+  const Ws<u64> W = ws_ptrs<u64>(P, dmem);
+  launch_clear<u64>(P, W, nullptr, 0, nullptr, st);
+  launch_encode<u64>(P, W, d_reads, d_offsets, st);
+  launch_extract<EX_ONE>(P, extract_args<u64>(P, W, d_offsets), st);
+  launch_partition<u64>(P, W, nullptr, st);
+  if (hipGetLastError() != hipSuccess) return cleanup(fail(KC_EDEVICE, "launch failed"));
+  u64 n_rec = 0;
+  u32 flags = 0;
+  if (hipMemcpyAsync(&n_rec, W.counters, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&flags, W.flags, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return cleanup(fail(KC_EDEVICE, "partition failed: %s", hipGetErrorString(hipGetLastError())));
+  if (flags & 1) return cleanup(fail(KC_EINVAL, "offsets decrease or lie past the reads"));
+  if (flags) return cleanup(fail(KC_EDEVICE, "internal capacity exceeded (flags=%u)", flags));
+  out->log2_buckets = (uint32_t)P.log_b;
+  out->record_words = (uint32_t)P.rec_words;
+  out->gmax = (uint32_t)P.gmax;
+  out->span = P.span;
+  out->n_records = n_rec;
+  out->records = (uint32_t*)malloc(std::max<u64>(1, n_rec * P.rec_words) * 4);
+  out->bucket_counts = (uint64_t*)malloc((u64)P.B * 8);
+  if (!out->records || !out->bucket_counts) return cleanup(fail(KC_ENOMEM, "host allocation failed"));
+  if ((n_rec && hipMemcpy(out->records, W.recB, n_rec * P.rec_words * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+      hipMemcpy(out->bucket_counts, W.bcnt, (u64)P.B * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return cleanup(fail(KC_EDEVICE, "D2H failed"));
   return cleanup(KC_OK);
 }

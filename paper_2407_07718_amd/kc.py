@@ -80,6 +80,12 @@ KC_N_STAGES = 8
 STAGES = ["encode", "extract", "partition", "expand", "block_sort", "wave_sort", "merge", "output"]
 
 
+class kc_partition(ctypes.Structure):
+    _fields_ = [("log2_buckets", ctypes.c_uint32), ("record_words", ctypes.c_uint32), ("gmax", ctypes.c_uint32),
+                ("span", ctypes.c_uint32), ("n_records", ctypes.c_uint64),
+                ("records", ctypes.POINTER(ctypes.c_uint32)), ("bucket_counts", ctypes.POINTER(ctypes.c_uint64))]
+
+
 class kc_stage_times(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * KC_N_STAGES), ("n_counts", ctypes.c_uint64)]
 
@@ -144,6 +150,9 @@ def _load() -> ctypes.CDLL:
     lib.kc_count_ext_device.restype = i32
     lib.kc_count_ext_device_async.argtypes = ext_args
     lib.kc_count_ext_device_async.restype = i32
+    lib.kc_partition_inspect.argtypes = [vp, vp, u64, i32, i32, P(kc_config), P(kc_partition)]
+    lib.kc_partition_inspect.restype = i32
+    lib.kc_partition_free.argtypes = [P(kc_partition)]
     lib.kc_profile.argtypes = [i32]
     lib.kc_profile.restype = i32
     lib.kc_profile_read.argtypes = [ctypes.POINTER(kc_stage_times)]
@@ -219,6 +228,35 @@ def kc_count(reads: np.ndarray, offsets: np.ndarray, k: int, m: int, min_freq: i
         return Result(kmers, counts, hist, res.totals.as_dict())
     finally:
         _lib.kc_result_free(ctypes.byref(res))
+
+
+@dataclass
+class Partition:
+    log2_buckets: int
+    gmax: int
+    span: int
+    records: np.ndarray         # uint64 [n_records, record_words / 2], bucket order
+    bucket_counts: np.ndarray   # uint64 [2^log2_buckets]: (records << 32) | k-mers
+
+
+def kc_partition_inspect(reads: np.ndarray, offsets: np.ndarray, k: int, m: int,
+                         cfg: Optional[kc_config] = None) -> Partition:
+    """The supermer records and per-bucket sizes after a plain count's first stage."""
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if reads.size == 0:
+        reads = np.zeros(1, dtype=np.uint8)
+    out = kc_partition()
+    _check(_lib.kc_partition_inspect(reads.ctypes.data, offsets.ctypes.data, offsets.shape[0] - 1, k, m,
+                                     ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(out)))
+    try:
+        n, rw, nb = int(out.n_records), int(out.record_words), 1 << int(out.log2_buckets)
+        words = np.ctypeslib.as_array(out.records, shape=(max(1, n * rw),))[: n * rw].copy()
+        recs = words.view(np.uint64).reshape(n, rw // 2)
+        bc = np.ctypeslib.as_array(out.bucket_counts, shape=(nb,)).copy()
+        return Partition(int(out.log2_buckets), int(out.gmax), int(out.span), recs, bc)
+    finally:
+        _lib.kc_partition_free(ctypes.byref(out))
 
 
 def _take_result(res: kc_result, hist_len: int) -> Result:

@@ -49,6 +49,18 @@ def test_host_api_rejects_bad_arguments(k, m, lo, hi, H):
     assert e.value.code == kc.KC_EINVAL
 
 
+def test_partition_inspection_rejects_bad_arguments():
+    from paper_2407_07718_amd import kc
+    reads = np.frombuffer(b"ACGT" * 20, dtype=np.uint8)
+    for k, m, offsets in [(0, 1, [0, 80]), (31, 31, [0, 80]), (64, 21, [0, 80]), (11, 5, [0, 50, 40, 80])]:
+        with pytest.raises(kc.KCError) as e:
+            kc.kc_partition_inspect(reads, np.array(offsets, dtype=np.uint64), k, m)
+        assert e.value.code == kc.KC_EINVAL
+    with pytest.raises(kc.KCError) as e:
+        kc.kc_partition_inspect(reads, np.array([0, 80], dtype=np.uint64), 31, 15, kc.make_config(log2_buckets=21))
+    assert e.value.code == kc.KC_EINVAL
+
+
 def test_host_api_rejects_decreasing_offsets():
     from paper_2407_07718_amd import kc
     reads = np.frombuffer(b"ACGT" * 20, dtype=np.uint8)
@@ -94,7 +106,7 @@ def test_binding_structs_match_the_c_compiler(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")
     structs = [kc.kc_config, kc.kc_totals, kc.kc_result, kc.kc_ext_result, kc.kc_job, kc.kc_server_cfg,
-               kc.kc_timing, kc.kc_stage_times]
+               kc.kc_timing, kc.kc_stage_times, kc.kc_partition]
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
     for st in structs:
         name = st.__name__
