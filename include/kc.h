@@ -302,8 +302,11 @@ typedef struct kc_server_cfg {
   uint32_t reserved;       /* must be 0 */
   uint64_t arena_bytes;    /* device memory the server allocates once and carves each
                               request's inputs, workspace and outputs from (first fit);
-                              0 = hbm_budget.  A request whose actual bytes exceed the
-                              whole arena fails with KC_ENOMEM. */
+                              0 = hbm_budget.  A request whose one-pass bytes exceed the
+                              whole arena is counted in rounds (as under hbm_budget of
+                              kc_config) within half of what the arena leaves after its
+                              inputs and outputs; one that no plan fits fails with
+                              KC_ENOMEM. */
   kc_config count;         /* tuning of each count (log2_buckets etc.) */
 } kc_server_cfg;
 
