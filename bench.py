@@ -11,7 +11,8 @@ the oracle's stored digests of the same workload.
 The same JSON line carries further legs: the long-read workload at k=51 (128-bit keys),
 the short-read workload (1,000,000 x 150 bp, k=31), the extension version (occurrence
 lists) on short reads, the CPU oracle and the CPU-parallel baseline on a bounded sample,
-the batched workload (256 read sets, one graph launch vs 256 plain counts) and the served
+the batched workload (256 read sets in one graph launch, several sets per count, vs one
+count per set in the same graph and vs 256 plain counts) and the served
 workload (Poisson arrivals of requests drawn from the batched sets).
 
     python bench.py [--steps K] [--warmup W] [--legs k51,short,ext,cpu,batch,serve]
@@ -348,9 +349,11 @@ def batch_reference(sets, scale: float) -> tuple:
 
 
 def batched_leg(args, torch, kc, synth) -> tuple:
-    """The batched workload: every set counted in one launch of a captured hipGraph (stream
-    lanes, autotuned configuration per set class) against one plain count per set in
-    sequence.  Both sides start from inputs resident in HBM."""
+    """The batched workload: every set counted in one launch of a captured hipGraph, with
+    the sets of one class sharing counts (one fixed launch sequence per count of up to
+    2^28 bases), against the same graph with one count per set on 8 stream lanes
+    (autotuned per set class) and against one plain count per set in sequence.  All start
+    from inputs resident in HBM."""
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     sets = synth.batch_sets(args.batch_sets, args.batch_scale)
@@ -385,24 +388,33 @@ def batched_leg(args, torch, kc, synth) -> tuple:
                                             d_c[:n].cpu().numpy().view(np.uint32), d_h.cpu().numpy().view(np.uint64)))
     del d_ws, d_k, d_c, d_h, d_t
     torch.cuda.empty_cache()
-    log("batched: graph")
-    t0 = time.perf_counter()
-    b = kc.DeviceBatch([(dr, do, rs.k, rs.m, rs.min_freq, rs.max_freq, HIST_LEN)
-                        for rs, (dr, do) in zip(sets, d_sets)], kc.make_config(autotune=True, lanes=8))
-    setup_s = time.perf_counter() - t0
-    times = []
-    for rep in range(4):            # replay 0 warms up
-        torch.cuda.synchronize()
+    def graph_batch(cfg, label):
+        log(f"batched: graph ({label})")
         t0 = time.perf_counter()
-        b.run()
-        if rep:
-            times.append(time.perf_counter() - t0)
-    batch_s = float(np.median(times))
-    batch_dig = []
-    for i in range(len(sets)):
-        r = b.result(i)
-        batch_dig.append(result_sha(r.kmers, r.counts, r.hist))
-    b.close()
+        b = kc.DeviceBatch([(dr, do, rs.k, rs.m, rs.min_freq, rs.max_freq, HIST_LEN)
+                            for rs, (dr, do) in zip(sets, d_sets)], cfg)
+        setup = time.perf_counter() - t0
+        times = []
+        for rep in range(4):            # replay 0 warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run()
+            if rep:
+                times.append(time.perf_counter() - t0)
+        dig = []
+        for i in range(len(sets)):
+            r = b.result(i)
+            dig.append(result_sha(r.kmers, r.counts, r.hist))
+        info = b.info()
+        b.close()
+        torch.cuda.empty_cache()
+        return float(np.median(times)), setup, dig, info
+
+    # several sets per count (one launch sequence per count of up to 2^28 bases of one
+    # class), then the same batch with one count per set on 8 lanes, autotuned
+    batch_s, setup_s, batch_dig, info = graph_batch(kc.make_config(), "several sets per count")
+    per_s, per_setup_s, per_dig, per_info = graph_batch(kc.make_config(autotune=True, lanes=8, per_set=True),
+                                                        "one count per set")
     del d_sets
     torch.cuda.empty_cache()
     res = {
@@ -412,11 +424,17 @@ def batched_leg(args, torch, kc, synth) -> tuple:
         "graph_replay_ms": round(batch_s * 1e3, 3), "sequential_plain_ms": round(plain_s * 1e3, 3),
         "speedup_vs_plain": round(plain_s / batch_s, 3),
         "value": n_kmers / batch_s, "plain_value": n_kmers / plain_s, "unit": "k-mers/s",
-        "setup_s": round(setup_s, 3), "lanes": 8, "autotune": True,
+        "counts_per_run": info["counts"], "sets_sharing_a_count": info["shared"], "lanes": info["lanes"],
+        "setup_s": round(setup_s, 3),
+        "per_set": {"graph_replay_ms": round(per_s * 1e3, 3), "value": n_kmers / per_s,
+                    "counts_per_run": per_info["counts"], "lanes": per_info["lanes"], "autotune": True,
+                    "setup_s": round(per_setup_s, 3), "bit_exact_vs_oracle": per_dig == ref},
+        "speedup_vs_per_set": round(per_s / batch_s, 3),
         "bit_exact_batch_vs_plain": batch_dig == plain_dig, "bit_exact_vs_oracle": batch_dig == ref,
         "reference": ref_kind, "reference_s": round(ref_s, 1), "gen_s": round(gen_s, 1),
     }
     assert res["bit_exact_batch_vs_plain"] and res["bit_exact_vs_oracle"], "batched results differ"
+    assert res["per_set"]["bit_exact_vs_oracle"], "per-set batched results differ"
     return res, sets, ref
 
 
@@ -750,6 +768,8 @@ def main():
     if "batch" in args.legs and args.batch_sets > 0:
         log(f"batched leg ({args.batch_sets} sets, scale {args.batch_scale})")
         out["batched"], sets, ref = batched_leg(args, torch, kc, synth)
+        out["batched"]["vs_single_count_rate"] = round(out["batched"]["value"] / out["value"], 4)
+        out["batched"]["per_set"]["vs_single_count_rate"] = round(out["batched"]["per_set"]["value"] / out["value"], 4)
         if "serve" in args.legs and args.serve_seconds > 0:
             log("serving leg")
             out["serving"] = serving_leg(args, kc, sets, ref)

@@ -57,6 +57,9 @@ typedef struct kc_config {
   uint32_t radix_bits;     /* extension version: digit width of its HBM radix passes, 8 or 9
                               (9 bits: 7 passes instead of 8 at k = 31); 0 = 8.  kc_autotune
                               returns the faster width for a job class. */
+  uint32_t per_set;        /* batch: 1 = one count per read set on the stream lanes; 0 = the
+                              read sets that share k, m, frequency window and hist_len are
+                              counted together, several sets per count (see kc_count_batch) */
 } kc_config;
 
 /* Totals of one count, as also written to device memory by kc_count_device. */
@@ -262,13 +265,23 @@ typedef struct kc_job {
 } kc_job;
 
 /* Count n_jobs independent read sets in one go (host buffers in, host results out).
- * All inputs are copied to the device once; jobs are assigned to cfg->lanes stream
- * lanes by the greedy largest-first rule (each lane with its own workspace) and the
- * whole schedule is captured as one hipGraph and launched once (cfg->no_graph = 1 to
- * launch on plain streams instead).  Each job's result equals kc_count of that job.
- * outs[i] is filled for every job on KC_OK (free each with kc_result_free).  Jobs may
- * mix k; a job with bad arguments fails the whole call with KC_EINVAL before any
- * device work. */
+ * All inputs are copied to the device once.  Jobs that share k, m, frequency window
+ * and hist_len are counted together, up to 2^28 bases and 512 sets per count (the
+ * paper's decoupling of tasks from workers, Section 3.4, several tasks per worker): the
+ * sets' bases are read in place as one joint input, each set owns its own range of
+ * buckets (so no bucket mixes sets), the counting kernels keep per-set histograms and
+ * totals, and the survivors are sorted once by (set, k-mer) -- a fixed launch sequence
+ * per count, however many sets it holds.  A job alone in its class, or with
+ * 2k + log2(sets) above 126, or any job with cfg->per_set = 1, is counted on its own.
+ * The counts are assigned to cfg->lanes stream lanes by the greedy largest-first rule
+ * (each lane with its own workspace; fewer lanes when the workspaces would not fit in
+ * free HBM) and the whole schedule is captured as one hipGraph and launched once
+ * (cfg->no_graph = 1 to launch on plain streams instead).  Each job's result equals
+ * kc_count of that job, except that the totals' chunks and list_entries are 0 for a
+ * set counted with others (those figures are not split by set), and autotune applies
+ * only to jobs counted on their own.  outs[i] is filled for every job on KC_OK (free
+ * each with kc_result_free).  Jobs may mix k; a job with bad arguments fails the whole
+ * call with KC_EINVAL before any device work. */
 int kc_count_batch(uint32_t n_jobs, const kc_job *jobs, kc_result *outs, const kc_config *cfg);
 
 /* A prepared batch over device-resident inputs, for repeated launches (benchmarks,
@@ -280,6 +293,10 @@ int kc_batch_create(uint32_t n_jobs, const kc_job *device_jobs, const kc_config 
 int kc_batch_run(kc_batch *b, void *stream);
 int kc_batch_result(kc_batch *b, uint32_t job, kc_result *out);
 int kc_batch_destroy(kc_batch *b);
+/* Shape of a prepared batch: *n_counts launch sequences per run (each count of several
+ * sets is one, each job counted on its own is one), *n_shared jobs counted with other
+ * sets, *lanes stream lanes.  Any pointer may be NULL. */
+int kc_batch_info(const kc_batch *b, uint32_t *n_counts, uint32_t *n_shared, uint32_t *lanes);
 
 /* Autotuner: times the count of one representative job under candidate bucket counts
  * and block shapes and returns the fastest setting in *out (its other fields copied

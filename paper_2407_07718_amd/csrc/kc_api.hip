@@ -555,11 +555,26 @@ Ws<K> ws_ptrs(const Plan& P, void* ws) {
 // slots: partition, bucket plan, the per-bucket sorts and counts, the merge of the heavy
 // buckets' chunk lists.  One pass runs it once; a memory-bounded count once per round
 // (blk_base: the round's dense record slots of every extract block; no stage marks).
+// Device side of a count over several read sets (null for one set): bucket -> set, the
+// merged lists' segment-start bits, the sets of the merged runs' survivors, and the
+// wide-key survivor buffers (capacity wide_cap).
+struct MultiDev {
+  u32 n_sets = 0;
+  const u32* bset = nullptr;
+  u32* seg_bits = nullptr;
+  u32* rset = nullptr;
+  k128* wide_k = nullptr;     // wide keys (set << 2k | k-mer) ...
+  void* pair_k = nullptr;     // ... or k-mers with value = count | set << cbits (cbits >= 0)
+  u32* wide_c = nullptr;
+  u64 wide_cap = 0;
+  int cbits = -1;
+};
+
 // Zero everything a count accumulates, and the packed words past the reads (one
 // launch).  d_hist / d_tot may be null (the partition inspection has none).
 template <typename K>
 void launch_clear(const Plan& P, const Ws<K>& W, uint64_t* d_hist, uint64_t hist_len, DevTotals* d_tot,
-                  hipStream_t st) {
+                  hipStream_t st, u64 n_tot = 1, u32* extra = nullptr, u64 extra_words = 0) {
   const u64 n32 = ceil_div(P.R, 32);
   FillList fl{};
   u64 most = 0;
@@ -572,7 +587,8 @@ void launch_clear(const Plan& P, const Ws<K>& W, uint64_t* d_hist, uint64_t hist
   };
   add(W.ctrl, 2ull * C_WORDS);
   if (d_hist) add(d_hist, 2ull * hist_len);
-  if (d_tot) add(d_tot, sizeof(DevTotals) / 4);
+  if (d_tot) add(d_tot, n_tot * sizeof(DevTotals) / 4);
+  if (extra) add(extra, extra_words);
   add(W.starts, P.n_mask);
   add(W.scnt, P.B);
   add(W.packed + 2 * n32, P.n_packed - 2 * n32);
@@ -665,7 +681,8 @@ void launch_partition(const Plan& P, const Ws<K>& W, const u32* blk_base, hipStr
 template <typename K>
 int count_buckets(const Plan& P, const Ws<K>& W, const u32* blk_base, uint32_t lo, uint32_t hi, uint64_t hist_len,
                   uint64_t* d_hist, DevTotals* d_tot, K* out_k, u32* out_c, const u64* out_base, u64 out_cap,
-                  bool marks, int n_cu, hipStream_t st) {
+                  bool marks, int n_cu, hipStream_t st, const MultiDev* md = nullptr) {
+  const bool ms = md != nullptr;
   int rc = KC_OK;
   if (marks) stage_mark(2, st);
   launch_partition<K>(P, W, blk_base, st);
@@ -709,28 +726,41 @@ int count_buckets(const Plan& P, const Ws<K>& W, const u32* blk_base, uint32_t l
   ca.kl_k = W.lk0;             // a chunk's list overwrites its own keys (read into LDS first)
   ca.kl_c = W.klsc;
   ca.kl_cnt = W.klcnt;
+  ca.bset = ms ? md->bset : nullptr;
+  ca.n_sets = ms ? md->n_sets : 1u;
   // large buckets: expand their k-mers into HBM, cut later into chunks
   hipLaunchKernelGGL((k_expand_large<K, 256>), dim3(1024), dim3(256), 0, st, ca, W.lk0);
   if (marks) stage_mark(4, st);
   constexpr bool WIDE = sizeof(K) == 16;
-  if (P.variant == 2) {
-    constexpr int T = 512, IT = WIDE ? 8 : 16;
+  auto block_sort = [&](auto kern, int T) -> int {
     int per_cu = 0;
-    if ((rc = blocks_per_cu(k_bucket_sort_count<K, T, IT>, T, &per_cu))) return rc;
-    hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
-  } else {
-    constexpr int T = 256, IT = WIDE ? 8 : 16;
-    int per_cu = 0;
-    if ((rc = blocks_per_cu(k_bucket_sort_count<K, T, IT>, T, &per_cu))) return rc;
-    hipLaunchKernelGGL((k_bucket_sort_count<K, T, IT>), dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+    int r = blocks_per_cu(kern, T, &per_cu);
+    if (r) return r;
+    hipLaunchKernelGGL(kern, dim3(std::max(1, per_cu) * n_cu), dim3(T), 0, st, ca);
+    return KC_OK;
+  };
+  {
+    constexpr int IT = WIDE ? 8 : 16;
+    if (P.variant == 2)
+      rc = ms ? block_sort(k_bucket_sort_count<K, 512, IT, true>, 512) : block_sort(k_bucket_sort_count<K, 512, IT>, 512);
+    else
+      rc = ms ? block_sort(k_bucket_sort_count<K, 256, IT, true>, 256) : block_sort(k_bucket_sort_count<K, 256, IT>, 256);
+    if (rc) return rc;
   }
   if (marks) stage_mark(5, st);
   {
     constexpr u32 WC = WIDE ? WAVE_CAP_128 : WAVE_CAP_64;
-    int per_cu = 0;
-    if ((rc = blocks_per_cu(k_wave_sort_count<K, WC, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &per_cu))) return rc;
-    hipLaunchKernelGGL((k_wave_sort_count<K, WC, WAVES_PER_BLOCK>), dim3(std::max(1, per_cu) * n_cu),
-                       dim3(WAVES_PER_BLOCK * 64), 0, st, ca, W.tiny, W.meta + 5);
+    auto wave_sort = [&](auto kern) -> int {
+      int per_cu = 0;
+      int r = blocks_per_cu(kern, WAVES_PER_BLOCK * 64, &per_cu);
+      if (r) return r;
+      hipLaunchKernelGGL(kern, dim3(std::max(1, per_cu) * n_cu), dim3(WAVES_PER_BLOCK * 64), 0, st, ca, W.tiny,
+                         W.meta + 5);
+      return KC_OK;
+    };
+    rc = ms ? wave_sort(k_wave_sort_count<K, WC, WAVES_PER_BLOCK, true>)
+            : wave_sort(k_wave_sort_count<K, WC, WAVES_PER_BLOCK>);
+    if (rc) return rc;
   }
   if (marks) stage_mark(6, st);
   // merge the chunks' (k-mer, count) lists: compact, sort by k-mer, sum each run's counts
@@ -749,17 +779,46 @@ int count_buckets(const Plan& P, const Ws<K>& W, const u32* blk_base, uint32_t l
   u32* lvs = W.kl0c;
   K* fk = W.kl1k;                    // the free buffer holds the merged runs' survivors
   u32* fc = W.kl1c;
-  hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, W.kl_nc, W.bc);
+  const u32* seg_bits = nullptr;
+  if (ms) {   // a heavy bucket's segment always starts a run (two sets may share a k-mer)
+    hipLaunchKernelGGL(k_seg_bits, grid_for(std::min<u64>(P.B, P.chunk_cap), 256, 1024), dim3(256), 0, st, W.seg,
+                       W.meta + 1, W.kl_nc, md->seg_bits);
+    seg_bits = md->seg_bits;
+  }
+  hipLaunchKernelGGL((k_rle_count<K>), dim3(P.nb_large), dim3(256), 0, st, lks, W.kl_nc, W.bc, seg_bits);
   hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, W.bc, W.bc, (const u64*)nullptr, (u64)P.nb_large,
                      W.nruns, (u64*)nullptr, 0ull);
-  hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, W.kl_nc, W.bc, W.hp);
-  hipLaunchKernelGGL((k_rle_runs<K>), dim3(RUN_BLOCKS), dim3(256), 0, st, ca, lks, lvs, W.kl_nc, W.hp, W.nruns, fk,
-                     fc, W.scnt + P.B);
+  hipLaunchKernelGGL((k_rle_heads<K>), dim3(P.nb_large), dim3(256), 0, st, lks, W.kl_nc, W.bc, W.hp, seg_bits);
+  if (ms)
+    hipLaunchKernelGGL((k_rle_runs<K, true>), dim3(RUN_BLOCKS), dim3(256), 0, st, ca, lks, lvs, W.kl_nc, W.hp,
+                       W.nruns, fk, fc, W.scnt + P.B, (const u64*)W.seg, md->rset);
+  else
+    hipLaunchKernelGGL((k_rle_runs<K>), dim3(RUN_BLOCKS), dim3(256), 0, st, ca, lks, lvs, W.kl_nc, W.hp, W.nruns, fk,
+                       fc, W.scnt + P.B, (const u64*)nullptr, (u32*)nullptr);
 
   if (marks) stage_mark(7, st);
   // ---- compact the survivors (buckets, then merged runs)
   scan_u32(W.scnt, W.soff, (const u64*)nullptr, (u64)P.B + RUN_BLOCKS, W.surv_n, W.scanbuf, st, W.surv_nc,
            P.surv_cap);
+  if (ms && md->cbits >= 0) {   // k-mers with count | set << cbits, sorted by k-mer then set
+    K* pk = reinterpret_cast<K*>(md->pair_k);
+    hipLaunchKernelGGL((k_gather_packed<K>), grid_for(P.B, 4, 4096), dim3(256), 0, st, W.s0k, W.s0c, W.kall,
+                       (const u64*)nullptr, 0u, md->bset, (const u32*)nullptr, W.scnt, W.soff, (u64)P.B, md->cbits,
+                       pk, md->wide_c, md->wide_cap);
+    hipLaunchKernelGGL((k_gather_packed<K>), grid_for(RUN_BLOCKS, 4, 4096), dim3(256), 0, st, fk, fc,
+                       (const u64*)nullptr, W.nruns, RUN_BLOCKS, (const u32*)nullptr, (const u32*)md->rset,
+                       W.scnt + P.B, W.soff + P.B, (u64)RUN_BLOCKS, md->cbits, pk, md->wide_c, md->wide_cap);
+    return KC_OK;
+  }
+  if (ms) {   // as wide keys (set << 2k | k-mer), sorted once by set and k-mer afterwards
+    hipLaunchKernelGGL((k_gather_wide<K>), grid_for(P.B, 4, 4096), dim3(256), 0, st, W.s0k, W.s0c, W.kall,
+                       (const u64*)nullptr, 0u, md->bset, (const u32*)nullptr, W.scnt, W.soff, (u64)P.B, P.k,
+                       md->wide_k, md->wide_c, md->wide_cap);
+    hipLaunchKernelGGL((k_gather_wide<K>), grid_for(RUN_BLOCKS, 4, 4096), dim3(256), 0, st, fk, fc,
+                       (const u64*)nullptr, W.nruns, RUN_BLOCKS, (const u32*)nullptr, (const u32*)md->rset,
+                       W.scnt + P.B, W.soff + P.B, (u64)RUN_BLOCKS, P.k, md->wide_k, md->wide_c, md->wide_cap);
+    return KC_OK;
+  }
   hipLaunchKernelGGL((k_gather_segments<K>), grid_for(P.B, 4, 4096), dim3(256), 0, st, W.s0k, W.s0c, W.kall,
                      (const u64*)nullptr, 0u, W.scnt, W.soff, (const u64*)nullptr, (u64)P.B, out_k, out_c, out_base,
                      out_cap);
@@ -773,7 +832,9 @@ int count_buckets(const Plan& P, const Ws<K>& W, const u32* blk_base, uint32_t l
 // top bits (in -> mid -> in), then each range sorted on chip into the caller's buffers.
 template <typename K>
 int sort_survivors(const Plan& P, const Ws<K>& W, K* in_k, u32* in_c, K* mid_k, u32* mid_c, const u64* n_ptr,
-                   u64 n_cap, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap, int n_cu, hipStream_t st) {
+                   u64 n_cap, uint64_t* d_kmers, uint32_t* d_counts, uint64_t pair_cap, int n_cu, hipStream_t st,
+                   int key_bits = 0) {
+  const int nbits = key_bits ? key_bits : 2 * P.k;   // significant bits of the keys
   MsdArgs ma;
   ma.in_k = in_k;
   ma.in_v = in_c;
@@ -785,7 +846,7 @@ int sort_survivors(const Plan& P, const Ws<K>& W, K* in_k, u32* in_c, K* mid_k, 
   ma.hist = W.mhist;
   ma.seg = W.seg;
   ma.n_seg = W.ctrl + C_NSEG;
-  ma.nbits = 2 * P.k;
+  ma.nbits = nbits;
   ma.target = seg_range_target<K>();
   // blocks of the coarse pass: about 16K survivors each at most, up to MSD_NB
   ma.nb = (u32)std::min<u64>(MSD_NB, std::max<u64>(1, ceil_div(n_cap, 16384)));
@@ -794,10 +855,10 @@ int sort_survivors(const Plan& P, const Ws<K>& W, K* in_k, u32* in_c, K* mid_k, 
   hipLaunchKernelGGL((k_msd_scatter<K>), dim3(ma.nb), dim3(512), 0, st, ma);
   hipLaunchKernelGGL((k_msd_fine<K>), dim3(256), dim3(1024), 0, st, ma);
   // the key ranges number 256 << g2, g2 growing with the survivor count (at most n_cap)
-  const u64 max_ranges = 256ull << msd_g2(n_cap, 2 * P.k, seg_range_target<K>());
+  const u64 max_ranges = 256ull << msd_g2(n_cap, nbits, seg_range_target<K>());
   int seg_grid = 0;
   return seg_sort<K>(in_k, in_c, mid_k, mid_c, reinterpret_cast<K*>(d_kmers), d_counts, pair_cap, W.seg,
-                     W.ctrl + C_NSEG, max_ranges, 2 * P.k, false, n_ptr, seg_range_target<K>(), n_cu, st, &seg_grid);
+                     W.ctrl + C_NSEG, max_ranges, nbits, false, n_ptr, seg_range_target<K>(), n_cu, st, &seg_grid);
 }
 
 template <typename K>
@@ -905,6 +966,15 @@ int warm_launch_facts() {
   if ((rc = blocks_per_cu(k_wave_sort_count<u64, WAVE_CAP_64, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v))) return rc;
   if ((rc = blocks_per_cu(k_wave_sort_count<k128, WAVE_CAP_128, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v)))
     return rc;
+  // the same kernels counting several read sets at once
+  if ((rc = blocks_per_cu(k_bucket_sort_count<u64, 256, 16, true>, 256, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<u64, 512, 16, true>, 512, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 256, 8, true>, 256, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 512, 8, true>, 512, &v))) return rc;
+  if ((rc = blocks_per_cu(k_wave_sort_count<u64, WAVE_CAP_64, WAVES_PER_BLOCK, true>, WAVES_PER_BLOCK * 64, &v)))
+    return rc;
+  if ((rc = blocks_per_cu(k_wave_sort_count<k128, WAVE_CAP_128, WAVES_PER_BLOCK, true>, WAVES_PER_BLOCK * 64, &v)))
+    return rc;
   if ((rc = blocks_per_cu(k_seg_sort<u64, 256, 16>, 256, &v))) return rc;
   if ((rc = blocks_per_cu(k_seg_sort<k128, 256, 8>, 256, &v))) return rc;
   if ((rc = blocks_per_cu(k_seg_wave<u64, seg_wave_cap<u64>(), SEG_WAVES_PER_BLOCK>, SEG_WAVES_PER_BLOCK * 64, &v)))
@@ -929,6 +999,297 @@ int enqueue_any(const Plan& P, void* ws, const uint8_t* d_reads, const uint64_t*
   if (P.key_words == 1)
     return enqueue<u64>(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_hist, d_tot, st);
   return enqueue<k128>(P, ws, d_reads, d_offsets, lo, hi, hist_len, d_kmers, d_counts, pair_cap, d_hist, d_tot, st);
+}
+
+// ---------------------------------------------------------------- several read sets in one count
+// Read sets of one (k, m, frequency window, histogram length), counted as one: their bases
+// are laid out back to back in one joint base space (each set from its own buffer, at a
+// multiple of 32), set s owns buckets [bbase[s], bbase[s] + 2^lb[s]) -- its own size rule,
+// shrunk until all fit 2^20 -- so that no bucket mixes sets; the counting kernels keep
+// per-set histograms and totals, and the survivors are sorted once by (set, k-mer) as wide
+// keys and split into the sets' outputs.  One fixed launch sequence, whatever the number
+// of sets.
+struct MultiSet {
+  const uint8_t* reads = nullptr;     // device: the set's read buffer
+  const uint64_t* offsets = nullptr;  // device: its offsets
+  u64 n_reads = 0, off0 = 0, R = 0, n_max = 0;   // host facts: offsets[0], bases, windows
+};
+
+struct MultiPlan {
+  Plan P;   // the joint count
+  int k = 0, m = 0;
+  u32 lo = 1, hi = 1;
+  u64 hist_len = 2;
+  u32 n_sets = 0, sbits = 1;
+  u64 R = 0, n_reads = 0, wide_cap = 0;
+  std::vector<u64> set_start, read_base, set_len, src_off;   // see SetTables
+  std::vector<const uint8_t*> src;
+  std::vector<const uint64_t*> offs;
+  std::vector<u32> bbase, lb;
+  // Survivor order: when count and set fit one 32-bit value (cbits = bits of max_freq,
+  // cbits + sbits <= 32) the survivors are sorted by k-mer with value count | set << cbits,
+  // then by set in one stable pass straight into the outputs; otherwise as wide keys
+  // set << 2k | k-mer.  Either way two pair buffers.
+  bool packed = false;
+  int cbits = 0;
+  u32 radix_nb = 1;
+  // scratch (reusable by the next count on the same stream): the joint count's workspace,
+  // then these regions
+  u64 o_segbits = 0, segbits_words = 0, o_rset = 0, o_joff = 0, o_wk[3] = {}, o_wc[3] = {}, o_rcnt = 0, o_rtot = 0,
+      scratch_bytes = 0;
+  // the count's own memory (tables and outputs, kept until the results are read)
+  u64 o_tab = 0, tab_bytes = 0, o_bset = 0, o_first = 0, o_hist = 0, o_tot = 0, o_outk = 0, o_outc = 0, own_bytes = 0;
+};
+
+constexpr u32 MULTI_MAX_SETS = 1u << SET_DB;   // the pass by set ranks up to 512 sets
+
+// Plan of one count over `sets`; false when they cannot share one (too many sets or
+// windows, wide keys over 126 bits, a bad configuration).
+bool make_multi_plan(const std::vector<MultiSet>& sets, int k, int m, u32 lo, u32 hi, u64 hist_len,
+                     const kc_config* cfg, MultiPlan* mp) {
+  const u32 S = (u32)sets.size();
+  if (S == 0 || S > MULTI_MAX_SETS) return false;
+  mp->k = k;
+  mp->m = m;
+  mp->lo = lo;
+  mp->hi = hi;
+  mp->hist_len = hist_len;
+  mp->n_sets = S;
+  mp->sbits = 1;
+  while ((1u << mp->sbits) < S) ++mp->sbits;
+  if (2 * k + (int)mp->sbits > 126) return false;
+  const int kw = k <= 31 ? 1 : 2;
+  const u32 variant = (cfg && cfg->small_variant) ? cfg->small_variant : default_variant(kw);
+  if (variant > 2) return false;
+  const u64 target = std::max<u64>(1, small_cap(kw, variant) / 3);
+  mp->set_start.assign(S + 1, 0);
+  mp->read_base.assign(S + 1, 0);
+  mp->set_len.assign(S, 0);
+  mp->src_off.assign(S, 0);
+  mp->src.assign(S, nullptr);
+  mp->offs.assign(S, nullptr);
+  mp->bbase.assign(S, 0);
+  mp->lb.assign(S, 1);
+  u64 pos = 0, reads = 0, n_max = 0, wide = 0;
+  for (u32 s = 0; s < S; ++s) {
+    pos = align_up(pos, 32);
+    mp->set_start[s] = pos;
+    mp->read_base[s] = reads;
+    mp->set_len[s] = sets[s].R;
+    mp->src_off[s] = sets[s].off0;
+    mp->src[s] = sets[s].reads;
+    mp->offs[s] = sets[s].offsets;
+    pos += sets[s].R;
+    reads += sets[s].n_reads;
+    n_max += sets[s].n_max;
+    wide += sets[s].n_max / std::max<u32>(1, lo) + 1;
+    int lb = 1;
+    while (lb < 20 && (sets[s].n_max >> lb) > target) ++lb;
+    mp->lb[s] = (u32)lb;
+  }
+  mp->set_start[S] = pos;
+  mp->read_base[S] = reads;
+  if (pos >= (1ull << 32) || n_max >= (1ull << 32)) return false;
+  // the sets' buckets must fit the 20-bit bucket field: halve the largest until they do
+  u64 nb = 0;
+  for (u32 s = 0; s < S; ++s) nb += 1ull << mp->lb[s];
+  while (nb > (1ull << 20)) {
+    u32 best = 0;
+    for (u32 s = 1; s < S; ++s)
+      if (mp->lb[s] > mp->lb[best] || (mp->lb[s] == mp->lb[best] && sets[s].n_max > sets[best].n_max)) best = s;
+    if (mp->lb[best] <= 1) return false;
+    nb -= 1ull << (mp->lb[best] - 1);
+    mp->lb[best] -= 1;
+  }
+  u64 acc = 0;
+  for (u32 s = 0; s < S; ++s) {
+    mp->bbase[s] = (u32)acc;
+    acc += 1ull << mp->lb[s];
+  }
+  int log_b = 1;
+  while ((1ull << log_b) < acc) ++log_b;
+  kc_config c{};
+  if (cfg) c = *cfg;
+  c.hbm_budget = 0;
+  c.log2_buckets = (u32)log_b;
+  mp->R = pos;
+  mp->n_reads = reads;
+  mp->wide_cap = wide;
+  if (!make_plan(pos, reads, n_max, k, m, lo, &c, &mp->P)) return false;
+  u64 o = align_up(mp->P.bytes, 256);
+  auto take = [&](u64 bytes) {
+    u64 r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  mp->segbits_words = mp->P.kl_cap / 32 + 2;
+  mp->o_segbits = take(4ull * mp->segbits_words);
+  mp->o_rset = take(4ull * mp->P.kl_cap);
+  mp->o_joff = take(8ull * (reads + 1));
+  mp->cbits = 32 - __builtin_clz(std::max<u32>(1, hi));
+  mp->packed = mp->cbits + (int)mp->sbits <= 32;
+  const u64 kb = mp->packed ? 8ull * kw : 16ull;
+  for (int i = 0; i < 2; ++i) {   // survivors and the sort's second buffer
+    mp->o_wk[i] = take(kb * wide);
+    mp->o_wc[i] = take(4ull * wide);
+  }
+  if (mp->packed) {
+    const u64 tile = (u64)RADIX_T * RADIX_ITEMS_64;
+    mp->radix_nb = (u32)std::min<u64>(1024, std::max<u64>(1, ceil_div(wide, tile * 2)));
+    mp->o_rcnt = take(4ull * RADIX_NB_MAX * mp->radix_nb);
+    mp->o_rtot = take(4ull * RADIX_NB_MAX);
+  }
+  mp->scratch_bytes = o;
+  o = 0;
+  mp->tab_bytes = 8ull * (S + 1) * 2 + 8ull * S * 4 + 4ull * S * 2;
+  mp->o_tab = take(mp->tab_bytes);
+  mp->o_bset = take(4ull * mp->P.B);
+  mp->o_first = take(8ull * (S + 1));
+  mp->o_hist = take(8ull * S * hist_len);
+  mp->o_tot = take(sizeof(DevTotals) * S);
+  mp->o_outk = take(8ull * kw * wide);
+  mp->o_outc = take(4ull * wide);
+  mp->own_bytes = o;
+  return true;
+}
+
+// Host image of the tables at o_tab (set_start, read_base, set_len, src_off, src, offs,
+// bbase, lb) and of the bucket -> set map at o_bset.
+void multi_tables(const MultiPlan& mp, std::vector<char>* tab, std::vector<u32>* bset) {
+  const u32 S = mp.n_sets;
+  tab->assign(mp.tab_bytes, 0);
+  char* p = tab->data();
+  auto put = [&](const void* src, size_t n) {
+    memcpy(p, src, n);
+    p += n;
+  };
+  put(mp.set_start.data(), 8ull * (S + 1));
+  put(mp.read_base.data(), 8ull * (S + 1));
+  put(mp.set_len.data(), 8ull * S);
+  put(mp.src_off.data(), 8ull * S);
+  put(mp.src.data(), 8ull * S);
+  put(mp.offs.data(), 8ull * S);
+  put(mp.bbase.data(), 4ull * S);
+  put(mp.lb.data(), 4ull * S);
+  bset->assign(mp.P.B, S - 1);   // buckets past the last set's stay empty
+  for (u32 s = 0; s < S; ++s)
+    for (u64 b = 0; b < (1ull << mp.lb[s]); ++b) (*bset)[mp.bbase[s] + b] = s;
+}
+
+SetTables set_tables(const MultiPlan& mp, void* own) {
+  const u32 S = mp.n_sets;
+  char* t = at<char>(own, mp.o_tab);
+  SetTables T;
+  T.set_start = reinterpret_cast<const u64*>(t);
+  T.read_base = T.set_start + (S + 1);
+  T.set_len = T.read_base + (S + 1);
+  T.src_off = T.set_len + S;
+  T.src = reinterpret_cast<const u8* const*>(T.src_off + S);
+  T.offs = reinterpret_cast<const u64* const*>(T.src + S);
+  T.bbase = reinterpret_cast<const u32*>(T.offs + S);
+  T.lb = T.bbase + S;
+  T.n_sets = S;
+  return T;
+}
+
+// Device outputs of a count over several sets: all pairs set by set (set s at
+// [first[s], first[s + 1])), the sets' histograms and totals.
+struct MultiOut {
+  void* kmers;
+  u32* counts;
+  u64* first;
+  u64* hist;
+  DevTotals* tot;
+};
+MultiOut multi_out(const MultiPlan& mp, void* own) {
+  return MultiOut{at<char>(own, mp.o_outk), at<u32>(own, mp.o_outc), at<u64>(own, mp.o_first),
+                  at<u64>(own, mp.o_hist), at<DevTotals>(own, mp.o_tot)};
+}
+
+// The launch sequence of one count over several sets: scratch of scratch_bytes, `own`
+// of own_bytes holding the tables (written by the caller beforehand) and the outputs.
+template <typename K>
+int enqueue_multi(const MultiPlan& mp, void* ws, void* own, hipStream_t st) {
+  int n_cu = 0;
+  int rc = device_info(&n_cu);
+  if (rc) return rc;
+  const Plan& P = mp.P;
+  Ws<K> W = ws_ptrs<K>(P, ws);
+  const SetTables T = set_tables(mp, own);
+  const MultiOut O = multi_out(mp, own);
+  u64* joff = at<u64>(ws, mp.o_joff);
+  MultiDev md;
+  md.n_sets = mp.n_sets;
+  md.bset = at<u32>(own, mp.o_bset);
+  md.seg_bits = at<u32>(ws, mp.o_segbits);
+  md.rset = at<u32>(ws, mp.o_rset);
+  md.wide_k = at<k128>(ws, mp.o_wk[0]);
+  md.pair_k = at<char>(ws, mp.o_wk[0]);
+  md.wide_c = at<u32>(ws, mp.o_wc[0]);
+  md.wide_cap = mp.wide_cap;
+  md.cbits = mp.packed ? mp.cbits : -1;
+  stage_mark(0, st);
+  launch_clear<K>(P, W, O.hist, mp.hist_len * mp.n_sets, O.tot, st, mp.n_sets, md.seg_bits, mp.segbits_words);
+  // joint offsets, then the encode straight from each set's buffer
+  hipLaunchKernelGGL(k_join_offsets, grid_for(mp.n_reads + 1, 256), dim3(256), 0, st, T, mp.n_reads, mp.R, joff);
+  if (mp.R)
+    hipLaunchKernelGGL(k_pack_sets, grid_for(ceil_div(mp.R, 32), 256), dim3(256), 0, st, T, mp.R, W.packed, W.nmask);
+  if (mp.n_reads)
+    hipLaunchKernelGGL(k_read_starts, grid_for(mp.n_reads, 256), dim3(256), 0, st, joff, mp.n_reads, mp.R, W.starts,
+                       W.flags);
+  ExtractArgs ea = extract_args<K>(P, W, joff);
+  ea.set_start = T.set_start;
+  ea.set_bbase = T.bbase;
+  ea.set_lb = T.lb;
+  ea.n_sets = mp.n_sets;
+  stage_mark(1, st);
+  launch_extract<EX_MULTI>(P, ea, st);
+  if ((rc = count_buckets<K>(P, W, nullptr, mp.lo, mp.hi, mp.hist_len, O.hist, O.tot, nullptr, nullptr, nullptr, ~0ull,
+                             true, n_cu, st, &md)))
+    return rc;
+  u64* n_wide = W.ctrl + C_POOL_NC;   // (a one-pass count leaves the pool words unused)
+  hipLaunchKernelGGL(k_clamp_u64, dim3(1), dim3(64), 0, st, W.surv_n, mp.wide_cap, n_wide);
+  if (mp.packed) {
+    // by k-mer (in place), then one stable pass by set straight into the outputs
+    K* ak = at<K>(ws, mp.o_wk[0]);
+    u32* av = at<u32>(ws, mp.o_wc[0]);
+    if ((rc = sort_survivors<K>(P, W, ak, av, at<K>(ws, mp.o_wk[1]), at<u32>(ws, mp.o_wc[1]), n_wide, mp.wide_cap,
+                                reinterpret_cast<uint64_t*>(ak), av, mp.wide_cap, n_cu, st)))
+      return rc;
+    u32* rcnt = at<u32>(ws, mp.o_rcnt);
+    u32* rtot = at<u32>(ws, mp.o_rtot);
+    hipLaunchKernelGGL(k_set_hist, dim3(mp.radix_nb), dim3(256), 0, st, av, n_wide, rcnt, mp.cbits);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << SET_DB), dim3(256), 0, st, rcnt, mp.radix_nb, rtot);
+    hipLaunchKernelGGL((k_set_scatter<K, 512, 8>), dim3(mp.radix_nb), dim3(512), 0, st, ak,
+                       reinterpret_cast<K*>(O.kmers), av, O.counts, n_wide, rcnt, rtot, mp.cbits);
+    hipLaunchKernelGGL(k_set_first, dim3(1), dim3(512), 0, st, rtot, mp.n_sets, O.first);
+    hipLaunchKernelGGL(k_finalize_sets, dim3(mp.n_sets), dim3(256), 0, st, O.tot, W.bcnt, T.bbase, T.lb, O.first,
+                       P.cap_tiny, P.cap, W.flags, W.counters, P.rec_cap, W.surv_n, mp.wide_cap);
+    stage_mark(8, st);
+    HIP_TRY(hipGetLastError());
+    return KC_OK;
+  }
+  // the wide survivors sorted by (set, k-mer), then split into the sets' outputs
+  const Ws<k128> W2 = ws_ptrs<k128>(P, ws);
+  k128* wk1 = at<k128>(ws, mp.o_wk[1]);
+  u32* wc1 = at<u32>(ws, mp.o_wc[1]);
+  // sorted in place (the key ranges' sorts write back over the input)
+  if ((rc = sort_survivors<k128>(P, W2, md.wide_k, md.wide_c, wk1, wc1, n_wide, mp.wide_cap,
+                                 reinterpret_cast<uint64_t*>(md.wide_k), md.wide_c, mp.wide_cap, n_cu, st,
+                                 2 * mp.k + (int)mp.sbits)))
+    return rc;
+  hipLaunchKernelGGL((k_split_wide<K>), grid_for(mp.wide_cap, 256, 4096), dim3(256), 0, st, md.wide_k, md.wide_c,
+                     n_wide,
+                     mp.wide_cap, mp.k, mp.n_sets, reinterpret_cast<K*>(O.kmers), O.counts, O.first);
+  hipLaunchKernelGGL(k_finalize_sets, dim3(mp.n_sets), dim3(256), 0, st, O.tot, W.bcnt, T.bbase, T.lb, O.first,
+                     P.cap_tiny, P.cap, W.flags, W.counters, P.rec_cap, W.surv_n, mp.wide_cap);
+  stage_mark(8, st);
+  HIP_TRY(hipGetLastError());
+  return KC_OK;
+}
+
+int enqueue_multi_any(const MultiPlan& mp, void* ws, void* own, hipStream_t st) {
+  return mp.P.key_words == 1 ? enqueue_multi<u64>(mp, ws, own, st) : enqueue_multi<k128>(mp, ws, own, st);
 }
 
 int device_common(const uint8_t* d_reads, uint64_t total_bases, const uint64_t* d_offsets, uint64_t n_reads, int k,

@@ -49,6 +49,10 @@ struct CountArgs {
   void* kl_k;              // (k-mer, count) list of chunk c at slots chunk_start[c] + i
   u32* kl_c;
   u32* kl_cnt;             // list length per chunk
+  // several read sets in one count: bucket b belongs to set bset[b], and hist / tot are
+  // arrays over the sets ([n_sets][hist_len] bins, [n_sets] totals)
+  const u32* bset;
+  u32 n_sets;
 };
 
 // ---------------------------------------------------------------------------- key mixing
@@ -208,6 +212,41 @@ __device__ __forceinline__ void run_stats_lanes(const RunSink& S, u64 c, bool ac
   if (act && c >= last) atomicAdd(S.lover, (unsigned long long)c);
   const u32 c32 = (u32)min(c, (u64)0xFFFFFFFFu);
   if (act && c32 > *(volatile u32*)S.lmax) atomicMax(S.lmax, c32);
+}
+
+// Several read sets in one count: the sink's global targets become those of set s.
+__device__ __forceinline__ void sink_to_set(RunSink& S, u64* hist, DevTotals* tot, u32 s) {
+  S.hist = hist + (u64)s * S.hist_len;
+  S.tot = tot + s;
+}
+
+// One wave's statistics (its own LDS slice) to the global targets, then cleared.
+__device__ __forceinline__ void flush_stats_wave(const RunSink& S, u64 ndist) {
+  const u32 H = (u32)min(S.hist_len, (u64)256);
+  __builtin_amdgcn_wave_barrier();
+  for (u32 i = lane_id(); i < H; i += 64) {
+    const u32 v = S.hist_s[i];
+    if (v) atomicAdd((unsigned long long*)&S.hist[i], (unsigned long long)v);
+    S.hist_s[i] = 0;
+  }
+  if (lane_id() == 0) {
+    if (*S.lmax) atomicMax((unsigned long long*)&S.tot->max_count, (unsigned long long)*S.lmax);
+    if (*S.lover) atomicAdd((unsigned long long*)&S.tot->overflow_sum, *S.lover);
+    if (ndist) atomicAdd((unsigned long long*)&S.tot->n_distinct, (unsigned long long)ndist);
+    *S.lmax = 0;
+    *S.lover = 0;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Statistics of one run straight to the global targets (runs of several sets in one
+// step; rare).
+__device__ __forceinline__ void run_stats_global(u64* hist, u64 hist_len, DevTotals* tot, u64 c) {
+  const u64 last = hist_len - 1;
+  atomicAdd((unsigned long long*)&hist[c < last ? c : last], 1ull);
+  if (c >= last) atomicAdd((unsigned long long*)&tot->overflow_sum, (unsigned long long)c);
+  atomicMax((unsigned long long*)&tot->max_count, (unsigned long long)c);
+  atomicAdd((unsigned long long*)&tot->n_distinct, 1ull);
 }
 
 __device__ __forceinline__ void flush_stats(const RunSink& S, u64 ndist) {
@@ -499,7 +538,7 @@ __device__ __forceinline__ u32 emit_runs_block(const K* keys, const u16* hp, u32
 // form of a heavy-hitter task (Section 3.5) -- merged later through HBM.  Items after
 // that are small buckets: their supermers are expanded into LDS, sorted, and their runs
 // are final counts.  Every item writes its output to its own slot range.
-template <typename K, int T, int ITEMS>
+template <typename K, int T, int ITEMS, bool MS = false>
 __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
   using SM = BucketSmem<K, T, ITEMS>;
   constexpr int CAP = SM::CAP;
@@ -520,7 +559,7 @@ __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
   K* skeys = reinterpret_cast<K*>(A.surv_k);
   const K* lkeys = reinterpret_cast<const K*>(A.lkeys);
   K* klk = reinterpret_cast<K*>(A.kl_k);
-  for (u64 item = blockIdx.x; item < n_chunks + n_small; item += gridDim.x) {
+  auto do_item = [&](u64 item) {
     __syncthreads();
     const bool chunk = item < n_chunks;
     u32 n, b = 0;
@@ -588,6 +627,36 @@ __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
       if (tid == 0) A.surv_cnt[b] = kept;
       ndist += nruns;
     }
+  };
+  if constexpr (!MS) {
+    for (u64 item = blockIdx.x; item < n_chunks + n_small; item += gridDim.x) do_item(item);
+  } else {
+    // Several read sets: chunks (no statistics) round-robin, then the small buckets in one
+    // contiguous range per block.  Buckets are numbered set by set, so a block meets few
+    // sets and flushes its statistics only when the set changes.
+    for (u64 item = blockIdx.x; item < n_chunks; item += gridDim.x) do_item(item);
+    const u64 per = (n_small + gridDim.x - 1) / gridDim.x;
+    const u64 ia = n_chunks + min(n_small, (u64)blockIdx.x * per), ie = n_chunks + min(n_small, (u64)(blockIdx.x + 1) * per);
+    u32 cur = ~0u;
+    for (u64 item = ia; item < ie; ++item) {
+      const u32 st = A.bset[A.small_list[item - n_chunks]];
+      if (st != cur) {
+        if (cur != ~0u) {
+          __syncthreads();
+          flush_stats(sink, tid == 0 ? ndist : 0);
+          __syncthreads();
+          for (u32 i = tid; i < 256; i += T) S.hist_s[i] = 0;
+          if (tid == 0) {
+            S.lmax = 0;
+            lover = 0;
+          }
+          ndist = 0;
+        }
+        sink_to_set(sink, A.hist, A.tot, st);
+        cur = st;
+      }
+      do_item(item);
+    }
   }
   __syncthreads();
   flush_stats(sink, tid == 0 ? ndist : 0);
@@ -653,20 +722,23 @@ __device__ __forceinline__ void wave_sort(WaveSmem<K, WCAP>& S, u32 n_pad, int p
   }
 }
 
-template <typename K, int WCAP, int WPB>
+template <typename K, int WCAP, int WPB, bool MS = false>
 __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const u32* __restrict__ tiny_list,
                                                                const u64* __restrict__ n_tiny_ptr) {
   static_assert(WCAP * 2 <= 256 * 12, "run heads reuse the rank tables");
+  constexpr int NS = MS ? WPB : 1;   // statistics slices: per block, or per wave for several sets
   __shared__ WaveSmem<K, WCAP> WS[WPB];
-  __shared__ u32 hist_s[256];
-  __shared__ u32 lmax;
-  __shared__ unsigned long long lover;
+  __shared__ u32 hist_s[NS][256];
+  __shared__ u32 lmax[NS];
+  __shared__ unsigned long long lover[NS];
   __shared__ u64 ndb;
   const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-  for (u32 i = tid; i < 256; i += blockDim.x) hist_s[i] = 0;
-  if (tid == 0) { lmax = 0; ndb = 0; lover = 0; }
+  for (u32 i = tid; i < NS * 256; i += blockDim.x) (&hist_s[0][0])[i] = 0;
+  if (tid < NS) { lmax[tid] = 0; lover[tid] = 0; }
+  if (tid == 0) ndb = 0;
   __syncthreads();
-  RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax, &lover};
+  const u32 sl = MS ? wave : 0u;
+  RunSink sink{hist_s[sl], A.hist_len, A.hist, A.tot, &lmax[sl], &lover[sl]};
   WaveSmem<K, WCAP>& S = WS[wave];
   const u64 n_tiny = *n_tiny_ptr;
   const int np = sort_passes<K>(A.k);
@@ -680,8 +752,28 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
   u8* const rid = reinterpret_cast<u8*>(&S.u);
   u16* const roff = reinterpret_cast<u16*>(rid + MAPB);
   constexpr int RW = sizeof(K) == 8 ? 4 : 8;
-  for (u64 item = gw; item < n_tiny; item += nw) {
+  // Several read sets: one contiguous range of tiny buckets per wave (buckets are
+  // numbered set by set, so a wave meets few sets and flushes its statistics only when
+  // the set changes).  One set: round-robin.
+  u64 item = gw, i_end = n_tiny, i_step = nw;
+  if constexpr (MS) {
+    const u64 per = (n_tiny + nw - 1) / nw;
+    item = min(n_tiny, gw * per);
+    i_end = min(n_tiny, item + per);
+    i_step = 1;
+  }
+  u32 cur = ~0u;
+  for (; item < i_end; item += i_step) {
     const u32 b = tiny_list[item];
+    if constexpr (MS) {
+      const u32 st = A.bset[b];
+      if (st != cur) {
+        if (cur != ~0u) flush_stats_wave(sink, ndist);
+        ndist = 0;
+        sink_to_set(sink, A.hist, A.tot, st);
+        cur = st;
+      }
+    }
     const u32 r0 = A.rec_off[b], nr = A.rec_off[b + 1] - r0;
     const u32 n = min((u32)A.bcnt[b], (u32)WCAP);
     // expand 64 records at a time.  For 128-bit keys key-parallel: lanes take the chunk's
@@ -756,9 +848,13 @@ __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const
     if (lane == 0) A.surv_cnt[b] = kept;
     ndist += nruns;
   }
-  if (lane == 0 && ndist) atomicAdd((unsigned long long*)&ndb, (unsigned long long)ndist);
-  __syncthreads();
-  flush_stats(sink, tid == 0 ? ndb : 0);
+  if constexpr (MS) {
+    flush_stats_wave(sink, ndist);
+  } else {
+    if (lane == 0 && ndist) atomicAdd((unsigned long long*)&ndb, (unsigned long long)ndist);
+    __syncthreads();
+    flush_stats(sink, tid == 0 ? ndb : 0);
+  }
 }
 
 // ---------------------------------------------------------------------------- large buckets
@@ -824,14 +920,23 @@ __global__ __launch_bounds__(T) void k_expand_large(CountArgs A, K* __restrict__
 }
 
 // Head counts per block range of the sorted large-key array.
+// Several read sets in one count: the merged lists of two heavy buckets of different
+// sets may hold the same k-mer, so a segment's first entry always starts a run
+// (seg_bits: one bit per entry; null for one set, where neighbouring buckets never
+// share a key).
+__device__ __forceinline__ bool seg_start(const u32* seg_bits, u64 i) {
+  return seg_bits && ((seg_bits[i >> 5] >> (i & 31)) & 1u);
+}
+
 template <typename K>
 __global__ __launch_bounds__(256) void k_rle_count(const K* __restrict__ keys, const u64* __restrict__ n_ptr,
-                                                   u32* __restrict__ bc) {
+                                                   u32* __restrict__ bc, const u32* __restrict__ seg_bits = nullptr) {
   __shared__ u64 scr[17];
   u64 s, e;
   block_range(*n_ptr, gridDim.x, &s, &e);
   u64 c = 0;
-  for (u64 i = s + threadIdx.x; i < e; i += 256) c += (i == 0 || !key_eq(keys[i], keys[i - 1])) ? 1 : 0;
+  for (u64 i = s + threadIdx.x; i < e; i += 256)
+    c += (i == 0 || !key_eq(keys[i], keys[i - 1]) || seg_start(seg_bits, i)) ? 1 : 0;
   u64 tot;
   block_exclusive_scan<u64>(c, scr, &tot);
   if (threadIdx.x == 0) bc[blockIdx.x] = (u32)tot;
@@ -840,14 +945,15 @@ __global__ __launch_bounds__(256) void k_rle_count(const K* __restrict__ keys, c
 // Head positions in order: hp[r] = index of the first key of run r.
 template <typename K>
 __global__ __launch_bounds__(256) void k_rle_heads(const K* __restrict__ keys, const u64* __restrict__ n_ptr,
-                                                   const u32* __restrict__ bc, u32* __restrict__ hp) {
+                                                   const u32* __restrict__ bc, u32* __restrict__ hp,
+                                                   const u32* __restrict__ seg_bits = nullptr) {
   __shared__ u64 scr[17];
   u64 s, e;
   block_range(*n_ptr, gridDim.x, &s, &e);
   u64 base = bc[blockIdx.x];
   for (u64 c0 = s; c0 < e; c0 += 256) {
     const u64 i = c0 + threadIdx.x;
-    const bool head = i < e && (i == 0 || !key_eq(keys[i], keys[i - 1]));
+    const bool head = i < e && (i == 0 || !key_eq(keys[i], keys[i - 1]) || seg_start(seg_bits, i));
     u64 tot;
     const u64 ex = block_exclusive_scan<u64>(head ? 1ull : 0ull, scr, &tot);
     if (head) hp[base + ex] = (u32)i;
@@ -855,26 +961,45 @@ __global__ __launch_bounds__(256) void k_rle_heads(const K* __restrict__ keys, c
   }
 }
 
+// Several read sets: the set of the list entry at position i, through its segment (one
+// per heavy bucket, in large-list order; seg[0..n_large] are their starts).
+__device__ __forceinline__ u32 entry_set(const CountArgs& A, const u64* seg, u64 n_large, u64 i) {
+  u64 lo = 0, hi = n_large;   // seg[lo] <= i < seg[hi]
+  while (hi - lo > 1) {
+    const u64 mid = (lo + hi) >> 1;
+    if (seg[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return A.bset[A.large_list[lo]];
+}
+
 // Runs of the sorted (k-mer, count) list: a run's count is the sum of its entries'
 // counts (the merge of the chunks' lists).  Block b takes a contiguous range of runs
 // [rs, re); its survivors go to slots rs + i and their number to blk_cnt[b].
-template <typename K>
+// Several read sets (MS): each run's set comes from its segment; the statistics of a
+// step of 256 runs of one set go through LDS (flushed when the set changes), those of a
+// step that crosses sets straight to the global targets; survivors' sets go to out_s.
+template <typename K, bool MS = false>
 __global__ __launch_bounds__(256) void k_rle_runs(CountArgs A, const K* __restrict__ keys, const u32* __restrict__ vals,
                                                   const u64* __restrict__ n_ptr, const u32* __restrict__ hp,
                                                   const u64* __restrict__ nruns_ptr, K* __restrict__ out_k,
-                                                  u32* __restrict__ out_c, u32* __restrict__ blk_cnt) {
+                                                  u32* __restrict__ out_c, u32* __restrict__ blk_cnt,
+                                                  const u64* __restrict__ seg = nullptr, u32* __restrict__ out_s = nullptr) {
   __shared__ u32 hist_s[256];
   __shared__ u32 lmax;
   __shared__ unsigned long long lover;
   __shared__ u64 scr[17];
+  __shared__ u32 step_set[2];
   for (u32 i = threadIdx.x; i < 256; i += blockDim.x) hist_s[i] = 0;
   if (threadIdx.x == 0) { lmax = 0; lover = 0; }
   __syncthreads();
   RunSink sink{hist_s, A.hist_len, A.hist, A.tot, &lmax, &lover};
   const u64 n = *n_ptr, nruns = *nruns_ptr;
+  const u64 n_large = MS ? A.meta[1] : 0;
   u64 rs, re;
   block_range(nruns, gridDim.x, &rs, &re);
-  u64 kept = 0;
+  u64 kept = 0, ndist = 0;
+  u32 cur = ~0u;
   for (u64 c0 = rs; c0 < re; c0 += blockDim.x) {
     const u64 r = c0 + threadIdx.x;
     bool surv = false;
@@ -885,17 +1010,55 @@ __global__ __launch_bounds__(256) void k_rle_runs(CountArgs A, const K* __restri
       for (u64 i = s; i < e; ++i) c += vals[i];
       surv = c >= A.min_freq && c <= A.max_freq;
     }
-    run_stats_lanes(sink, c, r < re);
+    u32 my_set = 0;
+    if constexpr (MS) {
+      if (threadIdx.x == 0) {
+        step_set[0] = entry_set(A, seg, n_large, hp[c0]);
+        step_set[1] = entry_set(A, seg, n_large, hp[min(re, c0 + blockDim.x) - 1]);
+      }
+      __syncthreads();
+      const u32 s0 = step_set[0], s1 = step_set[1];
+      if (s0 == s1) {
+        if (s0 != cur) {
+          if (cur != ~0u) {
+            flush_stats(sink, threadIdx.x == 0 ? ndist : 0);
+            __syncthreads();
+            for (u32 i = threadIdx.x; i < 256; i += blockDim.x) hist_s[i] = 0;
+            if (threadIdx.x == 0) { lmax = 0; lover = 0; }
+            __syncthreads();
+          }
+          ndist = 0;
+          sink_to_set(sink, A.hist, A.tot, s0);
+          cur = s0;
+        }
+        my_set = s0;
+        run_stats_lanes(sink, c, r < re);
+        ndist += min(re, c0 + blockDim.x) - c0;
+      } else {
+        if (r < re) {
+          my_set = entry_set(A, seg, n_large, s);
+          run_stats_global(A.hist + (u64)my_set * A.hist_len, A.hist_len, A.tot + my_set, c);
+        }
+      }
+    } else {
+      run_stats_lanes(sink, c, r < re);
+    }
     u64 tot;
     const u64 ex = block_exclusive_scan<u64>(surv ? 1ull : 0ull, scr, &tot);
     if (surv) {
       out_k[rs + kept + ex] = keys[s];
       out_c[rs + kept + ex] = (u32)c;
+      if constexpr (MS) out_s[rs + kept + ex] = my_set;
     }
     kept += tot;
   }
   if (threadIdx.x == 0) blk_cnt[blockIdx.x] = (u32)kept;
-  flush_stats(sink, threadIdx.x == 0 ? (re - rs) : 0);
+  if constexpr (MS) {
+    __syncthreads();
+    flush_stats(sink, threadIdx.x == 0 ? ndist : 0);
+  } else {
+    flush_stats(sink, threadIdx.x == 0 ? (re - rs) : 0);
+  }
 }
 
 // Gather of sparse segments into one dense array: segment i holds cnt[i] entries at
@@ -935,6 +1098,184 @@ __global__ __launch_bounds__(256) void k_gather_segments(const K* __restrict__ s
         dst_c[o + j] = src_c[base + j];
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------- several sets
+// Several read sets in one count: survivors are sorted once by (set, k-mer) as 128-bit
+// "wide" keys, set << 2k | k-mer (2k plus the set's bits at most 128).
+__device__ __forceinline__ k128 wide_of(u64 key, u32 s, int k) {
+  const int sh = 2 * k;   // < 64
+  return k128{key | ((u64)s << sh), (u64)s >> (64 - sh)};
+}
+__device__ __forceinline__ k128 wide_of(k128 key, u32 s, int k) {
+  return k128{key.lo, key.hi | ((u64)s << (2 * k - 64))};
+}
+__device__ __forceinline__ u32 wide_set(k128 w, int k) {
+  const int sh = 2 * k;
+  return sh < 64 ? (u32)((w.lo >> sh) | (w.hi << (64 - sh))) : (u32)(w.hi >> (sh - 64));
+}
+__device__ __forceinline__ void wide_key(k128 w, int k, u64* out) { out[0] = w.lo & ((1ull << (2 * k)) - 1ull); }
+__device__ __forceinline__ void wide_key(k128 w, int k, k128* out) {
+  *out = k128{w.lo, 2 * k == 64 ? 0ull : (w.hi & ((1ull << (2 * k - 64)) - 1ull))};
+}
+
+// One bit per merged-list entry at the start of each heavy bucket's segment (bits zeroed
+// before).
+__global__ __launch_bounds__(256) void k_seg_bits(const u64* __restrict__ seg, const u64* __restrict__ n_large_ptr,
+                                                  const u64* __restrict__ n_ent_ptr, u32* __restrict__ bits) {
+  const u64 n_large = *n_large_ptr, n_ent = *n_ent_ptr;
+  for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < n_large; i += (u64)gridDim.x * blockDim.x) {
+    const u64 p = seg[i];
+    if (p < n_ent) atomicOr(&bits[p >> 5], 1u << (p & 31));
+  }
+}
+
+// k_gather_segments for several sets: the same segments, written as wide keys.  The set
+// of segment i is bset[i] (bucket survivors), else that of each entry (src_set: merged
+// runs).
+template <typename K>
+__global__ __launch_bounds__(256) void k_gather_wide(const K* __restrict__ src_k, const u32* __restrict__ src_c,
+                                                     const u64* __restrict__ base_arr,
+                                                     const u64* __restrict__ base_range_n, u32 base_range_nb,
+                                                     const u32* __restrict__ bset, const u32* __restrict__ src_set,
+                                                     const u32* __restrict__ cnt, const u32* __restrict__ off,
+                                                     u64 n_seg, int k, k128* __restrict__ dst_k,
+                                                     u32* __restrict__ dst_c, u64 dst_cap) {
+  const u64 wave = (blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6;
+  const u64 n_waves = ((u64)gridDim.x * blockDim.x) >> 6;
+  const u32 lane = lane_id();
+  for (u64 i = wave; i < n_seg; i += n_waves) {
+    const u32 c = cnt[i];
+    if (!c) continue;
+    u64 base;
+    if (base_arr) {
+      base = base_arr[i];
+    } else {
+      const u64 nr = *base_range_n;
+      const u64 per = (nr + base_range_nb - 1) / base_range_nb;
+      base = min(nr, i * per);
+    }
+    const u64 o = off[i];
+    for (u32 j = lane; j < c; j += 64) {
+      if (o + j < dst_cap) {
+        const u32 st = bset ? bset[i] : src_set[base + j];
+        dst_k[o + j] = wide_of(src_k[base + j], st, k);
+        dst_c[o + j] = src_c[base + j];
+      }
+    }
+  }
+}
+
+// k_gather_segments for several sets when count and set share the 32-bit value:
+// value = count | set << cbits (the count is at most max_freq < 2^cbits).
+template <typename K>
+__global__ __launch_bounds__(256) void k_gather_packed(const K* __restrict__ src_k, const u32* __restrict__ src_c,
+                                                       const u64* __restrict__ base_arr,
+                                                       const u64* __restrict__ base_range_n, u32 base_range_nb,
+                                                       const u32* __restrict__ bset, const u32* __restrict__ src_set,
+                                                       const u32* __restrict__ cnt, const u32* __restrict__ off,
+                                                       u64 n_seg, int cbits, K* __restrict__ dst_k,
+                                                       u32* __restrict__ dst_c, u64 dst_cap) {
+  const u64 wave = (blockIdx.x * (u64)blockDim.x + threadIdx.x) >> 6;
+  const u64 n_waves = ((u64)gridDim.x * blockDim.x) >> 6;
+  const u32 lane = lane_id();
+  for (u64 i = wave; i < n_seg; i += n_waves) {
+    const u32 c = cnt[i];
+    if (!c) continue;
+    u64 base;
+    if (base_arr) {
+      base = base_arr[i];
+    } else {
+      const u64 nr = *base_range_n;
+      const u64 per = (nr + base_range_nb - 1) / base_range_nb;
+      base = min(nr, i * per);
+    }
+    const u64 o = off[i];
+    for (u32 j = lane; j < c; j += 64) {
+      if (o + j < dst_cap) {
+        const u32 st = bset ? bset[i] : src_set[base + j];
+        dst_k[o + j] = src_k[base + j];
+        dst_c[o + j] = src_c[base + j] | (st << cbits);
+      }
+    }
+  }
+}
+
+// Sorted wide pairs -> each set's pairs in the caller's buffers (set by set, back to
+// back) and first[s] = index of set s's first pair (first[n_sets] = all pairs).
+template <typename K>
+__global__ __launch_bounds__(256) void k_split_wide(const k128* __restrict__ wk, const u32* __restrict__ wc,
+                                                    const u64* __restrict__ n_ptr, u64 cap, int k, u32 n_sets,
+                                                    K* __restrict__ out_k, u32* __restrict__ out_c,
+                                                    u64* __restrict__ first) {
+  const u64 n = min(*n_ptr, cap);
+  if (n == 0) {
+    for (u64 t = blockIdx.x * (u64)blockDim.x + threadIdx.x; t <= n_sets; t += (u64)gridDim.x * blockDim.x)
+      first[t] = 0;
+    return;
+  }
+  for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+    const k128 w = wk[i];
+    const u32 st = wide_set(w, k);
+    wide_key(w, k, &out_k[i]);
+    out_c[i] = wc[i];
+    const u32 prev = i ? wide_set(wk[i - 1], k) + 1u : 0u;
+    for (u32 t = prev; t <= st && t < n_sets; ++t) first[t] = i;
+    if (i == n - 1)
+      for (u32 t = st + 1; t <= n_sets; ++t) first[t] = n;
+  }
+}
+
+// Per-set totals of a count over several sets: one block per set sums its buckets'
+// records and k-mers (windows) and bucket classes; pairs from the split; n_distinct,
+// overflow_sum and max_count were accumulated by the counting kernels.  Chunk and list
+// figures are not split by set (0).
+__global__ __launch_bounds__(256) void k_finalize_sets(DevTotals* __restrict__ tot, const u64* __restrict__ bcnt,
+                                                       const u32* __restrict__ set_bbase, const u32* __restrict__ set_lb,
+                                                       const u64* __restrict__ first, u32 cap_tiny, u32 cap_small,
+                                                       const u32* __restrict__ flags, const u64* __restrict__ counters,
+                                                       u64 rec_cap, const u64* __restrict__ surv_n, u64 surv_cap) {
+  __shared__ u64 red[8][256];
+  const u32 st = blockIdx.x;
+  const u32 b0 = set_bbase[st], nb = 1u << set_lb[st];
+  u64 q[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // records, windows, tiny b, tiny k, small b, small k, large b, large k
+  for (u32 i = threadIdx.x; i < nb; i += blockDim.x) {
+    const u64 c = bcnt[b0 + i];
+    const u64 nk = (u32)c, nr = c >> 32;
+    q[0] += nr;
+    q[1] += nk;
+    if (nk == 0) continue;
+    const int cl = nk > cap_small ? 3 : nk > cap_tiny ? 2 : 1;
+    q[2 * cl] += 1;
+    q[2 * cl + 1] += nk;
+  }
+  for (int j = 0; j < 8; ++j) red[j][threadIdx.x] = q[j];
+  __syncthreads();
+  for (u32 w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int j = 0; j < 8; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    DevTotals* t = tot + st;
+    t->n_records = red[0][0];
+    t->n_windows = red[1][0];
+    t->tiny_buckets = red[2][0];
+    t->tiny_kmers = red[3][0];
+    t->small_buckets = red[4][0];
+    t->small_kmers = red[5][0];
+    t->large_buckets = red[6][0];
+    t->large_keys = red[7][0];
+    t->n_pairs = first[st + 1] - first[st];
+    t->buckets = nb;
+    t->chunks = 0;
+    t->list_entries = 0;
+    t->n_occ = 0;
+    u64 f = *flags & 1u;
+    if (counters[0] > rec_cap) f |= 2u;
+    if (*surv_n > surv_cap) f |= 4u;   // survivors beyond the sort's capacity
+    t->flags = f;
   }
 }
 

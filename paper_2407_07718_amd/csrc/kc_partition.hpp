@@ -15,15 +15,23 @@
 // ASCII -> 2-bit codes (A0 C1 G2 T3, case-insensitive), 16 bases per u32 with the first
 // base in the low bits, and a one-bit-per-base mask of bytes that are not bases.
 // Thread t encodes bases [32t, 32t+32).
-__global__ __launch_bounds__(256) void k_pack(const u8* __restrict__ reads, u64 R,
-                                              u32* __restrict__ packed, u32* __restrict__ nmask) {
-  const u64 t = blockIdx.x * (u64)blockDim.x + threadIdx.x;
-  const u64 base = t * 32;
-  if (base >= R) return;
-  u32 bytes[8];
-  if (base + 32 <= R && ((((uintptr_t)reads) & 15) == 0)) {
-    const uint4* src = reinterpret_cast<const uint4*>(reads + base);
-    uint4 a = src[0], b = src[1];
+// Set holding base position `pos`: the last s with set_start[s] <= pos (binary search).
+__device__ __forceinline__ u32 set_of_pos(const u64* set_start, u32 n_sets, u64 pos) {
+  u32 lo = 0, hi = n_sets;   // set_start[lo] <= pos < set_start[hi]
+  while (hi - lo > 1) {
+    const u32 mid = (lo + hi) >> 1;
+    if (set_start[mid] <= pos) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// 32 bytes from src (bytes at or past `avail` read as 'N'), with two 16-byte loads when
+// all 32 are there and src is 16-byte aligned.
+__device__ __forceinline__ void load32(const u8* __restrict__ src, u64 avail, u32 (&bytes)[8]) {
+  if (avail >= 32 && ((((uintptr_t)src) & 15) == 0)) {
+    const uint4* v = reinterpret_cast<const uint4*>(src);
+    uint4 a = v[0], b = v[1];
     bytes[0] = a.x; bytes[1] = a.y; bytes[2] = a.z; bytes[3] = a.w;
     bytes[4] = b.x; bytes[5] = b.y; bytes[6] = b.z; bytes[7] = b.w;
   } else {
@@ -31,12 +39,76 @@ __global__ __launch_bounds__(256) void k_pack(const u8* __restrict__ reads, u64 
     for (int i = 0; i < 8; ++i) {
       u32 w = 0;
       for (int j = 0; j < 4; ++j) {
-        u64 p = base + i * 4 + j;
-        w |= (u32)(p < R ? reads[p] : (u8)'N') << (8 * j);
+        const u64 p = (u64)(i * 4 + j);
+        w |= (u32)(p < avail ? src[p] : (u8)'N') << (8 * j);
       }
       bytes[i] = w;
     }
   }
+}
+
+__device__ __forceinline__ void encode32(const u32 (&bytes)[8], u32* __restrict__ packed, u32* __restrict__ nmask,
+                                         u64 t);
+
+__global__ __launch_bounds__(256) void k_pack(const u8* __restrict__ reads, u64 R,
+                                              u32* __restrict__ packed, u32* __restrict__ nmask) {
+  const u64 t = blockIdx.x * (u64)blockDim.x + threadIdx.x;
+  const u64 base = t * 32;
+  if (base >= R) return;
+  u32 bytes[8];
+  load32(reads + base, R - base, bytes);
+  encode32(bytes, packed, nmask, t);
+}
+
+// Several read sets in one count: the joint base space holds set s at [set_start[s],
+// set_start[s] + set_len[s]) (set starts are multiples of 32; the gaps read as 'N'), its
+// bytes taken straight from the set's own buffer from src_off[s] on.
+struct SetTables {
+  const u64* set_start;    // [n_sets + 1]; [n_sets] = joint bases
+  const u64* read_base;    // [n_sets + 1] first joint read index of each set
+  const u64* set_len;      // [n_sets] bases of the set
+  const u64* src_off;      // [n_sets] the set's offsets[0]
+  const u8* const* src;    // [n_sets] the set's read buffer
+  const u64* const* offs;  // [n_sets] the set's offsets
+  const u32* bbase;        // [n_sets] first bucket
+  const u32* lb;           // [n_sets] log2 buckets
+  u32 n_sets;
+};
+
+__global__ __launch_bounds__(256) void k_pack_sets(SetTables T, u64 R, u32* __restrict__ packed,
+                                                   u32* __restrict__ nmask) {
+  const u64 t = blockIdx.x * (u64)blockDim.x + threadIdx.x;
+  const u64 base = t * 32;
+  if (base >= R) return;
+  const u32 s = set_of_pos(T.set_start, T.n_sets, base);
+  const u64 rel = base - T.set_start[s];
+  const u64 avail = T.set_len[s] > rel ? T.set_len[s] - rel : 0;
+  u32 bytes[8];
+  load32(T.src[s] + T.src_off[s] + rel, avail, bytes);
+  encode32(bytes, packed, nmask, t);
+}
+
+// Joint offsets: read r of set s starts at set_start[s] + (offs_s[r'] - offs_s[0]).
+__global__ __launch_bounds__(256) void k_join_offsets(SetTables T, u64 n_reads, u64 R, u64* __restrict__ joff) {
+  for (u64 r = blockIdx.x * (u64)blockDim.x + threadIdx.x; r <= n_reads; r += (u64)gridDim.x * blockDim.x) {
+    if (r == n_reads) {
+      joff[r] = R;
+      continue;
+    }
+    u32 lo = 0, hi = T.n_sets;   // the last set whose first read is at or before r
+    while (hi - lo > 1) {
+      const u32 mid = (lo + hi) >> 1;
+      if (T.read_base[mid] <= r) lo = mid;
+      else hi = mid;
+    }
+    joff[r] = T.set_start[lo] + (T.offs[lo][r - T.read_base[lo]] - T.src_off[lo]);
+  }
+}
+
+// 2-bit codes of 32 bytes (A0 C1 G2 T3, either case) and their non-base mask, for
+// thread t's words.
+__device__ __forceinline__ void encode32(const u32 (&bytes)[8], u32* __restrict__ packed, u32* __restrict__ nmask,
+                                         u64 t) {
   u32 pk0 = 0, pk1 = 0, nm = 0;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
@@ -87,12 +159,20 @@ struct ExtractArgs {
   const u32* blk_base;    // round: first record slot of each block (records packed densely)
   const u32* rng;         // round: coarse groups [rng[0], rng[1]) are written
   u32* hist_km;           // count pass: [C][nblk] k-mers per coarse group and block
+  // several read sets in one count (EX_MULTI): set s holds bases [set_start[s],
+  // set_start[s + 1]) and buckets [set_bbase[s], set_bbase[s] + 2^set_lb[s])
+  const u64* set_start;   // [n_sets + 1]
+  const u32* set_bbase;   // [n_sets]
+  const u32* set_lb;      // [n_sets]
+  u32 n_sets;
 };
 
 // k_extract modes: one pass over everything; a count pass that writes no records, only
 // the records and k-mers per coarse group and block; a round that writes only the records
-// of a range of coarse groups, densely from the block's base slot.
-constexpr int EX_ONE = 0, EX_COUNT = 1, EX_ROUND = 2;
+// of a range of coarse groups, densely from the block's base slot; one pass over several
+// read sets, each with its own range of buckets (the minimizer score modulo the set's
+// bucket count, offset by its first bucket), so that no bucket mixes sets.
+constexpr int EX_ONE = 0, EX_COUNT = 1, EX_ROUND = 2, EX_MULTI = 3;
 
 // A supermer record (16 bytes for k <= 31, 32 bytes for k >= 32) holds its bases, two
 // bits each from bit 0 (at most 51 / 115 bases), its bucket in 20 bits and (g - 1) in the
@@ -254,6 +334,9 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
     }
     bool c_open = false;
     u32 c_b = 0, c_pos = 0, c_p = 0;
+    // EX_MULTI: set of the span's first k-mer; later lanes step forward from it (sets
+    // are far longer than a span but may be short; every step is one compare)
+    const u32 s_span = MODE == EX_MULTI ? set_of_pos(A.set_start, A.n_sets, S0) : 0u;
     u32 carry[WIN_STEPS + 1];
 #pragma unroll
     for (int j = 0; j <= WIN_STEPS; ++j) carry[j] = 0xFFFFFFFFu;
@@ -271,7 +354,13 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs A) {
       const u32 x = in_span ? p + offm : 0u;
       const u64 cb = lds_bits64(ct, x) & kmask_cut;
       const u64 VM = __ballot(in_span && cb == 0 && ((nm[x >> 5] >> (x & 31)) & 1u) == 0);
-      const u32 b = mn & bmask;   // destination = score mod B (B a power of two)
+      u32 b = mn & bmask;   // destination = score mod B (B a power of two)
+      if constexpr (MODE == EX_MULTI) {
+        const u64 P = S0 + (in_span ? p : 0u);
+        u32 st = s_span;
+        while (st + 1 < A.n_sets && P >= A.set_start[st + 1]) ++st;
+        b = A.set_bbase[st] + (mn & ((1u << A.set_lb[st]) - 1u));
+      }
       // Runs of valid k-mers with one bucket, as wave masks: lane l continues the run of
       // lane l-1 (lane 0: of the run carried from the previous tile) if both are valid and
       // their buckets agree.

@@ -17,7 +17,7 @@
 namespace {
 
 struct JobInfo {
-  u64 R = 0, n_max = 0, pair_cap = 0;
+  u64 R = 0, n_max = 0, pair_cap = 0, off0 = 0;   // R = offsets[n_reads]; off0 = offsets[0]
   int key_words = 1;
 };
 
@@ -30,6 +30,7 @@ int host_job_info(const uint64_t* off, u64 n_reads, int k, uint32_t lo, JobInfo*
     if (L >= (u64)k) n_max += L - (u64)k + 1;
   }
   ji->R = n_reads ? off[n_reads] : 0;
+  ji->off0 = n_reads ? off[0] : 0;
   if (n_max >= (1ull << 32) || ji->R >= (1ull << 32))
     return fail(KC_EINVAL, "job exceeds 2^32 - 1 windows or bases");
   ji->n_max = n_max;
@@ -281,12 +282,21 @@ struct kc_batch {
     kc_config cfg;
     Plan P;
     int lane = 0;
+    int group = -1;   // counted with other sets: its group and its set index there
+    u32 set = 0;
     uint64_t* kmers = nullptr;
     uint32_t* counts = nullptr;
     uint64_t* hist = nullptr;
     DevTotals* tot = nullptr;
   };
+  // several sets counted as one (tables and outputs in `own`, scratch in the lane's ws)
+  struct Group {
+    MultiPlan mp;
+    int lane = 0;
+    char* own = nullptr;
+  };
   std::vector<Job> jobs;
+  std::vector<Group> groups;
   int lanes = 1;
   bool use_graph = true;
   std::vector<hipStream_t> streams;
@@ -307,6 +317,8 @@ struct kc_batch {
     for (auto s : streams) (void)hipStreamDestroy(s);
     if (origin) (void)hipStreamDestroy(origin);
     for (auto p : ws) (void)hipFree(p);
+    for (auto& G : groups)
+      if (G.own) (void)hipFree(G.own);
     if (out_mem) (void)hipFree(out_mem);
     if (owned_inputs) (void)hipFree(owned_inputs);
   }
@@ -316,8 +328,13 @@ struct kc_batch {
     HIP_TRY(hipEventRecord(fork, st));
     for (int l = 0; l < lanes; ++l) {
       HIP_TRY(hipStreamWaitEvent(streams[l], fork, 0));
+      for (auto& G : groups) {
+        if (G.lane != l) continue;
+        int rc = enqueue_multi_any(G.mp, ws[l], G.own, streams[l]);
+        if (rc) return rc;
+      }
       for (auto& J : jobs) {
-        if (J.lane != l) continue;
+        if (J.lane != l || J.group >= 0) continue;
         int rc = enqueue_any(J.P, ws[l], J.j.reads, J.j.offsets, J.j.min_freq, J.j.max_freq, J.j.hist_len, J.kmers,
                              J.counts, J.ji.pair_cap, J.hist, J.tot, streams[l]);
         if (rc) return rc;
@@ -331,16 +348,87 @@ struct kc_batch {
 
 namespace {
 
+// Jobs of one class (k, m, frequency window, hist_len) packed into counts of several
+// sets: largest first into the first count with room (at most MULTI_GROUP_BASES bases and
+// MULTI_MAX_SETS sets).  Counts of 2^28 bases keep every set at its own bucket size rule
+// (the 20-bit bucket field holds their buckets) and leave several counts to overlap on
+// the stream lanes: on the 5.6 Gbp batched workload 2^27, 2^28, 2^29 and 2^30 bases per
+// count measured 178, 181, 186 and 207 ms on 4 lanes.  A count left with one set, or whose plan fails, leaves its
+// jobs to be counted on their own.
+#ifndef KC_MULTI_GROUP_LOG2
+#define KC_MULTI_GROUP_LOG2 28
+#endif
+constexpr u64 MULTI_GROUP_BASES = 1ull << KC_MULTI_GROUP_LOG2;
+
+int form_groups(kc_batch* b, const kc_config* cfg) {
+  std::map<std::tuple<int, int, u32, u32, u64>, std::vector<u32>> cls;
+  for (u32 i = 0; i < b->jobs.size(); ++i) {
+    const kc_job& j = b->jobs[i].j;
+    cls[std::make_tuple(j.k, j.m, j.min_freq, j.max_freq, j.hist_len)].push_back(i);
+  }
+  for (auto& kv : cls) {
+    std::vector<u32> ids = kv.second;
+    std::stable_sort(ids.begin(), ids.end(), [&](u32 a, u32 c) {
+      return b->jobs[a].ji.R - b->jobs[a].ji.off0 > b->jobs[c].ji.R - b->jobs[c].ji.off0;
+    });
+    std::vector<std::vector<u32>> packs;
+    std::vector<u64> fill;
+    for (u32 id : ids) {
+      const u64 r = b->jobs[id].ji.R - b->jobs[id].ji.off0;
+      size_t g = 0;
+      while (g < packs.size() && (fill[g] + r > MULTI_GROUP_BASES || packs[g].size() >= MULTI_MAX_SETS)) ++g;
+      if (g == packs.size()) {
+        packs.emplace_back();
+        fill.push_back(0);
+      }
+      packs[g].push_back(id);
+      fill[g] += r;
+    }
+    for (auto& pk : packs) {
+      if (pk.size() < 2) continue;
+      std::sort(pk.begin(), pk.end());   // sets in job order
+      std::vector<MultiSet> sets;
+      for (u32 id : pk) {
+        const auto& J = b->jobs[id];
+        MultiSet ms;
+        ms.reads = J.j.reads;
+        ms.offsets = J.j.offsets;
+        ms.n_reads = J.j.n_reads;
+        ms.off0 = J.ji.off0;
+        ms.R = J.ji.R - J.ji.off0;
+        ms.n_max = J.ji.n_max;
+        sets.push_back(ms);
+      }
+      kc_batch::Group G;
+      const kc_job& j0 = b->jobs[pk[0]].j;
+      kc_config c{};
+      if (cfg) c = *cfg;
+      c.log2_buckets = 0;
+      if (!make_multi_plan(sets, j0.k, j0.m, j0.min_freq, j0.max_freq, j0.hist_len, &c, &G.mp)) continue;
+      for (u32 s = 0; s < pk.size(); ++s) {
+        b->jobs[pk[s]].group = (int)b->groups.size();
+        b->jobs[pk[s]].set = s;
+      }
+      b->groups.push_back(std::move(G));
+    }
+  }
+  return KC_OK;
+}
+
 // Build a batch over device jobs whose host-side facts (offsets checked) are known.
 int batch_build(std::vector<kc_batch::Job>&& jobs, const kc_config* cfg, kc_batch** out) {
   std::unique_ptr<kc_batch> b(new kc_batch());
   b->jobs = std::move(jobs);
   b->lanes = (int)std::max<u32>(1, std::min<u32>(cfg && cfg->lanes ? cfg->lanes : 8u, (u32)std::max<size_t>(1, b->jobs.size())));
   b->use_graph = !(cfg && cfg->no_graph);
+  if (!(cfg && cfg->per_set)) {
+    int rc = form_groups(b.get(), cfg);
+    if (rc) return rc;
+  }
   // per-job configuration: autotuned per job class, or the caller's
   for (auto& J : b->jobs) {
     J.cfg = cfg ? *cfg : kc_config{};
-    if (cfg && cfg->autotune) {
+    if (cfg && cfg->autotune && J.group < 0) {
       TuneKey key = tune_key(J.ji, J.j.k, J.j.n_reads);
       TuneVal tv{};
       bool have = false;
@@ -364,32 +452,67 @@ int batch_build(std::vector<kc_batch::Job>&& jobs, const kc_config* cfg, kc_batc
     if (!make_plan(J.ji.R, J.j.n_reads, J.ji.n_max, J.j.k, J.j.m, J.j.min_freq, &J.cfg, &J.P))
       return fail(KC_EINVAL, "bad kc_config");
   }
-  std::vector<u64> sizes;
-  for (auto& J : b->jobs) sizes.push_back(J.ji.R);
-  std::vector<int> lane = assign_lanes(sizes, b->lanes);
-  std::vector<u64> ws_bytes(b->lanes, 256);
-  u64 out_total = 0;
+  // schedule items: each group, and each job counted on its own
+  std::vector<u64> sizes, item_ws;
+  std::vector<int> item_group, item_job;
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    sizes.push_back(b->groups[g].mp.R);
+    item_ws.push_back(b->groups[g].mp.scratch_bytes);
+    item_group.push_back((int)g);
+    item_job.push_back(-1);
+  }
+  u64 out_total = 0, own_total = 0;
   for (size_t i = 0; i < b->jobs.size(); ++i) {
-    b->jobs[i].lane = lane[i];
-    ws_bytes[lane[i]] = std::max<u64>(ws_bytes[lane[i]], b->jobs[i].P.bytes);
+    if (b->jobs[i].group >= 0) continue;
+    sizes.push_back(b->jobs[i].ji.R);
+    item_ws.push_back(b->jobs[i].P.bytes);
+    item_group.push_back(-1);
+    item_job.push_back((int)i);
     out_total += outputs_bytes(b->jobs[i].ji, b->jobs[i].j.hist_len);
   }
-  u64 need = out_total;
-  for (u64 x : ws_bytes) need += x;
+  for (auto& G : b->groups) own_total += G.mp.own_bytes;
+  b->lanes = (int)std::max<size_t>(1, std::min<size_t>((size_t)b->lanes, sizes.size()));
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  const u64 limit = cfg && cfg->hbm_budget ? std::min<u64>(cfg->hbm_budget, free_b) : (u64)free_b;
+  // fewer lanes while the lanes' workspaces do not fit
+  std::vector<int> lane;
+  std::vector<u64> ws_bytes;
+  u64 need = 0;
+  for (;;) {
+    lane = assign_lanes(sizes, b->lanes);
+    ws_bytes.assign(b->lanes, 256);
+    for (size_t i = 0; i < sizes.size(); ++i) ws_bytes[lane[i]] = std::max<u64>(ws_bytes[lane[i]], item_ws[i]);
+    need = out_total + own_total;
+    for (u64 x : ws_bytes) need += x;
+    if (need <= limit || b->lanes == 1) break;
+    --b->lanes;
+  }
   if (cfg && cfg->hbm_budget && need > cfg->hbm_budget)
     return fail(KC_ENOMEM, "batch needs %llu bytes > budget %llu", (unsigned long long)need,
                 (unsigned long long)cfg->hbm_budget);
-  size_t free_b = 0, total_b = 0;
-  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
   if (need > free_b) return fail(KC_ENOMEM, "batch needs %llu bytes of HBM, %zu free", (unsigned long long)need, free_b);
+  for (size_t i = 0; i < sizes.size(); ++i) {
+    if (item_group[i] >= 0) b->groups[item_group[i]].lane = lane[i];
+    else b->jobs[item_job[i]].lane = lane[i];
+  }
   for (int l = 0; l < b->lanes; ++l) {
     char* p = nullptr;
     HIP_TRY(hipMalloc(&p, ws_bytes[l]));
     b->ws.push_back(p);
   }
+  for (auto& G : b->groups) {   // tables written once, before any capture
+    HIP_TRY(hipMalloc(&G.own, std::max<u64>(256, G.mp.own_bytes)));
+    std::vector<char> tab;
+    std::vector<u32> bset;
+    multi_tables(G.mp, &tab, &bset);
+    HIP_TRY(hipMemcpy(G.own + G.mp.o_tab, tab.data(), tab.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(G.own + G.mp.o_bset, bset.data(), 4 * bset.size(), hipMemcpyHostToDevice));
+  }
   HIP_TRY(hipMalloc(&b->out_mem, std::max<u64>(256, out_total)));
   char* o = b->out_mem;
   for (auto& J : b->jobs) {
+    if (J.group >= 0) continue;
     const u64 w = 8ull * J.ji.key_words;
     J.kmers = reinterpret_cast<uint64_t*>(o);
     J.counts = reinterpret_cast<uint32_t*>(o + align_up(w * J.ji.pair_cap, 256));
@@ -466,7 +589,27 @@ int kc_batch_result(kc_batch* b, uint32_t job, kc_result* out) {
   g_err.clear();
   if (!b || !out || job >= b->jobs.size()) return fail(KC_EINVAL, "bad batch result request");
   auto& J = b->jobs[job];
+  if (J.group >= 0) {
+    const auto& G = b->groups[J.group];
+    const MultiOut O = multi_out(G.mp, G.own);
+    u64 fr[2];
+    HIP_TRY(hipMemcpy(fr, O.first + J.set, 16, hipMemcpyDeviceToHost));
+    const int kw = G.mp.P.key_words;
+    return fetch_result(O.tot + J.set, reinterpret_cast<const uint64_t*>(O.kmers) + fr[0] * kw, O.counts + fr[0],
+                        O.hist + (u64)J.set * G.mp.hist_len, fr[1] - fr[0], G.mp.hist_len, kw, b->origin, out);
+  }
   return fetch_result(J.tot, J.kmers, J.counts, J.hist, J.ji.pair_cap, J.j.hist_len, J.ji.key_words, b->origin, out);
+}
+
+int kc_batch_info(const kc_batch* b, uint32_t* n_counts, uint32_t* n_shared, uint32_t* lanes) {
+  g_err.clear();
+  if (!b) return fail(KC_EINVAL, "NULL batch");
+  u32 solo = 0, shared = 0;
+  for (const auto& J : b->jobs) (J.group >= 0 ? shared : solo) += 1;
+  if (n_counts) *n_counts = (u32)b->groups.size() + solo;
+  if (n_shared) *n_shared = shared;
+  if (lanes) *lanes = (u32)b->lanes;
+  return KC_OK;
 }
 
 int kc_batch_destroy(kc_batch* b) {

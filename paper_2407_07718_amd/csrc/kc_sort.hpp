@@ -352,3 +352,107 @@ __global__ __launch_bounds__(T) void k_radix_downsweep(const K* __restrict__ kin
     __syncthreads();
   }
 }
+
+// ---------------------------------------------------------------------------- pass by set
+// One stable pass that orders (key, value) pairs by the set held in the value's bits above
+// cbits (sets < 512), keeping their order within each set; the values leave with the set
+// bits cleared.  k_set_hist counts the sets of each block's range (counts[s * nb + b]),
+// k_radix_rowscan turns the counts into offsets (totals = pairs per set), and
+// k_set_scatter ranks each tile by set in LDS, stages it in set order and writes one run
+// per set.
+constexpr int SET_DB = 9;
+
+__global__ __launch_bounds__(256) void k_set_hist(const u32* __restrict__ vals, const u64* __restrict__ n_ptr,
+                                                  u32* __restrict__ counts, int cbits) {
+  constexpr u32 NB = 1u << SET_DB;
+  __shared__ u32 h[4][NB];
+  const u32 nb = gridDim.x, tid = threadIdx.x, wave = tid >> 6;
+  for (u32 i = tid; i < 4 * NB; i += 256) (&h[0][0])[i] = 0;
+  __syncthreads();
+  u64 s, e;
+  block_range(*n_ptr, nb, &s, &e);
+  for (u64 i = s + tid; i < e; i += 256) atomicAdd(&h[wave][(vals[i] >> cbits) & (NB - 1)], 1u);
+  __syncthreads();
+  for (u32 d = tid; d < NB; d += 256) counts[(u64)d * nb + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+template <typename K, int T, int ITEMS>
+__global__ __launch_bounds__(T) void k_set_scatter(const K* __restrict__ kin, K* __restrict__ kout,
+                                                   const u32* __restrict__ vin, u32* __restrict__ vout,
+                                                   const u64* __restrict__ n_ptr, const u32* __restrict__ counts,
+                                                   const u32* __restrict__ totals, int cbits) {
+  constexpr int W = T / 64, TILE = T * ITEMS, NB = 1 << SET_DB;
+  static_assert(NB <= T, "one thread per set");
+  __shared__ RankSmem<W, SET_DB> S;
+  __shared__ K stage_k[TILE];
+  __shared__ u32 stage_v[TILE];
+  __shared__ u16 stage_d[TILE];
+  __shared__ u32 run_base[NB];
+  const u32 nb = gridDim.x, tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const u32 cmask = cbits >= 32 ? ~0u : ((1u << cbits) - 1u);
+  for (u32 i = tid; i < W * NB; i += T) (&S.tbl[0][0])[i] = 0;
+  {
+    const u64 t = tid < (u32)NB ? totals[tid] : 0u;
+    u64 all;
+    const u64 dbase = block_exclusive_scan<u64>(t, S.scr, &all);
+    if (tid < (u32)NB) run_base[tid] = (u32)dbase + counts[(u64)tid * nb + blockIdx.x];
+  }
+  __syncthreads();
+  u64 s, e;
+  block_range(*n_ptr, nb, &s, &e);
+  for (u64 t0 = s; t0 < e; t0 += TILE) {
+    const u32 nt = (u32)min((u64)TILE, e - t0);
+    const int per = (int)((nt + 64u * W - 1) / (64u * W));
+    K kr[ITEMS];
+    u32 vr[ITEMS], dg[ITEMS], rk[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+        if (idx < nt) {
+          kr[j] = kin[t0 + idx];
+          vr[j] = vin[t0 + idx];
+        } else {
+          kr[j] = key_zero<K>();
+          vr[j] = 0;
+        }
+        dg[j] = (vr[j] >> cbits) & (NB - 1);
+      }
+    }
+    rank_by_digit<T, ITEMS, SET_DB>(dg, rk, per, nt, S);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (j < per) {
+        const u32 idx = (wave * (u32)per + (u32)j) * 64u + lane;
+        if (idx < nt) {
+          stage_k[rk[j]] = kr[j];
+          stage_v[rk[j]] = vr[j] & cmask;
+          stage_d[rk[j]] = (u16)dg[j];
+        }
+      }
+    }
+    __syncthreads();
+    for (u32 i = tid; i < nt; i += T) {
+      const u32 d = stage_d[i];
+      const u64 dst = (u64)run_base[d] + (i - S.dstart[d]);
+      kout[dst] = stage_k[i];
+      vout[dst] = stage_v[i];
+    }
+    __syncthreads();
+    if (tid < (u32)NB) run_base[tid] += S.dstart[tid + 1] - S.dstart[tid];
+    __syncthreads();
+  }
+}
+
+// first[s] = pairs of the sets before s (exclusive scan of the per-set totals), s <= n_sets.
+__global__ __launch_bounds__(512) void k_set_first(const u32* __restrict__ totals, u32 n_sets,
+                                                   u64* __restrict__ first) {
+  __shared__ u64 scr[17];
+  const u32 tid = threadIdx.x;
+  const u64 v = tid < n_sets ? (u64)totals[tid] : 0ull;
+  u64 all;
+  const u64 ex = block_exclusive_scan<u64>(v, scr, &all);
+  if (tid < n_sets) first[tid] = ex;
+  if (tid == 0) first[n_sets] = all;
+}
+

@@ -31,7 +31,7 @@ class kc_config(ctypes.Structure):
     _fields_ = [("log2_buckets", ctypes.c_uint32), ("force_hbm", ctypes.c_uint32),
                 ("small_variant", ctypes.c_uint32), ("lanes", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("no_graph", ctypes.c_uint32), ("autotune", ctypes.c_uint32),
-                ("radix_bits", ctypes.c_uint32)]
+                ("radix_bits", ctypes.c_uint32), ("per_set", ctypes.c_uint32)]
 
 
 class kc_totals(ctypes.Structure):
@@ -124,6 +124,8 @@ def _load() -> ctypes.CDLL:
     lib.kc_batch_result.argtypes = [vp, u32, P(kc_result)]
     lib.kc_batch_result.restype = i32
     lib.kc_batch_destroy.argtypes = [vp]
+    lib.kc_batch_info.argtypes = [vp, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
+    lib.kc_batch_info.restype = i32
     lib.kc_batch_destroy.restype = i32
     lib.kc_autotune.argtypes = [P(kc_job), P(kc_config), P(kc_config), P(ctypes.c_double)]
     lib.kc_autotune.restype = i32
@@ -191,9 +193,9 @@ def kc_profile_read() -> dict:
 
 def make_config(log2_buckets: int = 0, force_hbm: bool = False, small_variant: int = 0,
                 hbm_budget: int = 0, lanes: int = 0, no_graph: bool = False, autotune: bool = False,
-                radix_bits: int = 0) -> kc_config:
+                radix_bits: int = 0, per_set: bool = False) -> kc_config:
     return kc_config(log2_buckets, int(force_hbm), small_variant, lanes, hbm_budget, int(no_graph), int(autotune),
-                     radix_bits)
+                     radix_bits, int(per_set))
 
 
 @dataclass
@@ -316,6 +318,12 @@ class DeviceBatch:
         res = kc_result()
         _check(_lib.kc_batch_result(self.h, i, ctypes.byref(res)))
         return _take_result(res, self.hist[i])
+
+    def info(self) -> dict:
+        """Launch sequences per run, jobs counted with other sets, stream lanes."""
+        n, sh, ln = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(_lib.kc_batch_info(self.h, ctypes.byref(n), ctypes.byref(sh), ctypes.byref(ln)))
+        return {"counts": int(n.value), "shared": int(sh.value), "lanes": int(ln.value)}
 
     def close(self) -> None:
         if self.h:

@@ -91,7 +91,7 @@ def test_header_declares_batch_and_server_entry_points():
 def test_struct_sizes_match_header_layout():
     from paper_2407_07718_amd import kc
     assert ctypes.sizeof(kc.kc_totals) == 17 * 8
-    assert ctypes.sizeof(kc.kc_config) == 4 * 4 + 8 + 3 * 4 + 4          # (tail padding to 8)
+    assert ctypes.sizeof(kc.kc_config) == 4 * 4 + 8 + 4 * 4
     assert ctypes.sizeof(kc.kc_job) == 8 * 3 + 4 * 4 + 8
     assert ctypes.sizeof(kc.kc_server_cfg) == 8 + 2 * 4 + 8 + ctypes.sizeof(kc.kc_config)
     assert ctypes.sizeof(kc.kc_timing) == 3 * 8 + 2 * 8

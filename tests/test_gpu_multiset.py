@@ -1,0 +1,162 @@
+"""Batched counting with several read sets per count (the default of kc_count_batch and
+kc_batch_*): sets of one class (k, m, frequency window, histogram length) share one
+count -- one joint input read in place from each set's buffer, per-set bucket ranges,
+per-set statistics, one sort of the survivors by (set, k-mer) -- and every set's result
+must equal the oracle's count of that set alone, element by element.
+
+Sets are drawn from a few shared genomes, so the same k-mers occur in many sets and must
+still be counted per set; the mix has empty sets, sets of reads shorter than k, all-N
+sets, lower-case bytes, bytes before the first read, short and long reads, 64-bit and
+128-bit keys, all buckets forced through the heavy-bucket lists (where two sets' lists
+meet), classes whose counts leave no room for the set in the survivors' 32-bit value
+(ordered as wide keys instead), and a class whose wide keys would exceed 126 bits
+(counted set by set)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_07718_amd import synth
+from tests.gpu_util import assert_same
+
+pytestmark = pytest.mark.gpu
+
+
+def _kc():
+    from paper_2407_07718_amd import kc
+    return kc
+
+
+def _set(rng, genome, kind):
+    if kind == "empty":
+        return np.zeros(0, np.uint8), np.zeros(1, np.uint64)
+    if kind == "short":
+        r, o = synth.sample_reads(rng, genome, rng.integers(0, 12, 30), p_sub=0.0)
+        return r, o
+    if kind == "alln":
+        return np.full(500, ord("N"), np.uint8), np.array([0, 200, 500], np.uint64)
+    if kind == "long":
+        lens = rng.integers(2000, 9000, int(rng.integers(1, 6)))
+    else:
+        lens = rng.integers(60, 300, int(rng.integers(20, 600)))
+    r, o = synth.sample_reads(rng, genome, lens, p_sub=0.01, p_n=0.002)
+    low = rng.random(r.shape[0]) < 0.05
+    r = r.copy()
+    r[low & (r >= 65) & (r <= 90)] += 32
+    if rng.random() < 0.3:   # bytes before the first read
+        pre = int(rng.integers(1, 40))
+        r = np.concatenate([np.full(pre, ord("G"), np.uint8), r])
+        o = o + np.uint64(pre)
+    return r, o
+
+
+def _jobs(seed, n, k, m, lo, hi, H):
+    kc = _kc()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    genomes = [synth.uniform_genome(rng, 30000) for _ in range(3)]
+    kinds = ["empty", "short", "alln", "long"] + ["reads"] * (n - 4)
+    rng.shuffle(kinds)
+    jobs = []
+    for kind in kinds:
+        r, o = _set(rng, genomes[int(rng.integers(0, 3))], kind)
+        jobs.append(kc.Job(r, o, k, m, lo, hi, H))
+    return jobs
+
+
+def _oracle(job):
+    return oracle.count(job.reads, job.offsets, job.k, job.min_freq, job.max_freq, job.hist_len)
+
+
+def _check_all(jobs, res, label):
+    assert len(res) == len(jobs)
+    for i, (j, got) in enumerate(zip(jobs, res)):
+        assert_same(got, _oracle(j), f"{label} set {i} (k={j.k})")
+
+
+@pytest.mark.parametrize("per_set", [0, 1])
+def test_many_sets_per_count_match_oracle(per_set):
+    kc = _kc()
+    jobs = (_jobs(1, 40, 31, 17, 2, 50, 1000) + _jobs(2, 25, 21, 11, 1, 100, 257)
+            + _jobs(3, 12, 51, 21, 2, 1000, 64))
+    print(f"case multiset: {len(jobs)} jobs per_set={per_set}", flush=True)
+    res = kc.kc_count_batch(jobs, kc.make_config(lanes=2, per_set=per_set))
+    _check_all(jobs, res, f"per_set={per_set}")
+
+
+def test_sets_through_heavy_bucket_lists():
+    """force_hbm: every bucket is cut into chunks whose lists are merged; neighbouring
+    lists of two sets hold the same k-mers and must stay apart."""
+    kc = _kc()
+    jobs = _jobs(4, 16, 31, 15, 1, 1000, 128) + _jobs(5, 10, 45, 21, 1, 1000, 128)
+    print(f"case multiset force_hbm: {len(jobs)} jobs", flush=True)
+    res = kc.kc_count_batch(jobs, kc.make_config(force_hbm=True, lanes=1))
+    _check_all(jobs, res, "force_hbm")
+
+
+def test_wide_key_order_when_counts_fill_the_value():
+    """max_freq of 2^30 leaves no room for the set beside the count in a 32-bit value: the
+    survivors are ordered as wide keys (set << 2k | k-mer) instead."""
+    kc = _kc()
+    jobs = _jobs(10, 9, 31, 17, 1, 1 << 30, 256) + _jobs(11, 6, 51, 21, 1, 1 << 30, 256)
+    print(f"case multiset wide keys: {len(jobs)} jobs", flush=True)
+    res = kc.kc_count_batch(jobs, kc.make_config(lanes=2))
+    _check_all(jobs, res, "wide keys")
+
+
+def test_wide_keys_over_126_bits_counted_per_set():
+    import torch
+    kc = _kc()
+    jobs = _jobs(6, 5, 63, 31, 1, 1000, 64)
+    print("case multiset k=63: per-set fallback", flush=True)
+    res = kc.kc_count_batch(jobs, kc.make_config(lanes=2))
+    _check_all(jobs, res, "k=63")
+    dev = torch.device("cuda:0")
+    sets = [(torch.from_numpy(np.concatenate([j.reads, np.zeros(16, np.uint8)])).to(dev),
+             torch.from_numpy(j.offsets.view(np.int64)).to(dev), j.k, j.m, j.min_freq, j.max_freq, j.hist_len)
+            for j in jobs]
+    b = kc.DeviceBatch(sets, kc.make_config(lanes=2))
+    try:
+        assert b.info()["counts"] == 5 and b.info()["shared"] == 0
+    finally:
+        b.close()
+
+
+def test_device_batch_of_many_sets_replays():
+    """A prepared batch over device-resident sets (graph captured once), replayed."""
+    import torch
+    kc = _kc()
+    jobs = _jobs(7, 30, 31, 17, 2, 50, 1000) + _jobs(8, 20, 21, 11, 2, 50, 1000)
+    dev = torch.device("cuda:0")
+    sets = []
+    for j in jobs:
+        d_r = torch.from_numpy(np.concatenate([j.reads, np.zeros(16, np.uint8)])).to(dev)
+        d_o = torch.from_numpy(j.offsets.view(np.int64)).to(dev)
+        sets.append((d_r, d_o, j.k, j.m, j.min_freq, j.max_freq, j.hist_len))
+    refs = [_oracle(j) for j in jobs]
+    print(f"case multiset device batch: {len(jobs)} jobs", flush=True)
+    b = kc.DeviceBatch(sets, kc.make_config(lanes=2))
+    try:
+        # two classes (k = 31 and 21), each one count: two launch sequences for 50 sets
+        assert b.info() == {"counts": 2, "shared": 50, "lanes": 2}, b.info()
+        for rep in range(3):
+            b.run()
+            for i, ref in enumerate(refs):
+                assert_same(b.result(i), ref, f"replay {rep} set {i}")
+    finally:
+        b.close()
+
+
+def test_larger_sets_share_a_count():
+    """Sets of 0.2-3 Mbp from shared genomes with repeats: many buckets per set, tiny,
+    small and large buckets all present."""
+    kc = _kc()
+    rng = np.random.Generator(np.random.PCG64(9))
+    g = synth.uniform_genome(rng, 400_000)
+    synth.add_repeat_families(rng, g, families=20, len_lo=500, len_hi=3000, copies_lo=5, copies_hi=40)
+    jobs = []
+    for i in range(12):
+        n = int(rng.integers(1500, 20000))
+        r, o = synth.sample_reads(rng, g, np.full(n, 150), p_sub=0.005)
+        jobs.append(kc.Job(r, o, 31, 17, 2, 1000, 65536))
+    print("case multiset larger sets: 12 jobs", flush=True)
+    res = kc.kc_count_batch(jobs, kc.make_config(lanes=1))
+    _check_all(jobs, res, "larger sets")
