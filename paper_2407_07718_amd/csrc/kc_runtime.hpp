@@ -353,7 +353,8 @@ namespace {
 // MULTI_MAX_SETS sets).  Counts of 2^28 bases keep every set at its own bucket size rule
 // (the 20-bit bucket field holds their buckets) and leave several counts to overlap on
 // the stream lanes: on the 5.6 Gbp batched workload 2^27, 2^28, 2^29 and 2^30 bases per
-// count measured 178, 181, 186 and 207 ms on 4 lanes.  A count left with one set, or whose plan fails, leaves its
+// count measured 178, 181, 186 and 207 ms on 4 lanes.  Counting the largest sets (over
+// 2^25, 2^26 or 2^27 bases) on their own instead measured the same.  A count left with one set, or whose plan fails, leaves its
 // jobs to be counted on their own.
 #ifndef KC_MULTI_GROUP_LOG2
 #define KC_MULTI_GROUP_LOG2 28
