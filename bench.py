@@ -582,7 +582,7 @@ def serving_leg(args, kc, sets, ref) -> dict:
 
             th = threading.Thread(target=producer)
             th.start()
-            lat, kmers, done_last, bad, foot, devb, inflight = [], 0, 0.0, 0, [], [], []
+            lat, kmers, done_last, bad, foot, devb, inflight, sizes = [], 0, 0.0, 0, [], [], [], []
             n_done = 0
             while n_done < arr.shape[0]:
                 with lock:
@@ -599,7 +599,8 @@ def serving_leg(args, kc, sets, ref) -> dict:
                     kmers += int(res.totals["n_windows"])
                     done_last = max(done_last, tm["done_s"])
                     foot.append(tm["footprint"])
-                    devb.append(tm["device_bytes"])
+                    devb.append(tm["device_bytes"] / max(1, tm["batched"]))   # its share of a shared count
+                    sizes.append(tm["batched"])
                     inflight.append((tm["admit_s"], tm["done_s"]))
                     if result_sha(res.kmers, res.counts, res.hist) != ref[i]:
                         bad += 1
@@ -614,10 +615,37 @@ def serving_leg(args, kc, sets, ref) -> dict:
                 "kmers_per_s": kmers / span if span > 0 else 0.0,
                 "offered_bases_per_s": float(sum(sets[int(i)].n_bases for i in pick)) / args.serve_seconds,
                 "max_in_flight": conc, "est_over_actual_bytes": round(float(np.sum(foot)) / float(np.sum(devb)), 3),
+                "max_requests_per_count": int(max(sizes)), "requests_in_shared_counts": int(sum(1 for b in sizes if b > 1)),
                 "bit_exact_vs_oracle": bad == 0,
             }
             all_ok &= bad == 0
             log(f"served {lam} req/s: {out['rates'][str(int(lam))]}")
+        # a burst: every request submitted at once, so that the queue holds many requests
+        # of each class (the server admits runs of one class as one count)
+        c0 = srv.clock()
+        tks = [srv.submit(j) for j in jobs]
+        done, bad, kmers, last, sizes = {}, 0, 0, 0.0, []
+        while len(done) < len(tks):
+            for i, tk in enumerate(tks):
+                if tk in done:
+                    continue
+                r = srv.poll(tk)
+                if r is None:
+                    continue
+                res, tm = r
+                done[tk] = True
+                kmers += int(res.totals["n_windows"])
+                last = max(last, tm["done_s"])
+                sizes.append(tm["batched"])
+                if result_sha(res.kmers, res.counts, res.hist) != ref[i]:
+                    bad += 1
+            time.sleep(0.0005)
+        out["burst"] = {"requests": len(tks), "ms": round((last - c0) * 1e3, 2), "kmers_per_s": kmers / (last - c0),
+                        "max_requests_per_count": int(max(sizes)),
+                        "requests_in_shared_counts": int(sum(1 for b in sizes if b > 1)),
+                        "bit_exact_vs_oracle": bad == 0}
+        all_ok &= bad == 0
+        log(f"served burst: {out['burst']}")
         out["all_bit_exact"] = all_ok
     finally:
         srv.close()

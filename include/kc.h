@@ -312,7 +312,10 @@ int kc_autotune(const kc_job *device_job, const kc_config *base, kc_config *out,
  * estimated footprint (read bytes x k, as the deployment sizes it) fits the remaining
  * HBM budget and a stream slot is free; admitted requests run concurrently on their
  * own streams and workspaces, so requests that arrive while others are on the GPU
- * overlap with them.  Results are identical to kc_count of the same job. */
+ * overlap with them.  Requests of one class (k, m, frequency window, hist_len) waiting
+ * together at the head of the queue are admitted as one count of several sets (as in
+ * kc_count_batch; up to 2^28 bases and 512 requests) when they fit together, unless
+ * count.per_set is 1.  Results are identical to kc_count of the same job. */
 typedef struct kc_server_cfg {
   uint64_t hbm_budget;     /* admission budget: sum of estimated footprints in flight */
   uint32_t slots;          /* requests in flight at most (streams); 0 = 8 */
@@ -333,7 +336,9 @@ typedef struct kc_timing {
   double done_s;
   uint64_t footprint;      /* estimated bytes used for admission (read bytes x k) */
   uint64_t device_bytes;   /* bytes actually carved from the arena (inputs, workspace,
-                              outputs) */
+                              outputs) for the count the request ran in */
+  uint32_t batched;        /* requests counted together in that count (1 = alone) */
+  uint32_t reserved;
 } kc_timing;
 
 typedef struct kc_server kc_server;

@@ -759,6 +759,18 @@ struct SrvJob {
   kc_timing tm{};
   u64 est = 0, bytes = 0, off = 0;
   int slot = -1;
+  // Several requests counted as one, led by this job: the others, the joint plan, the
+  // layout of the batch's arena block (at off, bytes long: each member's reads and
+  // offsets at in_off[s], then the count's scratch and its tables and outputs) and the
+  // host images of the tables (kept until the copies are done).
+  std::vector<SrvJob*> mates;
+  std::unique_ptr<MultiPlan> mp;
+  std::vector<u64> in_off;
+  u64 o_scratch = 0, o_own = 0;
+  std::vector<char> tab;
+  std::vector<u32> bset;
+  SrvJob* lead = nullptr;   // the leader of this job's batch (itself when it leads)
+  u32 set = 0;              // this job's set in the batch
 };
 
 struct Slot {
@@ -835,12 +847,165 @@ struct kc_server {
     slots[free_slot].job = J;
     J->state = J_RUNNING;
     J->tm.admit_s = now();
+    J->tm.batched = 1;
     return true;
+  }
+
+  static bool same_class(const SrvJob* a, const SrvJob* b) {
+    return a->job.k == b->job.k && a->job.m == b->job.m && a->job.min_freq == b->job.min_freq &&
+           a->job.max_freq == b->job.max_freq && a->job.hist_len == b->job.hist_len;
+  }
+
+  // With mu held: the head request and the requests of its class queued right behind it,
+  // admitted together as one count of several sets when at least two of them fit (a slot,
+  // the budget, one arena block); the batch shrinks from the back until it fits.  The
+  // members leave the queue here.
+  bool try_admit_batch() {
+    if (cfg.count.per_set || queue.size() < 2) return false;
+    int free_slot = -1;
+    for (size_t i = 0; i < slots.size(); ++i)
+      if (!slots[i].job) {
+        free_slot = (int)i;
+        break;
+      }
+    if (free_slot < 0) return false;
+    SrvJob* H = queue.front();
+    if (H->P.rounds > 1) return false;
+    std::vector<SrvJob*> group{H};
+    u64 bases = H->ji.R - H->ji.off0;
+    for (size_t i = 1; i < queue.size() && group.size() < MULTI_MAX_SETS; ++i) {
+      SrvJob* J = queue[i];
+      if (J->state != J_QUEUED || !same_class(J, H) || J->P.rounds > 1) break;
+      const u64 r = J->ji.R - J->ji.off0;
+      if (bases + r > MULTI_GROUP_BASES) break;
+      group.push_back(J);
+      bases += r;
+    }
+    while (group.size() >= 2) {
+      u64 est = 0;
+      std::vector<MultiSet> sets;
+      for (SrvJob* J : group) {
+        est += J->est;
+        MultiSet ms;
+        ms.n_reads = J->job.n_reads;
+        ms.off0 = J->ji.off0;
+        ms.R = J->ji.R - J->ji.off0;
+        ms.n_max = J->ji.n_max;
+        sets.push_back(ms);
+      }
+      std::unique_ptr<MultiPlan> mp(new MultiPlan());
+      // (a batch stays within the budget; only a request alone may exceed it, when
+      // nothing else runs)
+      if (est_used + est <= cfg.hbm_budget &&
+          make_multi_plan(sets, H->job.k, H->job.m, H->job.min_freq, H->job.max_freq, H->job.hist_len, &cfg.count,
+                          mp.get())) {
+        std::vector<u64> in_off;
+        u64 o = 0;
+        for (SrvJob* J : group) {
+          in_off.push_back(o);
+          o += align_up(J->ji.R + 16, 256) + align_up(8 * (J->job.n_reads + 1), 256);
+        }
+        const u64 o_scratch = o, o_own = align_up(o_scratch + mp->scratch_bytes, 256);
+        const u64 bytes = o_own + align_up(mp->own_bytes, 256);
+        u64 off = 0;
+        if (arena.alloc(bytes, &off)) {
+          H->mates.assign(group.begin() + 1, group.end());
+          H->mp = std::move(mp);
+          H->in_off = in_off;
+          H->o_scratch = o_scratch;
+          H->o_own = o_own;
+          H->off = off;
+          H->bytes = bytes;
+          H->slot = free_slot;
+          est_used += est;
+          slots[free_slot].job = H;
+          const double t = now();
+          for (u32 s = 0; s < group.size(); ++s) {
+            SrvJob* J = group[s];
+            J->lead = H;
+            J->set = s;
+            J->state = J_RUNNING;
+            J->tm.admit_s = t;
+            J->tm.device_bytes = bytes;
+            J->tm.batched = (u32)group.size();
+            queue.pop_front();   // the members are the queue's first group.size() entries
+          }
+          return true;
+        }
+      }
+      group.pop_back();
+    }
+    return false;
+  }
+
+  // Without mu: a batch's inputs to the device, its tables, and its count queued on the
+  // slot's stream.
+  void launch_batch(SrvJob* H) {
+    Slot& S = slots[H->slot];
+    char* base = arena.base + H->off;
+    MultiPlan& mp = *H->mp;
+    int rc = KC_OK;
+    for (u32 s = 0; s <= H->mates.size() && !rc; ++s) {
+      SrvJob* J = s ? H->mates[s - 1] : H;
+      uint8_t* d_reads = reinterpret_cast<uint8_t*>(base + H->in_off[s]);
+      uint64_t* d_off = reinterpret_cast<uint64_t*>(base + H->in_off[s] + align_up(J->ji.R + 16, 256));
+      if (J->ji.R && hipMemcpyAsync(d_reads, J->reads.data(), J->ji.R, hipMemcpyHostToDevice, S.st) != hipSuccess)
+        rc = fail(KC_EDEVICE, "H2D failed");
+      if (!rc && hipMemcpyAsync(d_off, J->offsets.data(), 8 * J->offsets.size(), hipMemcpyHostToDevice, S.st) !=
+                     hipSuccess)
+        rc = fail(KC_EDEVICE, "H2D failed");
+      mp.src[s] = d_reads;
+      mp.offs[s] = d_off;
+    }
+    char* own = base + H->o_own;
+    if (!rc) {
+      multi_tables(mp, &H->tab, &H->bset);
+      if (hipMemcpyAsync(own + mp.o_tab, H->tab.data(), H->tab.size(), hipMemcpyHostToDevice, S.st) != hipSuccess ||
+          hipMemcpyAsync(own + mp.o_bset, H->bset.data(), 4 * H->bset.size(), hipMemcpyHostToDevice, S.st) !=
+              hipSuccess)
+        rc = fail(KC_EDEVICE, "H2D failed");
+    }
+    if (!rc) rc = enqueue_multi_any(mp, base + H->o_scratch, own, S.st);
+    if (!rc && hipEventRecord(S.done, S.st) != hipSuccess) rc = fail(KC_EDEVICE, "event record failed");
+    if (rc) {
+      (void)hipStreamSynchronize(S.st);
+      H->err = g_err;
+      H->rc = rc;
+    }
+  }
+
+  // Without mu: each member's result of a finished batch to the host.
+  void collect_batch(SrvJob* H) {
+    const MultiPlan& mp = *H->mp;
+    const MultiOut O = multi_out(mp, arena.base + H->off + H->o_own);
+    const int kw = mp.P.key_words;
+    for (u32 s = 0; s <= H->mates.size(); ++s) {
+      SrvJob* J = s ? H->mates[s - 1] : H;
+      if (H->rc != KC_OK) {
+        J->rc = H->rc;
+        J->err = H->err;
+        continue;
+      }
+      u64 fr[2] = {0, 0};
+      if (hipMemcpyAsync(fr, O.first + s, 16, hipMemcpyDeviceToHost, slots[H->slot].st) != hipSuccess ||
+          hipStreamSynchronize(slots[H->slot].st) != hipSuccess) {
+        J->rc = fail(KC_EDEVICE, "D2H failed");
+        J->err = g_err;
+        continue;
+      }
+      J->rc = fetch_result(O.tot + s, reinterpret_cast<const uint64_t*>(O.kmers) + fr[0] * kw, O.counts + fr[0],
+                           O.hist + (u64)s * mp.hist_len, fr[1] - fr[0], mp.hist_len, kw, slots[H->slot].st, &J->res);
+      if (J->rc) J->err = g_err;
+    }
   }
 
   // Without mu (only this thread touches admitted jobs): inputs to the device and the
   // count queued on the slot's stream.
   void launch(SrvJob* J) {
+    if (J->mp) {
+      launch_batch(J);
+      return;
+    }
     Slot& S = slots[J->slot];
     const Ptrs d = ptrs(J);
     int rc = KC_OK;
@@ -861,6 +1026,10 @@ struct kc_server {
 
   // Without mu: results of a finished job to the host.
   void collect(SrvJob* J) {
+    if (J->mp) {
+      collect_batch(J);
+      return;
+    }
     if (J->rc != KC_OK) return;
     const Ptrs d = ptrs(J);
     J->rc = fetch_result(d.tot, d.kmers, d.counts, d.hist, J->ji.pair_cap, J->job.hist_len, J->ji.key_words,
@@ -871,15 +1040,22 @@ struct kc_server {
   // With mu held: the job of slot i is complete; its memory and budget go back.
   void retire(int i) {
     Slot& S = slots[i];
-    SrvJob* J = S.job;
-    J->state = J->rc ? J_FAILED : J_DONE;
-    J->tm.done_s = now();
-    arena.release(J->off, J->bytes);
-    est_used -= J->est;
-    J->reads.clear();
-    J->reads.shrink_to_fit();
-    J->offsets.clear();
-    J->offsets.shrink_to_fit();
+    SrvJob* H = S.job;
+    arena.release(H->off, H->bytes);
+    const double t = now();
+    for (size_t s = 0; s <= H->mates.size(); ++s) {
+      SrvJob* J = s ? H->mates[s - 1] : H;
+      J->state = J->rc ? J_FAILED : J_DONE;
+      J->tm.done_s = t;
+      est_used -= J->est;
+      J->reads.clear();
+      J->reads.shrink_to_fit();
+      J->offsets.clear();
+      J->offsets.shrink_to_fit();
+    }
+    H->mates.clear();   // members may be polled (and freed) from here on
+    H->tab.clear();
+    H->bset.clear();
     S.job = nullptr;
   }
 
@@ -913,6 +1089,11 @@ struct kc_server {
           SrvJob* J = queue.front();
           if (J->state == J_CANCELED) {
             queue.pop_front();
+            continue;
+          }
+          if (try_admit_batch()) {
+            admitted.push_back(J);
+            progress = true;
             continue;
           }
           if (!try_admit(J)) {

@@ -70,7 +70,8 @@ class kc_server_cfg(ctypes.Structure):
 
 class kc_timing(ctypes.Structure):
     _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
-                ("footprint", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64)]
+                ("footprint", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64), ("batched", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -94,7 +94,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(kc.kc_config) == 4 * 4 + 8 + 4 * 4
     assert ctypes.sizeof(kc.kc_job) == 8 * 3 + 4 * 4 + 8
     assert ctypes.sizeof(kc.kc_server_cfg) == 8 + 2 * 4 + 8 + ctypes.sizeof(kc.kc_config)
-    assert ctypes.sizeof(kc.kc_timing) == 3 * 8 + 2 * 8
+    assert ctypes.sizeof(kc.kc_timing) == 3 * 8 + 2 * 8 + 2 * 4
 
 
 def test_binding_structs_match_the_c_compiler(tmp_path):

@@ -160,3 +160,52 @@ def test_larger_sets_share_a_count():
     print("case multiset larger sets: 12 jobs", flush=True)
     res = kc.kc_count_batch(jobs, kc.make_config(lanes=1))
     _check_all(jobs, res, "larger sets")
+
+
+def _drain(srv, tickets, deadline_s=120.0):
+    import time
+    out, t0 = {}, time.time()
+    while len(out) < len(tickets):
+        assert time.time() - t0 < deadline_s, "server did not finish in time"
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.001)
+    return out
+
+
+@pytest.mark.parametrize("per_set", [0, 1])
+def test_server_batches_queued_requests(per_set):
+    """One slot busy with a large request while small ones queue behind it: requests of one
+    class waiting together are admitted as one count of several sets (unless per_set),
+    a request of another class in between splits the run, and every response equals the
+    oracle's count of that request alone."""
+    kc = _kc()
+    rng = np.random.Generator(np.random.PCG64(12))
+    g = synth.uniform_genome(rng, 300_000)
+    big_r, big_o = synth.sample_reads(rng, g, np.full(40_000, 150), p_sub=0.005)
+    small = _jobs(13, 16, 31, 17, 2, 50, 1000)
+    other = _jobs(14, 3, 21, 11, 2, 50, 1000)
+    order = small[:8] + other[:1] + small[8:] + other[1:]
+    print(f"case server batching per_set={per_set}: 1 large + {len(order)} queued", flush=True)
+    srv = kc.Server(hbm_budget=8 << 30, slots=1, count_cfg=kc.make_config(per_set=per_set), arena_bytes=8 << 30)
+    try:
+        t_big = srv.submit(kc.Job(big_r, big_o, 31, 17, 2, 50, 1000))
+        tickets = [srv.submit(j) for j in order]
+        out = _drain(srv, [t_big] + tickets)
+    finally:
+        srv.close()
+    assert_same(out[t_big][0], oracle.count(big_r, big_o, 31, 2, 50, 1000), "large request")
+    batched = []
+    for i, (j, t) in enumerate(zip(order, tickets)):
+        res, tm = out[t]
+        assert_same(res, _oracle(j), f"queued request {i}")
+        batched.append(tm["batched"])
+    print(f"batched sizes: {batched}", flush=True)
+    if per_set:
+        assert all(b == 1 for b in batched)
+    else:
+        assert max(batched) > 1          # the queued run of one class shared a count
+        assert batched[8] == 1           # the other-class request between them ran alone
