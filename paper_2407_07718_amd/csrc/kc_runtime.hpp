@@ -745,11 +745,60 @@ struct Arena {
 
 enum JobState { J_QUEUED, J_RUNNING, J_DONE, J_FAILED, J_CANCELED };
 
+// Pinned host buffers for the requests' inputs, so that their copies to the device run at
+// the link's speed and never stall the scheduler; reused (by size class: powers of two
+// from 1 MiB) and freed when the server ends.
+struct PinnedPool {
+  std::mutex mu;
+  std::multimap<u64, char*> free_bufs;   // size -> buffer
+  std::vector<char*> all;
+  static u64 size_class(u64 n) {
+    u64 c = 1ull << 20;
+    while (c < n) c <<= 1;
+    return c;
+  }
+  char* get(u64 n, u64* got) {
+    const u64 c = size_class(n);
+    {
+      std::lock_guard<std::mutex> g(mu);
+      auto it = free_bufs.find(c);
+      if (it != free_bufs.end()) {
+        char* p = it->second;
+        free_bufs.erase(it);
+        *got = c;
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    all.push_back(reinterpret_cast<char*>(p));
+    *got = c;
+    return reinterpret_cast<char*>(p);
+  }
+  void put(char* p, u64 c) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu);
+    free_bufs.emplace(c, p);
+  }
+  ~PinnedPool() {
+    for (char* p : all) (void)hipHostFree(p);
+  }
+};
+
 struct SrvJob {
   u64 ticket = 0;
   kc_job job{};
-  std::vector<uint8_t> reads;
-  std::vector<uint64_t> offsets;
+  // the request's reads (offsets[n_reads] bytes) and then its offsets, in a pinned buffer
+  // of `pool` (returned there when the job retires or is freed)
+  PinnedPool* pool = nullptr;
+  char* pin = nullptr;
+  u64 pin_bytes = 0;
+  ~SrvJob() {
+    if (pool) pool->put(pin, pin_bytes);
+  }
+  const uint8_t* reads() const { return reinterpret_cast<const uint8_t*>(pin); }
+  const uint64_t* offsets() const { return reinterpret_cast<const uint64_t*>(pin + align_up(ji.R, 256)); }
   JobInfo ji;
   Plan P;
   JobState state = J_QUEUED;
@@ -783,6 +832,7 @@ struct Slot {
 
 struct kc_server {
   kc_server_cfg cfg{};
+  PinnedPool pinned;   // (destroyed last: after the jobs that may still hold buffers)
   std::mutex mu;
   std::condition_variable cv;
   std::deque<SrvJob*> queue;
@@ -949,9 +999,9 @@ struct kc_server {
       SrvJob* J = s ? H->mates[s - 1] : H;
       uint8_t* d_reads = reinterpret_cast<uint8_t*>(base + H->in_off[s]);
       uint64_t* d_off = reinterpret_cast<uint64_t*>(base + H->in_off[s] + align_up(J->ji.R + 16, 256));
-      if (J->ji.R && hipMemcpyAsync(d_reads, J->reads.data(), J->ji.R, hipMemcpyHostToDevice, S.st) != hipSuccess)
+      if (J->ji.R && hipMemcpyAsync(d_reads, J->reads(), J->ji.R, hipMemcpyHostToDevice, S.st) != hipSuccess)
         rc = fail(KC_EDEVICE, "H2D failed");
-      if (!rc && hipMemcpyAsync(d_off, J->offsets.data(), 8 * J->offsets.size(), hipMemcpyHostToDevice, S.st) !=
+      if (!rc && hipMemcpyAsync(d_off, J->offsets(), 8 * (J->job.n_reads + 1), hipMemcpyHostToDevice, S.st) !=
                      hipSuccess)
         rc = fail(KC_EDEVICE, "H2D failed");
       mp.src[s] = d_reads;
@@ -1009,9 +1059,10 @@ struct kc_server {
     Slot& S = slots[J->slot];
     const Ptrs d = ptrs(J);
     int rc = KC_OK;
-    if (J->ji.R && hipMemcpyAsync(d.reads, J->reads.data(), J->ji.R, hipMemcpyHostToDevice, S.st) != hipSuccess)
+    if (J->ji.R && hipMemcpyAsync(d.reads, J->reads(), J->ji.R, hipMemcpyHostToDevice, S.st) != hipSuccess)
       rc = fail(KC_EDEVICE, "H2D failed");
-    if (!rc && hipMemcpyAsync(d.off, J->offsets.data(), 8 * J->offsets.size(), hipMemcpyHostToDevice, S.st) != hipSuccess)
+    if (!rc && hipMemcpyAsync(d.off, J->offsets(), 8 * (J->job.n_reads + 1), hipMemcpyHostToDevice, S.st) !=
+                   hipSuccess)
       rc = fail(KC_EDEVICE, "H2D failed");
     if (!rc)
       rc = enqueue_any(J->P, d.ws, d.reads, d.off, J->job.min_freq, J->job.max_freq, J->job.hist_len, d.kmers, d.counts,
@@ -1048,10 +1099,9 @@ struct kc_server {
       J->state = J->rc ? J_FAILED : J_DONE;
       J->tm.done_s = t;
       est_used -= J->est;
-      J->reads.clear();
-      J->reads.shrink_to_fit();
-      J->offsets.clear();
-      J->offsets.shrink_to_fit();
+      // (the slot's stream is complete: its copies from the pinned buffer are done)
+      pinned.put(J->pin, J->pin_bytes);
+      J->pin = nullptr;
     }
     H->mates.clear();   // members may be polled (and freed) from here on
     H->tab.clear();
@@ -1168,8 +1218,11 @@ int kc_server_submit(kc_server* s, const kc_job* job, uint64_t* ticket) {
   rc = host_job_info(job->offsets, job->n_reads, job->k, job->min_freq, &J->ji);
   if (rc) return rc;
   J->job = *job;
-  J->reads.assign(job->reads, job->reads + J->ji.R);
-  J->offsets.assign(job->offsets, job->offsets + job->n_reads + 1);
+  J->pool = &s->pinned;
+  J->pin = s->pinned.get(align_up(J->ji.R, 256) + 8 * (job->n_reads + 1), &J->pin_bytes);
+  if (!J->pin) return fail(KC_ENOMEM, "pinned host allocation failed");
+  if (J->ji.R) memcpy(J->pin, job->reads, J->ji.R);
+  memcpy(J->pin + align_up(J->ji.R, 256), job->offsets, 8 * (job->n_reads + 1));
   J->job.reads = nullptr;
   J->job.offsets = nullptr;
   if (!make_plan(J->ji.R, job->n_reads, J->ji.n_max, job->k, job->m, job->min_freq, &s->cfg.count, &J->P))
