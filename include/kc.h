@@ -295,8 +295,10 @@ int kc_batch_result(kc_batch *b, uint32_t job, kc_result *out);
 int kc_batch_destroy(kc_batch *b);
 /* Shape of a prepared batch: *n_counts launch sequences per run (each count of several
  * sets is one, each job counted on its own is one), *n_shared jobs counted with other
- * sets, *lanes stream lanes.  Any pointer may be NULL. */
-int kc_batch_info(const kc_batch *b, uint32_t *n_counts, uint32_t *n_shared, uint32_t *lanes);
+ * sets, *lanes stream lanes, *device_bytes device memory it holds (workspaces, tables,
+ * outputs; within cfg->hbm_budget when one was given).  Any pointer may be NULL. */
+int kc_batch_info(const kc_batch *b, uint32_t *n_counts, uint32_t *n_shared, uint32_t *lanes,
+                  uint64_t *device_bytes);
 
 /* Autotuner: times the count of one representative job under candidate bucket counts
  * and block shapes and returns the fastest setting in *out (its other fields copied

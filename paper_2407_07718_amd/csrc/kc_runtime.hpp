@@ -304,6 +304,7 @@ struct kc_batch {
   std::vector<char*> ws;
   char* out_mem = nullptr;
   char* owned_inputs = nullptr;
+  u64 device_bytes = 0;   // workspaces, tables and outputs (not the caller's inputs)
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
   hipGraph_t graph = nullptr;
@@ -493,6 +494,7 @@ int batch_build(std::vector<kc_batch::Job>&& jobs, const kc_config* cfg, kc_batc
     return fail(KC_ENOMEM, "batch needs %llu bytes > budget %llu", (unsigned long long)need,
                 (unsigned long long)cfg->hbm_budget);
   if (need > free_b) return fail(KC_ENOMEM, "batch needs %llu bytes of HBM, %zu free", (unsigned long long)need, free_b);
+  b->device_bytes = need;
   for (size_t i = 0; i < sizes.size(); ++i) {
     if (item_group[i] >= 0) b->groups[item_group[i]].lane = lane[i];
     else b->jobs[item_job[i]].lane = lane[i];
@@ -602,7 +604,8 @@ int kc_batch_result(kc_batch* b, uint32_t job, kc_result* out) {
   return fetch_result(J.tot, J.kmers, J.counts, J.hist, J.ji.pair_cap, J.j.hist_len, J.ji.key_words, b->origin, out);
 }
 
-int kc_batch_info(const kc_batch* b, uint32_t* n_counts, uint32_t* n_shared, uint32_t* lanes) {
+int kc_batch_info(const kc_batch* b, uint32_t* n_counts, uint32_t* n_shared, uint32_t* lanes,
+                  uint64_t* device_bytes) {
   g_err.clear();
   if (!b) return fail(KC_EINVAL, "NULL batch");
   u32 solo = 0, shared = 0;
@@ -610,6 +613,7 @@ int kc_batch_info(const kc_batch* b, uint32_t* n_counts, uint32_t* n_shared, uin
   if (n_counts) *n_counts = (u32)b->groups.size() + solo;
   if (n_shared) *n_shared = shared;
   if (lanes) *lanes = (u32)b->lanes;
+  if (device_bytes) *device_bytes = b->device_bytes;
   return KC_OK;
 }
 

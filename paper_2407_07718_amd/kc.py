@@ -125,7 +125,8 @@ def _load() -> ctypes.CDLL:
     lib.kc_batch_result.argtypes = [vp, u32, P(kc_result)]
     lib.kc_batch_result.restype = i32
     lib.kc_batch_destroy.argtypes = [vp]
-    lib.kc_batch_info.argtypes = [vp, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
+    lib.kc_batch_info.argtypes = [vp, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32),
+                                  P(ctypes.c_uint64)]
     lib.kc_batch_info.restype = i32
     lib.kc_batch_destroy.restype = i32
     lib.kc_autotune.argtypes = [P(kc_job), P(kc_config), P(kc_config), P(ctypes.c_double)]
@@ -322,9 +323,9 @@ class DeviceBatch:
 
     def info(self) -> dict:
         """Launch sequences per run, jobs counted with other sets, stream lanes."""
-        n, sh, ln = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
-        _check(_lib.kc_batch_info(self.h, ctypes.byref(n), ctypes.byref(sh), ctypes.byref(ln)))
-        return {"counts": int(n.value), "shared": int(sh.value), "lanes": int(ln.value)}
+        n, sh, ln, nb = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        _check(_lib.kc_batch_info(self.h, ctypes.byref(n), ctypes.byref(sh), ctypes.byref(ln), ctypes.byref(nb)))
+        return {"counts": int(n.value), "shared": int(sh.value), "lanes": int(ln.value), "device_bytes": int(nb.value)}
 
     def close(self) -> None:
         if self.h:

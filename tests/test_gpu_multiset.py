@@ -136,7 +136,8 @@ def test_device_batch_of_many_sets_replays():
     b = kc.DeviceBatch(sets, kc.make_config(lanes=2))
     try:
         # two classes (k = 31 and 21), each one count: two launch sequences for 50 sets
-        assert b.info() == {"counts": 2, "shared": 50, "lanes": 2}, b.info()
+        info = b.info()
+        assert (info["counts"], info["shared"], info["lanes"]) == (2, 50, 2), info
         for rep in range(3):
             b.run()
             for i, ref in enumerate(refs):
@@ -209,3 +210,60 @@ def test_server_batches_queued_requests(per_set):
     else:
         assert max(batched) > 1          # the queued run of one class shared a count
         assert batched[8] == 1           # the other-class request between them ran alone
+
+
+def test_batch_lanes_reduced_to_fit_the_budget():
+    """An HBM budget that holds one lane's workspace but not two: the batch runs on fewer
+    lanes instead of failing, with every set still equal to the oracle."""
+    import torch
+    kc = _kc()
+    jobs = _jobs(15, 12, 31, 17, 2, 50, 1000) + _jobs(16, 10, 21, 11, 2, 50, 1000)
+    dev = torch.device("cuda:0")
+    sets = [(torch.from_numpy(np.concatenate([j.reads, np.zeros(16, np.uint8)])).to(dev),
+             torch.from_numpy(j.offsets.view(np.int64)).to(dev), j.k, j.m, j.min_freq, j.max_freq, j.hist_len)
+            for j in jobs]
+    two = kc.DeviceBatch(sets, kc.make_config(lanes=2))
+    one = kc.DeviceBatch(sets, kc.make_config(lanes=1))
+    need2, need1 = two.info()["device_bytes"], one.info()["device_bytes"]
+    assert two.info()["lanes"] == 2 and one.info()["lanes"] == 1 and need1 < need2
+    two.close()
+    one.close()
+    budget = (need1 + need2) // 2
+    b = kc.DeviceBatch(sets, kc.make_config(lanes=2, hbm_budget=budget))
+    try:
+        print(f"case multiset lanes under budget {budget}: {b.info()}", flush=True)
+        assert b.info()["lanes"] == 1 and b.info()["device_bytes"] <= budget
+        b.run()
+        for i, j in enumerate(jobs):
+            assert_same(b.result(i), _oracle(j), f"budget set {i}")
+    finally:
+        b.close()
+
+
+def test_server_batch_shrinks_to_fit_the_arena():
+    """Queued requests of one class whose joint count would not fit the arena are admitted
+    in smaller batches (or alone); every response equals the oracle."""
+    kc = _kc()
+    rng = np.random.Generator(np.random.PCG64(17))
+    g = synth.uniform_genome(rng, 200_000)
+    jobs = []
+    for i in range(8):
+        r, o = synth.sample_reads(rng, g, np.full(6000, 150), p_sub=0.005)
+        jobs.append(kc.Job(r, o, 31, 17, 2, 50, 1000))
+    one = kc.kc_workspace_size(int(jobs[0].offsets[-1]), len(jobs[0].offsets) - 1, 31)
+    arena = int(one * 3.5)     # room for about two requests at a time, not eight together
+    big_r, big_o = synth.sample_reads(rng, g, np.full(12000, 150), p_sub=0.005)
+    print(f"case server batch vs arena {arena}", flush=True)
+    srv = kc.Server(hbm_budget=1 << 40, slots=1, arena_bytes=arena)
+    try:
+        t_big = srv.submit(kc.Job(big_r, big_o, 21, 11, 2, 50, 1000))   # another class, keeps the slot busy
+        tickets = [srv.submit(j) for j in jobs]
+        out = _drain(srv, [t_big] + tickets)
+    finally:
+        srv.close()
+    sizes = [out[t][1]["batched"] for t in tickets]
+    print(f"batched sizes: {sizes}", flush=True)
+    assert max(sizes) < len(jobs)
+    for i, (j, t) in enumerate(zip(jobs, tickets)):
+        assert out[t][1]["device_bytes"] <= arena
+        assert_same(out[t][0], _oracle(j), f"arena request {i}")
