@@ -116,8 +116,8 @@ int kc_count(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads, in
 void kc_result_free(kc_result *res);
 
 /* Bytes of device workspace kc_count_device needs for a read buffer of total_bases
- * bytes split into n_reads reads, at this k (0 on bad arguments, or when cfg->hbm_budget
- * is set and no plan fits it).
+ * bytes split into n_reads reads, at this k (0 on bad arguments, total_bases >= 2^32
+ * included, or when cfg->hbm_budget is set and no plan fits it).
  *
  * Memory-bounded counting (Section 3.1: with too little memory the paper sorts in place;
  * Section 3.3: the exchange runs in rounds of bounded size).  When cfg->hbm_budget is
@@ -211,8 +211,8 @@ int kc_count_ext(const uint8_t *reads, const uint64_t *offsets, uint64_t n_reads
 /* Release the arrays of a kc_ext_result filled by kc_count_ext (safe on a zeroed one). */
 void kc_ext_result_free(kc_ext_result *res);
 
-/* Bytes of device workspace kc_count_ext_device needs (0 on bad arguments, or when
- * cfg->hbm_budget is set and no plan fits it).
+/* Bytes of device workspace kc_count_ext_device needs (0 on bad arguments, total_bases
+ * or n_reads >= 2^32 included, or when cfg->hbm_budget is set and no plan fits it).
  *
  * Memory-bounded counting (Section 3.1: with too little memory for an out-of-place sort
  * the paper switches to an in-place one; Section 3.3: the exchange runs in rounds of

@@ -1647,7 +1647,7 @@ const char* kc_version(void) { return "kc 0.1 (gfx950)"; }
 const char* kc_last_error(void) { return g_err.c_str(); }
 
 size_t kc_workspace_size(uint64_t total_bases, uint64_t n_reads, int k, const kc_config* cfg) {
-  if (k < 1 || k > 63) return 0;
+  if (k < 1 || k > 63 || total_bases >= (1ull << 32)) return 0;
   Plan P;
   if (!make_plan(total_bases, n_reads, total_bases, k, 1, 1, cfg, &P)) return 0;
   if (fit_budget(&P, cfg)) {
@@ -1935,7 +1935,7 @@ int kc_partition_inspect(const uint8_t* reads, const uint64_t* offsets, uint64_t
 
 // ---------------------------------------------------------------- extension version
 size_t kc_ext_workspace_size(uint64_t total_bases, uint64_t n_reads, int k, const kc_config* cfg) {
-  if (k < 1 || k > 63) return 0;
+  if (k < 1 || k > 63 || total_bases >= (1ull << 32) || n_reads >= (1ull << 32)) return 0;
   ExtPlan P;
   if (!make_ext_plan(total_bases, n_reads, k, cfg ? cfg->hbm_budget : 0, &P)) return 0;
   return (size_t)P.bytes;

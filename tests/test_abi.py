@@ -80,6 +80,28 @@ def test_workspace_size_scales():
     assert kc.kc_workspace_size(1000, 10, 64) == 0
 
 
+def test_largest_input_accepted_and_one_base_more_refused():
+    """A count takes at most 2^32 - 1 bases (windows, read indices and positions are
+    32-bit); the workspace queries and the host APIs agree on that limit, and the host
+    APIs refuse from the offsets alone, before touching the reads."""
+    from paper_2407_07718_amd import kc
+    top = (1 << 32) - 1
+    for k in (31, 51):
+        assert kc.kc_workspace_size(top, 300_000, k) > 0
+        assert kc.kc_workspace_size(top + 1, 300_000, k) == 0
+        assert kc.kc_ext_workspace_size(top, 300_000, k) > 0
+        assert kc.kc_ext_workspace_size(top + 1, 300_000, k) == 0
+    assert kc.kc_ext_workspace_size(top, 1 << 32, 31) == 0
+    reads = np.frombuffer(b"ACGT" * 8, dtype=np.uint8)
+    offsets = np.array([0, 1 << 32], dtype=np.uint64)
+    with pytest.raises(kc.KCError) as e:
+        kc.kc_count(reads, offsets, 31, 17, 2, 50, 16)
+    assert e.value.code == kc.KC_EINVAL and "2^32" in str(e.value)
+    with pytest.raises(kc.KCError) as e:
+        kc.kc_count_ext(reads, offsets, 31, 2, 50, 16)
+    assert e.value.code == kc.KC_EINVAL and "2^32" in str(e.value)
+
+
 def test_header_declares_batch_and_server_entry_points():
     names = declared_functions()
     for n in ["kc_count_batch", "kc_batch_create", "kc_batch_run", "kc_batch_result", "kc_batch_destroy",
