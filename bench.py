@@ -8,14 +8,16 @@ keys), m=21, frequency filter [2, 200].  Inputs (ASCII reads and offsets) are re
 HBM before the timed region starts.  The result of the timed counts is compared with
 the oracle's stored digests of the same workload.
 
-The same JSON line carries further legs: the long-read workload at k=51 (128-bit keys),
+The same JSON line carries further legs: the host API on the same workload (reads in host
+memory, pairs back in host memory: PCIe copies, workspace allocation and the count), the
+long-read workload at k=51 (128-bit keys),
 the short-read workload (1,000,000 x 150 bp, k=31), the extension version (occurrence
 lists) on short reads, the CPU oracle and the CPU-parallel baseline on a bounded sample,
 the batched workload (256 read sets in one graph launch, several sets per count, vs one
 count per set in the same graph and vs 256 plain counts) and the served
 workload (Poisson arrivals of requests drawn from the batched sets).
 
-    python bench.py [--steps K] [--warmup W] [--legs k51,short,ext,cpu,batch,serve]
+    python bench.py [--steps K] [--warmup W] [--legs host,k51,short,ext,cpu,batch,serve]
     python bench.py --summarize-pmc FETCH_DIR WRITE_DIR --workload NAME   # profiles/hbm_traffic.json
 """
 from __future__ import annotations
@@ -38,7 +40,7 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 SRC_DIR = os.path.join(ROOT, "paper_2407_07718_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 GOLDEN = os.path.join(ROOT, "tests", "golden")
-ALL_LEGS = "k51,bounded,short,ext,cpu,batch,serve"
+ALL_LEGS = "host,k51,bounded,short,ext,cpu,batch,serve"
 HIST_LEN = 65536
 
 
@@ -277,6 +279,36 @@ def bounded_leg(torch, kc, rs, fracs=(0.2, 0.08), steps: int = 3) -> dict:
     del d_reads, d_offsets
     torch.cuda.empty_cache()
     return out
+
+
+def host_leg(kc, rs, device_sha: str, steps: int = 3) -> dict:
+    """The host API (kc_count) on the headline workload: reads and offsets in host memory,
+    pairs and histogram back in host memory.  Each call copies the reads to the device,
+    allocates its workspace and pinned result arrays, counts and copies the result back;
+    the wall time of the library call is taken (median of `steps` after one warm-up call,
+    whose result must equal the device API's).  Never the bench value."""
+    import ctypes
+    res = kc.kc_count(rs.reads, rs.offsets, rs.k, rs.m, rs.min_freq, rs.max_freq, HIST_LEN)
+    same = result_sha(res.kmers, res.counts, res.hist) == device_sha
+    assert same, "host API result differs from the device API's"
+    n_win = int(res.totals["n_windows"])
+    del res
+    reads = np.ascontiguousarray(rs.reads, dtype=np.uint8)
+    offs = np.ascontiguousarray(rs.offsets, dtype=np.uint64)
+    times = []
+    for _ in range(steps):
+        r = kc.kc_result()
+        t0 = time.perf_counter()
+        rc = kc._lib.kc_count(reads.ctypes.data, offs.ctypes.data, offs.shape[0] - 1, rs.k, rs.m, rs.min_freq,
+                              rs.max_freq, HIST_LEN, None, ctypes.byref(r))
+        times.append(time.perf_counter() - t0)
+        kc._lib.kc_result_free(ctypes.byref(r))
+        assert rc == 0, kc.kc_last_error()
+    ms = float(np.median(times)) * 1e3
+    return {"ms_per_call": round(ms, 2), "value": n_win / (ms * 1e-3), "unit": "k-mers/s", "calls": steps,
+            "input_bytes": int(rs.n_bases) + 8 * (int(rs.n_reads) + 1), "equal_to_device_result": same,
+            "includes": "H2D of reads and offsets from pageable memory, workspace and pinned result allocation, "
+                        "the count, D2H of pairs and histogram"}
 
 
 # ---------------------------------------------------------------------------- CPU baselines
@@ -766,6 +798,9 @@ def main():
     if "count_hbm" in head:
         out["count_hbm"] = head["count_hbm"]
     legs = {}
+    if "host" in args.legs:
+        log("leg: host API (PCIe copies included)")
+        legs["host_api"] = host_leg(kc, rs, head_sha)
     if "cpu" in args.legs:
         log("CPU oracle and CPU-parallel baseline on a sample")
         out["cpu_baseline"], out["cpu_parallel"] = cpu_legs(rs, args.cpu_sample_bases)
