@@ -190,6 +190,24 @@ def test_deterministic():
     assert np.array_equal(a.hist, b.hist)
 
 
+@pytest.mark.parametrize("k,m", [(31, 15), (21, 11), (32, 16), (51, 21)])
+def test_reverse_complemented_reads_give_the_same_result(k, m):
+    """Strand symmetry: every read replaced by its reverse complement (N bytes kept in
+    place of their mirror positions) gives the identical result, since a window and its
+    reverse complement have one canonical k-mer; both equal the oracle's.  3 Mbp of reads
+    from a 200 kb genome: many buckets, heavy and tiny ones."""
+    from tests import partition_brute as pb
+    reads, offsets = _genome_reads(900 + k, 20_000, 60, 240, genome=200_000, p_n=0.003)
+    rc = pb.reverse_complement_reads(reads, offsets)
+    assert not np.array_equal(rc, reads)
+    print(f"case strand symmetry: k={k} m={m} bases={reads.shape[0]}", flush=True)
+    a = device_count(reads, offsets, k, m, 1, 1000, 256)
+    b = device_count(rc, offsets, k, m, 1, 1000, 256)
+    ref = oracle.count(reads, offsets, k, 1, 1000, 256)
+    assert_same(a, ref, f"forward k={k}")
+    assert_same(b, ref, f"reverse complement k={k}")
+
+
 def test_short_read_config_full_size():
     rs = synth.config(2)
     print(f"case short-read full size: bases={rs.n_bases} reads={rs.n_reads}", flush=True)
