@@ -10,6 +10,7 @@ the oracle's stored digests of the same workload.
 
 The same JSON line carries further legs: the host API on the same workload (reads in host
 memory, pairs back in host memory: PCIe copies, workspace allocation and the count), the
+partition's balance and volume on the same workload (untimed diagnostics), the
 long-read workload at k=51 (128-bit keys),
 the short-read workload (1,000,000 x 150 bp, k=31), the extension version (occurrence
 lists) on short reads, the CPU oracle and the CPU-parallel baseline on a bounded sample,
@@ -17,7 +18,7 @@ the batched workload (256 read sets in one graph launch, several sets per count,
 count per set in the same graph and vs 256 plain counts) and the served
 workload (Poisson arrivals of requests drawn from the batched sets).
 
-    python bench.py [--steps K] [--warmup W] [--legs host,k51,short,ext,cpu,batch,serve]
+    python bench.py [--steps K] [--warmup W] [--legs host,partition,k51,short,ext,cpu,batch,serve]
     python bench.py --summarize-pmc FETCH_DIR WRITE_DIR --workload NAME   # profiles/hbm_traffic.json
 """
 from __future__ import annotations
@@ -40,7 +41,7 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 SRC_DIR = os.path.join(ROOT, "paper_2407_07718_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 GOLDEN = os.path.join(ROOT, "tests", "golden")
-ALL_LEGS = "host,k51,bounded,short,ext,cpu,batch,serve"
+ALL_LEGS = "host,partition,k51,bounded,short,ext,cpu,batch,serve"
 HIST_LEN = 65536
 
 
@@ -309,6 +310,35 @@ def host_leg(kc, rs, device_sha: str, steps: int = 3) -> dict:
             "input_bytes": int(rs.n_bases) + 8 * (int(rs.n_reads) + 1), "equal_to_device_result": same,
             "includes": "H2D of reads and offsets from pageable memory, workspace and pinned result allocation, "
                         "the count, D2H of pairs and histogram"}
+
+
+def partition_leg(kc, rs) -> dict:
+    """Untimed diagnostics of the first stage on the headline workload, through
+    kc_partition_inspect (the count's encode, extract and partition kernels): the k-mers per
+    bucket, the supermer length, the volume of the records against plain 8- or 16-byte
+    keys (the paper's supermers cut the exchange volume, Section 2.4), and the balance of
+    the k-mers over G destinations taking the buckets b with b mod G = g (the paper reports
+    the largest over the smallest destination, Section 3.2)."""
+    part = kc.kc_partition_inspect(rs.reads, rs.offsets, rs.k, rs.m)
+    bc = part.bucket_counts
+    km = (bc & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    nrec = (bc >> np.uint64(32)).astype(np.int64)
+    n_km, n_rec = int(km.sum()), int(nrec.sum())
+    rec_bytes = int(part.records.shape[1]) * 8
+    key_bytes = 8 if rs.k <= 31 else 16
+    ne = km[km > 0]
+    bal = {}
+    for G in (8, 64, 256):
+        per = np.bincount(np.arange(km.shape[0]) % G, weights=km, minlength=G)
+        bal[str(G)] = round(float(per.max() / max(1.0, per.min())), 4)
+    return {"buckets": int(km.shape[0]), "kmers": n_km, "records": n_rec,
+            "kmers_per_bucket": {"mean": round(n_km / km.shape[0], 2), "max": int(km.max()),
+                                 "min_nonempty": int(ne.min()) if ne.size else 0, "std": round(float(km.std()), 2),
+                                 "empty": int((km == 0).sum())},
+            "kmers_per_record": round(n_km / max(1, n_rec), 3), "record_bytes": rec_bytes,
+            "record_bytes_per_kmer": round(n_rec * rec_bytes / max(1, n_km), 3),
+            "volume_vs_plain_keys": round(n_rec * rec_bytes / max(1, n_km * key_bytes), 4),
+            "destination_max_over_min": bal}
 
 
 # ---------------------------------------------------------------------------- CPU baselines
@@ -801,6 +831,9 @@ def main():
     if "host" in args.legs:
         log("leg: host API (PCIe copies included)")
         legs["host_api"] = host_leg(kc, rs, head_sha)
+    if "partition" in args.legs:
+        log("leg: partition diagnostics")
+        legs["partition"] = partition_leg(kc, rs)
     if "cpu" in args.legs:
         log("CPU oracle and CPU-parallel baseline on a sample")
         out["cpu_baseline"], out["cpu_parallel"] = cpu_legs(rs, args.cpu_sample_bases)
