@@ -316,7 +316,7 @@ def partition_leg(kc, rs) -> dict:
     """Untimed diagnostics of the first stage on the headline workload, through
     kc_partition_inspect (the count's encode, extract and partition kernels): the k-mers per
     bucket, the supermer length, the volume of the records against plain 8- or 16-byte
-    keys (the paper's supermers cut the exchange volume, Section 2.4), and the balance of
+    keys (the paper's supermers cut the exchange volume, Section 3.2), and the balance of
     the k-mers over G destinations taking the buckets b with b mod G = g (the paper reports
     the largest over the smallest destination, Section 3.2)."""
     part = kc.kc_partition_inspect(rs.reads, rs.offsets, rs.k, rs.m)
