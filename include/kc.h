@@ -48,7 +48,9 @@ extern "C" {
 typedef struct kc_config {
   uint32_t log2_buckets;   /* buckets B = 2^log2_buckets (1..20); 0 = from the input size */
   uint32_t force_hbm;      /* 1 = route every bucket through the chunk-list merge (testing) */
-  uint32_t small_variant;  /* on-chip sort block shape: 0 auto, 1 = 256x16, 2 = 512x16 */
+  uint32_t small_variant;  /* on-chip sort block shape: 0 auto, 1 = 256x16, 2 = 512x16,
+                              3 = 256x8 with 16-bit digit counts (keys per thread halved for
+                              128-bit keys); auto = 3 for k <= 31, 1 for k >= 32 */
   uint32_t lanes;          /* batch / server: concurrent stream lanes (0 = 8) */
   uint64_t hbm_budget;     /* max bytes of a count's device workspace (see kc_workspace_size:
                               above it a count runs in rounds); 0 = no limit other than free HBM */

@@ -128,10 +128,19 @@ enum Ctrl : int {
 };
 static_assert(C_META + 8 <= C_FLAGS, "meta overlaps the flags");
 
-u32 default_variant(int key_words) { return key_words == 1 ? 1u : 1u; }
+// On-chip block shapes of the bucket sort: 1 = 256 threads x 16 keys (x 8 for 128-bit keys),
+// 2 = 512 x 16 (x 8), 3 = 256 x 8 (x 4) with 16-bit digit counts, whose 30 KB of LDS and
+// 91 VGPRs let five blocks share a CU instead of three.  Measured fastest: 3 for 64-bit
+// keys, 1 for 128-bit keys (where 3 sends too many buckets to the chunk lists).
+u32 default_variant(int key_words) { return key_words == 1 ? 3u : 1u; }
 u32 small_cap(int key_words, u32 variant) {
-  if (key_words == 1) return variant == 2 ? 512u * 16u : 256u * 16u;
-  return variant == 2 ? 512u * 8u : 256u * 8u;
+  if (key_words == 1) return variant == 2 ? 512u * 16u : variant == 3 ? 256u * 8u : 256u * 16u;
+  return variant == 2 ? 512u * 8u : variant == 3 ? 256u * 4u : 256u * 8u;
+}
+// Mean bucket size the bucket count aims at: about a third of the on-chip capacity (of the
+// 256 x 16 shape for the 256 x 8 one, whose gain is occupancy, not smaller buckets).
+u64 bucket_target(int key_words, u32 variant) {
+  return std::max<u64>(1, small_cap(key_words, variant == 3 ? 1u : variant) / 3);
 }
 
 void plan_layout(Plan* p);
@@ -148,7 +157,7 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
   const int cap_bases = k <= 31 ? 51 : 115;   // record bits left after bucket and g
   p->gmax = std::min(64, cap_bases - k + 1);
   p->variant = (cfg && cfg->small_variant) ? cfg->small_variant : default_variant(p->key_words);
-  if (p->variant > 2) return false;
+  if (p->variant > 3) return false;
   p->cap_chunk = small_cap(p->key_words, p->variant);
   p->cap = (cfg && cfg->force_hbm) ? 0u : p->cap_chunk;
   p->cap_tiny = (cfg && cfg->force_hbm) ? 0u : (p->key_words == 1 ? WAVE_CAP_64 : WAVE_CAP_128);
@@ -156,8 +165,7 @@ bool make_plan(u64 R, u64 n_reads, u64 n_max, int k, int m, uint32_t min_freq, c
     if (cfg->log2_buckets > 20) return false;
     p->log_b = (int)cfg->log2_buckets;
   } else {
-    // mean bucket about a third of the on-chip capacity
-    const u64 target = std::max<u64>(1, small_cap(p->key_words, p->variant) / 3);
+    const u64 target = bucket_target(p->key_words, p->variant);
     int lb = 1;
     while (lb < 20 && (n_max >> lb) > target) ++lb;
     p->log_b = lb;
@@ -740,9 +748,12 @@ int count_buckets(const Plan& P, const Ws<K>& W, const u32* blk_base, uint32_t l
     return KC_OK;
   };
   {
-    constexpr int IT = WIDE ? 8 : 16;
+    constexpr int IT = WIDE ? 8 : 16, IT3 = WIDE ? 4 : 8;
     if (P.variant == 2)
       rc = ms ? block_sort(k_bucket_sort_count<K, 512, IT, true>, 512) : block_sort(k_bucket_sort_count<K, 512, IT>, 512);
+    else if (P.variant == 3)
+      rc = ms ? block_sort(k_bucket_sort_count<K, 256, IT3, true, true>, 256)
+              : block_sort(k_bucket_sort_count<K, 256, IT3, false, true>, 256);
     else
       rc = ms ? block_sort(k_bucket_sort_count<K, 256, IT, true>, 256) : block_sort(k_bucket_sort_count<K, 256, IT>, 256);
     if (rc) return rc;
@@ -963,6 +974,8 @@ int warm_launch_facts() {
   if ((rc = blocks_per_cu(k_bucket_sort_count<u64, 512, 16>, 512, &v))) return rc;
   if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 256, 8>, 256, &v))) return rc;
   if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 512, 8>, 512, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<u64, 256, 8, false, true>, 256, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 256, 4, false, true>, 256, &v))) return rc;
   if ((rc = blocks_per_cu(k_wave_sort_count<u64, WAVE_CAP_64, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v))) return rc;
   if ((rc = blocks_per_cu(k_wave_sort_count<k128, WAVE_CAP_128, WAVES_PER_BLOCK>, WAVES_PER_BLOCK * 64, &v)))
     return rc;
@@ -971,6 +984,8 @@ int warm_launch_facts() {
   if ((rc = blocks_per_cu(k_bucket_sort_count<u64, 512, 16, true>, 512, &v))) return rc;
   if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 256, 8, true>, 256, &v))) return rc;
   if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 512, 8, true>, 512, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<u64, 256, 8, true, true>, 256, &v))) return rc;
+  if ((rc = blocks_per_cu(k_bucket_sort_count<k128, 256, 4, true, true>, 256, &v))) return rc;
   if ((rc = blocks_per_cu(k_wave_sort_count<u64, WAVE_CAP_64, WAVES_PER_BLOCK, true>, WAVES_PER_BLOCK * 64, &v)))
     return rc;
   if ((rc = blocks_per_cu(k_wave_sort_count<k128, WAVE_CAP_128, WAVES_PER_BLOCK, true>, WAVES_PER_BLOCK * 64, &v)))
@@ -1060,12 +1075,12 @@ bool make_multi_plan(const std::vector<MultiSet>& sets, int k, int m, u32 lo, u3
   if (2 * k + (int)mp->sbits > 126) return false;
   const int kw = k <= 31 ? 1 : 2;
   const u32 variant = (cfg && cfg->small_variant) ? cfg->small_variant : default_variant(kw);
-  if (variant > 2) return false;
+  if (variant > 3) return false;
   // mean bucket about a sixth of the on-chip capacity (a single count aims at a third):
   // several counts of several sets overlap on the stream lanes, and smaller buckets (more
   // of them sorted by one wave each) measured faster there -- the 5.6 Gbp batched workload
   // took 167 ms against 184 ms at a third and 181 ms at a twelfth
-  const u64 target = std::max<u64>(1, small_cap(kw, variant) / 6);
+  const u64 target = std::max<u64>(1, bucket_target(kw, variant) / 2);
   mp->set_start.assign(S + 1, 0);
   mp->read_base.assign(S + 1, 0);
   mp->set_len.assign(S, 0);

@@ -8,6 +8,8 @@
 // frequency requirement to another array (Section 3.1).  A bucket is a task (Section
 // 3.4): independent of all others because equal k-mers never span two buckets.
 #pragma once
+#include <type_traits>
+
 #include "kc_common.hpp"
 #include "kc_sort.hpp"
 
@@ -266,14 +268,17 @@ __device__ __forceinline__ void flush_stats(const RunSink& S, u64 ndist) {
 
 // ---------------------------------------------------------------------------- on-chip sort
 // Shared memory of one block of the bucket kernel.
-template <typename K, int T, int ITEMS>
+// With C16 the digit counts and offsets (at most CAP) are 16-bit, which saves LDS.
+template <typename K, int T, int ITEMS, bool C16 = false>
 struct BucketSmem {
   static constexpr int W = T / 64, CAP = T * ITEMS;
+  using CntT = std::conditional_t<C16, u16, u32>;
+  static_assert(!C16 || CAP < 65536, "16-bit digit offsets");
   K keys[CAP];
   union {
     struct {
       u64 tbl[W][256];              // lane masks per digit; all zero between uses
-      u32 cnt[2][W][256];           // per-wave digit counts -> per-wave digit offsets
+      CntT cnt[2][W][256];          // per-wave digit counts -> per-wave digit offsets
     } r;
     u16 hp[CAP];                    // run heads after the sort
   } u;
@@ -352,8 +357,8 @@ __device__ __forceinline__ u64 digit_peers(u64* tbl, u32 d, bool act) {
 // table per pass parity), gtot has 4 entries.  With `clear` the tables are zeroed first;
 // otherwise they must be as a previous call left them (tbl zero, the table of parity
 // p_begin zero).  n_pad is a multiple of 64 * W.  Block-wide: barriers inside.
-template <typename K, int T, int ITEMS, bool HASV>
-__device__ __forceinline__ void lds_sort_passes(K* keys, u32* vals, u64* tbl, u32* cnt, u32* gtot, u32 n_pad,
+template <typename K, int T, int ITEMS, bool HASV, typename CntT = u32>
+__device__ __forceinline__ void lds_sort_passes(K* keys, u32* vals, u64* tbl, CntT* cnt, u32* gtot, u32 n_pad,
                                                 int p_begin, int p_end, bool clear) {
   constexpr int W = T / 64;
   const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -369,7 +374,7 @@ __device__ __forceinline__ void lds_sort_passes(K* keys, u32* vals, u64* tbl, u3
   const int per = (int)(n_pad / (64u * W));
   u64* wtbl = tbl + wave * 256;
   for (int p = p_begin; p < p_end; ++p) {
-    u32* C = cnt + (p & 1) * (W * 256);
+    CntT* C = cnt + (p & 1) * (W * 256);
     K kr[ITEMS];
     u32 vr[HASV ? ITEMS : 1];
     u32 rk[ITEMS];
@@ -389,7 +394,7 @@ __device__ __forceinline__ void lds_sort_passes(K* keys, u32* vals, u64* tbl, u3
         const u32 base = C[wave * 256 + d];
         const u32 lr = mbcnt64(mask);
         if (lr == 0) {
-          C[wave * 256 + d] = base + (u32)__popcll(mask);
+          C[wave * 256 + d] = (CntT)(base + (u32)__popcll(mask));
           wtbl[d] = 0;
         }
         rk[j] = base + lr;
@@ -402,13 +407,13 @@ __device__ __forceinline__ void lds_sort_passes(K* keys, u32* vals, u64* tbl, u3
 #pragma unroll
       for (int v = 0; v < W; ++v) {
         const u32 x = C[v * 256 + tid];
-        C[v * 256 + tid] = col;
+        C[v * 256 + tid] = (CntT)col;
         col += x;
       }
       const u32 inc = wave_scan_u32(col);
       const u32 ex = inc - col;
 #pragma unroll
-      for (int v = 0; v < W; ++v) C[v * 256 + tid] += ex;
+      for (int v = 0; v < W; ++v) C[v * 256 + tid] = (CntT)(C[v * 256 + tid] + ex);
       if (lane == 63) gtot[wave] = inc;
     }
     __syncthreads();
@@ -424,14 +429,14 @@ __device__ __forceinline__ void lds_sort_passes(K* keys, u32* vals, u64* tbl, u3
       }
     }
     // the other count table is free again: clear it for the next pass
-    u32* nxt = cnt + ((p + 1) & 1) * (W * 256);
+    CntT* nxt = cnt + ((p + 1) & 1) * (W * 256);
     for (u32 i = tid; i < W * 256; i += T) nxt[i] = 0;
     __syncthreads();
   }
 }
 
-template <typename K, int T, int ITEMS>
-__device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS>& S, u32 n_pad, int p_begin, int p_end) {
+template <typename K, int T, int ITEMS, bool C16>
+__device__ __forceinline__ void bucket_sort(BucketSmem<K, T, ITEMS, C16>& S, u32 n_pad, int p_begin, int p_end) {
   lds_sort_passes<K, T, ITEMS, false>(S.keys, nullptr, &S.u.r.tbl[0][0], &S.u.r.cnt[0][0][0], S.gtot, n_pad, p_begin,
                                       p_end, p_begin == 0);
 }
@@ -454,8 +459,8 @@ __device__ __forceinline__ bool mixed_pair(const K* keys, u32 idx, u32 n, int bi
 }
 
 // Block-wide: does any group of equal low bits hold two distinct keys?
-template <typename K, int T, int ITEMS>
-__device__ __forceinline__ bool mixed_groups(BucketSmem<K, T, ITEMS>& S, u32 n, int bits) {
+template <typename K, int T, int ITEMS, bool C16>
+__device__ __forceinline__ bool mixed_groups(BucketSmem<K, T, ITEMS, C16>& S, u32 n, int bits) {
   bool bad = false;
   for (u32 idx = threadIdx.x; idx < n; idx += T) bad |= mixed_pair(S.keys, idx, n, bits);
   return __syncthreads_or(bad) != 0;
@@ -471,8 +476,8 @@ template <> __device__ __forceinline__ int sort_passes<u64>(int k) { return 2 * 
 template <> __device__ __forceinline__ int sort_passes<k128>(int k) { return (2 * k + 7) / 8; }
 
 // Run heads of the sorted keys[0, n) -> S.u.hp[0, nruns) in order.  Returns nruns.
-template <typename K, int T, int ITEMS>
-__device__ __forceinline__ u32 run_heads(BucketSmem<K, T, ITEMS>& S, u32 n) {
+template <typename K, int T, int ITEMS, bool C16>
+__device__ __forceinline__ u32 run_heads(BucketSmem<K, T, ITEMS, C16>& S, u32 n) {
   constexpr int W = T / 64;
   const u32 tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int per = (int)((n + 64u * W - 1) / (64u * W));
@@ -538,9 +543,9 @@ __device__ __forceinline__ u32 emit_runs_block(const K* keys, const u16* hp, u32
 // form of a heavy-hitter task (Section 3.5) -- merged later through HBM.  Items after
 // that are small buckets: their supermers are expanded into LDS, sorted, and their runs
 // are final counts.  Every item writes its output to its own slot range.
-template <typename K, int T, int ITEMS, bool MS = false>
+template <typename K, int T, int ITEMS, bool MS = false, bool C16 = false>
 __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
-  using SM = BucketSmem<K, T, ITEMS>;
+  using SM = BucketSmem<K, T, ITEMS, C16>;
   constexpr int CAP = SM::CAP;
   static_assert(sizeof(decltype(SM::u)) >= 4 * CAP, "expansion maps fit the rank tables");
   __shared__ SM S;
@@ -613,9 +618,9 @@ __global__ __launch_bounds__(T) void k_bucket_sort_count(CountArgs A) {
     for (u32 i = n + tid; i < n_pad; i += T) S.keys[i] = key_pad<K>();
     __syncthreads();
     const int p0 = mixed ? first_passes(n) : np;
-    bucket_sort<K, T, ITEMS>(S, n_pad, 0, p0);
-    if (p0 < np && mixed_groups<K, T, ITEMS>(S, n, 8 * p0)) bucket_sort<K, T, ITEMS>(S, n_pad, p0, np);
-    const u32 nruns = run_heads<K, T, ITEMS>(S, n);
+    bucket_sort(S, n_pad, 0, p0);
+    if (p0 < np && mixed_groups(S, n, 8 * p0)) bucket_sort(S, n_pad, p0, np);
+    const u32 nruns = run_heads(S, n);
     if (chunk) {
       const u32 kept =
           emit_runs_block<K>(S.keys, S.u.hp, nruns, n, false, 0, 0, sink, klk + ks, A.kl_c + ks, S.scr, mixed);

@@ -78,7 +78,7 @@ std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
 
 int auto_log_b(u64 n_max, int key_words, u32 variant) {
-  const u64 target = std::max<u64>(1, small_cap(key_words, variant) / 3);
+  const u64 target = bucket_target(key_words, variant);
   int lb = 1;
   while (lb < 20 && (n_max >> lb) > target) ++lb;
   return lb;
@@ -141,7 +141,7 @@ int autotune_device(const kc_job& j, const JobInfo& ji, const kc_config* base, k
   kc_config b{};
   if (base) b = *base;
   std::vector<TuneVal> cand;
-  for (u32 var : {1u, 2u})
+  for (u32 var : {1u, 2u, 3u})
     for (int d : {-1, 0, 1}) cand.push_back(TuneVal{d, var, 0.0});
   u64 ws_bytes = 0;
   for (auto& c : cand) {
