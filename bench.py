@@ -751,23 +751,32 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str) -> None:
 
     fs, ws = calib(fe), calib(wr)
     short = lambda n: n.split("(")[0].split("<")[0].strip().replace("void ", "")
-    kernels, total = {}, 0.0
+    # per kernel name (its template variants together): dispatch-weighted averages
+    acc = {}
     for name in sorted(set(fe) | set(wr)):
         if not short(name).startswith("k_"):
             continue            # calibration copy and fill, torch's own kernels
-        f_avg = float(np.mean(list(fe.get(name, {0: 0.0}).values())))
-        w_avg = float(np.mean(list(wr.get(name, {0: 0.0}).values())))
-        key = short(name)
+        f = list(fe.get(name, {}).values())
+        w = list(wr.get(name, {}).values())
+        a = acc.setdefault(short(name), {"f": 0.0, "nf": 0, "w": 0.0, "nw": 0, "variants": []})
+        a["f"] += sum(f)
+        a["nf"] += len(f)
+        a["w"] += sum(w)
+        a["nw"] += len(w)
+        a["variants"].append(name[:120])
+    kernels, total = {}, 0.0
+    for key, a in acc.items():
+        f_avg = a["f"] / max(1, a["nf"])
+        w_avg = a["w"] / max(1, a["nw"])
         b = 1024.0 * (f_avg * fs + w_avg * ws)
-        rec = kernels.setdefault(key, {"fetch_kib_per_dispatch": 0.0, "write_kib_per_dispatch": 0.0,
-                                       "traffic_bytes_per_launch": 0, "dispatches": 0, "variants": []})
-        n = len(fe.get(name, {}))
-        rec["variants"].append(name[:120])
-        rec["dispatches"] += n
-        rec["fetch_kib_per_dispatch"] = round(rec["fetch_kib_per_dispatch"] + f_avg, 1)
-        rec["write_kib_per_dispatch"] = round(rec["write_kib_per_dispatch"] + w_avg, 1)
-        rec["traffic_bytes_per_launch"] = int(rec["traffic_bytes_per_launch"] + b)
-        total += b * n
+        kernels[key] = {"fetch_kib_per_dispatch": round(f_avg, 1), "write_kib_per_dispatch": round(w_avg, 1),
+                        "traffic_bytes_per_launch": int(b), "dispatches": a["nf"], "variants": a["variants"]}
+    # bytes per count: the plain count's kernels over its k_extract dispatches; for the
+    # extension version its own kernels (k_ext_*, k_radix_*) over its k_ext_finalize
+    # dispatches (one per count, whatever its rounds)
+    ext = workload.startswith("ext")
+    own = {n: k for n, k in kernels.items() if not ext or n.startswith(("k_ext_", "k_radix_"))}
+    total = sum(k["traffic_bytes_per_launch"] * k["dispatches"] for k in own.values())
     try:
         with open(TRAFFIC_FILE) as f:
             data = json.load(f)
@@ -775,7 +784,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str) -> None:
         data = {}
     if data.get("src_hash") != src_hash():
         data = {"src_hash": src_hash(), "workloads": {}}
-    counts = max(1, max((k["dispatches"] for n, k in kernels.items() if n == "k_extract"), default=1))
+    per_count = "k_ext_finalize" if ext else "k_extract"
+    counts = max(1, max((k["dispatches"] for n, k in kernels.items() if n == per_count), default=1))
     data["workloads"][workload] = {"fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
                                    "counts_profiled": counts, "bytes_per_count": int(total / counts),
                                    "kernels": kernels}
