@@ -68,7 +68,9 @@ int fail(int code, const char* fmt, ...) {
 #define KC_RADIX_NB_MAX 1024
 #endif
 constexpr int RADIX_T = KC_RADIX_T;   // HBM radix passes: threads per block ...
-constexpr u32 WAVE_CAP_64 = 1024, WAVE_CAP_128 = 512;   // k-mers of a bucket sorted by one wave
+// k-mers of a bucket sorted by one wave: 896 64-bit keys keep a block of four waves within
+// 40 KB of LDS (16-bit digit counts), so that four blocks share a CU
+constexpr u32 WAVE_CAP_64 = 896, WAVE_CAP_128 = 512;
 constexpr int WAVES_PER_BLOCK = 4;
 constexpr int SEG_WAVES_PER_BLOCK = 2;   // k_seg_wave: more, smaller blocks measured slightly faster
 constexpr u32 RUN_BLOCKS = 1024;   // blocks of the merged-run kernel

@@ -677,7 +677,7 @@ struct WaveSmem {
   union {
     struct {
       u64 tbl[256];                 // lane masks per digit; all zero between uses
-      u32 cnt[256];                 // digit counts -> digit offsets
+      u16 cnt[256];                 // digit counts -> digit offsets (at most WCAP)
     } r;
     u16 hp[WCAP];                   // run heads after the sort
   } u;
@@ -703,7 +703,7 @@ __device__ __forceinline__ void wave_sort(WaveSmem<K, WCAP>& S, u32 n_pad, int p
         const u32 base = S.u.r.cnt[d];
         const u32 lr = mbcnt64(mask);
         if (lr == 0) {
-          S.u.r.cnt[d] = base + (u32)__popcll(mask);
+          S.u.r.cnt[d] = (u16)(base + (u32)__popcll(mask));
           S.u.r.tbl[d] = 0;
         }
         rk[j] = base + lr;
@@ -714,10 +714,10 @@ __device__ __forceinline__ void wave_sort(WaveSmem<K, WCAP>& S, u32 n_pad, int p
               c3 = S.u.r.cnt[4 * lane + 3];
     const u32 s4 = c0 + c1 + c2 + c3;
     const u32 ex = wave_scan_u32(s4) - s4;
-    S.u.r.cnt[4 * lane] = ex;
-    S.u.r.cnt[4 * lane + 1] = ex + c0;
-    S.u.r.cnt[4 * lane + 2] = ex + c0 + c1;
-    S.u.r.cnt[4 * lane + 3] = ex + c0 + c1 + c2;
+    S.u.r.cnt[4 * lane] = (u16)ex;
+    S.u.r.cnt[4 * lane + 1] = (u16)(ex + c0);
+    S.u.r.cnt[4 * lane + 2] = (u16)(ex + c0 + c1);
+    S.u.r.cnt[4 * lane + 3] = (u16)(ex + c0 + c1 + c2);
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       if (j < per) S.keys[S.u.r.cnt[key_digit(kr[j], 8 * p)] + rk[j]] = kr[j];
@@ -730,7 +730,7 @@ __device__ __forceinline__ void wave_sort(WaveSmem<K, WCAP>& S, u32 n_pad, int p
 template <typename K, int WCAP, int WPB, bool MS = false>
 __global__ __launch_bounds__(WPB * 64) void k_wave_sort_count(CountArgs A, const u32* __restrict__ tiny_list,
                                                                const u64* __restrict__ n_tiny_ptr) {
-  static_assert(WCAP * 2 <= 256 * 12, "run heads reuse the rank tables");
+  static_assert(sizeof(u16) * WCAP <= sizeof(WaveSmem<K, WCAP>::u), "run heads reuse the rank tables");
   constexpr int NS = MS ? WPB : 1;   // statistics slices: per block, or per wave for several sets
   __shared__ WaveSmem<K, WCAP> WS[WPB];
   __shared__ u32 hist_s[NS][256];
