@@ -82,6 +82,17 @@ def test_many_sets_per_count_match_oracle(per_set):
     _check_all(jobs, res, f"per_set={per_set}")
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_many_sets_per_count_every_block_shape(variant):
+    """The multi-set count with each on-chip block shape forced (the autotuner may pick
+    any of them), for 64- and 128-bit keys."""
+    kc = _kc()
+    jobs = _jobs(20, 12, 31, 17, 2, 50, 300) + _jobs(21, 8, 51, 21, 1, 100, 64)
+    print(f"case multiset block shape {variant}: {len(jobs)} jobs", flush=True)
+    res = kc.kc_count_batch(jobs, kc.make_config(lanes=2, small_variant=variant))
+    _check_all(jobs, res, f"small_variant={variant}")
+
+
 def test_sets_through_heavy_bucket_lists():
     """force_hbm: every bucket is cut into chunks whose lists are merged; neighbouring
     lists of two sets hold the same k-mers and must stay apart."""

@@ -55,7 +55,8 @@ def test_m_does_not_change_result(m):
 
 
 @pytest.mark.parametrize("cfg", [dict(force_hbm=True), dict(log2_buckets=1), dict(log2_buckets=20),
-                                 dict(small_variant=2), dict(log2_buckets=4, small_variant=2)])
+                                 dict(small_variant=1), dict(small_variant=2), dict(small_variant=3),
+                                 dict(log2_buckets=4, small_variant=2), dict(log2_buckets=6, small_variant=3)])
 @pytest.mark.parametrize("k", [31, 51])
 def test_paths_and_bucket_counts(cfg, k):
     kc = _kc()
